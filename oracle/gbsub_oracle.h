@@ -1,0 +1,116 @@
+/*
+ * gbsub_oracle.h -- plain FP64 CPU oracle of the iterative galactic-binary
+ * subtraction (TEST INFRASTRUCTURE ONLY).
+ *
+ * This is the reference that the HIP library is checked against.  Only the
+ * test suite, the smoke check and the benchmark's CPU-baseline leg may load
+ * it; the product path never does.  It shares no code, header, table or
+ * constant generator with the HIP library.
+ *
+ * What it computes follows the paper (De Santi et al., "Inferring the
+ * population properties of galactic binaries from LISA's stochastic
+ * foreground"):
+ *   - frequency grid with resolution 1/T_obs (Sec. "Coarse-graining of the
+ *     data": the subtraction output has resolution 1/T_obs);
+ *   - SciRDv1 instrumental noise S_AA (appendix "LISA instrumental noise")
+ *     divided by the TDI response R_AA (appendix "Characteristic strain",
+ *     TDI-response equation) to give a strain-equivalent PSD;
+ *   - SNR^2 = sum over the A and E channels of <h|h> (Eqs. "SNR inner product"
+ *     and "inner product") in the sky-averaged power form;
+ *   - the subtraction algorithm of the appendix "Subtraction algorithm":
+ *     initial SNR against S_instr, candidate cut rho >= kappa*rho_th, then
+ *     repeat { running-median (or running-mean) PSD estimate, SNR against it,
+ *     subtract every source with rho > rho_th } until nothing is subtracted.
+ * Precision: IEEE binary64, round-to-nearest, no FMA contraction
+ * (-ffp-contract=off), every sum in ascending index order.
+ */
+#ifndef GBSUB_ORACLE_H
+#define GBSUB_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORC_OK = 0, ORC_E_INVALID = -1, ORC_E_MAXITER = -6 };
+enum { ORC_MEDIAN = 0, ORC_MEAN = 1 };
+enum { ORC_TRACK_SWEEP = 0, ORC_TRACK_SINGLE = 1 };
+
+typedef struct {
+    double   t_obs_s, f_min_hz, f_max_hz;
+    int64_t  window_bins;       /* odd, >= 1 */
+    double   snr_threshold;     /* rho_th */
+    double   kappa;             /* candidate cut rho_0 >= kappa*rho_th */
+    double   median_scale;      /* C in S = C*median + S_instr */
+    int32_t  estimator;         /* ORC_MEDIAN | ORC_MEAN */
+    int32_t  track_model;       /* ORC_TRACK_SWEEP | ORC_TRACK_SINGLE */
+    int64_t  max_iter;          /* 0 = n_candidates + 1 */
+    double   oms_pm, tm_fm, arm_m;  /* SciRDv1: P = 15, A = 3, L = 2.5e9 m */
+    double   noise_scale;       /* test hook: S_instr is multiplied by this (1.0 normally) */
+} orc_config;
+
+typedef struct {
+    int64_t n_iter, n_bins, k0, n_candidates, n_resolved, n_near;
+    double  min_rel_margin;     /* min over evaluated (t,i) of |rho/rho_th - 1| */
+} orc_summary;
+
+/* Per-iteration trace: called after S^t and the candidates' rho^2 at t are
+ * known and before anything is subtracted.  X and S have n_bins entries;
+ * cand[j] is the source index of candidate j, rho2[j] its rho^2 at t, or -1
+ * if it was already resolved. */
+typedef void (*orc_trace_fn)(void *user, int64_t t, int64_t n_bins,
+                             const double *X, const double *S,
+                             int64_t n_cand, const int64_t *cand, const double *rho2);
+
+typedef struct {
+    /* outputs (any may be NULL) */
+    int32_t *iter_of;       /* [n] : t at which source i was resolved, -1 if never */
+    uint8_t *is_candidate;  /* [n] */
+    double  *rho0_sq;       /* [n] : rho^2 against S_instr */
+    double  *S_final;       /* [n_bins] */
+    double  *X_final;       /* [n_bins] */
+    /* near-threshold log: (t, i) with |rho_i/rho_th - 1| <= near_band */
+    double   near_band;     /* 1e-6 by default if <= 0 */
+    int64_t  near_cap;
+    int64_t *near_t, *near_i;
+    /* guided replay: for these (t, i) the decision is taken from over_dec
+     * (1 = resolve at t, 0 = do not) instead of from the comparison. */
+    int64_t  n_over;
+    const int64_t *over_t, *over_i;
+    const uint8_t *over_dec;
+    orc_trace_fn trace;
+    void    *trace_user;
+} orc_io;
+
+void    orc_default_config(orc_config *c);
+int     orc_set_threads(int n);           /* OpenMP threads; returns the count in use */
+
+/* O1: grid.  k0 = floor(f_min*T + 1/2), k1 = floor(f_max*T + 1/2), B = k1-k0+1. */
+int     orc_grid(double t_obs_s, double f_min_hz, double f_max_hz, int64_t *k0, int64_t *n_bins);
+
+/* O2: strain-equivalent instrumental PSD S_AA(f)/R_AA(f), and its parts. */
+double  orc_s_aa(double f, double oms_pm, double tm_fm, double arm_m);
+double  orc_r_aa(double f, double arm_m);
+double  orc_sinstr(double f, double oms_pm, double tm_fm, double arm_m);
+void    orc_sinstr_table(const orc_config *c, int64_t k0, int64_t n_bins, double *out);
+
+/* O3: power and track of one source.  Returns ORC_OK or ORC_E_INVALID. */
+int     orc_track(const orc_config *c, int64_t k0, int64_t n_bins, float A, float f, float fdot,
+                  int64_t *lo, int64_t *n, double *q, int64_t *glo, int64_t *ghi);
+
+/* O4: rho^2 = 4 q sum_{k in [glo,ghi]} 1/S[k] (0 if the range is empty). */
+double  orc_snr2(double q, int64_t glo, int64_t ghi, const double *S);
+
+/* O6: running-median (clamped full window of odd width W) and running-mean
+ * order statistics; out[k] = ((W+1)/2)-th smallest of the window of k. */
+void    orc_running_median(const double *X, int64_t n_bins, int64_t W, double *out);
+void    orc_running_mean_psd(const double *X, const double *Sx, int64_t n_bins, int64_t W, double *out);
+
+/* The whole subtraction.  Returns ORC_OK, ORC_E_INVALID or ORC_E_MAXITER. */
+int     orc_run(const orc_config *c, int64_t n, const float *A, const float *f, const float *fdot,
+                orc_io *io, orc_summary *sum);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,269 @@
+"""Python access to the FP64 CPU oracle (TEST INFRASTRUCTURE ONLY).
+
+Loads ``oracle/_build/libgbsub_oracle.so`` (built from ``gbsub_oracle.c`` by
+:func:`build` with gcc, FMA contraction off, OpenMP on) and wraps it with
+ctypes.  Only the tests, the smoke check and the benchmark's CPU-baseline leg
+use this module; the product library never does.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "gbsub_oracle.c")
+HDR = os.path.join(HERE, "gbsub_oracle.h")
+BUILD_DIR = os.path.join(HERE, "_build")
+LIB = os.path.join(BUILD_DIR, "libgbsub_oracle.so")
+
+OK, E_INVALID, E_MAXITER = 0, -1, -6
+MEDIAN, MEAN = 0, 1
+TRACK_SWEEP, TRACK_SINGLE = 0, 1
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle (gcc, -O2, no FMA contraction, OpenMP)."""
+    os.makedirs(BUILD_DIR, exist_ok=True)
+    if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= max(
+            os.path.getmtime(SRC), os.path.getmtime(HDR)):
+        return LIB
+    tmp = LIB + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+           "-fPIC", "-shared", "-Wall", "-o", tmp, SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+class Config(C.Structure):
+    _fields_ = [("t_obs_s", C.c_double), ("f_min_hz", C.c_double), ("f_max_hz", C.c_double),
+                ("window_bins", C.c_int64), ("snr_threshold", C.c_double), ("kappa", C.c_double),
+                ("median_scale", C.c_double), ("estimator", C.c_int32), ("track_model", C.c_int32),
+                ("max_iter", C.c_int64), ("oms_pm", C.c_double), ("tm_fm", C.c_double),
+                ("arm_m", C.c_double), ("noise_scale", C.c_double)]
+
+
+class Summary(C.Structure):
+    _fields_ = [("n_iter", C.c_int64), ("n_bins", C.c_int64), ("k0", C.c_int64),
+                ("n_candidates", C.c_int64), ("n_resolved", C.c_int64), ("n_near", C.c_int64),
+                ("min_rel_margin", C.c_double)]
+
+
+TRACE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_int64, C.c_int64, C.POINTER(C.c_double),
+                       C.POINTER(C.c_double), C.c_int64, C.POINTER(C.c_int64),
+                       C.POINTER(C.c_double))
+
+
+class IO(C.Structure):
+    _fields_ = [("iter_of", C.POINTER(C.c_int32)), ("is_candidate", C.POINTER(C.c_uint8)),
+                ("rho0_sq", C.POINTER(C.c_double)), ("S_final", C.POINTER(C.c_double)),
+                ("X_final", C.POINTER(C.c_double)), ("near_band", C.c_double),
+                ("near_cap", C.c_int64), ("near_t", C.POINTER(C.c_int64)),
+                ("near_i", C.POINTER(C.c_int64)), ("n_over", C.c_int64),
+                ("over_t", C.POINTER(C.c_int64)), ("over_i", C.POINTER(C.c_int64)),
+                ("over_dec", C.POINTER(C.c_uint8)), ("trace", TRACE_FN),
+                ("trace_user", C.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = build()
+        L = C.CDLL(path)
+        L.orc_default_config.argtypes = [C.POINTER(Config)]
+        L.orc_set_threads.argtypes = [C.c_int]
+        L.orc_set_threads.restype = C.c_int
+        L.orc_grid.argtypes = [C.c_double, C.c_double, C.c_double, C.POINTER(C.c_int64),
+                               C.POINTER(C.c_int64)]
+        L.orc_grid.restype = C.c_int
+        for name in ("orc_s_aa", "orc_sinstr"):
+            getattr(L, name).argtypes = [C.c_double] * 4
+            getattr(L, name).restype = C.c_double
+        L.orc_r_aa.argtypes = [C.c_double, C.c_double]
+        L.orc_r_aa.restype = C.c_double
+        L.orc_sinstr_table.argtypes = [C.POINTER(Config), C.c_int64, C.c_int64, C.c_void_p]
+        L.orc_track.argtypes = [C.POINTER(Config), C.c_int64, C.c_int64, C.c_float, C.c_float,
+                                C.c_float] + [C.POINTER(C.c_int64)] * 2 + [
+                                    C.POINTER(C.c_double)] + [C.POINTER(C.c_int64)] * 2
+        L.orc_track.restype = C.c_int
+        L.orc_snr2.argtypes = [C.c_double, C.c_int64, C.c_int64, C.c_void_p]
+        L.orc_snr2.restype = C.c_double
+        L.orc_running_median.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.c_void_p]
+        L.orc_running_mean_psd.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64,
+                                           C.c_void_p]
+        L.orc_run.argtypes = [C.POINTER(Config), C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
+                              C.POINTER(IO), C.POINTER(Summary)]
+        L.orc_run.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def set_threads(n: int = 0) -> int:
+    return lib().orc_set_threads(int(n))
+
+
+def make_config(run=None, **kw) -> Config:
+    """Oracle config from a ``RunConfig``-like object (or keywords)."""
+    c = Config()
+    lib().orc_default_config(C.byref(c))
+    src = {}
+    if run is not None:
+        src.update(run.as_dict() if hasattr(run, "as_dict") else dict(run))
+    src.update(kw)
+    for k, v in src.items():
+        if k in ("precision",):
+            continue
+        if k == "max_iter" and v is None:
+            v = 0
+        setattr(c, k, v)
+    return c
+
+
+def grid(t_obs_s: float, f_min_hz: float, f_max_hz: float):
+    k0, B = C.c_int64(), C.c_int64()
+    rc = lib().orc_grid(t_obs_s, f_min_hz, f_max_hz, C.byref(k0), C.byref(B))
+    if rc != OK:
+        raise ValueError("invalid grid")
+    return k0.value, B.value
+
+
+def sinstr(f: float, oms_pm=15.0, tm_fm=3.0, arm_m=2.5e9) -> float:
+    return lib().orc_sinstr(float(f), oms_pm, tm_fm, arm_m)
+
+
+def s_aa(f: float, oms_pm=15.0, tm_fm=3.0, arm_m=2.5e9) -> float:
+    return lib().orc_s_aa(float(f), oms_pm, tm_fm, arm_m)
+
+
+def r_aa(f: float, arm_m=2.5e9) -> float:
+    return lib().orc_r_aa(float(f), arm_m)
+
+
+def sinstr_table(cfg: Config) -> np.ndarray:
+    k0, B = grid(cfg.t_obs_s, cfg.f_min_hz, cfg.f_max_hz)
+    out = np.empty(B, np.float64)
+    lib().orc_sinstr_table(C.byref(cfg), k0, B, out.ctypes.data)
+    return out
+
+
+def track(cfg: Config, A: float, f: float, fdot: float):
+    k0, B = grid(cfg.t_obs_s, cfg.f_min_hz, cfg.f_max_hz)
+    lo, n, glo, ghi = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int64()
+    q = C.c_double()
+    rc = lib().orc_track(C.byref(cfg), k0, B, A, f, fdot, C.byref(lo), C.byref(n), C.byref(q),
+                         C.byref(glo), C.byref(ghi))
+    if rc != OK:
+        raise ValueError("invalid source")
+    return dict(lo=lo.value, n=n.value, q=q.value, glo=glo.value, ghi=ghi.value)
+
+
+def snr2(q: float, glo: int, ghi: int, S: np.ndarray) -> float:
+    S = np.ascontiguousarray(S, np.float64)
+    return lib().orc_snr2(q, glo, ghi, S.ctypes.data)
+
+
+def running_median(X: np.ndarray, W: int) -> np.ndarray:
+    X = np.ascontiguousarray(X, np.float64)
+    out = np.empty_like(X)
+    lib().orc_running_median(X.ctypes.data, X.shape[0], int(W), out.ctypes.data)
+    return out
+
+
+def running_mean_psd(X: np.ndarray, Sx: np.ndarray, W: int) -> np.ndarray:
+    X = np.ascontiguousarray(X, np.float64)
+    Sx = np.ascontiguousarray(Sx, np.float64)
+    out = np.empty_like(X)
+    lib().orc_running_mean_psd(X.ctypes.data, Sx.ctypes.data, X.shape[0], int(W),
+                               out.ctypes.data)
+    return out
+
+
+@dataclass
+class Result:
+    status: int
+    n_iter: int
+    n_bins: int
+    k0: int
+    n_candidates: int
+    n_resolved: int
+    n_near: int
+    min_rel_margin: float
+    iter_of: np.ndarray          # int32 [n], -1 = not resolved
+    is_candidate: np.ndarray     # bool [n]
+    rho0_sq: np.ndarray          # float64 [n]
+    S_final: np.ndarray | None
+    X_final: np.ndarray | None
+    near: list                   # [(t, i)]
+    trace: list                  # per iteration dicts when requested
+
+    def resolved_ids(self, ids: np.ndarray) -> np.ndarray:
+        sel = self.iter_of >= 0
+        order = np.argsort(ids[sel], kind="stable")
+        return ids[sel][order]
+
+
+def run(catalog, cfg: Config, *, spectra: bool = True, trace: bool = False,
+        near_cap: int = 4096, overrides=None) -> Result:
+    """Run the whole subtraction on ``catalog`` (arrays A, f, fdot)."""
+    A = np.ascontiguousarray(catalog.A, np.float32)
+    f = np.ascontiguousarray(catalog.f, np.float32)
+    fd = np.ascontiguousarray(catalog.fdot, np.float32)
+    n = A.shape[0]
+    k0, B = grid(cfg.t_obs_s, cfg.f_min_hz, cfg.f_max_hz)
+    iter_of = np.empty(max(n, 1), np.int32)
+    is_c = np.zeros(max(n, 1), np.uint8)
+    rho0 = np.zeros(max(n, 1), np.float64)
+    S = np.empty(B, np.float64) if spectra else None
+    X = np.empty(B, np.float64) if spectra else None
+    near_t = np.zeros(near_cap, np.int64)
+    near_i = np.zeros(near_cap, np.int64)
+    io = IO()
+    io.iter_of = iter_of.ctypes.data_as(C.POINTER(C.c_int32))
+    io.is_candidate = is_c.ctypes.data_as(C.POINTER(C.c_uint8))
+    io.rho0_sq = rho0.ctypes.data_as(C.POINTER(C.c_double))
+    if spectra:
+        io.S_final = S.ctypes.data_as(C.POINTER(C.c_double))
+        io.X_final = X.ctypes.data_as(C.POINTER(C.c_double))
+    io.near_band = 1e-6
+    io.near_cap = near_cap
+    io.near_t = near_t.ctypes.data_as(C.POINTER(C.c_int64))
+    io.near_i = near_i.ctypes.data_as(C.POINTER(C.c_int64))
+    keep = []
+    if overrides:
+        ot = np.array([o[0] for o in overrides], np.int64)
+        oi = np.array([o[1] for o in overrides], np.int64)
+        od = np.array([1 if o[2] else 0 for o in overrides], np.uint8)
+        keep += [ot, oi, od]
+        io.n_over = len(overrides)
+        io.over_t = ot.ctypes.data_as(C.POINTER(C.c_int64))
+        io.over_i = oi.ctypes.data_as(C.POINTER(C.c_int64))
+        io.over_dec = od.ctypes.data_as(C.POINTER(C.c_uint8))
+    traces = []
+    if trace:
+        def _cb(user, t, nb, Xp, Sp, nc, cp, rp):
+            traces.append(dict(
+                t=int(t),
+                X=np.ctypeslib.as_array(Xp, (nb,)).copy(),
+                S=np.ctypeslib.as_array(Sp, (nb,)).copy(),
+                cand=np.ctypeslib.as_array(cp, (nc,)).copy() if nc else np.zeros(0, np.int64),
+                rho2=np.ctypeslib.as_array(rp, (nc,)).copy() if nc else np.zeros(0)))
+        cb = TRACE_FN(_cb)
+        keep.append(cb)
+        io.trace = cb
+    summ = Summary()
+    rc = lib().orc_run(C.byref(cfg), n, A.ctypes.data, f.ctypes.data, fd.ctypes.data,
+                       C.byref(io), C.byref(summ))
+    nn = min(summ.n_near, near_cap)
+    return Result(status=rc, n_iter=summ.n_iter, n_bins=summ.n_bins, k0=summ.k0,
+                  n_candidates=summ.n_candidates, n_resolved=summ.n_resolved,
+                  n_near=summ.n_near, min_rel_margin=summ.min_rel_margin,
+                  iter_of=iter_of[:n].copy(), is_candidate=is_c[:n].astype(bool),
+                  rho0_sq=rho0[:n].copy(), S_final=S, X_final=X,
+                  near=[(int(near_t[j]), int(near_i[j])) for j in range(nn)], trace=traces)
