@@ -75,7 +75,7 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        path = build()
+        path = os.environ.get("GBSUB_ORACLE_LIB") or build()
         L = C.CDLL(path)
         L.orc_default_config.argtypes = [C.POINTER(Config)]
         L.orc_set_threads.argtypes = [C.c_int]

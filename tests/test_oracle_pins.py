@@ -1,0 +1,446 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Every expected value here comes from a closed form, a special case with a
+known answer, a library routine, brute force on tiny inputs, or an invariant:
+never from the oracle itself and never from the HIP path.
+"""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import scipy.ndimage
+
+from oracle import oracle as O
+from oracle import micro
+from paper_2602_18560_amd.inputs import YEAR_S, Population, draw_catalog
+from tests.helpers import C_MED, amp_for_power, bin_freq, catalog, small_run
+
+C_LIGHT = 299792458.0
+L_ARM = 2.5e9
+
+
+# --------------------------------------------------------------------------- constants
+
+def test_median_scale_is_closed_form():
+    # Eq. for C: (1 - 2/(9 nu))^-3 with nu = 2 degrees of freedom.
+    c = (1 - Fraction(2, 9 * 2)) ** -3
+    assert c == Fraction(729, 512)
+    cfg = O.make_config()
+    assert cfg.median_scale == 729.0 / 512.0
+    # The printed "1.4237" is within 2e-4 of the closed form (a truncation typo).
+    assert abs(float(c) - 1.4237) < 2e-4
+    assert cfg.snr_threshold == 7.0 and cfg.kappa * cfg.snr_threshold == 1.0
+
+
+# --------------------------------------------------------------------------- noise
+
+def _rcl_low_frequency(f):
+    """Robson, Cornish & Liu (2019) sky-averaged LISA sensitivity
+    S_n = 10/(3 L^2) (P_OMS + 4 P_acc / (2 pi f)^4) without its high-frequency
+    factor, SciRDv1 budget: P_OMS = (15 pm)^2 (1 + (2 mHz/f)^4),
+    P_acc = (3 fm/s^2)^2 (1 + (0.4 mHz/f)^2)(1 + (f/8 mHz)^4).  In the long-
+    wavelength limit (f << f*) S_AA / R_AA must reduce to it: the A-channel
+    response is 9/20 of the long-arm 16 u^4 and the noise combination is
+    12 P_TM + 3 P_OMS."""
+    p_oms = (15e-12) ** 2 * (1 + (2e-3 / f) ** 4)
+    p_acc = (3e-15) ** 2 * (1 + (4e-4 / f) ** 2) * (1 + (f / 8e-3) ** 4)
+    return 10.0 / (3.0 * L_ARM ** 2) * (p_oms + 4 * p_acc / (2 * math.pi * f) ** 4)
+
+
+@pytest.mark.parametrize("f", [1e-5, 3e-5, 1e-4, 3e-4, 1e-3])
+def test_sinstr_long_wavelength_limit(f):
+    u = 2 * math.pi * f * L_ARM / C_LIGHT
+    r = O.sinstr(f) / _rcl_low_frequency(f)
+    # First-order corrections: cos terms give -u^2/2 (TM) / -u^2/6 (OMS), the
+    # response denominator +0.7 u^2; the ratio is 1 + O(0.6 u^2).
+    assert abs(r - 1.0) <= 0.6 * u * u + 1e-13, (f, r)
+
+
+@pytest.mark.parametrize("f", [1e-5, 1e-4, 1e-3])
+def test_response_long_wavelength_limit(f):
+    u = 2 * math.pi * f * L_ARM / C_LIGHT
+    # 16 sin^2(u) u^2 (9/20)/(1+0.7u^2) -> 7.2 u^4 (1 - u^2/3 - 0.7 u^2 + ...)
+    r = O.r_aa(f) / (7.2 * u ** 4)
+    assert abs(r - 1.0) <= 1.1 * u * u + 1e-13
+
+
+def test_sinstr_magnitudes_and_shape():
+    # The foreground matters near 1 mHz (introduction): the instrument there
+    # sits at ~1e-38 /Hz and its bucket (minimum) lies at a few mHz.
+    f = np.geomspace(1e-4, 3e-2, 400)
+    s = np.array([O.sinstr(x) for x in f])
+    assert np.all(np.isfinite(s)) and np.all(s > 0)
+    kmin = int(np.argmin(s))
+    assert 3e-3 < f[kmin] < 2e-2
+    assert 1e-38 < O.sinstr(1e-3) < 3e-38
+    # steep f^-4 (TM) rise at low frequency
+    assert O.sinstr(1e-4) / O.sinstr(2e-4) > 8
+
+
+def test_grid_sizes_of_the_workloads():
+    k0, B = O.grid(YEAR_S, 3e-4, 1e-2)
+    assert (k0, B) == (9467, 306110)
+    k0, B = O.grid(4 * YEAR_S, 1e-4, 3e-2)
+    assert (k0, B) == (12623, 3774290)
+    k0, B = O.grid(YEAR_S, 1e-4, 3e-2)
+    assert B == 943573
+    k0, B = O.grid(2 * YEAR_S, 1e-4, 3e-2)
+    assert B == 1887145
+
+
+# --------------------------------------------------------------------------- median
+
+def _brute_median(X, W):
+    B = len(X)
+    if B < W:
+        return np.full(B, np.sort(X)[(B + 1) // 2 - 1])
+    h = (W - 1) // 2
+    out = np.empty(B)
+    for k in range(B):
+        a = min(max(k - h, 0), B - W)
+        out[k] = np.sort(X[a:a + W])[h]
+    return out
+
+
+@pytest.mark.parametrize("B,W", [(1, 1), (1, 3), (2, 3), (7, 3), (7, 7), (7, 9), (50, 1), (50, 5),
+                                 (200, 51), (200, 199), (200, 201), (200, 301), (513, 101)])
+def test_running_median_brute_force(B, W):
+    rng = np.random.default_rng(B * 1000 + W)
+    X = rng.exponential(1.0, B)
+    X[rng.random(B) < 0.3] = 0.0                       # many zeros
+    X[rng.random(B) < 0.2] = 0.5                       # exact duplicates
+    np.testing.assert_array_equal(O.running_median(X, W), _brute_median(X, W))
+
+
+@pytest.mark.parametrize("W", [3, 11, 101, 251])
+def test_running_median_matches_scipy_interior(W):
+    rng = np.random.default_rng(W)
+    X = rng.gamma(1.5, 2.0, 3000) * 1e-40
+    h = (W - 1) // 2
+    ref = scipy.ndimage.median_filter(X, size=W, mode="nearest")
+    got = O.running_median(X, W)
+    np.testing.assert_array_equal(got[h:len(X) - h], ref[h:len(X) - h])
+
+
+def test_running_median_is_1_lipschitz():
+    rng = np.random.default_rng(7)
+    X = rng.exponential(1.0, 2000)
+    Y = X + rng.uniform(-1e-3, 1e-3, 2000)
+    d = np.abs(O.running_median(X, 101) - O.running_median(Y, 101))
+    assert d.max() <= np.abs(X - Y).max()
+
+
+# --------------------------------------------------------------------------- closed-form catalogs
+
+@pytest.mark.parametrize("target_rho2", [60.0, 40.0])
+def test_lone_monochromatic_binary(target_rho2):
+    run, k0 = small_run(n_bins=200, W=5)
+    T = run.t_obs_s
+    c = 100
+    fc = bin_freq(k0, c, T)
+    sx = O.sinstr(fc)
+    P = target_rho2 * sx / 4.0
+    cat = catalog([amp_for_power(P, T)], [fc])
+    cfg = O.make_config(run)
+    r = O.run(cat, cfg)
+    A = float(cat.A[0])
+    rho2 = 2.0 * A * A * T / sx                        # 2 A^2 T / S_x(f_c)
+    assert r.rho0_sq[0] == pytest.approx(rho2, rel=1e-15)
+    Sx = O.sinstr_table(cfg)
+    np.testing.assert_array_equal(r.S_final, Sx)        # a single bin never reaches the median
+    if target_rho2 > 49:
+        assert r.iter_of.tolist() == [0] and r.n_iter == 2
+        assert np.all(r.X_final == 0)
+    else:
+        assert r.iter_of.tolist() == [-1] and r.n_iter == 1
+        assert r.X_final[c] == pytest.approx(A * A * T / 2, rel=1e-15)
+
+
+def test_all_below_threshold_single_pass():
+    run, k0 = small_run(n_bins=300, W=11)
+    T = run.t_obs_s
+    cfg = O.make_config(run)
+    Sx = O.sinstr_table(cfg)
+    rng = np.random.default_rng(1)
+    bins = rng.choice(300, 120, replace=False)
+    P = Sx[bins] * rng.uniform(0.01, 0.2, 120)         # rho_0^2 = 4P/S_x < 1
+    cat = catalog([amp_for_power(p, T) for p in P], [bin_freq(k0, b, T) for b in bins])
+    r = O.run(cat, cfg)
+    assert r.n_candidates == 0 and r.n_iter == 1 and r.n_resolved == 0
+    X = np.zeros(300)
+    A = cat.A.astype(np.float64)
+    X[bins] = A * A * T / 2
+    np.testing.assert_array_equal(r.X_final, X)
+    np.testing.assert_allclose(r.S_final, C_MED * _brute_median(X, 11) + Sx, rtol=1e-15)
+
+
+def test_all_above_threshold_sparse():
+    run, k0 = small_run(n_bins=300, W=5)               # h = 2
+    T = run.t_obs_s
+    cfg = O.make_config(run)
+    Sx = O.sinstr_table(cfg)
+    bins = np.arange(1, 300, 3)                        # <= 2 occupied bins per window
+    P = Sx[bins] * 50.0                                # rho^2 = 200 > 49 against S_x
+    cat = catalog([amp_for_power(p, T) for p in P], [bin_freq(k0, b, T) for b in bins])
+    r = O.run(cat, cfg)
+    assert r.n_iter == 2 and np.all(r.iter_of == 0)
+    np.testing.assert_array_equal(r.S_final, Sx)
+    assert np.all(r.X_final == 0)
+
+
+def _comb(n_bins, W, q_rel=1.0, seed=0):
+    run, k0 = small_run(n_bins=n_bins, W=W)
+    cfg = O.make_config(run)
+    Sx = O.sinstr_table(cfg)
+    q = q_rel * float(Sx.max())
+    T = run.t_obs_s
+    A = amp_for_power(q, T)
+    return run, k0, cfg, Sx, A, T
+
+
+def test_uniform_comb_resolves_nothing():
+    run, k0, cfg, Sx, A, T = _comb(240, 7, q_rel=3.0)
+    cat = catalog([A] * 240, [bin_freq(k0, b, T) for b in range(240)])
+    r = O.run(cat, cfg)
+    q = float(cat.A[0]) ** 2 * T / 2
+    assert r.n_candidates == 240                       # rho_0^2 = 4q/S_x >= 12
+    assert r.n_iter == 1 and r.n_resolved == 0         # rho^2 < 4/C < 49 always
+    np.testing.assert_array_equal(r.S_final, C_MED * q + Sx)
+
+
+def test_comb_plus_isolated_loud_sources():
+    run, k0, cfg, Sx, A, T = _comb(240, 7, q_rel=1.0)
+    q = float(np.float32(A)) ** 2 * T / 2
+    loud_bins = np.arange(5, 240, 10)                  # <= 1 loud bin per 7-bin window
+    S0 = C_MED * q + Sx[loud_bins]
+    factor = np.where(np.arange(len(loud_bins)) % 2 == 0, 2.0, 0.5)
+    PL = 49.0 / 4.0 * S0 * factor                      # x2 above / x2 below threshold
+    As = [A] * 240 + [amp_for_power(p, T) for p in PL]
+    fs = [bin_freq(k0, b, T) for b in range(240)] + [bin_freq(k0, b, T) for b in loud_bins]
+    r = O.run(catalog(As, fs), cfg)
+    expect = np.full(240 + len(loud_bins), -1)
+    expect[240:][factor > 1] = 0
+    np.testing.assert_array_equal(r.iter_of, expect)
+    assert r.n_iter == 2
+    np.testing.assert_array_equal(r.S_final, C_MED * q + Sx)
+
+
+def cascade_catalog(n_periods=40):
+    """Period-5 pattern [L, M, 0, L, M] with W = 5 (h = 2): every window holds
+    2 loud, 2 medium, 1 empty bin.  t=0: median = q_M, only loud sources
+    resolve (medium ones cannot: 4/C < 49); t=1: median = 0, medium sources
+    resolve against S_x; t=2: nothing left.  Margins are x2."""
+    B = 5 * n_periods
+    run, k0 = small_run(n_bins=B, W=5)
+    cfg = O.make_config(run)
+    Sx = O.sinstr_table(cfg)
+    T = run.t_obs_s
+    smax = float(Sx.max())
+    qM = 2.0 * 49.0 / 4.0 * smax                       # 4 qM / S_x >= 98 > 49
+    qL = 2.0 * 49.0 / 4.0 * (C_MED * qM + smax)        # 4 qL / (C qM + S_x) >= 98
+    kinds, bins = [], []
+    for b in range(B):
+        k = ("L", "M", None, "L", "M")[b % 5]
+        if k:
+            kinds.append(k)
+            bins.append(b)
+    A = [amp_for_power(qL if k == "L" else qM, T) for k in kinds]
+    cat = catalog(A, [bin_freq(k0, b, T) for b in bins])
+    return cat, run, np.array(kinds), np.array(bins)
+
+
+def test_three_iteration_cascade():
+    cat, run, kinds, bins = cascade_catalog()
+    r = O.run(cat, O.make_config(run))
+    assert r.n_iter == 3
+    np.testing.assert_array_equal(r.iter_of[kinds == "L"], 0)
+    np.testing.assert_array_equal(r.iter_of[kinds == "M"], 1)
+    np.testing.assert_array_equal(r.S_final, O.sinstr_table(O.make_config(run)))
+
+
+def test_max_iter_guard():
+    cat, run, _, _ = cascade_catalog(10)
+    r = O.run(cat, O.make_config(run, max_iter=2))
+    assert r.status == O.E_MAXITER
+    r = O.run(cat, O.make_config(run, max_iter=3))
+    assert r.status == O.OK and r.n_iter == 3
+
+
+def test_duplicate_sources_in_one_bin():
+    run, k0 = small_run(n_bins=100, W=5)
+    cfg = O.make_config(run)
+    Sx = O.sinstr_table(cfg)
+    T = run.t_obs_s
+    c = 50
+    q1, q2 = 30.0 * Sx[c], 5.0 * Sx[c]                 # rho^2 = 120 and 20 against S_x
+    cat = catalog([amp_for_power(q1, T), amp_for_power(q2, T)], [bin_freq(k0, c, T)] * 2)
+    r = O.run(cat, cfg)
+    assert r.iter_of.tolist() == [0, -1] and r.n_iter == 2
+    a2 = float(cat.A[1])
+    assert r.X_final[c] == a2 * a2 * T / 2
+    assert r.X_final.sum() == r.X_final[c]
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 7, 64])
+def test_track_model_width_and_snr(n):
+    run, k0 = small_run(n_bins=400, W=5)
+    cfg = O.make_config(run)
+    T = run.t_obs_s
+    Sx = O.sinstr_table(cfg)
+    fdot = (n - 0.5) / (T * T)                        # s = |fdot| T^2 = n - 1/2
+    f = bin_freq(k0, 200, T) - fdot * T / 2           # mid-track frequency at bin 200
+    tr = O.track(cfg, 1e-22, f, fdot)
+    assert tr["n"] == n
+    assert tr["lo"] == 200 - (n - 1) // 2
+    P = float(np.float32(1e-22)) ** 2 * T / 2
+    assert tr["q"] == pytest.approx(P / n, rel=1e-15)
+    lo, hi = tr["lo"], tr["lo"] + n - 1
+    rho2 = 4 * (P / n) * np.sum(1.0 / Sx[lo:hi + 1])
+    assert O.snr2(tr["q"], tr["glo"], tr["ghi"], Sx) == pytest.approx(rho2, rel=1e-14)
+    single = O.make_config(run, track_model=O.TRACK_SINGLE)
+    assert O.track(single, 1e-22, f, fdot)["n"] == 1
+
+
+def test_track_clipped_at_grid_edges():
+    run, k0 = small_run(n_bins=50, W=5)
+    cfg = O.make_config(run)
+    T = run.t_obs_s
+    fdot = (20 - 0.5) / (T * T)
+    tr = O.track(cfg, 1e-22, bin_freq(k0, 2, T) - fdot * T / 2, fdot)
+    assert tr["n"] == 20 and tr["lo"] < 0 and tr["glo"] == 0 and tr["ghi"] == tr["lo"] + 19
+    far = O.track(cfg, 1e-22, bin_freq(k0, 500, T), 0.0)
+    assert far["glo"] > far["ghi"]                    # empty: contributes nothing
+    Sx = O.sinstr_table(cfg)
+    assert O.snr2(far["q"], far["glo"], far["ghi"], Sx) == 0.0
+
+
+# --------------------------------------------------------------------------- invariants
+
+def _dense_catalog(n=3000, seed=11):
+    """A narrow-band dense catalog that needs several iterations."""
+    pop = Population(n=n, seed=seed, f_lo=1.0e-3, f_hi=1.02e-3, gamma=3.0, k=1.5, theta=2.0,
+                     rho=0.5)
+    cat = draw_catalog(pop)
+    cat.A *= np.float32(400.0)
+    run, _ = small_run(n_bins=700, f_min=0.9995e-3, W=21)
+    return cat, run
+
+
+def test_dense_catalog_iterates():
+    cat, run = _dense_catalog()
+    r = O.run(cat, O.make_config(run))
+    assert r.status == O.OK and r.n_iter >= 3
+
+
+def test_monotone_and_terminating():
+    cat, run = _dense_catalog()
+    cfg = O.make_config(run)
+    r = O.run(cat, cfg, trace=True)
+    Sx = O.sinstr_table(cfg)
+    assert len(r.trace) == r.n_iter <= r.n_candidates + 1
+    for a, b in zip(r.trace, r.trace[1:]):
+        assert np.all(b["X"] <= a["X"]) and np.all(b["S"] <= a["S"])
+        ok = (a["rho2"] >= 0) & (b["rho2"] >= 0)
+        assert np.all(b["rho2"][ok] >= a["rho2"][ok])
+    for tr in r.trace:
+        assert np.all(tr["S"] >= Sx)
+    counts = np.bincount(r.iter_of[r.iter_of >= 0], minlength=r.n_iter)
+    assert np.all(counts[:r.n_iter - 1] > 0) and counts[r.n_iter - 1] == 0
+    # resolved sources beat the threshold at their iteration; the survivors do not at the end
+    last = r.trace[-1]
+    assert np.all(last["rho2"][last["rho2"] >= 0] <= 49.0)
+
+
+def test_power_of_two_scaling_is_exact():
+    cat, run = _dense_catalog()
+    r1 = O.run(cat, O.make_config(run))
+    cat2 = cat.subset(np.arange(cat.n))
+    cat2.A *= np.float32(8.0)                          # A * 2^3, noise * 2^6
+    r2 = O.run(cat2, O.make_config(run, noise_scale=64.0))
+    np.testing.assert_array_equal(r1.iter_of, r2.iter_of)
+    np.testing.assert_array_equal(r1.S_final * 64.0, r2.S_final)
+    np.testing.assert_array_equal(r1.rho0_sq, r2.rho0_sq)
+
+
+def test_permutation_invariance():
+    cat, run = _dense_catalog()
+    cfg = O.make_config(run)
+    r1 = O.run(cat, cfg)
+    perm = np.random.default_rng(3).permutation(cat.n)
+    r2 = O.run(cat.subset(perm), cfg)
+    assert r1.n_iter == r2.n_iter
+    np.testing.assert_array_equal(r1.iter_of[perm], r2.iter_of)
+    np.testing.assert_allclose(r2.S_final, r1.S_final, rtol=1e-13)
+
+
+def test_kappa_cut_is_exact_for_the_median():
+    cat, run = _dense_catalog()
+    r1 = O.run(cat, O.make_config(run))
+    r0 = O.run(cat, O.make_config(run, kappa=0.0))     # every source evaluated
+    assert r0.n_candidates == cat.n
+    np.testing.assert_array_equal(r1.iter_of, r0.iter_of)
+    np.testing.assert_array_equal(r1.S_final, r0.S_final)
+
+
+# --------------------------------------------------------------------------- cross-check
+
+@pytest.mark.parametrize("seed", range(6))
+def test_micro_oracle_agrees_on_random_tiny_catalogs(seed):
+    rng = np.random.default_rng(100 + seed)
+    W = int(rng.choice([3, 5, 11, 21]))
+    nb = int(rng.integers(40, 300))
+    run, k0 = small_run(n_bins=nb, f_min=float(rng.uniform(1e-3, 5e-3)), W=W)
+    T = run.t_obs_s
+    n = int(rng.integers(1, 150))
+    f = (k0 + rng.uniform(-5, nb + 5, n)) / T
+    Sx0 = O.sinstr(float(f.mean()))
+    P = Sx0 * rng.exponential(8.0, n)
+    A = np.sqrt(2 * P / T)
+    fdot = rng.choice([0.0, 1.0], n) * rng.uniform(0, 12, n) / T ** 2
+    cat = catalog(A, f, fdot)
+    cfg = O.make_config(run)
+    r = O.run(cat, cfg)
+    it, n_iter, S, X, cand = micro.run(cat.A, cat.f, cat.fdot, T, run.f_min_hz, run.f_max_hz, W)
+    assert r.n_iter == n_iter
+    np.testing.assert_array_equal(r.iter_of, it)
+    np.testing.assert_array_equal(r.is_candidate, cand)
+    np.testing.assert_allclose(r.S_final, S, rtol=1e-12)
+    np.testing.assert_allclose(r.X_final, X, rtol=1e-12, atol=0)
+
+
+# --------------------------------------------------------------------------- validation
+
+def test_invalid_inputs_are_rejected():
+    run, k0 = small_run(n_bins=50, W=5)
+    T = run.t_obs_s
+    good = (1e-22, bin_freq(k0, 10, T), 0.0)
+    for bad in [(float("nan"), good[1], 0.0), (-1e-22, good[1], 0.0), (1e-22, 0.0, 0.0),
+                (1e-22, good[1], float("inf"))]:
+        r = O.run(catalog([good[0], bad[0]], [good[1], bad[1]], [0.0, bad[2]]), O.make_config(run))
+        assert r.status == O.E_INVALID
+    r = O.run(catalog(*[[x] for x in good]), O.make_config(run, window_bins=4))
+    assert r.status == O.E_INVALID
+    r = O.run(catalog(*[[x] for x in good]), O.make_config(run, f_max_hz=0.07))
+    assert r.status == O.E_INVALID
+    r = O.run(catalog(*[[x] for x in good]), O.make_config(run))
+    assert r.status == O.OK
+
+
+# --------------------------------------------------------------------------- mean estimator
+
+def test_running_mean_lone_binary_closed_form():
+    run, k0 = small_run(n_bins=300, W=21)
+    cfg = O.make_config(run)
+    Sx = O.sinstr_table(cfg)
+    X = np.zeros(300)
+    c, q = 150, 7e-40
+    X[c] = q
+    S = O.running_mean_psd(X, Sx, 21)
+    for k in (100, 139, 140, 150, 160, 161, 200):
+        a = min(max(k - 10, 0), 300 - 21)
+        inside = a <= c < a + 21
+        expect = (q * inside + Sx[a:a + 21].sum()) / 21
+        assert S[k] == pytest.approx(expect, rel=1e-14)
+    interior = scipy.ndimage.uniform_filter(X + Sx, size=21, mode="nearest")
+    np.testing.assert_allclose(S[10:290], interior[10:290], rtol=1e-12)
