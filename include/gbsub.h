@@ -1,0 +1,159 @@
+/*
+ * gbsub.h -- C ABI of the MI355X (gfx950) iterative galactic-binary
+ * subtraction library ``libgbsub.so``.
+ *
+ * The library turns a catalog of galactic binaries (amplitude A, frequency f,
+ * frequency derivative fdot) into the reconstructed total PSD
+ * S_n = S_instr + S_gal on the 1/T_obs frequency grid, following the
+ * subtraction algorithm of De Santi et al., "Inferring the population
+ * properties of galactic binaries from LISA's stochastic foreground",
+ * appendix "Subtraction algorithm" (initial SNR against S_instr, candidate
+ * cut rho >= kappa*rho_th, then repeat {running-median PSD estimate, SNR
+ * against it, subtract every source with rho > rho_th} until nothing is
+ * subtracted).  Power model: each source puts A^2 T/2 of one-sided power,
+ * spread uniformly over the 1 + floor(|fdot| T^2) bins of its linear
+ * frequency drift (Sec. "Signal parametrization"); SNR^2 = 4 q sum 1/S over
+ * those bins, the A and E channels of Eq. "SNR inner product"; S_instr is the
+ * SciRDv1 A-channel noise of appendix "LISA instrumental noise" divided by the
+ * TDI response of appendix "Characteristic strain".
+ *
+ * Conventions for every call:
+ *  - All functions are thread-compatible: one context per host thread.
+ *  - No call throws; every call returns a gbsub_status.  Outputs are valid
+ *    only on GBSUB_OK.  After GBSUB_E_DEVICE the context must be destroyed;
+ *    after GBSUB_E_INVALID, GBSUB_E_TRUNCATED or GBSUB_E_MAXITER it stays
+ *    usable.
+ *  - "Device pointer" means memory on the GPU the context was created on
+ *    (e.g. a torch CUDA tensor's data_ptr()); "host pointer" means ordinary
+ *    host memory.  The library never allocates device memory: every device
+ *    buffer (catalog, workspace, device-side outputs) belongs to the caller.
+ *  - ``stream`` is a hipStream_t passed as void* (NULL = the null stream).
+ */
+#ifndef GBSUB_H
+#define GBSUB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gbsub_ctx gbsub_ctx;              /* opaque, one per host thread */
+
+typedef enum {
+    GBSUB_OK = 0,
+    GBSUB_E_INVALID = -1,      /* bad argument, config or catalog entry */
+    GBSUB_E_NOMEM = -2,        /* host allocation failed / workspace too small */
+    GBSUB_E_DEVICE = -3,       /* HIP runtime or kernel error: destroy the context */
+    GBSUB_E_STATE = -4,        /* call out of order (e.g. results before any run) */
+    GBSUB_E_TRUNCATED = -5,    /* output capacity too small; *n holds the size needed */
+    GBSUB_E_MAXITER = -6       /* max_iter loop bodies ran and sources were still resolving */
+} gbsub_status;
+
+enum { GBSUB_MEDIAN = 0, GBSUB_MEAN = 1 };                 /* PSD estimator */
+enum { GBSUB_TRACK_SWEEP = 0, GBSUB_TRACK_SINGLE = 1 };    /* spectral support of a source */
+enum { GBSUB_FP64 = 0, GBSUB_FP32_COMP = 1, GBSUB_FP32_NAIVE = 2 };  /* accumulation precision */
+enum {                                                     /* gbsub_spectrum kinds */
+    GBSUB_SPEC_SN = 0,          /* S_n = C*median(X) + S_instr at the fixed point */
+    GBSUB_SPEC_X_RESIDUAL = 1,  /* X: per-bin power of the sources left unresolved */
+    GBSUB_SPEC_S_GAL = 2,       /* S_n - S_instr */
+    GBSUB_SPEC_S_INSTR = 3      /* S_instr on the grid */
+};
+
+/* Run parameters.  Grid: bins k = 0..B-1 at f_k = (k0+k)/T with
+ * k0 = floor(f_min*T + 1/2), B = floor(f_max*T + 1/2) - k0 + 1 (Sec.
+ * "Coarse-graining of the data": resolution 1/T_obs).  Window: window_bins
+ * (odd) consecutive bins, shifted inward at the grid edges; the median is
+ * the ((W+1)/2)-th smallest (Eq. "running median").  Candidate cut:
+ * rho_0^2 >= (kappa*rho_th)^2; resolve: rho^2 > rho_th^2. */
+typedef struct {
+    double   t_obs_s;          /* T_obs in seconds, > 0 */
+    double   f_min_hz;         /* grid start, > 0 */
+    double   f_max_hz;         /* grid end, f_min < f_max < c/(2 arm_m) */
+    uint32_t window_bins;      /* odd W, 1 <= W <= 2817 */
+    uint32_t estimator;        /* GBSUB_MEDIAN (GBSUB_MEAN: not supported, returns INVALID) */
+    double   snr_threshold;    /* rho_th, default 7 */
+    double   kappa;            /* candidate cut, default 1/rho_th */
+    double   median_scale;     /* C, default 729/512 = (1 - 2/18)^-3 */
+    uint32_t track_model;      /* GBSUB_TRACK_SWEEP (default) | GBSUB_TRACK_SINGLE */
+    uint32_t precision;        /* GBSUB_FP64 (default) | GBSUB_FP32_COMP | GBSUB_FP32_NAIVE */
+    uint32_t max_iter;         /* maximum loop bodies; 0 = n_candidates + 1 */
+    uint32_t reserved0;
+    double   oms_pm;           /* SciRDv1 OMS level P, default 15 (pm/sqrt(Hz)) */
+    double   tm_fm;            /* SciRDv1 test-mass level A, default 3 (fm/s^2/sqrt(Hz)) */
+    double   arm_m;            /* arm length L, default 2.5e9 m */
+} gbsub_config;
+
+/* A catalog in structure-of-arrays form.  A, f, fdot, id are DEVICE
+ * pointers to n entries each, read-only, not retained after gbsub_run
+ * returns.  Valid entries: finite A >= 0, finite f > 0, finite fdot,
+ * |fdot|*T^2 < 2^31 and |(f + fdot*T/2)*T| < 2^52.  ids are opaque. */
+typedef struct {
+    uint64_t        n;
+    const float    *A;
+    const float    *f;
+    const float    *fdot;
+    const uint32_t *id;
+} gbsub_catalog;
+
+typedef struct {
+    uint32_t n_iter;             /* loop bodies run, including the final one that resolved nothing */
+    uint32_t reserved0;
+    uint64_t n_bins;             /* B */
+    uint64_t n_candidates;       /* sources with rho_0 >= kappa*rho_th */
+    uint64_t n_resolved;         /* sources subtracted */
+    uint64_t n_near_threshold;   /* evaluations (t, i) with |rho/rho_th - 1| <= 1e-6 */
+    double   min_rel_margin;     /* min over evaluations of |rho/rho_th - 1| */
+} gbsub_summary;
+
+/* Fills *cfg with the paper's defaults (rho_th = 7, kappa = 1/7, C = 729/512,
+ * SciRDv1 P = 15, A = 3, L = 2.5e9 m, median estimator, sweep tracks, FP64)
+ * and T = 4 yr on [0.1, 30] mHz with W = 1001.  Never fails. */
+void gbsub_default_config(gbsub_config *cfg);
+
+/* Validates *cfg (host pointer) and creates a context bound to the current
+ * HIP device.  *out receives the context (host pointer owned by the library,
+ * freed by gbsub_destroy).  INVALID on a bad config, NOMEM if the host
+ * allocation fails, DEVICE if no HIP device is usable. */
+gbsub_status gbsub_create(const gbsub_config *cfg, gbsub_ctx **out);
+
+/* Bytes of device workspace that gbsub_run needs for a catalog of n_sources
+ * sources on this context's grid (written to *bytes, host pointer). */
+gbsub_status gbsub_workspace_size(const gbsub_ctx *ctx, uint64_t n_sources, uint64_t *bytes);
+
+/* Runs the whole subtraction on `cat` (host pointer to a struct holding
+ * device pointers).  `workspace` is a DEVICE pointer to at least
+ * gbsub_workspace_size() bytes, 256-byte aligned, owned by the caller and
+ * holding the results until the next run or destroy.  All work is enqueued
+ * on `stream`; the call returns after it has completed.  *out (host
+ * pointer, may be NULL) receives the summary.  INVALID for a bad catalog
+ * entry or too small a workspace, MAXITER if the loop did not settle within
+ * max_iter bodies, DEVICE on a HIP error. */
+gbsub_status gbsub_run(gbsub_ctx *ctx, const gbsub_catalog *cat, void *workspace,
+                       uint64_t ws_bytes, void *stream, gbsub_summary *out);
+
+/* Copies spectrum `kind` (GBSUB_SPEC_*) of the last successful run, B fp64
+ * values in grid order, to `out` (host pointer if out_on_device == 0, device
+ * pointer otherwise).  *n_bins (host) receives B.  TRUNCATED if cap < B,
+ * STATE if no run has completed. */
+gbsub_status gbsub_spectrum(const gbsub_ctx *ctx, uint32_t kind, double *out, uint64_t cap,
+                            uint64_t *n_bins, int out_on_device);
+
+/* Copies the resolved sources of the last successful run: ids[j] (uint32)
+ * in ascending id order, and iter_of[j] (int32, may be NULL) = the loop body
+ * t in which ids[j] was subtracted.  Host pointers if out_on_device == 0,
+ * device pointers otherwise.  *n (host) receives the count; TRUNCATED if
+ * cap is smaller.  STATE if no run has completed. */
+gbsub_status gbsub_resolved(const gbsub_ctx *ctx, uint32_t *ids, int32_t *iter_of, uint64_t cap,
+                            uint64_t *n, int out_on_device);
+
+/* Releases the context (NULL is ignored).  Does not touch caller memory. */
+void gbsub_destroy(gbsub_ctx *ctx);
+
+/* Static description of a status code; never NULL. */
+const char *gbsub_status_str(gbsub_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GBSUB_H */

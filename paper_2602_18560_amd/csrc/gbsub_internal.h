@@ -1,0 +1,101 @@
+// gbsub_internal.h -- shared definitions of the HIP kernels and the host
+// runtime of libgbsub (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gbs {
+
+constexpr int WG = 256;            // threads per workgroup for every tiled kernel
+constexpr int MMAX = 3072;         // median tile: outputs + W - 1 must fit
+constexpr int NARROW = 16;         // tracks of <= NARROW bins: SNR summed bin by bin
+constexpr int SNR_BLOCKS = 1024;   // fixed grid of the per-candidate kernels
+constexpr int NEW_CAP = 1 << 16;   // per-iteration counters kept (iterations beyond: not recorded)
+constexpr int KEYBITS = 24;        // bits of the per-tile order key of the median sort
+constexpr int CHP = 8;             // median start table: positions per row
+constexpr int RBS = 128;           // median start table: sorted ranks per column
+
+// Signed 128-bit fixed-point accumulator (two's complement: hi*2^64 + lo).
+// Every power is accumulated as an exact integer multiple of 2^L, so sums
+// and differences are exact and independent of the order of the atomics.
+struct alignas(16) I128 {
+    uint64_t lo;
+    int64_t hi;
+};
+
+// Device control block (lives in the workspace).
+struct Ctl {
+    uint32_t amax_bits;      // max over sources of the fp32 bits of A (A >= 0)
+    uint32_t bad;            // nonzero: an input entry failed validation
+    uint32_t n_cand;         // candidates
+    uint32_t done;           // the loop has settled
+    uint32_t n_iter;         // loop bodies run (valid when done)
+    uint32_t n_resolved;     // sources subtracted so far
+    uint32_t cnt_median;     // last-block tickets
+    uint32_t cnt_snr;
+    uint32_t n_res_out;      // resolved pairs written by the output kernel
+    uint32_t cur_new;        // sources subtracted in the current loop body
+    uint64_t n_near;         // evaluations within 1e-6 of the threshold
+    uint64_t min_margin;     // bits of min |rho/rho_th - 1| (non-negative double)
+};
+
+struct Grid {
+    int32_t B;               // bins
+    int32_t W;               // window (odd)
+    int32_t h;               // (W-1)/2
+    int32_t tile;            // bins per tile (multiple of WG)
+    int32_t nt;              // tiles = ceil(B / tile)
+    int32_t track_single;    // 1: every source occupies one bin
+    int64_t k0;              // first grid index
+    double T;                // observation time
+    double C;                // median scale
+    double rth2;             // rho_th^2
+    double cut2;             // (kappa rho_th)^2
+    double rth;              // rho_th
+    double oms_pm, tm_fm, arm_m;
+};
+
+// Pointers into the caller's workspace.
+struct Dev {
+    // grid tables (kept across runs with the same workspace and grid)
+    double *sx;              // [B]    S_instr
+    double *isx_pre;         // [B]    inclusive prefix of 1/S_instr inside each tile
+    double *isx_tsum;        // [nt]   tile sums of 1/S_instr
+    double *isx_tile;        // [nt+1] exclusive prefix of the tile sums
+    // per-run spectra
+    I128 *D;                 // [B+1]  fixed-point difference array of the binned power
+    I128 *Dtile;             // [nt+1] per-tile sums of D
+    I128 *Dcarry;            // [nt+1] exclusive prefix of Dtile
+    double *X;               // [B]    X^t
+    double *S;               // [B]    S^t
+    double *is_pre;          // [B]    inclusive prefix of 1/S^t inside each tile
+    double *is_tsum;         // [nt]   tile sums of 1/S^t
+    double *is_tile;         // [nt+1] exclusive prefix of the tile sums
+    int32_t *chgx;           // [nt+1] tiles whose X changes (difference counters)
+    int32_t *chgs;           // [nt+1] tiles whose S must be recomputed
+    uint8_t *xdirty;         // [nt]
+    uint8_t *sdirty;         // [nt]
+    // candidates (capacity: all sources)
+    uint32_t *c_src;         // source index
+    int32_t *c_glo, *c_ghi;  // clipped track
+    int32_t *c_iter;         // loop body that subtracted it, -1 while unresolved
+    double *c_q;             // per-bin power
+    uint64_t *c_qfx;         // per-bin power in fixed point
+    double *c_rho2;          // rho^2 at the last evaluation
+    uint32_t *n_new;         // [NEW_CAP] sources subtracted per loop body
+    uint32_t *res_id;        // [n] ids of the subtracted sources
+    int32_t *res_iter;       // [n] their loop body
+    Ctl *ctl;
+};
+
+// Kernel launchers (gbsub_kernels.hip); all enqueue on `st` and return the
+// launch status.
+hipError_t launch_grid_tables(const Grid &g, const Dev &d, hipStream_t st);
+hipError_t launch_reset(const Grid &g, const Dev &d, uint64_t n_src, hipStream_t st);
+hipError_t launch_prep(const Grid &g, const Dev &d, const float *A, const float *f,
+                       const float *fdot, uint64_t n, hipStream_t st);
+hipError_t launch_iteration(const Grid &g, const Dev &d, int t, hipStream_t st);
+hipError_t launch_outputs(const Grid &g, const Dev &d, const uint32_t *ids, hipStream_t st);
+
+}  // namespace gbs

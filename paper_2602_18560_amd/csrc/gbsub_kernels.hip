@@ -1,0 +1,908 @@
+// gbsub_kernels.hip -- HIP kernels (gfx950) of the iterative galactic-binary
+// subtraction.
+//
+// Data layout in HBM (all structure-of-arrays, see gbsub_internal.h):
+//   catalog     A, f, fdot fp32 [n]            read once by k_amax / k_prep
+//   S_instr     sx fp64 [B] + 1/S_instr prefix tables (per grid, cached)
+//   binned power D: 128-bit fixed-point difference array [B+1]; X = prefix(D)
+//   X, S, 1/S prefix: fp64 [B]; tile-level tables [nt+1]
+//   candidates  SoA records (source, clipped track, q, q in fixed point, iter)
+//
+// Every per-bin power sum is exact integer arithmetic on multiples of 2^L
+// (L from the largest amplitude), so the binned spectrum does not depend on
+// the order in which atomics land and subtracting a source is exact.  The
+// SNR and the median read fp64 values converted from it with one rounding.
+
+#include "gbsub_internal.h"
+
+#include <math.h>
+
+namespace gbs {
+
+#define DEVI __device__ __forceinline__
+
+// ------------------------------------------------------------------ helpers
+
+DEVI I128 i128_add(I128 a, I128 b)
+{
+    I128 r;
+    r.lo = a.lo + b.lo;
+    r.hi = a.hi + b.hi + (int64_t)(r.lo < a.lo);
+    return r;
+}
+
+DEVI I128 i128_from(int64_t v)
+{
+    I128 r;
+    r.lo = (uint64_t)v;
+    r.hi = v < 0 ? -1 : 0;
+    return r;
+}
+
+// Exact, order-independent: adds v into the 128-bit accumulator *p.
+DEVI void atomic_add_i128(I128 *p, int64_t v)
+{
+    const uint64_t vlo = (uint64_t)v;
+    const int64_t vhi = v < 0 ? -1 : 0;
+    const uint64_t old = atomicAdd((unsigned long long *)&p->lo, (unsigned long long)vlo);
+    const int64_t add_hi = vhi + (int64_t)((uint64_t)(old + vlo) < old);
+    if (add_hi != 0) atomicAdd((unsigned long long *)&p->hi, (unsigned long long)add_hi);
+}
+
+// Correctly rounded conversion of a non-negative 128-bit integer to fp64.
+DEVI double i128_to_double(I128 v)
+{
+    if (v.hi < 0) return 0.0;   // cannot happen for a sum of non-negative powers
+    if (v.hi == 0) return (double)v.lo;
+    const uint64_t hi = (uint64_t)v.hi;
+    const int lz = __clzll(hi);
+    uint64_t top = lz ? ((hi << lz) | (v.lo >> (64 - lz))) : hi;
+    const uint64_t rest = v.lo << lz;
+    top |= (uint64_t)(rest != 0);       // sticky bit keeps round-to-nearest exact
+    return ldexp((double)top, 64 - lz);
+}
+
+// Fixed-point unit 2^L: every per-bin power q <= A_max^2 T / 2 maps to an
+// integer below 2^62, so 2^65 sources fit in one 128-bit accumulator.
+DEVI int fx_exp(uint32_t amax_bits, double T)
+{
+    const double a = (double)__uint_as_float(amax_bits);
+    const double pmax = ((a * a) * T) * 0.5;
+    if (!(pmax > 0.0)) return 0;
+    return ilogb(pmax) - 61;
+}
+
+DEVI uint64_t to_fx(double q, int L) { return (uint64_t)rint(ldexp(q, -L)); }
+
+DEVI int lane_id() { return __lane_id(); }
+
+template <typename T>
+DEVI T shfl_up_t(T x, int d) { return __shfl_up(x, d, 64); }
+
+DEVI I128 shfl_up_t(I128 x, int d)
+{
+    I128 r;
+    r.lo = (uint64_t)__shfl_up((unsigned long long)x.lo, d, 64);
+    r.hi = (int64_t)__shfl_up((long long)x.hi, d, 64);
+    return r;
+}
+
+DEVI double add_t(double a, double b) { return a + b; }
+DEVI I128 add_t(I128 a, I128 b) { return i128_add(a, b); }
+DEVI uint32_t add_t(uint32_t a, uint32_t b) { return a + b; }
+
+template <typename T> DEVI T zero_t();
+template <> DEVI double zero_t<double>() { return 0.0; }
+template <> DEVI uint32_t zero_t<uint32_t>() { return 0u; }
+template <> DEVI I128 zero_t<I128>() { I128 z; z.lo = 0; z.hi = 0; return z; }
+
+// Inclusive scan across the 64 lanes of a wave.
+template <typename T>
+DEVI T wave_incl_scan(T x)
+{
+    const int lane = lane_id();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        T y = shfl_up_t(x, d);
+        if (lane >= d) x = add_t(x, y);
+    }
+    return x;
+}
+
+// Exclusive scan across the WG threads of a block; *total gets the block sum.
+// `sh` must hold WG/64 elements.  Contains __syncthreads().
+template <typename T>
+DEVI T block_excl_scan(T x, T *sh, T *total)
+{
+    const int lane = lane_id(), wave = threadIdx.x >> 6;
+    T inc = wave_incl_scan(x);
+    if (lane == 63) sh[wave] = inc;
+    __syncthreads();
+    T pre = zero_t<T>(), tot = zero_t<T>();
+#pragma unroll
+    for (int w = 0; w < WG / 64; ++w) {
+        if (w < wave) pre = add_t(pre, sh[w]);
+        tot = add_t(tot, sh[w]);
+    }
+    __syncthreads();
+    T ex = shfl_up_t(inc, 1);
+    if (lane == 0) ex = zero_t<T>();
+    *total = tot;
+    return add_t(pre, ex);
+}
+
+DEVI double wave_sum(double x)
+{
+    for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
+    return x;
+}
+
+// Window start of output k (clamped full window), grid of B >= W bins.
+DEVI int win_start(int k, int B, int W, int h)
+{
+    int a = k - h;
+    a = a < 0 ? 0 : a;
+    return a > B - W ? B - W : a;
+}
+
+// sum_{k=lo..hi} 1/v[k] from the tile tables (inclusive in-tile prefix `pre`,
+// exclusive tile prefix `tl`); short ranges are summed bin by bin in
+// ascending order.
+DEVI double range_inv_sum(const double *v, const double *pre, const double *tl, int lo, int hi,
+                          int tile)
+{
+    if (hi - lo + 1 <= NARROW) {
+        double s = 0.0;
+        for (int k = lo; k <= hi; ++k) s += 1.0 / v[k];
+        return s;
+    }
+    const int tlo = lo / tile, thi = hi / tile;
+    const double below = (lo % tile == 0) ? 0.0 : pre[lo - 1];
+    if (tlo == thi) return pre[hi] - below;
+    return ((tl[thi] - tl[tlo]) - below) + pre[hi];
+}
+
+// ------------------------------------------------------------------ grid tables
+
+// Strain-equivalent SciRDv1 A-channel noise: S_AA(f) / R_AA(f) with
+//   P_OMS = (P pm)^2 [1 + (2 mHz/f)^4] (2 pi f/c)^2,
+//   P_TM  = (A fm)^2 [1 + (0.4 mHz/f)^2][1 + (f/8 mHz)^4] (2 pi f)^-4 (2 pi f/c)^2,
+//   S_AA  = 8 sin^2 u {4 [1 + cos u + cos^2 u] P_TM + [2 + cos u] P_OMS},
+//   R_AA  = 16 sin^2 u u^2 (9/20) / (1 + 0.7 u^2),  u = f/f*, f* = c/(2 pi L)
+// (appendices "LISA instrumental noise" and "Characteristic strain").
+DEVI double sinstr_dev(double f, double oms_pm, double tm_fm, double arm_m)
+{
+    const double c = 299792458.0;
+    const double two_pi = 6.283185307179586;
+    const double u = f / (c / (two_pi * arm_m));
+    const double w = two_pi * f;
+    const double wc = w / c;
+    const double oms = oms_pm * 1e-12, tm = tm_fm * 1e-15;
+    const double a = 2e-3 / f, b = 4e-4 / f, e = f / 8e-3;
+    const double p_oms = (oms * oms) * (1.0 + a * a * a * a) * (wc * wc);
+    const double p_tm = (tm * tm) * (1.0 + b * b) * (1.0 + e * e * e * e) / (w * w * w * w) * (wc * wc);
+    double s, co;
+    sincos(u, &s, &co);
+    const double saa = 8.0 * (s * s) * (4.0 * (1.0 + co + co * co) * p_tm + (2.0 + co) * p_oms);
+    const double raa = 16.0 * (s * s) * (u * u) * (0.45 / (1.0 + 0.7 * (u * u)));
+    return saa / raa;
+}
+
+__global__ __launch_bounds__(WG) void k_sinstr(Grid g, double *sx)
+{
+    const int k = blockIdx.x * WG + threadIdx.x;
+    if (k >= g.B) return;
+    const double f = (double)(g.k0 + k) / g.T;
+    sx[k] = sinstr_dev(f, g.oms_pm, g.tm_fm, g.arm_m);
+}
+
+// In-tile inclusive prefix of 1/v and the tile sums (one block per tile).
+__global__ __launch_bounds__(WG) void k_inv_prefix(Grid g, const double *v, double *pre,
+                                                   double *tsum)
+{
+    __shared__ double sh[WG / 64];
+    const int tile = blockIdx.x, R = g.tile / WG;
+    const int base = tile * g.tile + threadIdx.x * R;
+    double loc[8];
+    double s = 0.0;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        const int k = base + r;
+        if (r < R) s += (k < g.B) ? 1.0 / v[k] : 0.0;
+        loc[r] = s;
+    }
+    double tot;
+    const double ex = block_excl_scan(s, sh, &tot);
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        const int k = base + r;
+        if (r < R && k < g.B) pre[k] = ex + loc[r];
+    }
+    if (threadIdx.x == 0) tsum[tile] = tot;
+}
+
+// Exclusive prefix over the tile sums (single block).
+template <typename T>
+DEVI void block_scan_array(const T *in, T *out, int n)
+{
+    __shared__ T sh[WG / 64];
+    T carry = zero_t<T>();
+    for (int base = 0; base < n; base += WG) {
+        const int i = base + threadIdx.x;
+        T x = (i < n) ? in[i] : zero_t<T>();
+        T tot;
+        T ex = block_excl_scan(x, sh, &tot);
+        if (i < n) out[i] = add_t(carry, ex);
+        carry = add_t(carry, tot);
+    }
+    if (threadIdx.x == 0) out[n] = carry;
+}
+
+__global__ __launch_bounds__(WG) void k_scan_f64(const double *in, double *out, int n)
+{
+    block_scan_array<double>(in, out, n);
+}
+
+// ------------------------------------------------------------------ reset
+
+__global__ __launch_bounds__(WG) void k_fill_u32(uint32_t *p, uint64_t n, uint32_t v)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (uint64_t)gridDim.x * WG)
+        p[i] = v;
+}
+
+__global__ void k_init_ctl(Ctl *c)
+{
+    if (threadIdx.x == 0) {
+        c->amax_bits = 0;
+        c->bad = 0;
+        c->n_cand = 0;
+        c->done = 0;
+        c->n_iter = 0;
+        c->n_resolved = 0;
+        c->cnt_median = 0;
+        c->cnt_snr = 0;
+        c->n_res_out = 0;
+        c->cur_new = 0;
+        c->n_near = 0;
+        c->min_margin = 0x7FF0000000000000ull;   // +inf
+    }
+}
+
+// ------------------------------------------------------------------ prep
+
+// Largest amplitude (fixed-point scale) and validation of A.
+__global__ __launch_bounds__(WG) void k_amax(const float *A, uint64_t n, Ctl *ctl)
+{
+    uint32_t m = 0, bad = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (uint64_t)gridDim.x * WG) {
+        const float a = A[i];
+        if (!(a >= 0.0f) || !isfinite(a)) bad = 1;
+        else if (a > 0.0f) m = max(m, __float_as_uint(a));
+    }
+    for (int d = 32; d >= 1; d >>= 1) {
+        m = max(m, (uint32_t)__shfl_xor((int)m, d, 64));
+        bad |= (uint32_t)__shfl_xor((int)bad, d, 64);
+    }
+    if (lane_id() == 0) {
+        if (m) atomicMax(&ctl->amax_bits, m);
+        if (bad) atomicOr(&ctl->bad, 1u);
+    }
+}
+
+// One pass over the catalog: power, track, rho_0^2 against S_instr,
+// candidate cut, binning of every source into D, candidate compaction.
+//   P = A^2 T / 2; mid-track frequency f + fdot T/2; centre bin
+//   floor(fbar T + 1/2) - k0; n = 1 + floor(|fdot| T^2) bins; q = P/n.
+// (Sec. "Signal parametrization"; appendix "Subtraction algorithm", steps
+// 2-3: SNR against S_instr and the cut rho >= kappa rho_th.)
+__global__ __launch_bounds__(WG) void k_prep(Grid g, Dev d, const float *A, const float *F,
+                                             const float *FD, uint64_t n)
+{
+    const int L = fx_exp(d.ctl->amax_bits, g.T);
+    const uint64_t stride = (uint64_t)gridDim.x * WG;
+    const uint64_t nr = (n + 63) & ~63ull;   // whole waves iterate together
+    for (uint64_t i = (uint64_t)blockIdx.x * WG + threadIdx.x; i < nr; i += stride) {
+        bool isc = false;
+        int glo = 0, ghi = -1;
+        double q = 0.0;
+        uint64_t qfx = 0;
+        if (i < n) {
+            const double a = (double)A[i], f = (double)F[i], fd = (double)FD[i];
+            bool ok = isfinite(a) && a >= 0.0 && isfinite(f) && f > 0.0 && isfinite(fd);
+            const double P = ((a * a) * g.T) * 0.5;
+            const double fbar = f + (fd * g.T) * 0.5;
+            const double x = fbar * g.T + 0.5;
+            const double s = (fabs(fd) * g.T) * g.T;
+            ok = ok && fabs(x) < 4503599627370496.0 && s < 2147483648.0;
+            if (!ok) {
+                atomicOr(&d.ctl->bad, 1u);
+            } else {
+                const int64_t c = (int64_t)floor(x) - g.k0;
+                const int64_t nn = g.track_single ? 1 : 1 + (int64_t)floor(s);
+                const int64_t lo = c - (nn - 1) / 2;
+                const int64_t hi = lo + nn - 1;
+                q = P / (double)nn;
+                const int64_t gl = lo < 0 ? 0 : lo;
+                const int64_t gh = hi > g.B - 1 ? g.B - 1 : hi;
+                if (gl <= gh) {
+                    glo = (int)gl;
+                    ghi = (int)gh;
+                    const double r2 = (4.0 * q) * range_inv_sum(d.sx, d.isx_pre, d.isx_tile, glo, ghi, g.tile);
+                    isc = r2 >= g.cut2;
+                    qfx = to_fx(q, L);
+                    if (qfx) {
+                        atomic_add_i128(&d.D[glo], (int64_t)qfx);
+                        atomic_add_i128(&d.D[ghi + 1], -(int64_t)qfx);
+                    }
+                }
+            }
+        }
+        const uint64_t mask = __ballot(isc);
+        if (mask) {
+            const int lane = lane_id();
+            const int leader = __ffsll((long long)mask) - 1;
+            uint32_t base = 0;
+            if (lane == leader) base = atomicAdd(&d.ctl->n_cand, (uint32_t)__popcll(mask));
+            base = (uint32_t)__shfl((int)base, leader, 64);
+            if (isc) {
+                const uint32_t j = base + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+                d.c_src[j] = (uint32_t)i;
+                d.c_glo[j] = glo;
+                d.c_ghi[j] = ghi;
+                d.c_q[j] = q;
+                d.c_qfx[j] = qfx;
+                d.c_iter[j] = -1;
+            }
+        }
+    }
+}
+
+// Per-tile sums of D (one block per tile), then their exclusive prefix.
+__global__ __launch_bounds__(WG) void k_dtile_sum(Grid g, Dev d)
+{
+    __shared__ I128 sh[WG / 64];
+    const int tile = blockIdx.x;
+    I128 s = zero_t<I128>();
+    for (int k = tile * g.tile + threadIdx.x; k < min((tile + 1) * g.tile, g.B); k += WG)
+        s = i128_add(s, d.D[k]);
+    I128 tot;
+    block_excl_scan(s, sh, &tot);
+    if (threadIdx.x == 0) d.Dtile[tile] = tot;
+}
+
+__global__ __launch_bounds__(WG) void k_dscan(Grid g, Dev d)
+{
+    block_scan_array<I128>(d.Dtile, d.Dcarry, g.nt);
+}
+
+// ------------------------------------------------------------------ X update
+
+// X[k] = 2^L * prefix(D)[k] for the tiles whose X changed.
+__global__ __launch_bounds__(WG) void k_xupdate(Grid g, Dev d)
+{
+    __shared__ I128 sh[WG / 64];
+    if (d.ctl->done) return;
+    const int tile = blockIdx.x;
+    if (!d.xdirty[tile]) return;
+    const int L = fx_exp(d.ctl->amax_bits, g.T);
+    const int R = g.tile / WG;
+    const int base = tile * g.tile + threadIdx.x * R;
+    I128 loc[8];
+    I128 s = zero_t<I128>();
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        const int k = base + r;
+        if (r < R && k < g.B) s = i128_add(s, d.D[k]);
+        loc[r] = s;
+    }
+    I128 tot;
+    I128 ex = block_excl_scan(s, sh, &tot);
+    ex = i128_add(ex, d.Dcarry[tile]);
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        const int k = base + r;
+        if (r < R && k < g.B) d.X[k] = ldexp(i128_to_double(i128_add(ex, loc[r])), L);
+    }
+}
+
+// ------------------------------------------------------------------ running median
+//
+// S[k] = C * median{X[a_k .. a_k+W-1]} + S_instr[k]   (Eq. "running median").
+//
+// One block per tile of `tile` outputs.  The union of the tile's windows
+// (tile + W - 1 bins) is loaded once and sorted in LDS (stable LSD radix
+// sort on a per-tile 24-bit order key, then an exact repair of key ties by
+// the full fp64 value).  Each thread then owns R = tile/256 consecutive
+// outputs: it locates the median of its first window through a small 2-D
+// count table (positions x sorted ranks) and slides the window one bin at a
+// time, moving the median pointer along the sorted order (one element leaves,
+// one enters; the pointer moves to the neighbouring active element when the
+// count below it changes).  Selection is exact: no arithmetic touches X.
+
+struct MedianSmem {
+    uint32_t key[2][MMAX];            // sort keys; afterwards the start table (u16)
+    uint32_t cnt[16 * WG];            // radix offsets; afterwards the medians (f64)
+    uint16_t pos[2][MMAX];            // positions (relative to the union start)
+    uint16_t rank[MMAX];              // sorted index of each position
+    uint64_t red[2 * (WG / 64)];
+    uint32_t wsc[(WG / 64) * 8];
+    double dsh[WG / 64];
+    int flag;
+    int last;
+};
+
+DEVI uint32_t radix_key(uint64_t bits, uint64_t mn, int shift) { return (uint32_t)((bits - mn) >> shift); }
+
+// Stable LSD radix sort of (key, pos) over M elements with 4-bit digits.
+// Returns the buffer index that holds the result.
+DEVI int radix_sort_tile(MedianSmem &sm, int M, int passes)
+{
+    const int tid = threadIdx.x;
+    const int CH = (M + WG - 1) / WG;
+    const int beg = tid * CH, end = min(beg + CH, M);
+    int in = 0;
+    for (int ps = 0; ps < passes; ++ps) {
+        const int sh = 4 * ps;
+        const uint32_t *kin = sm.key[in];
+        const uint16_t *pin = sm.pos[in];
+        uint32_t *kout = sm.key[in ^ 1];
+        uint16_t *pout = sm.pos[in ^ 1];
+        // per-thread digit counts, 4 bits each (CH <= 12 < 16)
+        uint64_t c = 0;
+        for (int i = beg; i < end; ++i) c += 1ull << (4 * ((kin[i] >> sh) & 15u));
+        // 16-bit fields, two digits per word; one block-wide scan of 8 words
+        uint32_t w[8], inc[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            w[j] = (uint32_t)((c >> (8 * j)) & 15u) | ((uint32_t)((c >> (8 * j + 4)) & 15u) << 16);
+            inc[j] = wave_incl_scan(w[j]);
+        }
+        const int lane = lane_id(), wave = tid >> 6;
+        if (lane == 63) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) sm.wsc[wave * 8 + j] = inc[j];
+        }
+        __syncthreads();
+        // digit bases (exclusive over the 16 digit totals) + own offset
+        uint32_t run = 0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            uint32_t pre = 0, tot = 0;
+#pragma unroll
+            for (int v = 0; v < WG / 64; ++v) {
+                const uint32_t x = sm.wsc[v * 8 + j];
+                pre += (v < wave) ? x : 0u;
+                tot += x;
+            }
+            const uint32_t ex = pre + inc[j] - w[j];
+            sm.cnt[(2 * j) * WG + tid] = run + (ex & 0xFFFFu);
+            run += tot & 0xFFFFu;
+            sm.cnt[(2 * j + 1) * WG + tid] = run + (ex >> 16);
+            run += tot >> 16;
+        }
+        // stable scatter (thread chunks are contiguous in the current order)
+        for (int i = beg; i < end; ++i) {
+            const uint32_t k = kin[i];
+            const uint32_t dg = (k >> sh) & 15u;
+            const uint32_t dst = sm.cnt[dg * WG + tid]++;
+            kout[dst] = k;
+            pout[dst] = pin[i];
+        }
+        __syncthreads();
+        in ^= 1;
+    }
+    return in;
+}
+
+__global__ __launch_bounds__(WG) void k_median(Grid g, Dev d)
+{
+    __shared__ MedianSmem sm;
+    if (d.ctl->done) return;
+    const int tile = blockIdx.x, tid = threadIdx.x;
+    const int B = g.B, W = g.W, h = g.h;
+
+    if (d.sdirty[tile]) {
+        const int t0 = tile * g.tile;
+        const int t1 = min(t0 + g.tile, B);
+        const bool whole = B < W;
+        const int u0 = whole ? 0 : win_start(t0, B, W, h);
+        const int u1 = whole ? B - 1 : win_start(t1 - 1, B, W, h) + W - 1;
+        const int M = u1 - u0 + 1;
+        const double *X = d.X + u0;
+
+        // ---- load: order key relative to the tile minimum
+        uint64_t mn = ~0ull, mx = 0;
+        for (int i = tid; i < M; i += WG) {
+            const uint64_t b = (uint64_t)__double_as_longlong(X[i]);
+            mn = b < mn ? b : mn;
+            mx = b > mx ? b : mx;
+        }
+        for (int s = 32; s >= 1; s >>= 1) {
+            const uint64_t a = (uint64_t)__shfl_xor((long long)mn, s, 64);
+            const uint64_t b = (uint64_t)__shfl_xor((long long)mx, s, 64);
+            mn = a < mn ? a : mn;
+            mx = b > mx ? b : mx;
+        }
+        if (lane_id() == 0) {
+            sm.red[tid >> 6] = mn;
+            sm.red[(WG / 64) + (tid >> 6)] = mx;
+        }
+        __syncthreads();
+        mn = sm.red[0];
+        mx = sm.red[WG / 64];
+        for (int w = 1; w < WG / 64; ++w) {
+            mn = sm.red[w] < mn ? sm.red[w] : mn;
+            mx = sm.red[WG / 64 + w] > mx ? sm.red[WG / 64 + w] : mx;
+        }
+        const uint64_t span = mx - mn;
+        const int span_bits = span ? 64 - __clzll(span) : 0;
+        const int shift = span_bits > KEYBITS ? span_bits - KEYBITS : 0;
+        const int key_bits = span_bits - shift;
+        const int passes = (key_bits + 3) / 4;
+        for (int i = tid; i < M; i += WG) {
+            sm.key[0][i] = radix_key((uint64_t)__double_as_longlong(X[i]), mn, shift);
+            sm.pos[0][i] = (uint16_t)i;
+        }
+        __syncthreads();
+
+        // ---- sort
+        const int rb = radix_sort_tile(sm, M, passes);
+        uint32_t *skey = sm.key[rb];
+        uint16_t *spos = sm.pos[rb];
+
+        // ---- repair key ties: order equal keys by (fp64 value, position)
+        if (shift > 0) {
+            for (;;) {
+                if (tid == 0) sm.flag = 0;
+                __syncthreads();
+                int swapped = 0;
+                for (int par = 0; par < 2; ++par) {
+                    for (int i = par + 2 * tid; i + 1 < M; i += 2 * WG) {
+                        if (skey[i] != skey[i + 1]) continue;
+                        const uint16_t pa = spos[i], pb = spos[i + 1];
+                        const uint64_t ba = (uint64_t)__double_as_longlong(X[pa]);
+                        const uint64_t bb = (uint64_t)__double_as_longlong(X[pb]);
+                        if (ba > bb || (ba == bb && pa > pb)) {
+                            spos[i] = pb;
+                            spos[i + 1] = pa;
+                            swapped = 1;
+                        }
+                    }
+                    __syncthreads();
+                }
+                if (swapped) sm.flag = 1;
+                __syncthreads();
+                const int any = sm.flag;
+                __syncthreads();
+                if (!any) break;
+            }
+        }
+        for (int i = tid; i < M; i += WG) sm.rank[spos[i]] = (uint16_t)i;
+        __syncthreads();
+
+        double *medv = reinterpret_cast<double *>(sm.cnt);
+        const int R = g.tile / WG;
+        if (whole) {
+            const double m = X[spos[(B + 1) / 2 - 1]];
+            for (int r = 0; r < R; ++r) medv[tid * R + r] = m;
+        } else {
+            // ---- start table: tbl[c][b] = #{p < c*CHP : rank[p] < b*RBS}
+            uint16_t *tbl = reinterpret_cast<uint16_t *>(sm.key);   // keys no longer needed
+            const int NC = (M + CHP - 1) / CHP, NB = (M + RBS - 1) / RBS;
+            const int ld = NB + 1;
+            for (int c = tid; c <= NC; c += WG) {
+                uint16_t *row = tbl + c * ld;
+                for (int b = 0; b <= NB; ++b) row[b] = 0;
+                if (c >= 1) {
+                    for (int p = (c - 1) * CHP; p < min(c * CHP, M); ++p) row[sm.rank[p] / RBS + 1]++;
+                    for (int b = 1; b <= NB; ++b) row[b] += row[b - 1];
+                }
+            }
+            __syncthreads();
+            {   // prefix over rows, each column split into segments
+                const int nseg = WG / ld;
+                const int rows = NC + 1;
+                const int seglen = (rows + nseg - 1) / nseg;
+                const int col = tid % ld, seg = tid / ld;
+                uint32_t segsum = 0;
+                const bool act = seg < nseg;
+                const int r0 = seg * seglen, r1 = min(r0 + seglen, rows);
+                if (act)
+                    for (int r = r0; r < r1; ++r) {
+                        segsum += tbl[r * ld + col];
+                        tbl[r * ld + col] = (uint16_t)segsum;
+                    }
+                __syncthreads();
+                uint32_t add = 0;
+                if (act)
+                    for (int s2 = 0; s2 < seg; ++s2) {
+                        const int rr = min((s2 + 1) * seglen, rows) - 1;
+                        if (rr >= s2 * seglen) add += tbl[rr * ld + col];
+                    }
+                __syncthreads();
+                if (act && add)
+                    for (int r = r0; r < r1; ++r) tbl[r * ld + col] = (uint16_t)(tbl[r * ld + col] + add);
+                __syncthreads();
+            }
+
+            // ---- walks: thread owns outputs [kb, ke)
+            const int kb = t0 + tid * R;
+            const int ke = min(kb + R, t1);
+            if (kb < ke) {
+                int w0 = win_start(kb, B, W, h) - u0;
+                // start: (h+1)-th element of sorted order inside [w0, w0+W)
+                const int cL = w0 / CHP, nl = w0 % CHP;
+                const int xr = w0 + W;
+                const int cR = xr / CHP, nr = xr % CHP;
+                uint32_t rl[CHP], rr[CHP];
+#pragma unroll
+                for (int i = 0; i < CHP; ++i) {
+                    rl[i] = (i < nl) ? sm.rank[cL * CHP + i] : 0xFFFFFFFFu;
+                    rr[i] = (i < nr) ? sm.rank[cR * CHP + i] : 0xFFFFFFFFu;
+                }
+                auto count = [&](int b) -> int {
+                    const uint32_t lim = (uint32_t)(b * RBS);
+                    int cnt = (int)tbl[cR * ld + b] - (int)tbl[cL * ld + b];
+#pragma unroll
+                    for (int i = 0; i < CHP; ++i) cnt += (int)(rr[i] < lim) - (int)(rl[i] < lim);
+                    return cnt;
+                };
+                int lo = 1, hi2 = NB;
+                while (lo < hi2) {
+                    const int mid = (lo + hi2) >> 1;
+                    if (count(mid) >= h + 1) hi2 = mid; else lo = mid + 1;
+                }
+                int base = count(lo - 1);
+                int j = (lo - 1) * RBS;
+                for (; j < M - 1; ++j) {       // the bound only guards a broken invariant
+                    if ((unsigned)(spos[j] - w0) < (unsigned)W) {
+                        if (++base == h + 1) break;
+                    }
+                }
+                medv[kb - t0] = X[spos[j]];
+                for (int k = kb + 1; k < ke; ++k) {
+                    const int w1 = win_start(k, B, W, h) - u0;
+                    if (w1 != w0) {
+                        const int rout = sm.rank[w0];
+                        const int rin = sm.rank[w0 + W];
+                        w0 = w1;
+                        const int below = h - (rout < j) + (rin < j);
+                        bool down;
+                        bool move = true;
+                        if (rout == j) down = rin < j;
+                        else if (below == h + 1) down = true;
+                        else if (below == h - 1) down = false;
+                        else { move = false; down = false; }
+                        if (move) {
+                            if (down) { do { --j; } while (j > 0 && (unsigned)(spos[j] - w0) >= (unsigned)W); }
+                            else      { do { ++j; } while (j < M - 1 && (unsigned)(spos[j] - w0) >= (unsigned)W); }
+                        }
+                    }
+                    medv[k - t0] = X[spos[j]];
+                }
+            }
+        }
+        __syncthreads();
+
+        // ---- S = C med + S_instr, in-tile prefix of 1/S and the tile sum
+        {
+            const int base = t0 + tid * R;
+            double loc[8], s = 0.0;
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                const int k = base + r;
+                if (r < R && k < t1) {
+                    const double Sk = g.C * medv[k - t0] + d.sx[k];
+                    d.S[k] = Sk;
+                    s += 1.0 / Sk;
+                }
+                loc[r] = s;
+            }
+            double tot;
+            const double ex = block_excl_scan(s, sm.dsh, &tot);
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                const int k = base + r;
+                if (r < R && k < t1) d.is_pre[k] = ex + loc[r];
+            }
+            if (tid == 0) d.is_tsum[tile] = tot;
+        }
+    }
+
+    // ---- the last block to finish scans the tile sums
+    __syncthreads();
+    if (tid == 0) {
+        __threadfence();
+        const uint32_t tk = atomicAdd(&d.ctl->cnt_median, 1u);
+        sm.last = (tk == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (sm.last) {
+        __threadfence();
+        block_scan_array<double>(d.is_tsum, d.is_tile, g.nt);
+        if (tid == 0) d.ctl->cnt_median = 0;
+    }
+}
+
+// ------------------------------------------------------------------ SNR, decisions, subtraction
+
+// rho^2 = 4 q sum_{k in track} 1/S^t[k] for every unsubtracted candidate;
+// rho^2 > rho_th^2 subtracts the source from D at once (appendix
+// "Subtraction algorithm", steps 6-9); the last block prepares the next body.
+__global__ __launch_bounds__(WG) void k_snr(Grid g, Dev d, int t)
+{
+    __shared__ int last;
+    if (d.ctl->done) return;
+    const uint32_t nc = d.ctl->n_cand;
+    uint32_t my_new = 0;
+    uint64_t near = 0;
+    double minm = INFINITY;
+    for (uint32_t j = blockIdx.x * WG + threadIdx.x; j < nc; j += gridDim.x * WG) {
+        if (d.c_iter[j] >= 0) continue;
+        const int glo = d.c_glo[j], ghi = d.c_ghi[j];
+        const double q = d.c_q[j];
+        const double r2 = (4.0 * q) * range_inv_sum(d.S, d.is_pre, d.is_tile, glo, ghi, g.tile);
+        d.c_rho2[j] = r2;
+        const double rel = fabs(sqrt(r2) / g.rth - 1.0);
+        minm = fmin(minm, rel);
+        near += rel <= 1e-6;
+        if (r2 > g.rth2) {
+            d.c_iter[j] = t;
+            ++my_new;
+            const int64_t v = (int64_t)d.c_qfx[j];
+            if (v) {
+                atomic_add_i128(&d.D[glo], -v);
+                atomic_add_i128(&d.D[ghi + 1], v);
+                atomic_add_i128(&d.Dtile[glo / g.tile], -v);
+                if (ghi + 1 < g.B) atomic_add_i128(&d.Dtile[(ghi + 1) / g.tile], v);
+            }
+            atomicAdd(&d.chgx[glo / g.tile], 1);
+            atomicAdd(&d.chgx[ghi / g.tile + 1], -1);
+            const int slo = max(glo - g.h, 0), shi = min(ghi + g.h, g.B - 1);
+            atomicAdd(&d.chgs[slo / g.tile], 1);
+            atomicAdd(&d.chgs[shi / g.tile + 1], -1);
+        }
+    }
+    // block totals
+    for (int s = 32; s >= 1; s >>= 1) {
+        my_new += (uint32_t)__shfl_xor((int)my_new, s, 64);
+        near += (uint64_t)__shfl_xor((long long)near, s, 64);
+        minm = fmin(minm, __shfl_xor(minm, s, 64));
+    }
+    if (lane_id() == 0) {
+        if (my_new) atomicAdd(&d.ctl->cur_new, my_new);
+        if (near) atomicAdd((unsigned long long *)&d.ctl->n_near, (unsigned long long)near);
+        if (minm < INFINITY)
+            atomicMin((unsigned long long *)&d.ctl->min_margin, (unsigned long long)__double_as_longlong(minm));
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        last = atomicAdd(&d.ctl->cnt_snr, 1u) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    // tail: carries of D, dirty tiles for the next body, loop control
+    block_scan_array<I128>(d.Dtile, d.Dcarry, g.nt);
+    {
+        __shared__ uint32_t shx[WG / 64], shs[WG / 64];
+        uint32_t cx = 0, cs = 0;
+        for (int base = 0; base < g.nt; base += WG) {
+            const int i = base + threadIdx.x;
+            const int vx = (i < g.nt) ? d.chgx[i] : 0;
+            const int vs = (i < g.nt) ? d.chgs[i] : 0;
+            uint32_t tx, ts;
+            const uint32_t ex = block_excl_scan((uint32_t)vx, shx, &tx);
+            const uint32_t es = block_excl_scan((uint32_t)vs, shs, &ts);
+            if (i < g.nt) {
+                d.xdirty[i] = (int32_t)(cx + ex + (uint32_t)vx) > 0;
+                d.sdirty[i] = (int32_t)(cs + es + (uint32_t)vs) > 0;
+                d.chgx[i] = 0;
+                d.chgs[i] = 0;
+            }
+            cx += tx;
+            cs += ts;
+        }
+        if (threadIdx.x == 0) {
+            d.chgx[g.nt] = 0;
+            d.chgs[g.nt] = 0;
+        }
+    }
+    if (threadIdx.x == 0) {
+        const uint32_t nw = d.ctl->cur_new;
+        if (t < NEW_CAP) d.n_new[t] = nw;
+        d.ctl->n_resolved += nw;
+        d.ctl->cur_new = 0;
+        if (nw == 0) {
+            d.ctl->done = 1;
+            d.ctl->n_iter = (uint32_t)t + 1;
+        }
+        d.ctl->cnt_snr = 0;
+    }
+}
+
+// ------------------------------------------------------------------ outputs
+
+__global__ __launch_bounds__(WG) void k_res_out(Dev d, const uint32_t *ids)
+{
+    const uint32_t nc = d.ctl->n_cand;
+    const uint32_t ncr = (nc + 63) & ~63u;
+    for (uint32_t j = blockIdx.x * WG + threadIdx.x; j < ncr; j += gridDim.x * WG) {
+        const bool r = j < nc && d.c_iter[j] >= 0;
+        const uint64_t mask = __ballot(r);
+        if (!mask) continue;
+        const int lane = lane_id();
+        const int leader = __ffsll((long long)mask) - 1;
+        uint32_t base = 0;
+        if (lane == leader) base = atomicAdd(&d.ctl->n_res_out, (uint32_t)__popcll(mask));
+        base = (uint32_t)__shfl((int)base, leader, 64);
+        if (r) {
+            const uint32_t o = base + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+            d.res_id[o] = ids[d.c_src[j]];
+            d.res_iter[o] = d.c_iter[j];
+        }
+    }
+}
+
+// ------------------------------------------------------------------ launchers
+
+static unsigned blocks_for(uint64_t n, unsigned cap = 4096)
+{
+    uint64_t b = (n + WG - 1) / WG;
+    if (b < 1) b = 1;
+    return (unsigned)(b > cap ? cap : b);
+}
+
+hipError_t launch_grid_tables(const Grid &g, const Dev &d, hipStream_t st)
+{
+    k_sinstr<<<(g.B + WG - 1) / WG, WG, 0, st>>>(g, d.sx);
+    k_inv_prefix<<<g.nt, WG, 0, st>>>(g, d.sx, d.isx_pre, d.isx_tsum);
+    k_scan_f64<<<1, WG, 0, st>>>(d.isx_tsum, d.isx_tile, g.nt);
+    return hipGetLastError();
+}
+
+hipError_t launch_reset(const Grid &g, const Dev &d, uint64_t n_src, hipStream_t st)
+{
+    (void)n_src;
+    k_init_ctl<<<1, 64, 0, st>>>(d.ctl);
+    const uint64_t dwords = (uint64_t)(g.B + 1) * 4;   // D as u32 words
+    k_fill_u32<<<blocks_for(dwords), WG, 0, st>>>(reinterpret_cast<uint32_t *>(d.D), dwords, 0u);
+    k_fill_u32<<<blocks_for((g.nt + 1) * 4ull), WG, 0, st>>>(reinterpret_cast<uint32_t *>(d.Dtile), (g.nt + 1) * 4ull, 0u);
+    k_fill_u32<<<blocks_for(g.nt + 1), WG, 0, st>>>(reinterpret_cast<uint32_t *>(d.chgx), g.nt + 1, 0u);
+    k_fill_u32<<<blocks_for(g.nt + 1), WG, 0, st>>>(reinterpret_cast<uint32_t *>(d.chgs), g.nt + 1, 0u);
+    const uint64_t flag_words = ((uint64_t)g.nt + 3) / 4;
+    k_fill_u32<<<blocks_for(flag_words), WG, 0, st>>>(reinterpret_cast<uint32_t *>(d.xdirty), flag_words, 0x01010101u);
+    k_fill_u32<<<blocks_for(flag_words), WG, 0, st>>>(reinterpret_cast<uint32_t *>(d.sdirty), flag_words, 0x01010101u);
+    return hipGetLastError();
+}
+
+hipError_t launch_prep(const Grid &g, const Dev &d, const float *A, const float *f,
+                       const float *fdot, uint64_t n, hipStream_t st)
+{
+    if (n > 0) {
+        k_amax<<<blocks_for(n, 2048), WG, 0, st>>>(A, n, d.ctl);
+        k_prep<<<blocks_for(n, 8192), WG, 0, st>>>(g, d, A, f, fdot, n);
+    }
+    k_dtile_sum<<<g.nt, WG, 0, st>>>(g, d);
+    k_dscan<<<1, WG, 0, st>>>(g, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_iteration(const Grid &g, const Dev &d, int t, hipStream_t st)
+{
+    k_xupdate<<<g.nt, WG, 0, st>>>(g, d);
+    k_median<<<g.nt, WG, 0, st>>>(g, d);
+    k_snr<<<SNR_BLOCKS, WG, 0, st>>>(g, d, t);
+    return hipGetLastError();
+}
+
+hipError_t launch_outputs(const Grid &g, const Dev &d, const uint32_t *ids, hipStream_t st)
+{
+    (void)g;
+    k_res_out<<<SNR_BLOCKS, WG, 0, st>>>(d, ids);
+    return hipGetLastError();
+}
+
+}  // namespace gbs

@@ -1,0 +1,261 @@
+"""Python binding of ``libgbsub.so`` (ctypes): argument marshalling only.
+
+Every step of the subtraction runs in the HIP kernels behind the C ABI of
+``include/gbsub.h``.  PyTorch supplies device memory (tensors) and streams;
+the binding passes their raw pointers.  There is no CPU fallback: if the
+library is missing, or no GPU is visible, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_lib", "libgbsub.so")
+
+OK, E_INVALID, E_NOMEM, E_DEVICE, E_STATE, E_TRUNCATED, E_MAXITER = 0, -1, -2, -3, -4, -5, -6
+MEDIAN, MEAN = 0, 1
+TRACK_SWEEP, TRACK_SINGLE = 0, 1
+FP64, FP32_COMP, FP32_NAIVE = 0, 1, 2
+SPEC_SN, SPEC_X_RESIDUAL, SPEC_S_GAL, SPEC_S_INSTR = 0, 1, 2, 3
+
+EXPORTS = ["gbsub_default_config", "gbsub_create", "gbsub_workspace_size", "gbsub_run",
+           "gbsub_spectrum", "gbsub_resolved", "gbsub_destroy", "gbsub_status_str"]
+
+
+class GbsubError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {status_str(status)} ({status})")
+
+
+class Config(C.Structure):
+    _fields_ = [("t_obs_s", C.c_double), ("f_min_hz", C.c_double), ("f_max_hz", C.c_double),
+                ("window_bins", C.c_uint32), ("estimator", C.c_uint32),
+                ("snr_threshold", C.c_double), ("kappa", C.c_double), ("median_scale", C.c_double),
+                ("track_model", C.c_uint32), ("precision", C.c_uint32), ("max_iter", C.c_uint32),
+                ("reserved0", C.c_uint32), ("oms_pm", C.c_double), ("tm_fm", C.c_double),
+                ("arm_m", C.c_double)]
+
+
+class CatalogStruct(C.Structure):
+    _fields_ = [("n", C.c_uint64), ("A", C.c_void_p), ("f", C.c_void_p), ("fdot", C.c_void_p),
+                ("id", C.c_void_p)]
+
+
+class SummaryStruct(C.Structure):
+    _fields_ = [("n_iter", C.c_uint32), ("reserved0", C.c_uint32), ("n_bins", C.c_uint64),
+                ("n_candidates", C.c_uint64), ("n_resolved", C.c_uint64),
+                ("n_near_threshold", C.c_uint64), ("min_rel_margin", C.c_double)]
+
+
+_lib = None
+
+
+def load(path: str | None = None):
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = path or LIB_PATH
+    if not os.path.exists(path):
+        raise RuntimeError(f"libgbsub.so not built ({path}); run python -m paper_2602_18560_amd.build")
+    # PyTorch ships its own HIP runtime (same soname as ROCm's).  Loading torch
+    # first makes libgbsub bind to that one runtime, so torch's streams and
+    # allocations are the library's too.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    L = C.CDLL(path)
+    L.gbsub_default_config.argtypes = [C.POINTER(Config)]
+    L.gbsub_default_config.restype = None
+    L.gbsub_create.argtypes = [C.POINTER(Config), C.POINTER(C.c_void_p)]
+    L.gbsub_workspace_size.argtypes = [C.c_void_p, C.c_uint64, C.POINTER(C.c_uint64)]
+    L.gbsub_run.argtypes = [C.c_void_p, C.POINTER(CatalogStruct), C.c_void_p, C.c_uint64,
+                            C.c_void_p, C.POINTER(SummaryStruct)]
+    L.gbsub_spectrum.argtypes = [C.c_void_p, C.c_uint32, C.c_void_p, C.c_uint64,
+                                 C.POINTER(C.c_uint64), C.c_int]
+    L.gbsub_resolved.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64,
+                                 C.POINTER(C.c_uint64), C.c_int]
+    L.gbsub_destroy.argtypes = [C.c_void_p]
+    L.gbsub_destroy.restype = None
+    L.gbsub_status_str.argtypes = [C.c_int]
+    L.gbsub_status_str.restype = C.c_char_p
+    for name in ("gbsub_create", "gbsub_workspace_size", "gbsub_run", "gbsub_spectrum",
+                 "gbsub_resolved"):
+        getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def status_str(s: int) -> str:
+    try:
+        return load().gbsub_status_str(int(s)).decode()
+    except Exception:
+        return "status"
+
+
+def default_config(**kw) -> Config:
+    c = Config()
+    load().gbsub_default_config(C.byref(c))
+    for k, v in kw.items():
+        setattr(c, k, v)
+    return c
+
+
+def config_from_run(run, **kw) -> Config:
+    """``Config`` from an ``inputs.RunConfig`` (or a dict of the same keys)."""
+    d = run.as_dict() if hasattr(run, "as_dict") else dict(run)
+    d.update(kw)
+    c = default_config()
+    for k, v in d.items():
+        if k == "max_iter" and v is None:
+            v = 0
+        setattr(c, k, v)
+    return c
+
+
+@dataclass
+class Summary:
+    n_iter: int
+    n_bins: int
+    n_candidates: int
+    n_resolved: int
+    n_near_threshold: int
+    min_rel_margin: float
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("gbsub needs a ROCm GPU (torch.cuda.is_available() is False)")
+    return torch
+
+
+class DeviceCatalog:
+    """A catalog resident on the GPU (torch tensors: A, f, fdot fp32; id int32)."""
+
+    def __init__(self, A, f, fdot, ids):
+        self.A, self.f, self.fdot, self.id = A, f, fdot, ids
+        self.n = int(A.shape[0])
+
+    @classmethod
+    def from_host(cls, cat, device="cuda", stream=None):
+        torch = _torch()
+        t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a)).to(device, non_blocking=False)
+        return cls(t(cat.A.astype(np.float32), None), t(cat.f.astype(np.float32), None),
+                   t(cat.fdot.astype(np.float32), None), t(cat.id.astype(np.uint32).view(np.int32), None))
+
+    def struct(self) -> CatalogStruct:
+        for x in (self.A, self.f, self.fdot, self.id):
+            if not (x.is_cuda and x.is_contiguous() and x.element_size() == 4 and x.shape[0] == self.n):
+                raise ValueError("catalog arrays must be contiguous 4-byte GPU tensors of length n")
+        return CatalogStruct(self.n, self.A.data_ptr(), self.f.data_ptr(), self.fdot.data_ptr(),
+                             self.id.data_ptr())
+
+
+class Context:
+    """One subtraction context (``gbsub_create``) bound to the current GPU."""
+
+    def __init__(self, cfg: Config):
+        self._L = load()
+        _torch()
+        h = C.c_void_p()
+        st = self._L.gbsub_create(C.byref(cfg), C.byref(h))
+        if st != OK:
+            raise GbsubError(st, "gbsub_create")
+        self.h = h
+        self.cfg = cfg
+        self.workspace = None
+
+    def close(self):
+        if getattr(self, "h", None):
+            self._L.gbsub_destroy(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def workspace_size(self, n: int) -> int:
+        b = C.c_uint64()
+        st = self._L.gbsub_workspace_size(self.h, int(n), C.byref(b))
+        if st != OK:
+            raise GbsubError(st, "gbsub_workspace_size")
+        return b.value
+
+    def ensure_workspace(self, n: int, device="cuda"):
+        torch = _torch()
+        need = self.workspace_size(n)
+        if self.workspace is None or self.workspace.numel() < need:
+            self.workspace = torch.empty(need + 256, dtype=torch.uint8, device=device)
+        return self.workspace
+
+    def _ws_ptr(self, ws):
+        p = ws.data_ptr()
+        return (p + 255) & ~255, ws.numel() - (((p + 255) & ~255) - p)
+
+    def run_raw(self, cat: DeviceCatalog, ws=None, stream=None) -> tuple[int, Summary]:
+        torch = _torch()
+        ws = self.ensure_workspace(cat.n) if ws is None else ws
+        ptr, nbytes = self._ws_ptr(ws)
+        s = SummaryStruct()
+        sp = (stream or torch.cuda.current_stream()).cuda_stream
+        cs = cat.struct()
+        st = self._L.gbsub_run(self.h, C.byref(cs), C.c_void_p(ptr), nbytes, C.c_void_p(sp),
+                               C.byref(s))
+        return st, Summary(s.n_iter, s.n_bins, s.n_candidates, s.n_resolved, s.n_near_threshold,
+                           s.min_rel_margin)
+
+    def run(self, cat: DeviceCatalog, ws=None, stream=None) -> Summary:
+        st, s = self.run_raw(cat, ws, stream)
+        if st != OK:
+            raise GbsubError(st, "gbsub_run")
+        return s
+
+    def spectrum(self, kind: int = SPEC_SN, out=None) -> np.ndarray:
+        """Host copy (numpy) of a spectrum, or a device copy into tensor `out`."""
+        n = C.c_uint64()
+        st = self._L.gbsub_spectrum(self.h, kind, None, 0, C.byref(n), 0)
+        if st not in (OK, E_TRUNCATED):
+            raise GbsubError(st, "gbsub_spectrum")
+        if out is not None:
+            st = self._L.gbsub_spectrum(self.h, kind, C.c_void_p(out.data_ptr()), out.numel(),
+                                        C.byref(n), 1)
+            if st != OK:
+                raise GbsubError(st, "gbsub_spectrum")
+            return out
+        buf = np.empty(n.value, np.float64)
+        st = self._L.gbsub_spectrum(self.h, kind, buf.ctypes.data, buf.shape[0], C.byref(n), 0)
+        if st != OK:
+            raise GbsubError(st, "gbsub_spectrum")
+        return buf
+
+    def resolved(self):
+        """(ids uint32 ascending, iter_of int32) of the last run."""
+        n = C.c_uint64()
+        st = self._L.gbsub_resolved(self.h, None, None, 0, C.byref(n), 0)
+        if st not in (OK, E_TRUNCATED):
+            raise GbsubError(st, "gbsub_resolved")
+        ids = np.empty(n.value, np.uint32)
+        it = np.empty(n.value, np.int32)
+        st = self._L.gbsub_resolved(self.h, ids.ctypes.data, it.ctypes.data, ids.shape[0],
+                                    C.byref(n), 0)
+        if st != OK:
+            raise GbsubError(st, "gbsub_resolved")
+        return ids, it
+
+
+def subtract(cat, run, **kw):
+    """Convenience: host catalog + RunConfig -> (summary, S_n, resolved ids, iter_of)."""
+    ctx = Context(config_from_run(run, **kw))
+    try:
+        dc = DeviceCatalog.from_host(cat)
+        s = ctx.run(dc)
+        S = ctx.spectrum(SPEC_SN)
+        ids, it = ctx.resolved()
+        return s, S, ids, it
+    finally:
+        ctx.close()
