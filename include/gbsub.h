@@ -147,6 +147,27 @@ gbsub_status gbsub_spectrum(const gbsub_ctx *ctx, uint32_t kind, double *out, ui
 gbsub_status gbsub_resolved(const gbsub_ctx *ctx, uint32_t *ids, int32_t *iter_of, uint64_t cap,
                             uint64_t *n, int out_on_device);
 
+/* Per-kernel timing of the runs made while profiling is enabled. */
+typedef struct {
+    char     name[24];           /* kernel family: "tables", "reset", "prep", "xupdate",
+                                    "median", "snr", "output" */
+    uint64_t launches;           /* launches that did work (bodies past the settled one excluded) */
+    double   total_ms;           /* sum of HIP-event durations on the run's stream */
+    double   units;              /* work units processed by those launches */
+    char     unit[16];           /* "bins", "sources", "candidates" */
+} gbsub_kernel_stat;
+
+/* Enables (1) or disables (0) profiling and clears the accumulated stats.
+ * While enabled, gbsub_run brackets every kernel launch with HIP events on
+ * its stream (host-side events only; no device memory). */
+gbsub_status gbsub_set_profiling(gbsub_ctx *ctx, int enable);
+
+/* Copies up to `cap` accumulated kernel stats into out[] (host pointer);
+ * *n (host) receives the number of kernel families (7).  TRUNCATED if
+ * cap < 7. */
+gbsub_status gbsub_kernel_stats(const gbsub_ctx *ctx, gbsub_kernel_stat *out, uint32_t cap,
+                                uint32_t *n);
+
 /* Releases the context (NULL is ignored).  Does not touch caller memory. */
 void gbsub_destroy(gbsub_ctx *ctx);
 

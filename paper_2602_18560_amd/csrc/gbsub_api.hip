@@ -27,10 +27,52 @@ struct gbsub_ctx {
     Dev dev;
     void *ws;
     gbsub_summary summ;
-    uint32_t n_res;
+    uint32_t n_cand;
     // the S_instr tables in `tables_ws` were computed for this grid
     void *tables_ws;
     Ctl *host_ctl;     // pinned
+    // profiling
+    bool profiling;
+    struct Rec { int kid; int64_t t; hipEvent_t a, b; };
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used;
+    std::vector<Rec> recs;
+    uint64_t k_launches[K_COUNT];
+    double k_ms[K_COUNT];
+    double k_units[K_COUNT];
+
+    hipEvent_t next_event()
+    {
+        if (ev_used == ev_pool.size()) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            ev_pool.push_back(e);
+        }
+        return ev_pool[ev_used++];
+    }
+
+    // Launches through `fn`, bracketed by events when profiling.
+    template <typename F>
+    hipError_t timed(int kid, int64_t t, hipStream_t st, F fn)
+    {
+        if (!profiling) return fn();
+        hipEvent_t a = next_event(), b = next_event();
+        if (!a || !b) return hipErrorOutOfMemory;
+        hipError_t e = hipEventRecord(a, st);
+        if (e == hipSuccess) e = fn();
+        if (e == hipSuccess) e = hipEventRecord(b, st);
+        recs.push_back({kid, t, a, b});
+        return e;
+    }
+
+    void clear_stats()
+    {
+        for (int k = 0; k < K_COUNT; ++k) {
+            k_launches[k] = 0;
+            k_ms[k] = 0.0;
+            k_units[k] = 0.0;
+        }
+    }
 };
 
 namespace {
@@ -49,11 +91,16 @@ uint64_t carve(const Grid &g, uint64_t n, char *base, Dev *d)
         return p;
     };
     const uint64_t B = (uint64_t)g.B, nt = (uint64_t)g.nt, nn = n ? n : 1;
+    const uint64_t max_events = 2 * n;
+    const uint64_t ev_chunks = (max_events + ACC_EV - 1) / ACC_EV;
     Dev t{};
+    t.max_chunks = (uint32_t)(ev_chunks + nt);
+    t.max_slots = (uint32_t)(2 * ev_chunks + 2);
     t.sx = (double *)take(B * 8);
     t.isx_pre = (double *)take(B * 8);
     t.isx_tsum = (double *)take(nt * 8);
     t.isx_tile = (double *)take((nt + 1) * 8);
+    t.Xn = (I128 *)take(B * 16);
     t.D = (I128 *)take((B + 1) * 16);
     t.Dtile = (I128 *)take((nt + 1) * 16);
     t.Dcarry = (I128 *)take((nt + 1) * 16);
@@ -66,16 +113,29 @@ uint64_t carve(const Grid &g, uint64_t n, char *base, Dev *d)
     t.chgs = (int32_t *)take((nt + 1) * 4);
     t.xdirty = (uint8_t *)take(align_up(nt));
     t.sdirty = (uint8_t *)take(align_up(nt));
+    t.btot = (uint32_t *)take(nt * 4);
+    t.bbase = (uint32_t *)take((nt + 1) * 4);
+    t.cursor = (uint32_t *)take(nt * 4);
+    t.nch = (uint32_t *)take(nt * 4);
+    t.chunk_base = (uint32_t *)take((nt + 1) * 4);
+    t.slot_base = (uint32_t *)take(nt * 4);
+    t.ev_key = (uint32_t *)take((max_events ? max_events : 1) * 4);
+    t.ev_val = (int64_t *)take((max_events ? max_events : 1) * 8);
+    t.partial = (I128 *)take((uint64_t)t.max_slots * 2 * (uint64_t)g.tile * 16);
+    t.amax_part = (uint32_t *)take((uint64_t)AMAX_BLOCKS * 4);
     t.c_src = (uint32_t *)take(nn * 4);
+    t.c_id = (uint32_t *)take(nn * 4);
     t.c_glo = (int32_t *)take(nn * 4);
     t.c_ghi = (int32_t *)take(nn * 4);
     t.c_iter = (int32_t *)take(nn * 4);
     t.c_q = (double *)take(nn * 8);
     t.c_qfx = (uint64_t *)take(nn * 8);
     t.c_rho2 = (double *)take(nn * 8);
+    t.b_new = (uint32_t *)take((uint64_t)SNR_BLOCKS * 4);
+    t.b_near = (uint64_t *)take((uint64_t)SNR_BLOCKS * 8);
+    t.b_evals = (uint64_t *)take((uint64_t)SNR_BLOCKS * 8);
+    t.b_minm = (double *)take((uint64_t)SNR_BLOCKS * 8);
     t.n_new = (uint32_t *)take((uint64_t)NEW_CAP * 4);
-    t.res_id = (uint32_t *)take(nn * 4);
-    t.res_iter = (int32_t *)take(nn * 4);
     t.ctl = (Ctl *)take(sizeof(Ctl));
     if (d) *d = t;
     return off;
@@ -109,10 +169,11 @@ gbsub_status validate(const gbsub_config *c, Grid *g)
     r.h = (r.W - 1) / 2;
     // tile: outputs + W - 1 must fit the median kernel's LDS union
     int tile = ((MMAX - (r.W - 1)) / WG) * WG;
-    if (tile > 2048) tile = 2048;
+    if (tile > TILE_MAX) tile = TILE_MAX;
     if (tile < WG) return GBSUB_E_INVALID;
     r.tile = tile;
     r.nt = (r.B + tile - 1) / tile;
+    if (r.nt > NBK_MAX) return GBSUB_E_INVALID;
     r.track_single = c->track_model == GBSUB_TRACK_SINGLE;
     r.T = c->t_obs_s;
     r.C = c->median_scale;
@@ -183,6 +244,9 @@ gbsub_status gbsub_create(const gbsub_config *cfg, gbsub_ctx **out)
     c->ws = nullptr;
     c->tables_ws = nullptr;
     c->host_ctl = nullptr;
+    c->profiling = false;
+    c->ev_used = 0;
+    c->clear_stats();
     if (hipHostMalloc((void **)&c->host_ctl, sizeof(Ctl), hipHostMallocDefault) != hipSuccess) {
         delete c;
         return GBSUB_E_DEVICE;
@@ -195,12 +259,13 @@ void gbsub_destroy(gbsub_ctx *c)
 {
     if (!c) return;
     if (c->host_ctl) (void)hipHostFree(c->host_ctl);
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     delete c;
 }
 
 gbsub_status gbsub_workspace_size(const gbsub_ctx *c, uint64_t n, uint64_t *bytes)
 {
-    if (!c || !bytes || n >= (1ull << 32)) return GBSUB_E_INVALID;
+    if (!c || !bytes || n >= (1ull << 31)) return GBSUB_E_INVALID;
     *bytes = carve(c->g, n, nullptr, nullptr);
     return GBSUB_OK;
 }
@@ -209,7 +274,7 @@ gbsub_status gbsub_run(gbsub_ctx *c, const gbsub_catalog *cat, void *ws, uint64_
                        void *stream, gbsub_summary *out)
 {
     if (!c || !cat || !ws) return GBSUB_E_INVALID;
-    if (cat->n >= (1ull << 32)) return GBSUB_E_INVALID;
+    if (cat->n >= (1ull << 31)) return GBSUB_E_INVALID;
     if (cat->n > 0 && (!cat->A || !cat->f || !cat->fdot || !cat->id)) return GBSUB_E_INVALID;
     if (((uintptr_t)ws & 255u) != 0) return GBSUB_E_INVALID;
     const uint64_t need = carve(c->g, cat->n, nullptr, nullptr);
@@ -223,14 +288,17 @@ gbsub_status gbsub_run(gbsub_ctx *c, const gbsub_catalog *cat, void *ws, uint64_
     carve(c->g, cat->n, (char *)ws, &d);
     const Grid &g = c->g;
 
+    c->ev_used = 0;
+    c->recs.clear();
     hipError_t e = hipSuccess;
     if (c->tables_ws != ws) {
-        e = launch_grid_tables(g, d, st);
+        e = c->timed(K_TABLES, -1, st, [&] { return launch_grid_tables(g, d, st); });
         if (e != hipSuccess) return GBSUB_E_DEVICE;
         c->tables_ws = ws;
     }
-    e = launch_reset(g, d, cat->n, st);
-    if (e == hipSuccess) e = launch_prep(g, d, cat->A, cat->f, cat->fdot, cat->n, st);
+    e = c->timed(K_RESET, -1, st, [&] { return launch_reset(g, d, cat->n, st); });
+    if (e == hipSuccess)
+        e = c->timed(K_PREP, -1, st, [&] { return launch_prep(g, d, cat->A, cat->f, cat->fdot, cat->n, st); });
     if (e == hipSuccess) e = hipMemcpyAsync(c->host_ctl, d.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) {
@@ -246,7 +314,12 @@ gbsub_status gbsub_run(gbsub_ctx *c, const gbsub_catalog *cat, void *ws, uint64_
     uint64_t chunk = 4;
     for (;;) {
         const uint64_t k = std::min(chunk, max_iter - t);
-        for (uint64_t i = 0; i < k && e == hipSuccess; ++i) e = launch_iteration(g, d, (int)(t + i), st);
+        for (uint64_t i = 0; i < k && e == hipSuccess; ++i) {
+            const int ti = (int)(t + i);
+            e = c->timed(K_XUPDATE, ti, st, [&] { return launch_xupdate(g, d, st); });
+            if (e == hipSuccess) e = c->timed(K_MEDIAN, ti, st, [&] { return launch_median(g, d, st); });
+            if (e == hipSuccess) e = c->timed(K_SNR, ti, st, [&] { return launch_snr(g, d, ti, st); });
+        }
         t += k;
         if (e == hipSuccess) e = hipMemcpyAsync(c->host_ctl, d.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -258,12 +331,30 @@ gbsub_status gbsub_run(gbsub_ctx *c, const gbsub_catalog *cat, void *ws, uint64_
         }
         chunk = std::min<uint64_t>(chunk * 2, 32);
     }
-    e = launch_outputs(g, d, cat->id, st);
+    e = c->timed(K_OUTPUT, -1, st, [&] { return launch_outputs(g, d, cat->id, st); });
     if (e == hipSuccess) e = hipMemcpyAsync(c->host_ctl, d.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return GBSUB_E_DEVICE;
 
     const Ctl &h = *c->host_ctl;
+    if (c->profiling) {
+        const int64_t n_body = status == GBSUB_OK ? (int64_t)h.n_iter : (int64_t)t;
+        for (const auto &r : c->recs) {
+            if (r.t >= n_body) continue;        // bodies enqueued past the settled one
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) return GBSUB_E_DEVICE;
+            c->k_ms[r.kid] += ms;
+            c->k_launches[r.kid] += 1;
+        }
+        c->k_units[K_PREP] += (double)cat->n;
+        c->k_units[K_RESET] += (double)g.B;
+        c->k_units[K_XUPDATE] += (double)h.units_x;
+        c->k_units[K_MEDIAN] += (double)h.units_med;
+        c->k_units[K_SNR] += (double)h.units_snr;
+        c->k_units[K_OUTPUT] += (double)h.n_cand;
+        for (const auto &r : c->recs)
+            if (r.kid == K_TABLES) c->k_units[K_TABLES] += (double)g.B;
+    }
     gbsub_summary s{};
     s.n_iter = status == GBSUB_OK ? h.n_iter : (uint32_t)t;
     s.n_bins = (uint64_t)g.B;
@@ -278,7 +369,7 @@ gbsub_status gbsub_run(gbsub_ctx *c, const gbsub_catalog *cat, void *ws, uint64_
     c->summ = s;
     c->dev = d;
     c->ws = ws;
-    c->n_res = h.n_res_out;
+    c->n_cand = h.n_cand;
     c->have_result = true;
     return GBSUB_OK;
 }
@@ -315,20 +406,28 @@ gbsub_status gbsub_resolved(const gbsub_ctx *c, uint32_t *ids, int32_t *iter_of,
 {
     if (!c || !n) return GBSUB_E_INVALID;
     if (!c->have_result) return GBSUB_E_STATE;
-    const uint64_t m = c->n_res;
+    if (hipSetDevice(c->device) != hipSuccess) return GBSUB_E_DEVICE;
+    const uint64_t nc = c->n_cand;
+    std::vector<uint32_t> id(nc);
+    std::vector<int32_t> it(nc);
+    hipError_t e = hipSuccess;
+    if (nc) {
+        e = hipMemcpy(id.data(), c->dev.c_id, nc * 4, hipMemcpyDeviceToHost);
+        if (e == hipSuccess) e = hipMemcpy(it.data(), c->dev.c_iter, nc * 4, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return GBSUB_E_DEVICE;
+    }
+    std::vector<uint64_t> key;
+    key.reserve(c->summ.n_resolved);
+    for (uint64_t j = 0; j < nc; ++j)
+        if (it[j] >= 0) key.push_back(((uint64_t)id[j] << 32) | (uint32_t)it[j]);
+    std::sort(key.begin(), key.end());
+    const uint64_t m = key.size();
     *n = m;
     if (cap < m) return GBSUB_E_TRUNCATED;
     if (m == 0) return GBSUB_OK;
     if (!ids) return GBSUB_E_INVALID;
-    if (hipSetDevice(c->device) != hipSuccess) return GBSUB_E_DEVICE;
-    std::vector<uint32_t> id(m);
-    std::vector<int32_t> it(m);
-    hipError_t e = hipMemcpy(id.data(), c->dev.res_id, m * 4, hipMemcpyDeviceToHost);
-    if (e == hipSuccess) e = hipMemcpy(it.data(), c->dev.res_iter, m * 4, hipMemcpyDeviceToHost);
-    if (e != hipSuccess) return GBSUB_E_DEVICE;
-    std::vector<uint64_t> key(m);
-    for (uint64_t j = 0; j < m; ++j) key[j] = ((uint64_t)id[j] << 32) | (uint32_t)it[j];
-    std::sort(key.begin(), key.end());
+    id.resize(m);
+    it.resize(m);
     for (uint64_t j = 0; j < m; ++j) {
         id[j] = (uint32_t)(key[j] >> 32);
         it[j] = (int32_t)(uint32_t)key[j];
@@ -337,6 +436,34 @@ gbsub_status gbsub_resolved(const gbsub_ctx *c, uint32_t *ids, int32_t *iter_of,
     e = hipMemcpy(ids, id.data(), m * 4, kd);
     if (e == hipSuccess && iter_of) e = hipMemcpy(iter_of, it.data(), m * 4, kd);
     return dev_err(e);
+}
+
+gbsub_status gbsub_set_profiling(gbsub_ctx *c, int enable)
+{
+    if (!c) return GBSUB_E_INVALID;
+    c->profiling = enable != 0;
+    c->clear_stats();
+    return GBSUB_OK;
+}
+
+gbsub_status gbsub_kernel_stats(const gbsub_ctx *c, gbsub_kernel_stat *out, uint32_t cap, uint32_t *n)
+{
+    if (!c || !n) return GBSUB_E_INVALID;
+    static const char *names[K_COUNT] = {"tables", "reset", "prep", "xupdate", "median", "snr", "output"};
+    static const char *units[K_COUNT] = {"bins", "bins", "sources", "bins", "bins", "candidates",
+                                         "candidates"};
+    *n = K_COUNT;
+    if (cap < (uint32_t)K_COUNT) return GBSUB_E_TRUNCATED;
+    if (!out) return GBSUB_E_INVALID;
+    for (int k = 0; k < K_COUNT; ++k) {
+        std::memset(&out[k], 0, sizeof(out[k]));
+        std::strncpy(out[k].name, names[k], sizeof(out[k].name) - 1);
+        std::strncpy(out[k].unit, units[k], sizeof(out[k].unit) - 1);
+        out[k].launches = c->k_launches[k];
+        out[k].total_ms = c->k_ms[k];
+        out[k].units = c->k_units[k];
+    }
+    return GBSUB_OK;
 }
 
 }  // extern "C"

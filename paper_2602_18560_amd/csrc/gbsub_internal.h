@@ -9,8 +9,14 @@ namespace gbs {
 
 constexpr int WG = 256;            // threads per workgroup for every tiled kernel
 constexpr int MMAX = 3072;         // median tile: outputs + W - 1 must fit
+constexpr int TILE_MAX = 2048;     // bins per tile (also the binning bucket)
+constexpr int NBK_MAX = 8192;      // tiles the prep histogram can hold (B <= 8192 tiles)
 constexpr int NARROW = 16;         // tracks of <= NARROW bins: SNR summed bin by bin
 constexpr int SNR_BLOCKS = 1024;   // fixed grid of the per-candidate kernels
+constexpr int PREP_SRC = 8192;     // sources per prep block
+constexpr int ACC_EV = 65536;      // binning events per accumulation block
+constexpr int RED_BINS = 256;      // bins per reduction block of the hot buckets
+constexpr int AMAX_BLOCKS = 1024;  // grid of the amplitude-maximum kernel
 constexpr int NEW_CAP = 1 << 16;   // per-iteration counters kept (iterations beyond: not recorded)
 constexpr int KEYBITS = 24;        // bits of the per-tile order key of the median sort
 constexpr int CHP = 8;             // median start table: positions per row
@@ -32,13 +38,19 @@ struct Ctl {
     uint32_t done;           // the loop has settled
     uint32_t n_iter;         // loop bodies run (valid when done)
     uint32_t n_resolved;     // sources subtracted so far
-    uint32_t cnt_median;     // last-block tickets
-    uint32_t cnt_snr;
-    uint32_t n_res_out;      // resolved pairs written by the output kernel
-    uint32_t cur_new;        // sources subtracted in the current loop body
+    uint32_t n_chunks;       // accumulation blocks of the binning
+    uint32_t cand_cursor;    // candidate slots handed out
+    uint32_t n_events;       // binning events
+    uint32_t pad0;
     uint64_t n_near;         // evaluations within 1e-6 of the threshold
     uint64_t min_margin;     // bits of min |rho/rho_th - 1| (non-negative double)
+    uint64_t units_x;        // bins converted by k_xupdate
+    uint64_t units_med;      // median outputs computed by k_median
+    uint64_t units_snr;      // candidate evaluations by k_snr
 };
+
+// Kernels that the profiling mode times separately.
+enum KernelId { K_TABLES = 0, K_RESET, K_PREP, K_XUPDATE, K_MEDIAN, K_SNR, K_OUTPUT, K_COUNT };
 
 struct Grid {
     int32_t B;               // bins
@@ -63,8 +75,9 @@ struct Dev {
     double *isx_pre;         // [B]    inclusive prefix of 1/S_instr inside each tile
     double *isx_tsum;        // [nt]   tile sums of 1/S_instr
     double *isx_tile;        // [nt+1] exclusive prefix of the tile sums
-    // per-run spectra
-    I128 *D;                 // [B+1]  fixed-point difference array of the binned power
+    // binned power: X = Xn + prefix(D), all exact 128-bit fixed point
+    I128 *Xn;                // [B]    sources whose clipped track is one bin
+    I128 *D;                 // [B+1]  difference array of the wider tracks
     I128 *Dtile;             // [nt+1] per-tile sums of D
     I128 *Dcarry;            // [nt+1] exclusive prefix of Dtile
     double *X;               // [B]    X^t
@@ -76,17 +89,34 @@ struct Dev {
     int32_t *chgs;           // [nt+1] tiles whose S must be recomputed
     uint8_t *xdirty;         // [nt]
     uint8_t *sdirty;         // [nt]
+    // binning by tile (multisplit): events sorted by tile
+    uint32_t *btot;          // [nt]   events per tile
+    uint32_t *bbase;         // [nt+1] first event of each tile
+    uint32_t *cursor;        // [nt]   scatter cursors
+    uint32_t *nch;           // [nt]   accumulation blocks per tile
+    uint32_t *chunk_base;    // [nt+1]
+    uint32_t *slot_base;     // [nt]   partial-sum slots of tiles with several blocks
+    uint32_t *ev_key;        // [2n]   bin | (1<<31 for difference events)
+    int64_t *ev_val;         // [2n]   signed fixed-point power
+    I128 *partial;           // [slots][2][tile] partial sums of the hot tiles
+    uint32_t *amax_part;     // [AMAX_BLOCKS]
     // candidates (capacity: all sources)
     uint32_t *c_src;         // source index
+    uint32_t *c_id;          // its id (written at the end of a run)
     int32_t *c_glo, *c_ghi;  // clipped track
     int32_t *c_iter;         // loop body that subtracted it, -1 while unresolved
     double *c_q;             // per-bin power
     uint64_t *c_qfx;         // per-bin power in fixed point
     double *c_rho2;          // rho^2 at the last evaluation
+    // per-block partial results of k_snr
+    uint32_t *b_new;         // [SNR_BLOCKS]
+    uint64_t *b_near;        // [SNR_BLOCKS]
+    uint64_t *b_evals;       // [SNR_BLOCKS]
+    double *b_minm;          // [SNR_BLOCKS]
     uint32_t *n_new;         // [NEW_CAP] sources subtracted per loop body
-    uint32_t *res_id;        // [n] ids of the subtracted sources
-    int32_t *res_iter;       // [n] their loop body
     Ctl *ctl;
+    uint32_t max_slots;      // capacity of `partial`
+    uint32_t max_chunks;     // grid of the accumulation kernel
 };
 
 // Kernel launchers (gbsub_kernels.hip); all enqueue on `st` and return the
@@ -95,7 +125,9 @@ hipError_t launch_grid_tables(const Grid &g, const Dev &d, hipStream_t st);
 hipError_t launch_reset(const Grid &g, const Dev &d, uint64_t n_src, hipStream_t st);
 hipError_t launch_prep(const Grid &g, const Dev &d, const float *A, const float *f,
                        const float *fdot, uint64_t n, hipStream_t st);
-hipError_t launch_iteration(const Grid &g, const Dev &d, int t, hipStream_t st);
+hipError_t launch_xupdate(const Grid &g, const Dev &d, hipStream_t st);
+hipError_t launch_median(const Grid &g, const Dev &d, hipStream_t st);
+hipError_t launch_snr(const Grid &g, const Dev &d, int t, hipStream_t st);
 hipError_t launch_outputs(const Grid &g, const Dev &d, const uint32_t *ids, hipStream_t st);
 
 }  // namespace gbs

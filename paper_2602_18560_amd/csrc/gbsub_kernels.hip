@@ -251,7 +251,7 @@ __global__ __launch_bounds__(WG) void k_fill_u32(uint32_t *p, uint64_t n, uint32
         p[i] = v;
 }
 
-__global__ void k_init_ctl(Ctl *c)
+__global__ void k_init_ctl(Ctl *c, int B)
 {
     if (threadIdx.x == 0) {
         c->amax_bits = 0;
@@ -260,115 +260,362 @@ __global__ void k_init_ctl(Ctl *c)
         c->done = 0;
         c->n_iter = 0;
         c->n_resolved = 0;
-        c->cnt_median = 0;
-        c->cnt_snr = 0;
-        c->n_res_out = 0;
-        c->cur_new = 0;
+        c->n_chunks = 0;
+        c->cand_cursor = 0;
+        c->n_events = 0;
         c->n_near = 0;
         c->min_margin = 0x7FF0000000000000ull;   // +inf
+        c->units_x = (uint64_t)B;                // the first body converts and filters every bin
+        c->units_med = (uint64_t)B;
+        c->units_snr = 0;
     }
 }
 
 // ------------------------------------------------------------------ prep
+//
+// Per source (Sec. "Signal parametrization"; appendix "Subtraction
+// algorithm", steps 2-3): power P = A^2 T / 2, mid-track frequency
+// f + fdot T/2, centre bin floor(fbar T + 1/2) - k0, n = 1 + floor(|fdot| T^2)
+// bins, per-bin power q = P/n, track clipped to the grid; rho_0^2 against
+// S_instr; candidate iff rho_0^2 >= (kappa rho_th)^2.
+//
+// Binning without contended global atomics: a count pass tallies binning
+// events per tile in LDS and publishes one atomic per non-empty (block,
+// tile); after a scan of the tile totals, a scatter pass writes every event
+// to its tile's contiguous segment; accumulation blocks then sum up to
+// ACC_EV events of one tile in LDS (exact 128-bit integers) and write the
+// tile's bins, hot tiles through partial sums reduced by a last pass.
 
-// Largest amplitude (fixed-point scale) and validation of A.
-__global__ __launch_bounds__(WG) void k_amax(const float *A, uint64_t n, Ctl *ctl)
+struct Trk {
+    bool ok, live, cand;
+    int glo, ghi;
+    double q;
+    uint64_t qfx;
+};
+
+DEVI Trk track_of(const Grid &g, const Dev &d, float Af, float Ff, float FDf, int L)
 {
+    Trk t;
+    t.ok = false;
+    t.live = false;
+    t.cand = false;
+    t.glo = 0;
+    t.ghi = -1;
+    t.q = 0.0;
+    t.qfx = 0;
+    const double a = (double)Af, f = (double)Ff, fd = (double)FDf;
+    bool ok = isfinite(a) && a >= 0.0 && isfinite(f) && f > 0.0 && isfinite(fd);
+    const double P = ((a * a) * g.T) * 0.5;
+    const double fbar = f + (fd * g.T) * 0.5;
+    const double x = fbar * g.T + 0.5;
+    const double s = (fabs(fd) * g.T) * g.T;
+    ok = ok && fabs(x) < 4503599627370496.0 && s < 2147483648.0;
+    if (!ok) return t;
+    t.ok = true;
+    const int64_t c = (int64_t)floor(x) - g.k0;
+    const int64_t nn = g.track_single ? 1 : 1 + (int64_t)floor(s);
+    const int64_t lo = c - (nn - 1) / 2;
+    const int64_t hi = lo + nn - 1;
+    t.q = P / (double)nn;
+    const int64_t gl = lo < 0 ? 0 : lo;
+    const int64_t gh = hi > g.B - 1 ? g.B - 1 : hi;
+    if (gl > gh) return t;
+    t.live = true;
+    t.glo = (int)gl;
+    t.ghi = (int)gh;
+    const double r2 = (4.0 * t.q) * range_inv_sum(d.sx, d.isx_pre, d.isx_tile, t.glo, t.ghi, g.tile);
+    t.cand = r2 >= g.cut2;
+    t.qfx = to_fx(t.q, L);
+    return t;
+}
+
+// Largest amplitude (fixed-point scale) and validation of A: per-block
+// maxima, then one block reduces them.
+__global__ __launch_bounds__(WG) void k_amax(const float *A, uint64_t n, Dev d)
+{
+    __shared__ uint32_t sm[WG / 64];
     uint32_t m = 0, bad = 0;
     for (uint64_t i = (uint64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (uint64_t)gridDim.x * WG) {
         const float a = A[i];
         if (!(a >= 0.0f) || !isfinite(a)) bad = 1;
         else if (a > 0.0f) m = max(m, __float_as_uint(a));
     }
-    for (int d = 32; d >= 1; d >>= 1) {
-        m = max(m, (uint32_t)__shfl_xor((int)m, d, 64));
-        bad |= (uint32_t)__shfl_xor((int)bad, d, 64);
+    for (int s = 32; s >= 1; s >>= 1) {
+        m = max(m, (uint32_t)__shfl_xor((int)m, s, 64));
+        bad |= (uint32_t)__shfl_xor((int)bad, s, 64);
     }
-    if (lane_id() == 0) {
-        if (m) atomicMax(&ctl->amax_bits, m);
-        if (bad) atomicOr(&ctl->bad, 1u);
+    if (lane_id() == 0) sm[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t r = sm[0];
+        for (int w = 1; w < WG / 64; ++w) r = max(r, sm[w]);
+        d.amax_part[blockIdx.x] = r;
+    }
+    if (bad && lane_id() == 0) atomicOr(&d.ctl->bad, 1u);
+}
+
+__global__ __launch_bounds__(WG) void k_amax_reduce(Dev d, int nparts)
+{
+    uint32_t m = 0;
+    for (int i = threadIdx.x; i < nparts; i += WG) m = max(m, d.amax_part[i]);
+    for (int s = 32; s >= 1; s >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, s, 64));
+    __shared__ uint32_t sm[WG / 64];
+    if (lane_id() == 0) sm[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < WG / 64; ++w) m = max(m, sm[w]);
+        d.ctl->amax_bits = max(sm[0], m);
     }
 }
 
-// One pass over the catalog: power, track, rho_0^2 against S_instr,
-// candidate cut, binning of every source into D, candidate compaction.
-//   P = A^2 T / 2; mid-track frequency f + fdot T/2; centre bin
-//   floor(fbar T + 1/2) - k0; n = 1 + floor(|fdot| T^2) bins; q = P/n.
-// (Sec. "Signal parametrization"; appendix "Subtraction algorithm", steps
-// 2-3: SNR against S_instr and the cut rho >= kappa rho_th.)
-__global__ __launch_bounds__(WG) void k_prep(Grid g, Dev d, const float *A, const float *F,
-                                             const float *FD, uint64_t n)
+// Binning events of one source: a one-bin track adds q to Xn at that bin; a
+// wider one adds +q at its first bin and -q after its last bin in D.
+DEVI int tile_of(int bin, int tile) { return bin / tile; }
+
+// Count pass: events per tile and candidates of this block.
+__global__ __launch_bounds__(WG) void k_prep_count(Grid g, Dev d, const float *A, const float *F,
+                                                   const float *FD, uint64_t n)
 {
+    __shared__ uint32_t hist[NBK_MAX];
+    __shared__ uint32_t scand;
+    for (int b = threadIdx.x; b < g.nt; b += WG) hist[b] = 0;
+    if (threadIdx.x == 0) scand = 0;
+    __syncthreads();
     const int L = fx_exp(d.ctl->amax_bits, g.T);
-    const uint64_t stride = (uint64_t)gridDim.x * WG;
-    const uint64_t nr = (n + 63) & ~63ull;   // whole waves iterate together
-    for (uint64_t i = (uint64_t)blockIdx.x * WG + threadIdx.x; i < nr; i += stride) {
-        bool isc = false;
-        int glo = 0, ghi = -1;
-        double q = 0.0;
-        uint64_t qfx = 0;
-        if (i < n) {
-            const double a = (double)A[i], f = (double)F[i], fd = (double)FD[i];
-            bool ok = isfinite(a) && a >= 0.0 && isfinite(f) && f > 0.0 && isfinite(fd);
-            const double P = ((a * a) * g.T) * 0.5;
-            const double fbar = f + (fd * g.T) * 0.5;
-            const double x = fbar * g.T + 0.5;
-            const double s = (fabs(fd) * g.T) * g.T;
-            ok = ok && fabs(x) < 4503599627370496.0 && s < 2147483648.0;
-            if (!ok) {
-                atomicOr(&d.ctl->bad, 1u);
+    const uint64_t base = (uint64_t)blockIdx.x * PREP_SRC;
+    uint32_t cc = 0, bad = 0;
+    for (int r = 0; r < PREP_SRC / WG; ++r) {
+        const uint64_t i = base + (uint64_t)r * WG + threadIdx.x;
+        if (i >= n) break;
+        const Trk t = track_of(g, d, A[i], F[i], FD[i], L);
+        if (!t.ok) {
+            bad = 1;
+            continue;
+        }
+        if (t.live && t.qfx) {
+            atomicAdd(&hist[tile_of(t.glo, g.tile)], 1u);
+            if (t.glo != t.ghi && t.ghi + 1 < g.B) atomicAdd(&hist[tile_of(t.ghi + 1, g.tile)], 1u);
+        }
+        cc += t.cand;
+    }
+    for (int s = 32; s >= 1; s >>= 1) cc += (uint32_t)__shfl_xor((int)cc, s, 64);
+    if (lane_id() == 0 && cc) atomicAdd(&scand, cc);
+    __syncthreads();
+    for (int b = threadIdx.x; b < g.nt; b += WG)
+        if (hist[b]) atomicAdd(&d.btot[b], hist[b]);
+    if (threadIdx.x == 0 && scand) atomicAdd(&d.ctl->n_cand, scand);
+    if (bad) atomicOr(&d.ctl->bad, 1u);
+}
+
+// Plan (one block): tile bases, scatter cursors, accumulation blocks and
+// partial-sum slots; clears the tile sums of D.
+__global__ __launch_bounds__(WG) void k_prep_plan(Grid g, Dev d)
+{
+    __shared__ uint32_t sh[WG / 64];
+    uint32_t carry_e = 0, carry_c = 0, carry_s = 0;
+    for (int base = 0; base < g.nt; base += WG) {
+        const int b = base + threadIdx.x;
+        const uint32_t cnt = b < g.nt ? d.btot[b] : 0u;
+        const uint32_t nc = b < g.nt ? max(1u, (cnt + ACC_EV - 1) / ACC_EV) : 0u;
+        const uint32_t ns = nc > 1 ? nc : 0u;
+        uint32_t te, tc, ts;
+        const uint32_t ee = block_excl_scan(cnt, sh, &te);
+        const uint32_t ec = block_excl_scan(nc, sh, &tc);
+        const uint32_t es = block_excl_scan(ns, sh, &ts);
+        if (b < g.nt) {
+            d.bbase[b] = carry_e + ee;
+            d.cursor[b] = carry_e + ee;
+            d.nch[b] = nc;
+            d.chunk_base[b] = carry_c + ec;
+            d.slot_base[b] = carry_s + es;
+            d.Dtile[b].lo = 0;
+            d.Dtile[b].hi = 0;
+        }
+        carry_e += te;
+        carry_c += tc;
+        carry_s += ts;
+    }
+    if (threadIdx.x == 0) {
+        d.bbase[g.nt] = carry_e;
+        d.chunk_base[g.nt] = carry_c;
+        d.Dtile[g.nt].lo = 0;
+        d.Dtile[g.nt].hi = 0;
+        d.ctl->n_events = carry_e;
+        d.ctl->n_chunks = carry_c;
+        if (carry_s > d.max_slots || carry_c > d.max_chunks) d.ctl->bad |= 2u;   // cannot happen: sized for the worst case
+    }
+}
+
+// Scatter pass: recount, reserve each tile's range once, write the events
+// and the candidate records.
+__global__ __launch_bounds__(WG) void k_prep_scatter(Grid g, Dev d, const float *A, const float *F,
+                                                     const float *FD, uint64_t n)
+{
+    __shared__ uint32_t cur[NBK_MAX];
+    __shared__ uint32_t scand, cbase;
+    for (int b = threadIdx.x; b < g.nt; b += WG) cur[b] = 0;
+    if (threadIdx.x == 0) scand = 0;
+    __syncthreads();
+    const int L = fx_exp(d.ctl->amax_bits, g.T);
+    const uint64_t base = (uint64_t)blockIdx.x * PREP_SRC;
+    uint32_t cc = 0;
+    for (int r = 0; r < PREP_SRC / WG; ++r) {
+        const uint64_t i = base + (uint64_t)r * WG + threadIdx.x;
+        if (i >= n) break;
+        const Trk t = track_of(g, d, A[i], F[i], FD[i], L);
+        if (!t.ok) continue;
+        if (t.live && t.qfx) {
+            atomicAdd(&cur[tile_of(t.glo, g.tile)], 1u);
+            if (t.glo != t.ghi && t.ghi + 1 < g.B) atomicAdd(&cur[tile_of(t.ghi + 1, g.tile)], 1u);
+        }
+        cc += t.cand;
+    }
+    for (int s = 32; s >= 1; s >>= 1) cc += (uint32_t)__shfl_xor((int)cc, s, 64);
+    if (lane_id() == 0 && cc) atomicAdd(&scand, cc);
+    __syncthreads();
+    for (int b = threadIdx.x; b < g.nt; b += WG)
+        if (cur[b]) cur[b] = atomicAdd(&d.cursor[b], cur[b]);
+    if (threadIdx.x == 0) {
+        cbase = scand ? atomicAdd(&d.ctl->cand_cursor, scand) : 0u;
+        scand = 0;
+    }
+    __syncthreads();
+    for (int r = 0; r < PREP_SRC / WG; ++r) {
+        const uint64_t i = base + (uint64_t)r * WG + threadIdx.x;
+        if (i >= n) break;
+        const Trk t = track_of(g, d, A[i], F[i], FD[i], L);
+        if (!t.ok) continue;
+        if (t.live && t.qfx) {
+            if (t.glo == t.ghi) {
+                const uint32_t p = atomicAdd(&cur[tile_of(t.glo, g.tile)], 1u);
+                d.ev_key[p] = (uint32_t)t.glo;
+                d.ev_val[p] = (int64_t)t.qfx;
             } else {
-                const int64_t c = (int64_t)floor(x) - g.k0;
-                const int64_t nn = g.track_single ? 1 : 1 + (int64_t)floor(s);
-                const int64_t lo = c - (nn - 1) / 2;
-                const int64_t hi = lo + nn - 1;
-                q = P / (double)nn;
-                const int64_t gl = lo < 0 ? 0 : lo;
-                const int64_t gh = hi > g.B - 1 ? g.B - 1 : hi;
-                if (gl <= gh) {
-                    glo = (int)gl;
-                    ghi = (int)gh;
-                    const double r2 = (4.0 * q) * range_inv_sum(d.sx, d.isx_pre, d.isx_tile, glo, ghi, g.tile);
-                    isc = r2 >= g.cut2;
-                    qfx = to_fx(q, L);
-                    if (qfx) {
-                        atomic_add_i128(&d.D[glo], (int64_t)qfx);
-                        atomic_add_i128(&d.D[ghi + 1], -(int64_t)qfx);
-                    }
+                uint32_t p = atomicAdd(&cur[tile_of(t.glo, g.tile)], 1u);
+                d.ev_key[p] = (uint32_t)t.glo | 0x80000000u;
+                d.ev_val[p] = (int64_t)t.qfx;
+                if (t.ghi + 1 < g.B) {
+                    p = atomicAdd(&cur[tile_of(t.ghi + 1, g.tile)], 1u);
+                    d.ev_key[p] = (uint32_t)(t.ghi + 1) | 0x80000000u;
+                    d.ev_val[p] = -(int64_t)t.qfx;
                 }
             }
         }
-        const uint64_t mask = __ballot(isc);
-        if (mask) {
-            const int lane = lane_id();
-            const int leader = __ffsll((long long)mask) - 1;
-            uint32_t base = 0;
-            if (lane == leader) base = atomicAdd(&d.ctl->n_cand, (uint32_t)__popcll(mask));
-            base = (uint32_t)__shfl((int)base, leader, 64);
-            if (isc) {
-                const uint32_t j = base + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
-                d.c_src[j] = (uint32_t)i;
-                d.c_glo[j] = glo;
-                d.c_ghi[j] = ghi;
-                d.c_q[j] = q;
-                d.c_qfx[j] = qfx;
-                d.c_iter[j] = -1;
-            }
+        if (t.cand) {
+            const uint32_t j = cbase + atomicAdd(&scand, 1u);
+            d.c_src[j] = (uint32_t)i;
+            d.c_glo[j] = t.glo;
+            d.c_ghi[j] = t.ghi;
+            d.c_q[j] = t.q;
+            d.c_qfx[j] = t.qfx;
+            d.c_iter[j] = -1;
         }
     }
 }
 
-// Per-tile sums of D (one block per tile), then their exclusive prefix.
-__global__ __launch_bounds__(WG) void k_dtile_sum(Grid g, Dev d)
+DEVI void lds_add_i128(I128 *p, int64_t v)
 {
+    const uint64_t vlo = (uint64_t)v;
+    const int64_t vhi = v < 0 ? -1 : 0;
+    const uint64_t old = atomicAdd((unsigned long long *)&p->lo, (unsigned long long)vlo);
+    const int64_t add_hi = vhi + (int64_t)((uint64_t)(old + vlo) < old);
+    if (add_hi != 0) atomicAdd((unsigned long long *)&p->hi, (unsigned long long)add_hi);
+}
+
+DEVI void atomic_add_i128_full(I128 *p, I128 v)
+{
+    const uint64_t old = atomicAdd((unsigned long long *)&p->lo, (unsigned long long)v.lo);
+    const int64_t add_hi = v.hi + (int64_t)((uint64_t)(old + v.lo) < old);
+    if (add_hi != 0) atomicAdd((unsigned long long *)&p->hi, (unsigned long long)add_hi);
+}
+
+// Accumulation: block c sums up to ACC_EV events of one tile in LDS.
+__global__ __launch_bounds__(WG) void k_accum(Grid g, Dev d)
+{
+    __shared__ I128 xn[TILE_MAX];
+    __shared__ I128 dd[TILE_MAX];
     __shared__ I128 sh[WG / 64];
-    const int tile = blockIdx.x;
-    I128 s = zero_t<I128>();
-    for (int k = tile * g.tile + threadIdx.x; k < min((tile + 1) * g.tile, g.B); k += WG)
-        s = i128_add(s, d.D[k]);
-    I128 tot;
-    block_excl_scan(s, sh, &tot);
-    if (threadIdx.x == 0) d.Dtile[tile] = tot;
+    const uint32_t c = blockIdx.x;
+    if (c >= d.ctl->n_chunks) return;
+    // tile b: the last with chunk_base[b] <= c
+    int lo = 0, hi = g.nt - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (d.chunk_base[mid] <= c) lo = mid; else hi = mid - 1;
+    }
+    const int b = lo;
+    const uint32_t ci = c - d.chunk_base[b];
+    const uint32_t e0 = d.bbase[b] + ci * ACC_EV;
+    const uint32_t e1 = min(e0 + (uint32_t)ACC_EV, d.bbase[b + 1]);
+    const int k0 = b * g.tile;
+    for (int k = threadIdx.x; k < g.tile; k += WG) {
+        xn[k].lo = 0; xn[k].hi = 0;
+        dd[k].lo = 0; dd[k].hi = 0;
+    }
+    __syncthreads();
+    for (uint32_t e = e0 + threadIdx.x; e < e1; e += WG) {
+        const uint32_t key = d.ev_key[e];
+        const int64_t v = d.ev_val[e];
+        const int k = (int)(key & 0x7FFFFFFFu) - k0;
+        lds_add_i128((key >> 31) ? &dd[k] : &xn[k], v);
+    }
+    __syncthreads();
+    const int nbin = min(g.tile, g.B - k0);
+    if (d.nch[b] == 1) {
+        I128 s = zero_t<I128>();
+        for (int k = threadIdx.x; k < g.tile; k += WG) {
+            if (k < nbin) {
+                d.Xn[k0 + k] = xn[k];
+                d.D[k0 + k] = dd[k];
+                s = i128_add(s, dd[k]);
+            }
+        }
+        I128 tot;
+        block_excl_scan(s, sh, &tot);
+        if (threadIdx.x == 0) d.Dtile[b] = tot;
+    } else {
+        I128 *slot = d.partial + (size_t)(d.slot_base[b] + ci) * 2 * g.tile;
+        for (int k = threadIdx.x; k < g.tile; k += WG) {
+            slot[k] = xn[k];
+            slot[g.tile + k] = dd[k];
+        }
+    }
+}
+
+// Hot tiles (several accumulation blocks): sum the partials, RED_BINS bins
+// per block.
+__global__ __launch_bounds__(RED_BINS) void k_accum_reduce(Grid g, Dev d)
+{
+    __shared__ I128 sh[RED_BINS / 64];
+    const int per = g.tile / RED_BINS;
+    const int b = blockIdx.x / per, part = blockIdx.x % per;
+    const uint32_t nc = d.nch[b];
+    if (nc <= 1) return;
+    const int k = part * RED_BINS + threadIdx.x;
+    const int k0 = b * g.tile;
+    const int nbin = min(g.tile, g.B - k0);
+    I128 x = zero_t<I128>(), y = zero_t<I128>();
+    const I128 *slot = d.partial + (size_t)d.slot_base[b] * 2 * g.tile;
+    for (uint32_t s = 0; s < nc; ++s) {
+        x = i128_add(x, slot[(size_t)s * 2 * g.tile + k]);
+        y = i128_add(y, slot[(size_t)s * 2 * g.tile + g.tile + k]);
+    }
+    I128 dsum = zero_t<I128>();
+    if (k < nbin) {
+        d.Xn[k0 + k] = x;
+        d.D[k0 + k] = y;
+        dsum = y;
+    }
+    // block sum of D into the tile sum (one exact 128-bit atomic per block)
+    const int lane = lane_id(), wave = threadIdx.x >> 6;
+    I128 inc = wave_incl_scan(dsum);
+    if (lane == 63) sh[wave] = inc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        I128 t = zero_t<I128>();
+        for (int w = 0; w < RED_BINS / 64; ++w) t = i128_add(t, sh[w]);
+        atomic_add_i128_full(&d.Dtile[b], t);
+    }
 }
 
 __global__ __launch_bounds__(WG) void k_dscan(Grid g, Dev d)
@@ -378,11 +625,11 @@ __global__ __launch_bounds__(WG) void k_dscan(Grid g, Dev d)
 
 // ------------------------------------------------------------------ X update
 
-// X[k] = 2^L * prefix(D)[k] for the tiles whose X changed.
+// X[k] = 2^L * (Xn[k] + prefix(D)[k]) for the tiles whose X changed.
 __global__ __launch_bounds__(WG) void k_xupdate(Grid g, Dev d)
 {
     __shared__ I128 sh[WG / 64];
-    if (d.ctl->done) return;
+    if (d.ctl->done || d.ctl->bad) return;
     const int tile = blockIdx.x;
     if (!d.xdirty[tile]) return;
     const int L = fx_exp(d.ctl->amax_bits, g.T);
@@ -402,7 +649,8 @@ __global__ __launch_bounds__(WG) void k_xupdate(Grid g, Dev d)
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
         const int k = base + r;
-        if (r < R && k < g.B) d.X[k] = ldexp(i128_to_double(i128_add(ex, loc[r])), L);
+        if (r < R && k < g.B)
+            d.X[k] = ldexp(i128_to_double(i128_add(i128_add(ex, loc[r]), d.Xn[k])), L);
     }
 }
 
@@ -498,7 +746,7 @@ DEVI int radix_sort_tile(MedianSmem &sm, int M, int passes)
 __global__ __launch_bounds__(WG) void k_median(Grid g, Dev d)
 {
     __shared__ MedianSmem sm;
-    if (d.ctl->done) return;
+    if (d.ctl->done || d.ctl->bad) return;
     const int tile = blockIdx.x, tid = threadIdx.x;
     const int B = g.B, W = g.W, h = g.h;
 
@@ -710,36 +958,35 @@ __global__ __launch_bounds__(WG) void k_median(Grid g, Dev d)
         }
     }
 
-    // ---- the last block to finish scans the tile sums
-    __syncthreads();
-    if (tid == 0) {
-        __threadfence();
-        const uint32_t tk = atomicAdd(&d.ctl->cnt_median, 1u);
-        sm.last = (tk == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (sm.last) {
-        __threadfence();
-        block_scan_array<double>(d.is_tsum, d.is_tile, g.nt);
-        if (tid == 0) d.ctl->cnt_median = 0;
-    }
+}
+
+// Exclusive prefix of the tile sums of 1/S (one block).
+__global__ __launch_bounds__(WG) void k_med_tail(Grid g, Dev d)
+{
+    if (d.ctl->done || d.ctl->bad) return;
+    block_scan_array<double>(d.is_tsum, d.is_tile, g.nt);
 }
 
 // ------------------------------------------------------------------ SNR, decisions, subtraction
 
-// rho^2 = 4 q sum_{k in track} 1/S^t[k] for every unsubtracted candidate;
-// rho^2 > rho_th^2 subtracts the source from D at once (appendix
-// "Subtraction algorithm", steps 6-9); the last block prepares the next body.
+// rho^2 = 4 q sum_{k in track} 1/S^t[k] for every unsubtracted candidate
+// (Eq. "SNR inner product" in the sky-averaged power form); rho^2 >
+// rho_th^2 subtracts the source from the binned power at once (appendix
+// "Subtraction algorithm", steps 6-9: the data X^{t+1} no longer holds it).
+// Per-block counts go to arrays; k_snr_tail combines them.
 __global__ __launch_bounds__(WG) void k_snr(Grid g, Dev d, int t)
 {
-    __shared__ int last;
-    if (d.ctl->done) return;
+    __shared__ uint64_t s_near[WG / 64], s_evals[WG / 64];
+    __shared__ uint32_t s_new[WG / 64];
+    __shared__ double s_min[WG / 64];
+    if (d.ctl->done || d.ctl->bad) return;
     const uint32_t nc = d.ctl->n_cand;
     uint32_t my_new = 0;
-    uint64_t near = 0;
+    uint64_t near = 0, evals = 0;
     double minm = INFINITY;
     for (uint32_t j = blockIdx.x * WG + threadIdx.x; j < nc; j += gridDim.x * WG) {
         if (d.c_iter[j] >= 0) continue;
+        ++evals;
         const int glo = d.c_glo[j], ghi = d.c_ghi[j];
         const double q = d.c_q[j];
         const double r2 = (4.0 * q) * range_inv_sum(d.S, d.is_pre, d.is_tile, glo, ghi, g.tile);
@@ -752,10 +999,16 @@ __global__ __launch_bounds__(WG) void k_snr(Grid g, Dev d, int t)
             ++my_new;
             const int64_t v = (int64_t)d.c_qfx[j];
             if (v) {
-                atomic_add_i128(&d.D[glo], -v);
-                atomic_add_i128(&d.D[ghi + 1], v);
-                atomic_add_i128(&d.Dtile[glo / g.tile], -v);
-                if (ghi + 1 < g.B) atomic_add_i128(&d.Dtile[(ghi + 1) / g.tile], v);
+                if (glo == ghi) {
+                    atomic_add_i128(&d.Xn[glo], -v);
+                } else {
+                    atomic_add_i128(&d.D[glo], -v);
+                    atomic_add_i128(&d.Dtile[glo / g.tile], -v);
+                    if (ghi + 1 < g.B) {
+                        atomic_add_i128(&d.D[ghi + 1], v);
+                        atomic_add_i128(&d.Dtile[(ghi + 1) / g.tile], v);
+                    }
+                }
             }
             atomicAdd(&d.chgx[glo / g.tile], 1);
             atomicAdd(&d.chgx[ghi / g.tile + 1], -1);
@@ -764,86 +1017,140 @@ __global__ __launch_bounds__(WG) void k_snr(Grid g, Dev d, int t)
             atomicAdd(&d.chgs[shi / g.tile + 1], -1);
         }
     }
-    // block totals
     for (int s = 32; s >= 1; s >>= 1) {
         my_new += (uint32_t)__shfl_xor((int)my_new, s, 64);
         near += (uint64_t)__shfl_xor((long long)near, s, 64);
+        evals += (uint64_t)__shfl_xor((long long)evals, s, 64);
         minm = fmin(minm, __shfl_xor(minm, s, 64));
     }
+    const int w = threadIdx.x >> 6;
     if (lane_id() == 0) {
-        if (my_new) atomicAdd(&d.ctl->cur_new, my_new);
-        if (near) atomicAdd((unsigned long long *)&d.ctl->n_near, (unsigned long long)near);
-        if (minm < INFINITY)
-            atomicMin((unsigned long long *)&d.ctl->min_margin, (unsigned long long)__double_as_longlong(minm));
+        s_new[w] = my_new;
+        s_near[w] = near;
+        s_evals[w] = evals;
+        s_min[w] = minm;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        __threadfence();
-        last = atomicAdd(&d.ctl->cnt_snr, 1u) == gridDim.x - 1;
+        for (int v = 1; v < WG / 64; ++v) {
+            s_new[0] += s_new[v];
+            s_near[0] += s_near[v];
+            s_evals[0] += s_evals[v];
+            s_min[0] = fmin(s_min[0], s_min[v]);
+        }
+        d.b_new[blockIdx.x] = s_new[0];
+        d.b_near[blockIdx.x] = s_near[0];
+        d.b_evals[blockIdx.x] = s_evals[0];
+        d.b_minm[blockIdx.x] = s_min[0];
+    }
+}
+
+// One block: combines the per-block counts, carries of D, dirty tiles of
+// the next body, loop control.
+__global__ __launch_bounds__(WG) void k_snr_tail(Grid g, Dev d, int t, int nblocks)
+{
+    __shared__ uint32_t shu[WG / 64], shx[WG / 64], shs[WG / 64];
+    __shared__ uint64_t s64[2 * (WG / 64)];
+    __shared__ double sd[WG / 64];
+    if (d.ctl->done || d.ctl->bad) return;
+    uint32_t nw = 0;
+    uint64_t near = 0, evals = 0;
+    double minm = INFINITY;
+    for (int i = threadIdx.x; i < nblocks; i += WG) {
+        nw += d.b_new[i];
+        near += d.b_near[i];
+        evals += d.b_evals[i];
+        minm = fmin(minm, d.b_minm[i]);
+    }
+    for (int s = 32; s >= 1; s >>= 1) {
+        nw += (uint32_t)__shfl_xor((int)nw, s, 64);
+        near += (uint64_t)__shfl_xor((long long)near, s, 64);
+        evals += (uint64_t)__shfl_xor((long long)evals, s, 64);
+        minm = fmin(minm, __shfl_xor(minm, s, 64));
+    }
+    const int w = threadIdx.x >> 6;
+    if (lane_id() == 0) {
+        shu[w] = nw;
+        s64[w] = near;
+        s64[WG / 64 + w] = evals;
+        sd[w] = minm;
     }
     __syncthreads();
-    if (!last) return;
-    __threadfence();
-    // tail: carries of D, dirty tiles for the next body, loop control
+    nw = 0; near = 0; evals = 0; minm = INFINITY;
+    for (int v = 0; v < WG / 64; ++v) {
+        nw += shu[v];
+        near += s64[v];
+        evals += s64[WG / 64 + v];
+        minm = fmin(minm, sd[v]);
+    }
+    __syncthreads();
     block_scan_array<I128>(d.Dtile, d.Dcarry, g.nt);
-    {
-        __shared__ uint32_t shx[WG / 64], shs[WG / 64];
-        uint32_t cx = 0, cs = 0;
-        for (int base = 0; base < g.nt; base += WG) {
-            const int i = base + threadIdx.x;
-            const int vx = (i < g.nt) ? d.chgx[i] : 0;
-            const int vs = (i < g.nt) ? d.chgs[i] : 0;
-            uint32_t tx, ts;
-            const uint32_t ex = block_excl_scan((uint32_t)vx, shx, &tx);
-            const uint32_t es = block_excl_scan((uint32_t)vs, shs, &ts);
-            if (i < g.nt) {
-                d.xdirty[i] = (int32_t)(cx + ex + (uint32_t)vx) > 0;
-                d.sdirty[i] = (int32_t)(cs + es + (uint32_t)vs) > 0;
-                d.chgx[i] = 0;
-                d.chgs[i] = 0;
-            }
-            cx += tx;
-            cs += ts;
+    uint32_t cx = 0, cs = 0;
+    uint64_t ux = 0, us = 0;
+    for (int base = 0; base < g.nt; base += WG) {
+        const int i = base + threadIdx.x;
+        const int vx = (i < g.nt) ? d.chgx[i] : 0;
+        const int vs = (i < g.nt) ? d.chgs[i] : 0;
+        uint32_t tx, ts;
+        const uint32_t ex = block_excl_scan((uint32_t)vx, shx, &tx);
+        const uint32_t es = block_excl_scan((uint32_t)vs, shs, &ts);
+        if (i < g.nt) {
+            const bool dx = (int32_t)(cx + ex + (uint32_t)vx) > 0;
+            const bool ds = (int32_t)(cs + es + (uint32_t)vs) > 0;
+            d.xdirty[i] = dx;
+            d.sdirty[i] = ds;
+            const int width = min(g.tile, g.B - i * g.tile);
+            ux += dx ? width : 0;
+            us += ds ? width : 0;
+            d.chgx[i] = 0;
+            d.chgs[i] = 0;
         }
-        if (threadIdx.x == 0) {
-            d.chgx[g.nt] = 0;
-            d.chgs[g.nt] = 0;
-        }
+        cx += tx;
+        cs += ts;
     }
+    for (int s = 32; s >= 1; s >>= 1) {
+        ux += (uint64_t)__shfl_xor((long long)ux, s, 64);
+        us += (uint64_t)__shfl_xor((long long)us, s, 64);
+    }
+    __syncthreads();
+    if (lane_id() == 0) {
+        s64[w] = ux;
+        s64[WG / 64 + w] = us;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
-        const uint32_t nw = d.ctl->cur_new;
-        if (t < NEW_CAP) d.n_new[t] = nw;
-        d.ctl->n_resolved += nw;
-        d.ctl->cur_new = 0;
-        if (nw == 0) {
-            d.ctl->done = 1;
-            d.ctl->n_iter = (uint32_t)t + 1;
+        ux = 0; us = 0;
+        for (int v = 0; v < WG / 64; ++v) {
+            ux += s64[v];
+            us += s64[WG / 64 + v];
         }
-        d.ctl->cnt_snr = 0;
+        d.chgx[g.nt] = 0;
+        d.chgs[g.nt] = 0;
+        Ctl *c = d.ctl;
+        if (t < NEW_CAP) d.n_new[t] = nw;
+        c->n_resolved += nw;
+        c->n_near += near;
+        c->units_snr += evals;
+        if (minm < __longlong_as_double((long long)c->min_margin))
+            c->min_margin = (uint64_t)__double_as_longlong(minm);
+        if (nw == 0) {
+            c->done = 1;
+            c->n_iter = (uint32_t)t + 1;
+        } else {
+            c->units_x += ux;
+            c->units_med += us;
+        }
     }
 }
 
 // ------------------------------------------------------------------ outputs
 
-__global__ __launch_bounds__(WG) void k_res_out(Dev d, const uint32_t *ids)
+// ids of the candidates (the catalog is not retained after the run).
+__global__ __launch_bounds__(WG) void k_cand_ids(Dev d, const uint32_t *ids)
 {
     const uint32_t nc = d.ctl->n_cand;
-    const uint32_t ncr = (nc + 63) & ~63u;
-    for (uint32_t j = blockIdx.x * WG + threadIdx.x; j < ncr; j += gridDim.x * WG) {
-        const bool r = j < nc && d.c_iter[j] >= 0;
-        const uint64_t mask = __ballot(r);
-        if (!mask) continue;
-        const int lane = lane_id();
-        const int leader = __ffsll((long long)mask) - 1;
-        uint32_t base = 0;
-        if (lane == leader) base = atomicAdd(&d.ctl->n_res_out, (uint32_t)__popcll(mask));
-        base = (uint32_t)__shfl((int)base, leader, 64);
-        if (r) {
-            const uint32_t o = base + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
-            d.res_id[o] = ids[d.c_src[j]];
-            d.res_iter[o] = d.c_iter[j];
-        }
-    }
+    for (uint32_t j = blockIdx.x * WG + threadIdx.x; j < nc; j += gridDim.x * WG)
+        d.c_id[j] = ids[d.c_src[j]];
 }
 
 // ------------------------------------------------------------------ launchers
@@ -866,10 +1173,8 @@ hipError_t launch_grid_tables(const Grid &g, const Dev &d, hipStream_t st)
 hipError_t launch_reset(const Grid &g, const Dev &d, uint64_t n_src, hipStream_t st)
 {
     (void)n_src;
-    k_init_ctl<<<1, 64, 0, st>>>(d.ctl);
-    const uint64_t dwords = (uint64_t)(g.B + 1) * 4;   // D as u32 words
-    k_fill_u32<<<blocks_for(dwords), WG, 0, st>>>(reinterpret_cast<uint32_t *>(d.D), dwords, 0u);
-    k_fill_u32<<<blocks_for((g.nt + 1) * 4ull), WG, 0, st>>>(reinterpret_cast<uint32_t *>(d.Dtile), (g.nt + 1) * 4ull, 0u);
+    k_init_ctl<<<1, 64, 0, st>>>(d.ctl, g.B);
+    k_fill_u32<<<blocks_for(g.nt), WG, 0, st>>>(d.btot, (uint64_t)g.nt, 0u);
     k_fill_u32<<<blocks_for(g.nt + 1), WG, 0, st>>>(reinterpret_cast<uint32_t *>(d.chgx), g.nt + 1, 0u);
     k_fill_u32<<<blocks_for(g.nt + 1), WG, 0, st>>>(reinterpret_cast<uint32_t *>(d.chgs), g.nt + 1, 0u);
     const uint64_t flag_words = ((uint64_t)g.nt + 3) / 4;
@@ -881,27 +1186,45 @@ hipError_t launch_reset(const Grid &g, const Dev &d, uint64_t n_src, hipStream_t
 hipError_t launch_prep(const Grid &g, const Dev &d, const float *A, const float *f,
                        const float *fdot, uint64_t n, hipStream_t st)
 {
+    const unsigned nblk = (unsigned)((n + PREP_SRC - 1) / PREP_SRC);
     if (n > 0) {
-        k_amax<<<blocks_for(n, 2048), WG, 0, st>>>(A, n, d.ctl);
-        k_prep<<<blocks_for(n, 8192), WG, 0, st>>>(g, d, A, f, fdot, n);
+        const unsigned na = blocks_for(n, AMAX_BLOCKS);
+        k_amax<<<na, WG, 0, st>>>(A, n, d);
+        k_amax_reduce<<<1, WG, 0, st>>>(d, (int)na);
+        k_prep_count<<<nblk, WG, 0, st>>>(g, d, A, f, fdot, n);
     }
-    k_dtile_sum<<<g.nt, WG, 0, st>>>(g, d);
+    k_prep_plan<<<1, WG, 0, st>>>(g, d);
+    if (n > 0) k_prep_scatter<<<nblk, WG, 0, st>>>(g, d, A, f, fdot, n);
+    k_accum<<<d.max_chunks, WG, 0, st>>>(g, d);
+    k_accum_reduce<<<g.nt * (g.tile / RED_BINS), RED_BINS, 0, st>>>(g, d);
     k_dscan<<<1, WG, 0, st>>>(g, d);
     return hipGetLastError();
 }
 
-hipError_t launch_iteration(const Grid &g, const Dev &d, int t, hipStream_t st)
+hipError_t launch_xupdate(const Grid &g, const Dev &d, hipStream_t st)
 {
     k_xupdate<<<g.nt, WG, 0, st>>>(g, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_median(const Grid &g, const Dev &d, hipStream_t st)
+{
     k_median<<<g.nt, WG, 0, st>>>(g, d);
+    k_med_tail<<<1, WG, 0, st>>>(g, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_snr(const Grid &g, const Dev &d, int t, hipStream_t st)
+{
     k_snr<<<SNR_BLOCKS, WG, 0, st>>>(g, d, t);
+    k_snr_tail<<<1, WG, 0, st>>>(g, d, t, SNR_BLOCKS);
     return hipGetLastError();
 }
 
 hipError_t launch_outputs(const Grid &g, const Dev &d, const uint32_t *ids, hipStream_t st)
 {
     (void)g;
-    k_res_out<<<SNR_BLOCKS, WG, 0, st>>>(d, ids);
+    k_cand_ids<<<SNR_BLOCKS, WG, 0, st>>>(d, ids);
     return hipGetLastError();
 }
 

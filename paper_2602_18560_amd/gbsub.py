@@ -23,7 +23,8 @@ FP64, FP32_COMP, FP32_NAIVE = 0, 1, 2
 SPEC_SN, SPEC_X_RESIDUAL, SPEC_S_GAL, SPEC_S_INSTR = 0, 1, 2, 3
 
 EXPORTS = ["gbsub_default_config", "gbsub_create", "gbsub_workspace_size", "gbsub_run",
-           "gbsub_spectrum", "gbsub_resolved", "gbsub_destroy", "gbsub_status_str"]
+           "gbsub_spectrum", "gbsub_resolved", "gbsub_destroy", "gbsub_status_str",
+           "gbsub_set_profiling", "gbsub_kernel_stats"]
 
 
 class GbsubError(RuntimeError):
@@ -44,6 +45,11 @@ class Config(C.Structure):
 class CatalogStruct(C.Structure):
     _fields_ = [("n", C.c_uint64), ("A", C.c_void_p), ("f", C.c_void_p), ("fdot", C.c_void_p),
                 ("id", C.c_void_p)]
+
+
+class KernelStat(C.Structure):
+    _fields_ = [("name", C.c_char * 24), ("launches", C.c_uint64), ("total_ms", C.c_double),
+                ("units", C.c_double), ("unit", C.c_char * 16)]
 
 
 class SummaryStruct(C.Structure):
@@ -85,8 +91,10 @@ def load(path: str | None = None):
     L.gbsub_destroy.restype = None
     L.gbsub_status_str.argtypes = [C.c_int]
     L.gbsub_status_str.restype = C.c_char_p
+    L.gbsub_set_profiling.argtypes = [C.c_void_p, C.c_int]
+    L.gbsub_kernel_stats.argtypes = [C.c_void_p, C.c_void_p, C.c_uint32, C.POINTER(C.c_uint32)]
     for name in ("gbsub_create", "gbsub_workspace_size", "gbsub_run", "gbsub_spectrum",
-                 "gbsub_resolved"):
+                 "gbsub_resolved", "gbsub_set_profiling", "gbsub_kernel_stats"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -232,6 +240,22 @@ class Context:
         if st != OK:
             raise GbsubError(st, "gbsub_spectrum")
         return buf
+
+    def set_profiling(self, on: bool = True):
+        st = self._L.gbsub_set_profiling(self.h, 1 if on else 0)
+        if st != OK:
+            raise GbsubError(st, "gbsub_set_profiling")
+
+    def kernel_stats(self) -> dict:
+        """{family: dict(launches, total_ms, units, unit)} accumulated while profiling."""
+        arr = (KernelStat * 16)()
+        n = C.c_uint32()
+        st = self._L.gbsub_kernel_stats(self.h, arr, 16, C.byref(n))
+        if st != OK:
+            raise GbsubError(st, "gbsub_kernel_stats")
+        return {arr[i].name.decode(): dict(launches=arr[i].launches, total_ms=arr[i].total_ms,
+                                           units=arr[i].units, unit=arr[i].unit.decode())
+                for i in range(n.value)}
 
     def resolved(self):
         """(ids uint32 ascending, iter_of int32) of the last run."""

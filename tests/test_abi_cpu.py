@@ -34,6 +34,7 @@ def test_struct_layouts_match_header():
     assert C.sizeof(G.Config) == 96
     assert C.sizeof(G.CatalogStruct) == 40
     assert C.sizeof(G.SummaryStruct) == 48
+    assert C.sizeof(G.KernelStat) == 64
 
 
 def test_default_config_is_the_papers():
