@@ -18,9 +18,10 @@ constexpr int ACC_EV = 65536;      // binning events per accumulation block
 constexpr int RED_BINS = 256;      // bins per reduction block of the hot buckets
 constexpr int AMAX_BLOCKS = 1024;  // grid of the amplitude-maximum kernel
 constexpr int NEW_CAP = 1 << 16;   // per-iteration counters kept (iterations beyond: not recorded)
-constexpr int KEYBITS = 24;        // bits of the per-tile order key of the median sort
-constexpr int CHP = 8;             // median start table: positions per row
-constexpr int RBS = 128;           // median start table: sorted ranks per column
+constexpr int KEYBITS = 20;        // bits of the per-tile order key of the median sort
+constexpr int POSBITS = 12;        // sort word = key << 12 | position (MMAX <= 4096)
+constexpr int CHP = 16;            // median start table: positions per row
+constexpr int RBS = 64;            // median start table: sorted ranks per column
 
 // Signed 128-bit fixed-point accumulator (two's complement: hi*2^64 + lo).
 // Every power is accumulated as an exact integer multiple of 2^L, so sums

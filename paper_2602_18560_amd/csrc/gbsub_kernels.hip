@@ -659,83 +659,125 @@ __global__ __launch_bounds__(WG) void k_xupdate(Grid g, Dev d)
 // S[k] = C * median{X[a_k .. a_k+W-1]} + S_instr[k]   (Eq. "running median").
 //
 // One block per tile of `tile` outputs.  The union of the tile's windows
-// (tile + W - 1 bins) is loaded once and sorted in LDS (stable LSD radix
-// sort on a per-tile 24-bit order key, then an exact repair of key ties by
-// the full fp64 value).  Each thread then owns R = tile/256 consecutive
-// outputs: it locates the median of its first window through a small 2-D
-// count table (positions x sorted ranks) and slides the window one bin at a
-// time, moving the median pointer along the sorted order (one element leaves,
-// one enters; the pointer moves to the neighbouring active element when the
-// count below it changes).  Selection is exact: no arithmetic touches X.
+// (tile + W - 1 bins) is loaded once into LDS and sorted there: a stable LSD
+// radix sort on a per-tile 20-bit order key (the fp64 bit pattern minus the
+// tile minimum, shifted), then an exact repair that orders equal keys by
+// the full fp64 value.  Each thread owns R = tile/256 consecutive outputs: it
+// locates the median of its first window through a 2-D count table
+// (positions x sorted ranks) and slides the window one bin at a time,
+// moving the median pointer along the sorted order when the count of active
+// elements below it changes.  Selection is exact: no arithmetic touches X.
+
+constexpr int MCH = MMAX / WG;             // union elements per thread in the sort
+constexpr int NCMAX = MMAX / CHP;          // start-table rows (+1)
+constexpr int NBMAX = MMAX / RBS;          // start-table columns (+1)
+constexpr int TLD = NBMAX + 1;             // start-table row stride (u16)
+constexpr int TWORDS = (NBMAX + 2) / 2;    // 16-bit fields of a table row, two per word
 
 struct MedianSmem {
-    uint32_t key[2][MMAX];            // sort keys; afterwards the start table (u16)
-    uint32_t cnt[16 * WG];            // radix offsets; afterwards the medians (f64)
-    uint16_t pos[2][MMAX];            // positions (relative to the union start)
-    uint16_t rank[MMAX];              // sorted index of each position
+    double xv[MMAX];                       // X over the union, position order
+    uint32_t kp[2][MMAX];                  // sort words: key << POSBITS | position
+    uint16_t rank[MMAX];                   // sorted index of each position
+    union {
+        uint16_t off[16 * WG];             // radix: per-thread digit offsets
+        uint16_t tbl[(NCMAX + 1) * TLD];   // start table
+    } u;
+    uint32_t wsc[(WG / 64) * TWORDS];      // cross-wave scan exchange
     uint64_t red[2 * (WG / 64)];
-    uint32_t wsc[(WG / 64) * 8];
     double dsh[WG / 64];
     int flag;
-    int last;
 };
 
-DEVI uint32_t radix_key(uint64_t bits, uint64_t mn, int shift) { return (uint32_t)((bits - mn) >> shift); }
+// Inclusive scan of a u32 across the 64 lanes of a wave (DPP row shifts and
+// row broadcasts; every lane must be active).
+DEVI uint32_t wave_scan_u32(uint32_t v)
+{
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, false);   // row_shr:1
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, false);   // row_shr:2
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, false);   // row_shr:4
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, false);   // row_shr:8
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false);   // row_bcast:15
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false);   // row_bcast:31
+    return v;
+}
 
-// Stable LSD radix sort of (key, pos) over M elements with 4-bit digits.
-// Returns the buffer index that holds the result.
+// Block-wide exclusive scan of NW words per thread (fields must not
+// overflow); tot[] receives the block totals.  Contains two barriers.
+template <int NW>
+DEVI void block_scan_words(const uint32_t (&w)[NW], uint32_t (&ex)[NW], uint32_t (&tot)[NW],
+                           uint32_t *wsc)
+{
+    const int lane = lane_id(), wave = threadIdx.x >> 6;
+    uint32_t inc[NW];
+#pragma unroll
+    for (int j = 0; j < NW; ++j) inc[j] = wave_scan_u32(w[j]);
+    if (lane == 63) {
+#pragma unroll
+        for (int j = 0; j < NW; ++j) wsc[wave * NW + j] = inc[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < NW; ++j) {
+        uint32_t pre = 0, t = 0;
+#pragma unroll
+        for (int v = 0; v < WG / 64; ++v) {
+            const uint32_t x = wsc[v * NW + j];
+            pre += (v < wave) ? x : 0u;
+            t += x;
+        }
+        ex[j] = pre + inc[j] - w[j];
+        tot[j] = t;
+    }
+    __syncthreads();
+}
+
+// Stable LSD radix sort of the M words in sm.kp[0] by bits [POSBITS,
+// POSBITS + 4*passes), 4 bits per pass; returns the buffer holding the
+// result.  Thread chunks are contiguous in the current order; within-chunk
+// ranks are kept in registers.
 DEVI int radix_sort_tile(MedianSmem &sm, int M, int passes)
 {
     const int tid = threadIdx.x;
     const int CH = (M + WG - 1) / WG;
-    const int beg = tid * CH, end = min(beg + CH, M);
+    const int beg = tid * CH;
     int in = 0;
     for (int ps = 0; ps < passes; ++ps) {
-        const int sh = 4 * ps;
-        const uint32_t *kin = sm.key[in];
-        const uint16_t *pin = sm.pos[in];
-        uint32_t *kout = sm.key[in ^ 1];
-        uint16_t *pout = sm.pos[in ^ 1];
-        // per-thread digit counts, 4 bits each (CH <= 12 < 16)
+        const int sh = POSBITS + 4 * ps;
+        const uint32_t *kin = sm.kp[in];
+        uint32_t *kout = sm.kp[in ^ 1];
+        uint32_t e[MCH];
+        uint32_t lr[MCH];
         uint64_t c = 0;
-        for (int i = beg; i < end; ++i) c += 1ull << (4 * ((kin[i] >> sh) & 15u));
-        // 16-bit fields, two digits per word; one block-wide scan of 8 words
-        uint32_t w[8], inc[8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
+        for (int i = 0; i < MCH; ++i) e[i] = (i < CH && beg + i < M) ? kin[beg + i] : 0u;
+#pragma unroll
+        for (int i = 0; i < MCH; ++i) {
+            if (i < CH && beg + i < M) {
+                const uint32_t dg = (e[i] >> sh) & 15u;
+                lr[i] = (uint32_t)(c >> (4 * dg)) & 15u;
+                c += 1ull << (4 * dg);
+            }
+        }
+        uint32_t w[8], ex[8], tot[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
             w[j] = (uint32_t)((c >> (8 * j)) & 15u) | ((uint32_t)((c >> (8 * j + 4)) & 15u) << 16);
-            inc[j] = wave_incl_scan(w[j]);
-        }
-        const int lane = lane_id(), wave = tid >> 6;
-        if (lane == 63) {
-#pragma unroll
-            for (int j = 0; j < 8; ++j) sm.wsc[wave * 8 + j] = inc[j];
-        }
-        __syncthreads();
-        // digit bases (exclusive over the 16 digit totals) + own offset
+        block_scan_words<8>(w, ex, tot, sm.wsc);
         uint32_t run = 0;
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
-            uint32_t pre = 0, tot = 0;
-#pragma unroll
-            for (int v = 0; v < WG / 64; ++v) {
-                const uint32_t x = sm.wsc[v * 8 + j];
-                pre += (v < wave) ? x : 0u;
-                tot += x;
-            }
-            const uint32_t ex = pre + inc[j] - w[j];
-            sm.cnt[(2 * j) * WG + tid] = run + (ex & 0xFFFFu);
-            run += tot & 0xFFFFu;
-            sm.cnt[(2 * j + 1) * WG + tid] = run + (ex >> 16);
-            run += tot >> 16;
+            sm.u.off[(2 * j) * WG + tid] = (uint16_t)(run + (ex[j] & 0xFFFFu));
+            run += tot[j] & 0xFFFFu;
+            sm.u.off[(2 * j + 1) * WG + tid] = (uint16_t)(run + (ex[j] >> 16));
+            run += tot[j] >> 16;
         }
-        // stable scatter (thread chunks are contiguous in the current order)
-        for (int i = beg; i < end; ++i) {
-            const uint32_t k = kin[i];
-            const uint32_t dg = (k >> sh) & 15u;
-            const uint32_t dst = sm.cnt[dg * WG + tid]++;
-            kout[dst] = k;
-            pout[dst] = pin[i];
+        // offsets are private to the thread: no barrier before reading them
+#pragma unroll
+        for (int i = 0; i < MCH; ++i) {
+            if (i < CH && beg + i < M) {
+                const uint32_t dg = (e[i] >> sh) & 15u;
+                kout[sm.u.off[dg * WG + tid] + lr[i]] = e[i];
+            }
         }
         __syncthreads();
         in ^= 1;
@@ -749,215 +791,267 @@ __global__ __launch_bounds__(WG) void k_median(Grid g, Dev d)
     if (d.ctl->done || d.ctl->bad) return;
     const int tile = blockIdx.x, tid = threadIdx.x;
     const int B = g.B, W = g.W, h = g.h;
+    if (!d.sdirty[tile]) return;
 
-    if (d.sdirty[tile]) {
-        const int t0 = tile * g.tile;
-        const int t1 = min(t0 + g.tile, B);
-        const bool whole = B < W;
-        const int u0 = whole ? 0 : win_start(t0, B, W, h);
-        const int u1 = whole ? B - 1 : win_start(t1 - 1, B, W, h) + W - 1;
-        const int M = u1 - u0 + 1;
-        const double *X = d.X + u0;
+    const int t0 = tile * g.tile;
+    const int t1 = min(t0 + g.tile, B);
+    const bool whole = B < W;
+    const int u0 = whole ? 0 : win_start(t0, B, W, h);
+    const int u1 = whole ? B - 1 : win_start(t1 - 1, B, W, h) + W - 1;
+    const int M = u1 - u0 + 1;
 
-        // ---- load: order key relative to the tile minimum
-        uint64_t mn = ~0ull, mx = 0;
-        for (int i = tid; i < M; i += WG) {
-            const uint64_t b = (uint64_t)__double_as_longlong(X[i]);
+    // ---- load the union (all loads in flight together); tile min / max
+    double xr[MCH];
+#pragma unroll
+    for (int i = 0; i < MCH; ++i) {
+        const int p = tid + i * WG;
+        xr[i] = p < M ? d.X[u0 + p] : 0.0;
+    }
+    uint64_t mn = ~0ull, mx = 0;
+#pragma unroll
+    for (int i = 0; i < MCH; ++i) {
+        const int p = tid + i * WG;
+        if (p < M) {
+            sm.xv[p] = xr[i];
+            const uint64_t b = (uint64_t)__double_as_longlong(xr[i]);
             mn = b < mn ? b : mn;
             mx = b > mx ? b : mx;
         }
-        for (int s = 32; s >= 1; s >>= 1) {
-            const uint64_t a = (uint64_t)__shfl_xor((long long)mn, s, 64);
-            const uint64_t b = (uint64_t)__shfl_xor((long long)mx, s, 64);
-            mn = a < mn ? a : mn;
-            mx = b > mx ? b : mx;
+    }
+    for (int s = 32; s >= 1; s >>= 1) {
+        const uint64_t a = (uint64_t)__shfl_xor((long long)mn, s, 64);
+        const uint64_t b = (uint64_t)__shfl_xor((long long)mx, s, 64);
+        mn = a < mn ? a : mn;
+        mx = b > mx ? b : mx;
+    }
+    if (lane_id() == 0) {
+        sm.red[tid >> 6] = mn;
+        sm.red[(WG / 64) + (tid >> 6)] = mx;
+    }
+    __syncthreads();
+    mn = sm.red[0];
+    mx = sm.red[WG / 64];
+    for (int w = 1; w < WG / 64; ++w) {
+        mn = sm.red[w] < mn ? sm.red[w] : mn;
+        mx = sm.red[WG / 64 + w] > mx ? sm.red[WG / 64 + w] : mx;
+    }
+    const uint64_t span = mx - mn;
+    const int span_bits = span ? 64 - __clzll(span) : 0;
+    const int shift = span_bits > KEYBITS ? span_bits - KEYBITS : 0;
+    const int passes = (span_bits - shift + 3) / 4;
+#pragma unroll
+    for (int i = 0; i < MCH; ++i) {
+        const int p = tid + i * WG;
+        if (p < M) {
+            const uint32_t key = (uint32_t)(((uint64_t)__double_as_longlong(xr[i]) - mn) >> shift);
+            sm.kp[0][p] = (key << POSBITS) | (uint32_t)p;
         }
-        if (lane_id() == 0) {
-            sm.red[tid >> 6] = mn;
-            sm.red[(WG / 64) + (tid >> 6)] = mx;
-        }
-        __syncthreads();
-        mn = sm.red[0];
-        mx = sm.red[WG / 64];
-        for (int w = 1; w < WG / 64; ++w) {
-            mn = sm.red[w] < mn ? sm.red[w] : mn;
-            mx = sm.red[WG / 64 + w] > mx ? sm.red[WG / 64 + w] : mx;
-        }
-        const uint64_t span = mx - mn;
-        const int span_bits = span ? 64 - __clzll(span) : 0;
-        const int shift = span_bits > KEYBITS ? span_bits - KEYBITS : 0;
-        const int key_bits = span_bits - shift;
-        const int passes = (key_bits + 3) / 4;
-        for (int i = tid; i < M; i += WG) {
-            sm.key[0][i] = radix_key((uint64_t)__double_as_longlong(X[i]), mn, shift);
-            sm.pos[0][i] = (uint16_t)i;
-        }
-        __syncthreads();
+    }
+    __syncthreads();
 
-        // ---- sort
-        const int rb = radix_sort_tile(sm, M, passes);
-        uint32_t *skey = sm.key[rb];
-        uint16_t *spos = sm.pos[rb];
+    // ---- sort
+    const int rb = radix_sort_tile(sm, M, passes);
+    uint32_t *sw = sm.kp[rb];
 
-        // ---- repair key ties: order equal keys by (fp64 value, position)
-        if (shift > 0) {
-            for (;;) {
-                if (tid == 0) sm.flag = 0;
-                __syncthreads();
-                int swapped = 0;
-                for (int par = 0; par < 2; ++par) {
-                    for (int i = par + 2 * tid; i + 1 < M; i += 2 * WG) {
-                        if (skey[i] != skey[i + 1]) continue;
-                        const uint16_t pa = spos[i], pb = spos[i + 1];
-                        const uint64_t ba = (uint64_t)__double_as_longlong(X[pa]);
-                        const uint64_t bb = (uint64_t)__double_as_longlong(X[pb]);
-                        if (ba > bb || (ba == bb && pa > pb)) {
-                            spos[i] = pb;
-                            spos[i + 1] = pa;
-                            swapped = 1;
-                        }
-                    }
-                    __syncthreads();
-                }
-                if (swapped) sm.flag = 1;
-                __syncthreads();
-                const int any = sm.flag;
-                __syncthreads();
-                if (!any) break;
-            }
-        }
-        for (int i = tid; i < M; i += WG) sm.rank[spos[i]] = (uint16_t)i;
-        __syncthreads();
-
-        double *medv = reinterpret_cast<double *>(sm.cnt);
-        const int R = g.tile / WG;
-        if (whole) {
-            const double m = X[spos[(B + 1) / 2 - 1]];
-            for (int r = 0; r < R; ++r) medv[tid * R + r] = m;
-        } else {
-            // ---- start table: tbl[c][b] = #{p < c*CHP : rank[p] < b*RBS}
-            uint16_t *tbl = reinterpret_cast<uint16_t *>(sm.key);   // keys no longer needed
-            const int NC = (M + CHP - 1) / CHP, NB = (M + RBS - 1) / RBS;
-            const int ld = NB + 1;
-            for (int c = tid; c <= NC; c += WG) {
-                uint16_t *row = tbl + c * ld;
-                for (int b = 0; b <= NB; ++b) row[b] = 0;
-                if (c >= 1) {
-                    for (int p = (c - 1) * CHP; p < min(c * CHP, M); ++p) row[sm.rank[p] / RBS + 1]++;
-                    for (int b = 1; b <= NB; ++b) row[b] += row[b - 1];
-                }
-            }
+    // ---- repair key ties: order equal keys by (fp64 value, position)
+    if (shift > 0) {
+        for (;;) {
+            if (tid == 0) sm.flag = 0;
             __syncthreads();
-            {   // prefix over rows, each column split into segments
-                const int nseg = WG / ld;
-                const int rows = NC + 1;
-                const int seglen = (rows + nseg - 1) / nseg;
-                const int col = tid % ld, seg = tid / ld;
-                uint32_t segsum = 0;
-                const bool act = seg < nseg;
-                const int r0 = seg * seglen, r1 = min(r0 + seglen, rows);
-                if (act)
-                    for (int r = r0; r < r1; ++r) {
-                        segsum += tbl[r * ld + col];
-                        tbl[r * ld + col] = (uint16_t)segsum;
+            int swapped = 0;
+            for (int par = 0; par < 2; ++par) {
+                for (int i = par + 2 * tid; i + 1 < M; i += 2 * WG) {
+                    const uint32_t a = sw[i], b = sw[i + 1];
+                    if ((a >> POSBITS) != (b >> POSBITS)) continue;
+                    const uint32_t pa = a & 0xFFFu, pb = b & 0xFFFu;
+                    const uint64_t ba = (uint64_t)__double_as_longlong(sm.xv[pa]);
+                    const uint64_t bb = (uint64_t)__double_as_longlong(sm.xv[pb]);
+                    if (ba > bb || (ba == bb && pa > pb)) {
+                        sw[i] = b;
+                        sw[i + 1] = a;
+                        swapped = 1;
                     }
-                __syncthreads();
-                uint32_t add = 0;
-                if (act)
-                    for (int s2 = 0; s2 < seg; ++s2) {
-                        const int rr = min((s2 + 1) * seglen, rows) - 1;
-                        if (rr >= s2 * seglen) add += tbl[rr * ld + col];
-                    }
-                __syncthreads();
-                if (act && add)
-                    for (int r = r0; r < r1; ++r) tbl[r * ld + col] = (uint16_t)(tbl[r * ld + col] + add);
+                }
                 __syncthreads();
             }
+            if (swapped) sm.flag = 1;
+            __syncthreads();
+            const int any = sm.flag;
+            __syncthreads();
+            if (!any) break;
+        }
+    }
+    for (int i = tid; i < M; i += WG) sm.rank[sw[i] & 0xFFFu] = (uint16_t)i;
+    __syncthreads();
 
-            // ---- walks: thread owns outputs [kb, ke)
-            const int kb = t0 + tid * R;
-            const int ke = min(kb + R, t1);
-            if (kb < ke) {
-                int w0 = win_start(kb, B, W, h) - u0;
-                // start: (h+1)-th element of sorted order inside [w0, w0+W)
-                const int cL = w0 / CHP, nl = w0 % CHP;
-                const int xr = w0 + W;
-                const int cR = xr / CHP, nr = xr % CHP;
-                uint32_t rl[CHP], rr[CHP];
+    const int R = g.tile / WG;
+    const int kb = t0 + tid * R;
+    const int ke = min(kb + R, t1);
+    double med[8];
+    if (whole) {
+        const double m = sm.xv[sw[(B + 1) / 2 - 1] & 0xFFFu];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) med[r] = m;
+    } else {
+        // ---- start table: tbl[c][b] = #{p < c*CHP : rank[p] < b*RBS}
+        const int NC = (M + CHP - 1) / CHP, NB = (M + RBS - 1) / RBS;
+        {
+            // thread t counts chunk t (row t+1), columns as 8-bit fields
+            uint64_t hcol[(NBMAX + 8) / 8];
+#pragma unroll
+            for (int j = 0; j < (NBMAX + 8) / 8; ++j) hcol[j] = 0;
+            if (tid < NC) {
 #pragma unroll
                 for (int i = 0; i < CHP; ++i) {
-                    rl[i] = (i < nl) ? sm.rank[cL * CHP + i] : 0xFFFFFFFFu;
-                    rr[i] = (i < nr) ? sm.rank[cR * CHP + i] : 0xFFFFFFFFu;
-                }
-                auto count = [&](int b) -> int {
-                    const uint32_t lim = (uint32_t)(b * RBS);
-                    int cnt = (int)tbl[cR * ld + b] - (int)tbl[cL * ld + b];
+                    const int p = tid * CHP + i;
+                    if (p < M) {
+                        const int col = sm.rank[p] / RBS + 1;   // counts ranks < b*RBS for b >= col
 #pragma unroll
-                    for (int i = 0; i < CHP; ++i) cnt += (int)(rr[i] < lim) - (int)(rl[i] < lim);
-                    return cnt;
-                };
-                int lo = 1, hi2 = NB;
-                while (lo < hi2) {
-                    const int mid = (lo + hi2) >> 1;
-                    if (count(mid) >= h + 1) hi2 = mid; else lo = mid + 1;
-                }
-                int base = count(lo - 1);
-                int j = (lo - 1) * RBS;
-                for (; j < M - 1; ++j) {       // the bound only guards a broken invariant
-                    if ((unsigned)(spos[j] - w0) < (unsigned)W) {
-                        if (++base == h + 1) break;
+                        for (int j = 0; j < (NBMAX + 8) / 8; ++j)
+                            hcol[j] += ((col >> 3) == j) ? (1ull << (8 * (col & 7))) : 0ull;
                     }
                 }
-                medv[kb - t0] = X[spos[j]];
-                for (int k = kb + 1; k < ke; ++k) {
-                    const int w1 = win_start(k, B, W, h) - u0;
-                    if (w1 != w0) {
-                        const int rout = sm.rank[w0];
-                        const int rin = sm.rank[w0 + W];
-                        w0 = w1;
-                        const int below = h - (rout < j) + (rin < j);
-                        bool down;
-                        bool move = true;
-                        if (rout == j) down = rin < j;
-                        else if (below == h + 1) down = true;
-                        else if (below == h - 1) down = false;
-                        else { move = false; down = false; }
-                        if (move) {
-                            if (down) { do { --j; } while (j > 0 && (unsigned)(spos[j] - w0) >= (unsigned)W); }
-                            else      { do { ++j; } while (j < M - 1 && (unsigned)(spos[j] - w0) >= (unsigned)W); }
+            }
+            // cumulative over columns (fields <= CHP, no overflow)
+            uint64_t carry = 0;
+#pragma unroll
+            for (int j = 0; j < (NBMAX + 8) / 8; ++j) {
+                uint64_t x = hcol[j];
+                x += x << 8;
+                x += x << 16;
+                x += x << 32;
+                x += carry * 0x0101010101010101ull;
+                carry = x >> 56;
+                hcol[j] = x;
+            }
+            // 16-bit fields, two per word; scan over threads (rows)
+            uint32_t w[TWORDS], ex[TWORDS], tot[TWORDS];
+#pragma unroll
+            for (int k = 0; k < TWORDS; ++k) {
+                const int b0 = 2 * k, b1 = 2 * k + 1;
+                const uint32_t v0 = (uint32_t)(hcol[b0 >> 3] >> (8 * (b0 & 7))) & 0xFFu;
+                const uint32_t v1 = (uint32_t)(hcol[b1 >> 3] >> (8 * (b1 & 7))) & 0xFFu;
+                w[k] = v0 | (v1 << 16);
+            }
+            block_scan_words<TWORDS>(w, ex, tot, sm.wsc);
+            if (tid < NC) {
+                uint16_t *row = sm.u.tbl + (tid + 1) * TLD;
+#pragma unroll
+                for (int k = 0; k < TWORDS; ++k) {
+                    const uint32_t inc = ex[k] + w[k];
+                    if (2 * k <= NB) row[2 * k] = (uint16_t)(inc & 0xFFFFu);
+                    if (2 * k + 1 <= NB) row[2 * k + 1] = (uint16_t)(inc >> 16);
+                }
+            }
+            if (tid <= NB) sm.u.tbl[tid] = 0;
+            __syncthreads();
+        }
+
+        // ---- walks: thread owns outputs [kb, ke)
+        if (kb < ke) {
+            int w0 = win_start(kb, B, W, h) - u0;
+            const int cL = w0 / CHP, nl = w0 % CHP;
+            const int xr2 = w0 + W;
+            const int cR = xr2 / CHP, nr = xr2 % CHP;
+            uint32_t rl[CHP], rrr[CHP];
+#pragma unroll
+            for (int i = 0; i < CHP; ++i) {
+                rl[i] = (i < nl) ? sm.rank[cL * CHP + i] : 0xFFFFFFFFu;
+                rrr[i] = (i < nr) ? sm.rank[cR * CHP + i] : 0xFFFFFFFFu;
+            }
+            auto count = [&](int b) -> int {
+                const uint32_t lim = (uint32_t)(b * RBS);
+                int cnt = (int)sm.u.tbl[cR * TLD + b] - (int)sm.u.tbl[cL * TLD + b];
+#pragma unroll
+                for (int i = 0; i < CHP; ++i) cnt += (int)(rrr[i] < lim) - (int)(rl[i] < lim);
+                return cnt;
+            };
+            int lo = 1, hi2 = NB;
+            while (lo < hi2) {
+                const int mid = (lo + hi2) >> 1;
+                if (count(mid) >= h + 1) hi2 = mid; else lo = mid + 1;
+            }
+            int base = count(lo - 1);
+            int j = (lo - 1) * RBS;
+            // scan the rank block 8 at a time for the (h+1)-th active element
+            for (bool found = false; !found && j < M;) {
+                uint32_t v[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) v[i] = (j + i < M) ? sw[j + i] : 0xFFFFFFFFu;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    if (!found) {
+                        const bool act = (j + i < M) && ((v[i] & 0xFFFu) - (uint32_t)w0 < (uint32_t)W);
+                        if (act && ++base == h + 1) {
+                            found = true;
+                            j += i;
                         }
                     }
-                    medv[k - t0] = X[spos[j]];
                 }
+                if (!found) j += 8;
             }
-        }
-        __syncthreads();
-
-        // ---- S = C med + S_instr, in-tile prefix of 1/S and the tile sum
-        {
-            const int base = t0 + tid * R;
-            double loc[8], s = 0.0;
+            if (j > M - 1) j = M - 1;          // guards a broken invariant only
+            // rank of the element leaving / entering at each step
+            uint32_t ro[8], ri[8];
 #pragma unroll
-            for (int r = 0; r < 8; ++r) {
-                const int k = base + r;
-                if (r < R && k < t1) {
-                    const double Sk = g.C * medv[k - t0] + d.sx[k];
-                    d.S[k] = Sk;
-                    s += 1.0 / Sk;
+            for (int r = 1; r < 8; ++r) {
+                const int k = kb + r;
+                const int ws = k < ke ? win_start(k, B, W, h) - u0 : w0;
+                const int wp = k < ke ? win_start(k - 1, B, W, h) - u0 : w0;
+                ro[r] = (ws != wp) ? sm.rank[wp] : 0xFFFFFFFFu;
+                ri[r] = (ws != wp) ? sm.rank[wp + W] : 0xFFFFFFFFu;
+            }
+            int js[8];
+            js[0] = j;
+#pragma unroll
+            for (int r = 1; r < 8; ++r) {
+                const int k = kb + r;
+                if (k < ke) {
+                    const int ws = win_start(k, B, W, h) - u0;
+                    if (ro[r] != 0xFFFFFFFFu) {
+                        const int rout = (int)ro[r], rin = (int)ri[r];
+                        const int below = h - (rout < j) + (rin < j);
+                        int dir = 0;
+                        if (rout == j) dir = (rin < j) ? -1 : 1;
+                        else if (below == h + 1) dir = -1;
+                        else if (below == h - 1) dir = 1;
+                        if (dir < 0) {
+                            do { --j; } while (j > 0 && (sw[j] & 0xFFFu) - (uint32_t)ws >= (uint32_t)W);
+                        } else if (dir > 0) {
+                            do { ++j; } while (j < M - 1 && (sw[j] & 0xFFFu) - (uint32_t)ws >= (uint32_t)W);
+                        }
+                    }
                 }
-                loc[r] = s;
+                js[r] = j;
             }
-            double tot;
-            const double ex = block_excl_scan(s, sm.dsh, &tot);
 #pragma unroll
-            for (int r = 0; r < 8; ++r) {
-                const int k = base + r;
-                if (r < R && k < t1) d.is_pre[k] = ex + loc[r];
-            }
-            if (tid == 0) d.is_tsum[tile] = tot;
+            for (int r = 0; r < 8; ++r) med[r] = (kb + r < ke) ? sm.xv[sw[js[r]] & 0xFFFu] : 0.0;
         }
     }
 
+    // ---- S = C med + S_instr on the thread's own outputs; in-tile prefix
+    // of 1/S and the tile sum
+    {
+        double loc[8], s = 0.0;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const int k = kb + r;
+            if (r < R && k < ke) {
+                const double Sk = g.C * med[r] + d.sx[k];
+                d.S[k] = Sk;
+                s += 1.0 / Sk;
+            }
+            loc[r] = s;
+        }
+        double tot;
+        const double ex = block_excl_scan(s, sm.dsh, &tot);
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const int k = kb + r;
+            if (r < R && k < ke) d.is_pre[k] = ex + loc[r];
+        }
+        if (tid == 0) d.is_tsum[tile] = tot;
+    }
 }
 
 // Exclusive prefix of the tile sums of 1/S (one block).
