@@ -168,6 +168,62 @@ gbsub_status gbsub_set_profiling(gbsub_ctx *ctx, int enable);
 gbsub_status gbsub_kernel_stats(const gbsub_ctx *ctx, gbsub_kernel_stat *out, uint32_t cap,
                                 uint32_t *n);
 
+/* ---------------------------------------------------------------- batches
+ * Many catalogs, possibly on different grids, share every kernel launch of
+ * the loop: one launch covers all slots (one slot per catalog), and a slot
+ * whose loop has settled does nothing.  Catalogs are admitted and retired
+ * between steps (continuous batching).  Each admitted slot uses its own
+ * context (configuration, results) and its own workspace; the results of a
+ * retired slot are read with gbsub_spectrum / gbsub_resolved on that context.
+ * Results are identical to gbsub_run on the same context and catalog. */
+typedef struct gbsub_batch gbsub_batch;
+
+enum {                                   /* slot states reported by gbsub_batch_poll */
+    GBSUB_SLOT_RUNNING = 0,
+    GBSUB_SLOT_SETTLED = 1,              /* the resolved set stopped changing */
+    GBSUB_SLOT_MAXITER = 2,              /* max_iter bodies ran, sources still resolving */
+    GBSUB_SLOT_INVALID = 3,              /* an input entry failed validation */
+    GBSUB_SLOT_FREE = 255
+};
+
+/* Bytes of DEVICE memory for the descriptor table of max_slots slots. */
+gbsub_status gbsub_batch_table_size(uint32_t max_slots, uint64_t *bytes);
+
+/* Creates a batch of up to max_slots (1..4096) slots on the current device.
+ * `table` is a DEVICE pointer to gbsub_batch_table_size() bytes, 256-byte
+ * aligned, owned by the caller and kept until gbsub_batch_destroy. */
+gbsub_status gbsub_batch_create(uint32_t max_slots, void *table, uint64_t table_bytes,
+                                gbsub_batch **out);
+
+/* Admits `cat` (device arrays, read until the slot is retired) into a free
+ * slot with context `ctx` and its DEVICE workspace (gbsub_workspace_size()
+ * bytes for cat->n, owned by the caller until retirement).  Enqueues the
+ * grid tables, reset and prep on `stream` and returns at once; *slot (host)
+ * receives the slot index.  INVALID for bad arguments or a context that
+ * already holds a slot, NOMEM if no slot is free. */
+gbsub_status gbsub_batch_admit(gbsub_batch *b, gbsub_ctx *ctx, const gbsub_catalog *cat,
+                               void *workspace, uint64_t ws_bytes, void *stream, uint32_t *slot);
+
+/* Enqueues n_bodies loop bodies for every slot on `stream` (captured once in
+ * a HIP graph and replayed when `stream` is not the null stream); returns
+ * at once. */
+gbsub_status gbsub_batch_step(gbsub_batch *b, uint32_t n_bodies, void *stream);
+
+/* Waits for `stream`, then writes the state of slot i to state[i] (host,
+ * cap >= max_slots entries) and the number of slots still running to
+ * *n_running (host, may be NULL). */
+gbsub_status gbsub_batch_poll(gbsub_batch *b, void *stream, uint8_t *state, uint32_t cap,
+                              uint32_t *n_running);
+
+/* Retires a slot that is no longer running: its results become the last
+ * run of its context, *out (host, may be NULL) receives the summary, and the
+ * slot is freed.  Returns the slot's outcome: OK, MAXITER or INVALID;
+ * STATE if the slot is free or still running. */
+gbsub_status gbsub_batch_retire(gbsub_batch *b, uint32_t slot, void *stream, gbsub_summary *out);
+
+/* Releases the batch (NULL is ignored); caller memory is not touched. */
+void gbsub_batch_destroy(gbsub_batch *b);
+
 /* Releases the context (NULL is ignored).  Does not touch caller memory. */
 void gbsub_destroy(gbsub_ctx *ctx);
 

@@ -1,10 +1,14 @@
 // gbsub_api.hip -- host runtime and C ABI of libgbsub (see include/gbsub.h).
 //
 // The runtime validates the configuration, carves the caller's workspace,
-// enqueues the kernels of gbsub_kernels.hip and drives the loop: loop bodies
-// are enqueued in growing chunks without waiting, every kernel of a body
-// exits at once after the device-side "settled" flag is set, and the host
-// reads the 64-byte control block once per chunk.
+// writes slot descriptors (grid, workspace pointers, catalog) to device
+// memory and enqueues the kernels of gbsub_kernels.hip.  Kernels read the
+// descriptor of slot blockIdx.y, so a single catalog (gbsub_run, a one-slot
+// table inside its workspace) and a batch of catalogs (gbsub_batch_*, a table
+// in a caller buffer) use the same launches.  Loop bodies are enqueued in
+// chunks without waiting; every kernel of a body exits at once after the
+// slot's device-side "settled" flag is set, and the host reads the control
+// blocks once per chunk.
 
 #include "gbsub_internal.h"
 #include "gbsub.h"
@@ -31,6 +35,8 @@ struct gbsub_ctx {
     // the S_instr tables in `tables_ws` were computed for this grid
     void *tables_ws;
     Ctl *host_ctl;     // pinned
+    Slot *host_slot;   // pinned staging of the one-slot table
+    int batch_slot;    // slot held in a batch, -1 if none
     // profiling
     bool profiling;
     struct Rec { int kid; int64_t t; hipEvent_t a, b; };
@@ -94,6 +100,7 @@ uint64_t carve(const Grid &g, uint64_t n, char *base, Dev *d)
     const uint64_t max_events = 2 * n;
     const uint64_t ev_chunks = (max_events + ACC_EV - 1) / ACC_EV;
     Dev t{};
+    take(sizeof(Slot));                      // the one-slot table of gbsub_run
     t.max_chunks = (uint32_t)(ev_chunks + nt);
     t.max_slots = (uint32_t)(2 * ev_chunks + 2);
     t.sx = (double *)take(B * 8);
@@ -184,8 +191,87 @@ gbsub_status validate(const gbsub_config *c, Grid *g)
     r.oms_pm = c->oms_pm;
     r.tm_fm = c->tm_fm;
     r.arm_m = c->arm_m;
+    r.max_iter = c->max_iter;
     *g = r;
     return GBSUB_OK;
+}
+
+unsigned blocks_for(uint64_t n, unsigned cap)
+{
+    uint64_t b = (n + WG - 1) / WG;
+    if (b < 1) b = 1;
+    return (unsigned)(b > cap ? cap : b);
+}
+
+Slot make_slot(const Grid &g, const Dev &d, const gbsub_catalog *cat)
+{
+    Slot sl{};
+    sl.g = g;
+    sl.d = d;
+    sl.A = cat->A;
+    sl.F = cat->f;
+    sl.FD = cat->fdot;
+    sl.ids = cat->id;
+    sl.n = cat->n;
+    sl.active = 1;
+    return sl;
+}
+
+// Launch extents covering one slot.
+Dims dims_of(const Slot &sl)
+{
+    Dims dm{};
+    dm.ns = 1;
+    dm.maxB = sl.g.B;
+    dm.maxnt = sl.g.nt;
+    dm.maxtile = sl.g.tile;
+    dm.prep_blocks = (uint32_t)((sl.n + PREP_SRC - 1) / PREP_SRC);
+    dm.accum_blocks = sl.d.max_chunks;
+    dm.amax_blocks = blocks_for(sl.n, AMAX_BLOCKS);
+    return dm;
+}
+
+void widen(Dims &a, const Dims &b)
+{
+    a.maxB = std::max(a.maxB, b.maxB);
+    a.maxnt = std::max(a.maxnt, b.maxnt);
+    a.maxtile = std::max(a.maxtile, b.maxtile);
+    a.prep_blocks = std::max(a.prep_blocks, b.prep_blocks);
+    a.accum_blocks = std::max(a.accum_blocks, b.accum_blocks);
+    a.amax_blocks = std::max(a.amax_blocks, b.amax_blocks);
+}
+
+gbsub_status check_catalog(const gbsub_ctx *c, const gbsub_catalog *cat, void *ws, uint64_t ws_bytes)
+{
+    if (!c || !cat || !ws) return GBSUB_E_INVALID;
+    if (cat->n >= (1ull << 31)) return GBSUB_E_INVALID;
+    if (cat->n > 0 && (!cat->A || !cat->f || !cat->fdot || !cat->id)) return GBSUB_E_INVALID;
+    if (((uintptr_t)ws & 255u) != 0) return GBSUB_E_INVALID;
+    if (ws_bytes < carve(c->g, cat->n, nullptr, nullptr)) return GBSUB_E_INVALID;
+    return GBSUB_OK;
+}
+
+gbsub_status use_device(int dev)
+{
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return GBSUB_E_DEVICE;
+    if (cur != dev && hipSetDevice(dev) != hipSuccess) return GBSUB_E_DEVICE;
+    return GBSUB_OK;
+}
+
+// Summary of a settled slot from its control block.
+gbsub_summary summary_of(const Grid &g, const Ctl &h)
+{
+    gbsub_summary s{};
+    s.n_iter = h.n_iter;
+    s.n_bins = (uint64_t)g.B;
+    s.n_candidates = h.n_cand;
+    s.n_resolved = h.n_resolved;
+    s.n_near_threshold = h.n_near;
+    double mm;
+    std::memcpy(&mm, &h.min_margin, 8);
+    s.min_rel_margin = mm;
+    return s;
 }
 
 }  // namespace
@@ -244,10 +330,14 @@ gbsub_status gbsub_create(const gbsub_config *cfg, gbsub_ctx **out)
     c->ws = nullptr;
     c->tables_ws = nullptr;
     c->host_ctl = nullptr;
+    c->host_slot = nullptr;
+    c->batch_slot = -1;
     c->profiling = false;
     c->ev_used = 0;
     c->clear_stats();
-    if (hipHostMalloc((void **)&c->host_ctl, sizeof(Ctl), hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc((void **)&c->host_ctl, sizeof(Ctl), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&c->host_slot, sizeof(Slot), hipHostMallocDefault) != hipSuccess) {
+        if (c->host_ctl) (void)hipHostFree(c->host_ctl);
         delete c;
         return GBSUB_E_DEVICE;
     }
@@ -259,6 +349,7 @@ void gbsub_destroy(gbsub_ctx *c)
 {
     if (!c) return;
     if (c->host_ctl) (void)hipHostFree(c->host_ctl);
+    if (c->host_slot) (void)hipHostFree(c->host_slot);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     delete c;
 }
@@ -273,78 +364,67 @@ gbsub_status gbsub_workspace_size(const gbsub_ctx *c, uint64_t n, uint64_t *byte
 gbsub_status gbsub_run(gbsub_ctx *c, const gbsub_catalog *cat, void *ws, uint64_t ws_bytes,
                        void *stream, gbsub_summary *out)
 {
-    if (!c || !cat || !ws) return GBSUB_E_INVALID;
-    if (cat->n >= (1ull << 31)) return GBSUB_E_INVALID;
-    if (cat->n > 0 && (!cat->A || !cat->f || !cat->fdot || !cat->id)) return GBSUB_E_INVALID;
-    if (((uintptr_t)ws & 255u) != 0) return GBSUB_E_INVALID;
-    const uint64_t need = carve(c->g, cat->n, nullptr, nullptr);
-    if (ws_bytes < need) return GBSUB_E_INVALID;
+    gbsub_status st0 = check_catalog(c, cat, ws, ws_bytes);
+    if (st0 != GBSUB_OK) return st0;
+    if (c->batch_slot >= 0) return GBSUB_E_STATE;
     c->have_result = false;
-    int cur = -1;
-    if (hipGetDevice(&cur) != hipSuccess) return GBSUB_E_DEVICE;
-    if (cur != c->device && hipSetDevice(c->device) != hipSuccess) return GBSUB_E_DEVICE;
+    if (use_device(c->device) != GBSUB_OK) return GBSUB_E_DEVICE;
     hipStream_t st = (hipStream_t)stream;
     Dev d;
     carve(c->g, cat->n, (char *)ws, &d);
     const Grid &g = c->g;
+    Slot *ds = reinterpret_cast<Slot *>(ws);    // one-slot table at the start of the workspace
+    *c->host_slot = make_slot(g, d, cat);
+    const Dims dm = dims_of(*c->host_slot);
 
     c->ev_used = 0;
     c->recs.clear();
-    hipError_t e = hipSuccess;
-    if (c->tables_ws != ws) {
-        e = c->timed(K_TABLES, -1, st, [&] { return launch_grid_tables(g, d, st); });
-        if (e != hipSuccess) return GBSUB_E_DEVICE;
-        c->tables_ws = ws;
+    hipError_t e = hipMemcpyAsync(ds, c->host_slot, sizeof(Slot), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && c->tables_ws != ws) {
+        e = c->timed(K_TABLES, -1, st, [&] { return launch_grid_tables(ds, dm, st); });
+        if (e == hipSuccess) c->tables_ws = ws;
     }
-    e = c->timed(K_RESET, -1, st, [&] { return launch_reset(g, d, cat->n, st); });
-    if (e == hipSuccess)
-        e = c->timed(K_PREP, -1, st, [&] { return launch_prep(g, d, cat->A, cat->f, cat->fdot, cat->n, st); });
-    if (e == hipSuccess) e = hipMemcpyAsync(c->host_ctl, d.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e == hipSuccess) e = c->timed(K_RESET, -1, st, [&] { return launch_reset(ds, dm, st); });
+    if (e == hipSuccess) e = c->timed(K_PREP, -1, st, [&] { return launch_prep(ds, dm, st); });
     if (e != hipSuccess) {
         c->tables_ws = nullptr;
         return GBSUB_E_DEVICE;
     }
-    if (c->host_ctl->bad) return GBSUB_E_INVALID;
-    const uint64_t n_cand = c->host_ctl->n_cand;
-    const uint64_t max_iter = c->cfg.max_iter ? c->cfg.max_iter : n_cand + 1;
-
-    gbsub_status status = GBSUB_OK;
-    uint64_t t = 0;
-    uint64_t chunk = 4;
+    // loop bodies in growing chunks; the device enforces max_iter
+    uint64_t t = 0, chunk = 4;
+    const uint64_t guard = (uint64_t)cat->n + 2 + (c->cfg.max_iter ? c->cfg.max_iter : 0);
     for (;;) {
-        const uint64_t k = std::min(chunk, max_iter - t);
-        for (uint64_t i = 0; i < k && e == hipSuccess; ++i) {
-            const int ti = (int)(t + i);
-            e = c->timed(K_XUPDATE, ti, st, [&] { return launch_xupdate(g, d, st); });
-            if (e == hipSuccess) e = c->timed(K_MEDIAN, ti, st, [&] { return launch_median(g, d, st); });
-            if (e == hipSuccess) e = c->timed(K_SNR, ti, st, [&] { return launch_snr(g, d, ti, st); });
+        for (uint64_t i = 0; i < chunk && e == hipSuccess; ++i) {
+            const int64_t ti = (int64_t)(t + i);
+            e = c->timed(K_XUPDATE, ti, st, [&] { return launch_xupdate(ds, dm, st); });
+            if (e == hipSuccess) e = c->timed(K_MEDIAN, ti, st, [&] { return launch_median(ds, dm, st); });
+            if (e == hipSuccess) e = c->timed(K_SNR, ti, st, [&] { return launch_snr(ds, dm, st); });
         }
-        t += k;
+        t += chunk;
         if (e == hipSuccess) e = hipMemcpyAsync(c->host_ctl, d.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess) return GBSUB_E_DEVICE;
+        if (c->host_ctl->bad) return GBSUB_E_INVALID;
         if (c->host_ctl->done) break;
-        if (t >= max_iter) {
-            status = GBSUB_E_MAXITER;
-            break;
-        }
+        if (t > guard) return GBSUB_E_DEVICE;   // the device loop must settle within n + 1 bodies
         chunk = std::min<uint64_t>(chunk * 2, 32);
     }
-    e = c->timed(K_OUTPUT, -1, st, [&] { return launch_outputs(g, d, cat->id, st); });
+    e = c->timed(K_OUTPUT, -1, st, [&] { return launch_outputs(ds, dm, st); });
     if (e == hipSuccess) e = hipMemcpyAsync(c->host_ctl, d.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return GBSUB_E_DEVICE;
 
     const Ctl &h = *c->host_ctl;
+    const gbsub_status status = h.status == 6 ? GBSUB_E_MAXITER : GBSUB_OK;
     if (c->profiling) {
-        const int64_t n_body = status == GBSUB_OK ? (int64_t)h.n_iter : (int64_t)t;
+        const int64_t n_body = (int64_t)h.n_iter;
         for (const auto &r : c->recs) {
             if (r.t >= n_body) continue;        // bodies enqueued past the settled one
             float ms = 0.f;
             if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) return GBSUB_E_DEVICE;
             c->k_ms[r.kid] += ms;
             c->k_launches[r.kid] += 1;
+            if (r.kid == K_TABLES) c->k_units[K_TABLES] += (double)g.B;
         }
         c->k_units[K_PREP] += (double)cat->n;
         c->k_units[K_RESET] += (double)g.B;
@@ -352,18 +432,8 @@ gbsub_status gbsub_run(gbsub_ctx *c, const gbsub_catalog *cat, void *ws, uint64_
         c->k_units[K_MEDIAN] += (double)h.units_med;
         c->k_units[K_SNR] += (double)h.units_snr;
         c->k_units[K_OUTPUT] += (double)h.n_cand;
-        for (const auto &r : c->recs)
-            if (r.kid == K_TABLES) c->k_units[K_TABLES] += (double)g.B;
     }
-    gbsub_summary s{};
-    s.n_iter = status == GBSUB_OK ? h.n_iter : (uint32_t)t;
-    s.n_bins = (uint64_t)g.B;
-    s.n_candidates = h.n_cand;
-    s.n_resolved = h.n_resolved;
-    s.n_near_threshold = h.n_near;
-    double mm;
-    std::memcpy(&mm, &h.min_margin, 8);
-    s.min_rel_margin = mm;
+    const gbsub_summary s = summary_of(g, h);
     if (out) *out = s;
     if (status != GBSUB_OK) return status;
     c->summ = s;
@@ -463,6 +533,243 @@ gbsub_status gbsub_kernel_stats(const gbsub_ctx *c, gbsub_kernel_stat *out, uint
         out[k].total_ms = c->k_ms[k];
         out[k].units = c->k_units[k];
     }
+    return GBSUB_OK;
+}
+
+
+// ---------------------------------------------------------------- batches
+
+struct gbsub_batch {
+    uint32_t max_slots;
+    int device;
+    Slot *table;                       // device
+    Slot *host_table;                  // pinned staging, one entry per slot
+    Ctl *host_ctls;                    // pinned
+    std::vector<gbsub_ctx *> owner;
+    std::vector<void *> ws;            // each slot's workspace
+    std::vector<uint8_t> state;
+    Dims dims;                         // covers every slot admitted so far
+    bool have_dims;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    uint32_t graph_bodies;
+    Dims graph_dims;
+    hipStream_t graph_stream;
+};
+
+namespace {
+bool same_dims(const Dims &a, const Dims &b)
+{
+    return a.ns == b.ns && a.maxB == b.maxB && a.maxnt == b.maxnt && a.maxtile == b.maxtile;
+}
+
+void drop_graph(gbsub_batch *b)
+{
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+}
+
+hipError_t enqueue_bodies(const Slot *ds, const Dims &dm, uint32_t n, hipStream_t st)
+{
+    hipError_t e = hipSuccess;
+    for (uint32_t i = 0; i < n && e == hipSuccess; ++i) {
+        e = launch_xupdate(ds, dm, st);
+        if (e == hipSuccess) e = launch_median(ds, dm, st);
+        if (e == hipSuccess) e = launch_snr(ds, dm, st);
+    }
+    return e;
+}
+}  // namespace
+
+gbsub_status gbsub_batch_table_size(uint32_t max_slots, uint64_t *bytes)
+{
+    if (!bytes || max_slots < 1 || max_slots > 4096) return GBSUB_E_INVALID;
+    *bytes = align_up((uint64_t)max_slots * sizeof(Slot));
+    return GBSUB_OK;
+}
+
+gbsub_status gbsub_batch_create(uint32_t max_slots, void *table, uint64_t table_bytes, gbsub_batch **out)
+{
+    if (!out) return GBSUB_E_INVALID;
+    *out = nullptr;
+    uint64_t need = 0;
+    if (gbsub_batch_table_size(max_slots, &need) != GBSUB_OK || !table || table_bytes < need ||
+        ((uintptr_t)table & 255u) != 0)
+        return GBSUB_E_INVALID;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return GBSUB_E_DEVICE;
+    gbsub_batch *b = new (std::nothrow) gbsub_batch();
+    if (!b) return GBSUB_E_NOMEM;
+    b->max_slots = max_slots;
+    b->device = dev;
+    b->table = (Slot *)table;
+    b->host_table = nullptr;
+    b->host_ctls = nullptr;
+    b->owner.assign(max_slots, nullptr);
+    b->ws.assign(max_slots, nullptr);
+    b->state.assign(max_slots, (uint8_t)GBSUB_SLOT_FREE);
+    b->have_dims = false;
+    b->graph = nullptr;
+    b->exec = nullptr;
+    b->graph_bodies = 0;
+    b->graph_stream = nullptr;
+    if (hipHostMalloc((void **)&b->host_table, sizeof(Slot) * max_slots, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&b->host_ctls, sizeof(Ctl) * max_slots, hipHostMallocDefault) != hipSuccess) {
+        gbsub_batch_destroy(b);
+        return GBSUB_E_DEVICE;
+    }
+    std::memset(b->host_table, 0, sizeof(Slot) * max_slots);    // every slot inactive
+    if (hipMemcpy(b->table, b->host_table, sizeof(Slot) * max_slots, hipMemcpyHostToDevice) != hipSuccess) {
+        gbsub_batch_destroy(b);
+        return GBSUB_E_DEVICE;
+    }
+    *out = b;
+    return GBSUB_OK;
+}
+
+void gbsub_batch_destroy(gbsub_batch *b)
+{
+    if (!b) return;
+    drop_graph(b);
+    for (gbsub_ctx *c : b->owner)
+        if (c) c->batch_slot = -1;
+    if (b->host_table) (void)hipHostFree(b->host_table);
+    if (b->host_ctls) (void)hipHostFree(b->host_ctls);
+    delete b;
+}
+
+gbsub_status gbsub_batch_admit(gbsub_batch *b, gbsub_ctx *c, const gbsub_catalog *cat, void *ws,
+                               uint64_t ws_bytes, void *stream, uint32_t *slot)
+{
+    if (!b || !slot) return GBSUB_E_INVALID;
+    gbsub_status st0 = check_catalog(c, cat, ws, ws_bytes);
+    if (st0 != GBSUB_OK) return st0;
+    if (c->batch_slot >= 0 || c->device != b->device) return GBSUB_E_INVALID;
+    uint32_t k = 0;
+    while (k < b->max_slots && b->state[k] != GBSUB_SLOT_FREE) ++k;
+    if (k == b->max_slots) return GBSUB_E_NOMEM;
+    if (use_device(b->device) != GBSUB_OK) return GBSUB_E_DEVICE;
+    hipStream_t st = (hipStream_t)stream;
+    Dev d;
+    carve(c->g, cat->n, (char *)ws, &d);
+    b->host_table[k] = make_slot(c->g, d, cat);
+    const Dims one = dims_of(b->host_table[k]);
+    Slot *ds = b->table + k;
+    hipError_t e = hipMemcpyAsync(ds, &b->host_table[k], sizeof(Slot), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && c->tables_ws != ws) {
+        e = launch_grid_tables(ds, one, st);
+        if (e == hipSuccess) c->tables_ws = ws;
+    }
+    if (e == hipSuccess) e = launch_reset(ds, one, st);
+    if (e == hipSuccess) e = launch_prep(ds, one, st);
+    if (e != hipSuccess) {
+        c->tables_ws = nullptr;
+        return GBSUB_E_DEVICE;
+    }
+    c->have_result = false;
+    c->batch_slot = (int)k;
+    b->owner[k] = c;
+    b->ws[k] = ws;
+    b->state[k] = GBSUB_SLOT_RUNNING;
+    if (!b->have_dims) {
+        b->dims = one;
+        b->have_dims = true;
+    } else {
+        widen(b->dims, one);
+    }
+    b->dims.ns = (int)b->max_slots;
+    *slot = k;
+    return GBSUB_OK;
+}
+
+gbsub_status gbsub_batch_step(gbsub_batch *b, uint32_t n, void *stream)
+{
+    if (!b || n == 0) return GBSUB_E_INVALID;
+    if (!b->have_dims) return GBSUB_OK;
+    if (use_device(b->device) != GBSUB_OK) return GBSUB_E_DEVICE;
+    hipStream_t st = (hipStream_t)stream;
+    if (!st) return b->dims.ns ? (enqueue_bodies(b->table, b->dims, n, st) == hipSuccess ? GBSUB_OK : GBSUB_E_DEVICE) : GBSUB_OK;
+    if (!b->exec || b->graph_bodies != n || !same_dims(b->graph_dims, b->dims) || b->graph_stream != st) {
+        drop_graph(b);
+        hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            const hipError_t e1 = enqueue_bodies(b->table, b->dims, n, st);
+            e = hipStreamEndCapture(st, &b->graph);
+            if (e1 != hipSuccess) e = e1;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            drop_graph(b);
+            return GBSUB_E_DEVICE;
+        }
+        b->graph_bodies = n;
+        b->graph_dims = b->dims;
+        b->graph_stream = st;
+    }
+    return hipGraphLaunch(b->exec, st) == hipSuccess ? GBSUB_OK : GBSUB_E_DEVICE;
+}
+
+gbsub_status gbsub_batch_poll(gbsub_batch *b, void *stream, uint8_t *state, uint32_t cap, uint32_t *n_running)
+{
+    if (!b || !state || cap < b->max_slots) return GBSUB_E_INVALID;
+    if (use_device(b->device) != GBSUB_OK) return GBSUB_E_DEVICE;
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = hipSuccess;
+    for (uint32_t k = 0; k < b->max_slots && e == hipSuccess; ++k)
+        if (b->owner[k])
+            e = hipMemcpyAsync(&b->host_ctls[k], b->host_table[k].d.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return GBSUB_E_DEVICE;
+    uint32_t running = 0;
+    for (uint32_t k = 0; k < b->max_slots; ++k) {
+        if (b->owner[k]) {
+            const Ctl &h = b->host_ctls[k];
+            b->state[k] = h.bad ? GBSUB_SLOT_INVALID
+                        : !h.done ? GBSUB_SLOT_RUNNING
+                        : h.status == 6 ? GBSUB_SLOT_MAXITER : GBSUB_SLOT_SETTLED;
+            running += b->state[k] == GBSUB_SLOT_RUNNING;
+        }
+        state[k] = b->state[k];
+    }
+    if (n_running) *n_running = running;
+    return GBSUB_OK;
+}
+
+gbsub_status gbsub_batch_retire(gbsub_batch *b, uint32_t k, void *stream, gbsub_summary *out)
+{
+    if (!b || k >= b->max_slots) return GBSUB_E_INVALID;
+    if (!b->owner[k] || b->state[k] == GBSUB_SLOT_RUNNING || b->state[k] == GBSUB_SLOT_FREE)
+        return GBSUB_E_STATE;
+    if (use_device(b->device) != GBSUB_OK) return GBSUB_E_DEVICE;
+    hipStream_t st = (hipStream_t)stream;
+    gbsub_ctx *c = b->owner[k];
+    const Slot sl = b->host_table[k];
+    Slot *ds = b->table + k;
+    const uint8_t outcome = b->state[k];
+    hipError_t e = hipSuccess;
+    if (outcome == GBSUB_SLOT_SETTLED) e = launch_outputs(ds, dims_of(sl), st);
+    if (e == hipSuccess) e = hipMemcpyAsync(&b->host_ctls[k], sl.d.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st);
+    b->host_table[k].active = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(ds, &b->host_table[k], sizeof(Slot), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return GBSUB_E_DEVICE;
+    const Ctl &h = b->host_ctls[k];
+    const gbsub_summary s = summary_of(sl.g, h);
+    if (out) *out = s;
+    b->owner[k] = nullptr;
+    const void *wsk = b->ws[k];
+    b->ws[k] = nullptr;
+    b->state[k] = GBSUB_SLOT_FREE;
+    c->batch_slot = -1;
+    if (outcome == GBSUB_SLOT_INVALID) return GBSUB_E_INVALID;
+    if (outcome == GBSUB_SLOT_MAXITER) return GBSUB_E_MAXITER;
+    c->summ = s;
+    c->dev = sl.d;
+    c->ws = const_cast<void *>(wsk);
+    c->n_cand = h.n_cand;
+    c->have_result = true;
     return GBSUB_OK;
 }
 

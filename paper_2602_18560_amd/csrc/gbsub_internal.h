@@ -42,12 +42,14 @@ struct Ctl {
     uint32_t n_chunks;       // accumulation blocks of the binning
     uint32_t cand_cursor;    // candidate slots handed out
     uint32_t n_events;       // binning events
-    uint32_t pad0;
+    uint32_t iter;           // index t of the next loop body
     uint64_t n_near;         // evaluations within 1e-6 of the threshold
     uint64_t min_margin;     // bits of min |rho/rho_th - 1| (non-negative double)
     uint64_t units_x;        // bins converted by k_xupdate
     uint64_t units_med;      // median outputs computed by k_median
     uint64_t units_snr;      // candidate evaluations by k_snr
+    uint32_t status;         // 0 running/settled, 6 = max_iter reached with sources still resolving
+    uint32_t pad1;
 };
 
 // Kernels that the profiling mode times separately.
@@ -67,6 +69,8 @@ struct Grid {
     double cut2;             // (kappa rho_th)^2
     double rth;              // rho_th
     double oms_pm, tm_fm, arm_m;
+    uint32_t max_iter;       // loop bodies allowed; 0 = candidates + 1
+    uint32_t pad;
 };
 
 // Pointers into the caller's workspace.
@@ -120,15 +124,34 @@ struct Dev {
     uint32_t max_chunks;     // grid of the accumulation kernel
 };
 
+// One catalog of a launch: its grid, workspace, catalog.  Kernels read the
+// descriptor of slot blockIdx.y from a device array, so one launch serves a
+// whole batch of catalogs with different grids; inactive slots exit at once.
+struct Slot {
+    Grid g;
+    Dev d;
+    const float *A, *F, *FD;
+    const uint32_t *ids;
+    uint64_t n;
+    uint32_t active;
+    uint32_t pad;
+};
+
+// Launch extents: the largest per-slot block counts of a set of slots.
+struct Dims {
+    int ns;                  // slots (gridDim.y)
+    int maxB, maxnt, maxtile;
+    uint32_t prep_blocks, accum_blocks, amax_blocks;
+};
+
 // Kernel launchers (gbsub_kernels.hip); all enqueue on `st` and return the
-// launch status.
-hipError_t launch_grid_tables(const Grid &g, const Dev &d, hipStream_t st);
-hipError_t launch_reset(const Grid &g, const Dev &d, uint64_t n_src, hipStream_t st);
-hipError_t launch_prep(const Grid &g, const Dev &d, const float *A, const float *f,
-                       const float *fdot, uint64_t n, hipStream_t st);
-hipError_t launch_xupdate(const Grid &g, const Dev &d, hipStream_t st);
-hipError_t launch_median(const Grid &g, const Dev &d, hipStream_t st);
-hipError_t launch_snr(const Grid &g, const Dev &d, int t, hipStream_t st);
-hipError_t launch_outputs(const Grid &g, const Dev &d, const uint32_t *ids, hipStream_t st);
+// launch status.  `ds` is the device array of `dm.ns` slot descriptors.
+hipError_t launch_grid_tables(const Slot *ds, const Dims &dm, hipStream_t st);
+hipError_t launch_reset(const Slot *ds, const Dims &dm, hipStream_t st);
+hipError_t launch_prep(const Slot *ds, const Dims &dm, hipStream_t st);
+hipError_t launch_xupdate(const Slot *ds, const Dims &dm, hipStream_t st);
+hipError_t launch_median(const Slot *ds, const Dims &dm, hipStream_t st);
+hipError_t launch_snr(const Slot *ds, const Dims &dm, hipStream_t st);
+hipError_t launch_outputs(const Slot *ds, const Dims &dm, hipStream_t st);
 
 }  // namespace gbs

@@ -188,20 +188,30 @@ DEVI double sinstr_dev(double f, double oms_pm, double tm_fm, double arm_m)
     return saa / raa;
 }
 
-__global__ __launch_bounds__(WG) void k_sinstr(Grid g, double *sx)
+__global__ __launch_bounds__(WG) void k_sinstr(const Slot *S)
 {
+    const Slot &sl = S[blockIdx.y];
+    if (!sl.active) return;
+    const Grid g = sl.g;
+    const Dev d = sl.d;
     const int k = blockIdx.x * WG + threadIdx.x;
     if (k >= g.B) return;
     const double f = (double)(g.k0 + k) / g.T;
-    sx[k] = sinstr_dev(f, g.oms_pm, g.tm_fm, g.arm_m);
+    d.sx[k] = sinstr_dev(f, g.oms_pm, g.tm_fm, g.arm_m);
 }
 
 // In-tile inclusive prefix of 1/v and the tile sums (one block per tile).
-__global__ __launch_bounds__(WG) void k_inv_prefix(Grid g, const double *v, double *pre,
-                                                   double *tsum)
+__global__ __launch_bounds__(WG) void k_inv_prefix(const Slot *S)
 {
     __shared__ double sh[WG / 64];
+    const Slot &sl = S[blockIdx.y];
+    if (!sl.active) return;
+    const Grid g = sl.g;
+    const Dev d = sl.d;
+    const double *v = d.sx;
+    double *pre = d.isx_pre, *tsum = d.isx_tsum;
     const int tile = blockIdx.x, R = g.tile / WG;
+    if (tile >= g.nt) return;
     const int base = tile * g.tile + threadIdx.x * R;
     double loc[8];
     double s = 0.0;
@@ -238,22 +248,27 @@ DEVI void block_scan_array(const T *in, T *out, int n)
     if (threadIdx.x == 0) out[n] = carry;
 }
 
-__global__ __launch_bounds__(WG) void k_scan_f64(const double *in, double *out, int n)
+__global__ __launch_bounds__(WG) void k_sx_scan(const Slot *S)
 {
-    block_scan_array<double>(in, out, n);
+    const Slot &sl = S[blockIdx.y];
+    if (!sl.active) return;
+    const Grid g = sl.g;
+    const Dev d = sl.d;
+    block_scan_array<double>(d.isx_tsum, d.isx_tile, g.nt);
 }
 
 // ------------------------------------------------------------------ reset
 
-__global__ __launch_bounds__(WG) void k_fill_u32(uint32_t *p, uint64_t n, uint32_t v)
+// Clears the per-run state of a slot: control block, tile counters, dirty
+// flags (every tile is dirty for the first loop body).
+__global__ __launch_bounds__(WG) void k_reset(const Slot *S)
 {
-    for (uint64_t i = (uint64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (uint64_t)gridDim.x * WG)
-        p[i] = v;
-}
-
-__global__ void k_init_ctl(Ctl *c, int B)
-{
-    if (threadIdx.x == 0) {
+    const Slot &sl = S[blockIdx.y];
+    if (!sl.active) return;
+    const Grid g = sl.g;
+    const Dev d = sl.d;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        Ctl *c = d.ctl;
         c->amax_bits = 0;
         c->bad = 0;
         c->n_cand = 0;
@@ -263,11 +278,22 @@ __global__ void k_init_ctl(Ctl *c, int B)
         c->n_chunks = 0;
         c->cand_cursor = 0;
         c->n_events = 0;
+        c->iter = 0;
         c->n_near = 0;
         c->min_margin = 0x7FF0000000000000ull;   // +inf
-        c->units_x = (uint64_t)B;                // the first body converts and filters every bin
-        c->units_med = (uint64_t)B;
+        c->units_x = (uint64_t)g.B;              // the first body converts and filters every bin
+        c->units_med = (uint64_t)g.B;
         c->units_snr = 0;
+        c->status = 0;
+    }
+    for (int i = blockIdx.x * WG + threadIdx.x; i <= g.nt; i += gridDim.x * WG) {
+        if (i < g.nt) {
+            d.btot[i] = 0;
+            d.xdirty[i] = 1;
+            d.sdirty[i] = 1;
+        }
+        d.chgx[i] = 0;
+        d.chgs[i] = 0;
     }
 }
 
@@ -331,9 +357,14 @@ DEVI Trk track_of(const Grid &g, const Dev &d, float Af, float Ff, float FDf, in
 
 // Largest amplitude (fixed-point scale) and validation of A: per-block
 // maxima, then one block reduces them.
-__global__ __launch_bounds__(WG) void k_amax(const float *A, uint64_t n, Dev d)
+__global__ __launch_bounds__(WG) void k_amax(const Slot *S)
 {
     __shared__ uint32_t sm[WG / 64];
+    const Slot &sl = S[blockIdx.y];
+    if (!sl.active) return;
+    const Dev d = sl.d;
+    const float *A = sl.A;
+    const uint64_t n = sl.n;
     uint32_t m = 0, bad = 0;
     for (uint64_t i = (uint64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (uint64_t)gridDim.x * WG) {
         const float a = A[i];
@@ -354,8 +385,11 @@ __global__ __launch_bounds__(WG) void k_amax(const float *A, uint64_t n, Dev d)
     if (bad && lane_id() == 0) atomicOr(&d.ctl->bad, 1u);
 }
 
-__global__ __launch_bounds__(WG) void k_amax_reduce(Dev d, int nparts)
+__global__ __launch_bounds__(WG) void k_amax_reduce(const Slot *S, int nparts)
 {
+    const Slot &sl = S[blockIdx.y];
+    if (!sl.active) return;
+    const Dev d = sl.d;
     uint32_t m = 0;
     for (int i = threadIdx.x; i < nparts; i += WG) m = max(m, d.amax_part[i]);
     for (int s = 32; s >= 1; s >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, s, 64));
@@ -373,8 +407,7 @@ __global__ __launch_bounds__(WG) void k_amax_reduce(Dev d, int nparts)
 DEVI int tile_of(int bin, int tile) { return bin / tile; }
 
 // Count pass: events per tile and candidates of this block.
-__global__ __launch_bounds__(WG) void k_prep_count(Grid g, Dev d, const float *A, const float *F,
-                                                   const float *FD, uint64_t n)
+DEVI void k_prep_count_body(Grid g, Dev d, const float *A, const float *F, const float *FD, uint64_t n)
 {
     __shared__ uint32_t hist[NBK_MAX];
     __shared__ uint32_t scand;
@@ -407,11 +440,28 @@ __global__ __launch_bounds__(WG) void k_prep_count(Grid g, Dev d, const float *A
     if (bad) atomicOr(&d.ctl->bad, 1u);
 }
 
+__global__ __launch_bounds__(WG) void k_prep_count(const Slot *S)
+{
+    const Slot &sl = S[blockIdx.y];
+    if (!sl.active || (uint64_t)blockIdx.x * PREP_SRC >= sl.n) return;
+    const Grid g = sl.g;
+    const Dev d = sl.d;
+    const float *A = sl.A, *F = sl.F, *FD = sl.FD;
+    const uint64_t n = sl.n;
+    k_prep_count_body(g, d, A, F, FD, n);
+}
+
+
 // Plan (one block): tile bases, scatter cursors, accumulation blocks and
 // partial-sum slots; clears the tile sums of D.
-__global__ __launch_bounds__(WG) void k_prep_plan(Grid g, Dev d)
+__global__ __launch_bounds__(WG) void k_prep_plan(const Slot *S)
 {
     __shared__ uint32_t sh[WG / 64];
+    const Slot &sl = S[blockIdx.y];
+    if (!sl.active) return;
+    const Grid g = sl.g;
+    const Dev d = sl.d;
+
     uint32_t carry_e = 0, carry_c = 0, carry_s = 0;
     for (int base = 0; base < g.nt; base += WG) {
         const int b = base + threadIdx.x;
@@ -448,8 +498,7 @@ __global__ __launch_bounds__(WG) void k_prep_plan(Grid g, Dev d)
 
 // Scatter pass: recount, reserve each tile's range once, write the events
 // and the candidate records.
-__global__ __launch_bounds__(WG) void k_prep_scatter(Grid g, Dev d, const float *A, const float *F,
-                                                     const float *FD, uint64_t n)
+DEVI void k_prep_scatter_body(Grid g, Dev d, const float *A, const float *F, const float *FD, uint64_t n)
 {
     __shared__ uint32_t cur[NBK_MAX];
     __shared__ uint32_t scand, cbase;
@@ -513,6 +562,18 @@ __global__ __launch_bounds__(WG) void k_prep_scatter(Grid g, Dev d, const float 
     }
 }
 
+__global__ __launch_bounds__(WG) void k_prep_scatter(const Slot *S)
+{
+    const Slot &sl = S[blockIdx.y];
+    if (!sl.active || (uint64_t)blockIdx.x * PREP_SRC >= sl.n) return;
+    const Grid g = sl.g;
+    const Dev d = sl.d;
+    const float *A = sl.A, *F = sl.F, *FD = sl.FD;
+    const uint64_t n = sl.n;
+    k_prep_scatter_body(g, d, A, F, FD, n);
+}
+
+
 DEVI void lds_add_i128(I128 *p, int64_t v)
 {
     const uint64_t vlo = (uint64_t)v;
@@ -530,11 +591,16 @@ DEVI void atomic_add_i128_full(I128 *p, I128 v)
 }
 
 // Accumulation: block c sums up to ACC_EV events of one tile in LDS.
-__global__ __launch_bounds__(WG) void k_accum(Grid g, Dev d)
+__global__ __launch_bounds__(WG) void k_accum(const Slot *S)
 {
     __shared__ I128 xn[TILE_MAX];
     __shared__ I128 dd[TILE_MAX];
     __shared__ I128 sh[WG / 64];
+    const Slot &sl = S[blockIdx.y];
+    if (!sl.active) return;
+    const Grid g = sl.g;
+    const Dev d = sl.d;
+
     const uint32_t c = blockIdx.x;
     if (c >= d.ctl->n_chunks) return;
     // tile b: the last with chunk_base[b] <= c
@@ -584,11 +650,16 @@ __global__ __launch_bounds__(WG) void k_accum(Grid g, Dev d)
 
 // Hot tiles (several accumulation blocks): sum the partials, RED_BINS bins
 // per block.
-__global__ __launch_bounds__(RED_BINS) void k_accum_reduce(Grid g, Dev d)
+__global__ __launch_bounds__(RED_BINS) void k_accum_reduce(const Slot *S)
 {
     __shared__ I128 sh[RED_BINS / 64];
+    const Slot &sl = S[blockIdx.y];
+    if (!sl.active) return;
+    const Grid g = sl.g;
+    const Dev d = sl.d;
     const int per = g.tile / RED_BINS;
     const int b = blockIdx.x / per, part = blockIdx.x % per;
+    if (b >= g.nt) return;
     const uint32_t nc = d.nch[b];
     if (nc <= 1) return;
     const int k = part * RED_BINS + threadIdx.x;
@@ -618,20 +689,29 @@ __global__ __launch_bounds__(RED_BINS) void k_accum_reduce(Grid g, Dev d)
     }
 }
 
-__global__ __launch_bounds__(WG) void k_dscan(Grid g, Dev d)
+__global__ __launch_bounds__(WG) void k_dscan(const Slot *S)
 {
+    const Slot &sl = S[blockIdx.y];
+    if (!sl.active) return;
+    const Grid g = sl.g;
+    const Dev d = sl.d;
+
     block_scan_array<I128>(d.Dtile, d.Dcarry, g.nt);
 }
 
 // ------------------------------------------------------------------ X update
 
 // X[k] = 2^L * (Xn[k] + prefix(D)[k]) for the tiles whose X changed.
-__global__ __launch_bounds__(WG) void k_xupdate(Grid g, Dev d)
+__global__ __launch_bounds__(WG) void k_xupdate(const Slot *S)
 {
     __shared__ I128 sh[WG / 64];
+    const Slot &sl = S[blockIdx.y];
+    if (!sl.active) return;
+    const Grid g = sl.g;
+    const Dev d = sl.d;
     if (d.ctl->done || d.ctl->bad) return;
     const int tile = blockIdx.x;
-    if (!d.xdirty[tile]) return;
+    if (tile >= g.nt || !d.xdirty[tile]) return;
     const int L = fx_exp(d.ctl->amax_bits, g.T);
     const int R = g.tile / WG;
     const int base = tile * g.tile + threadIdx.x * R;
@@ -785,13 +865,17 @@ DEVI int radix_sort_tile(MedianSmem &sm, int M, int passes)
     return in;
 }
 
-__global__ __launch_bounds__(WG) void k_median(Grid g, Dev d)
+__global__ __launch_bounds__(WG) void k_median(const Slot *S)
 {
     __shared__ MedianSmem sm;
+    const Slot &sl = S[blockIdx.y];
+    if (!sl.active) return;
+    const Grid g = sl.g;
+    const Dev d = sl.d;
     if (d.ctl->done || d.ctl->bad) return;
     const int tile = blockIdx.x, tid = threadIdx.x;
     const int B = g.B, W = g.W, h = g.h;
-    if (!d.sdirty[tile]) return;
+    if (tile >= g.nt || !d.sdirty[tile]) return;
 
     const int t0 = tile * g.tile;
     const int t1 = min(t0 + g.tile, B);
@@ -1055,8 +1139,13 @@ __global__ __launch_bounds__(WG) void k_median(Grid g, Dev d)
 }
 
 // Exclusive prefix of the tile sums of 1/S (one block).
-__global__ __launch_bounds__(WG) void k_med_tail(Grid g, Dev d)
+__global__ __launch_bounds__(WG) void k_med_tail(const Slot *S)
 {
+    const Slot &sl = S[blockIdx.y];
+    if (!sl.active) return;
+    const Grid g = sl.g;
+    const Dev d = sl.d;
+
     if (d.ctl->done || d.ctl->bad) return;
     block_scan_array<double>(d.is_tsum, d.is_tile, g.nt);
 }
@@ -1068,12 +1157,17 @@ __global__ __launch_bounds__(WG) void k_med_tail(Grid g, Dev d)
 // rho_th^2 subtracts the source from the binned power at once (appendix
 // "Subtraction algorithm", steps 6-9: the data X^{t+1} no longer holds it).
 // Per-block counts go to arrays; k_snr_tail combines them.
-__global__ __launch_bounds__(WG) void k_snr(Grid g, Dev d, int t)
+__global__ __launch_bounds__(WG) void k_snr(const Slot *S)
 {
     __shared__ uint64_t s_near[WG / 64], s_evals[WG / 64];
     __shared__ uint32_t s_new[WG / 64];
     __shared__ double s_min[WG / 64];
+    const Slot &sl = S[blockIdx.y];
+    if (!sl.active) return;
+    const Grid g = sl.g;
+    const Dev d = sl.d;
     if (d.ctl->done || d.ctl->bad) return;
+    const int t = (int)d.ctl->iter;
     const uint32_t nc = d.ctl->n_cand;
     uint32_t my_new = 0;
     uint64_t near = 0, evals = 0;
@@ -1141,12 +1235,17 @@ __global__ __launch_bounds__(WG) void k_snr(Grid g, Dev d, int t)
 
 // One block: combines the per-block counts, carries of D, dirty tiles of
 // the next body, loop control.
-__global__ __launch_bounds__(WG) void k_snr_tail(Grid g, Dev d, int t, int nblocks)
+__global__ __launch_bounds__(WG) void k_snr_tail(const Slot *S, int nblocks)
 {
     __shared__ uint32_t shu[WG / 64], shx[WG / 64], shs[WG / 64];
     __shared__ uint64_t s64[2 * (WG / 64)];
     __shared__ double sd[WG / 64];
+    const Slot &sl = S[blockIdx.y];
+    if (!sl.active) return;
+    const Grid g = sl.g;
+    const Dev d = sl.d;
     if (d.ctl->done || d.ctl->bad) return;
+    const int t = (int)d.ctl->iter;
     uint32_t nw = 0;
     uint64_t near = 0, evals = 0;
     double minm = INFINITY;
@@ -1227,10 +1326,16 @@ __global__ __launch_bounds__(WG) void k_snr_tail(Grid g, Dev d, int t, int nbloc
         c->units_snr += evals;
         if (minm < __longlong_as_double((long long)c->min_margin))
             c->min_margin = (uint64_t)__double_as_longlong(minm);
+        const uint32_t mi = g.max_iter ? g.max_iter : c->n_cand + 1;
         if (nw == 0) {
             c->done = 1;
             c->n_iter = (uint32_t)t + 1;
+        } else if ((uint32_t)t + 1 >= mi) {
+            c->done = 1;                 // the loop did not settle within max_iter bodies
+            c->status = 6;
+            c->n_iter = (uint32_t)t + 1;
         } else {
+            c->iter = (uint32_t)t + 1;
             c->units_x += ux;
             c->units_med += us;
         }
@@ -1240,8 +1345,12 @@ __global__ __launch_bounds__(WG) void k_snr_tail(Grid g, Dev d, int t, int nbloc
 // ------------------------------------------------------------------ outputs
 
 // ids of the candidates (the catalog is not retained after the run).
-__global__ __launch_bounds__(WG) void k_cand_ids(Dev d, const uint32_t *ids)
+__global__ __launch_bounds__(WG) void k_cand_ids(const Slot *S)
 {
+    const Slot &sl = S[blockIdx.y];
+    if (!sl.active) return;
+    const Dev d = sl.d;
+    const uint32_t *ids = sl.ids;
     const uint32_t nc = d.ctl->n_cand;
     for (uint32_t j = blockIdx.x * WG + threadIdx.x; j < nc; j += gridDim.x * WG)
         d.c_id[j] = ids[d.c_src[j]];
@@ -1249,76 +1358,59 @@ __global__ __launch_bounds__(WG) void k_cand_ids(Dev d, const uint32_t *ids)
 
 // ------------------------------------------------------------------ launchers
 
-static unsigned blocks_for(uint64_t n, unsigned cap = 4096)
+hipError_t launch_grid_tables(const Slot *ds, const Dims &dm, hipStream_t st)
 {
-    uint64_t b = (n + WG - 1) / WG;
-    if (b < 1) b = 1;
-    return (unsigned)(b > cap ? cap : b);
-}
-
-hipError_t launch_grid_tables(const Grid &g, const Dev &d, hipStream_t st)
-{
-    k_sinstr<<<(g.B + WG - 1) / WG, WG, 0, st>>>(g, d.sx);
-    k_inv_prefix<<<g.nt, WG, 0, st>>>(g, d.sx, d.isx_pre, d.isx_tsum);
-    k_scan_f64<<<1, WG, 0, st>>>(d.isx_tsum, d.isx_tile, g.nt);
+    k_sinstr<<<dim3((dm.maxB + WG - 1) / WG, dm.ns), WG, 0, st>>>(ds);
+    k_inv_prefix<<<dim3(dm.maxnt, dm.ns), WG, 0, st>>>(ds);
+    k_sx_scan<<<dim3(1, dm.ns), WG, 0, st>>>(ds);
     return hipGetLastError();
 }
 
-hipError_t launch_reset(const Grid &g, const Dev &d, uint64_t n_src, hipStream_t st)
+hipError_t launch_reset(const Slot *ds, const Dims &dm, hipStream_t st)
 {
-    (void)n_src;
-    k_init_ctl<<<1, 64, 0, st>>>(d.ctl, g.B);
-    k_fill_u32<<<blocks_for(g.nt), WG, 0, st>>>(d.btot, (uint64_t)g.nt, 0u);
-    k_fill_u32<<<blocks_for(g.nt + 1), WG, 0, st>>>(reinterpret_cast<uint32_t *>(d.chgx), g.nt + 1, 0u);
-    k_fill_u32<<<blocks_for(g.nt + 1), WG, 0, st>>>(reinterpret_cast<uint32_t *>(d.chgs), g.nt + 1, 0u);
-    const uint64_t flag_words = ((uint64_t)g.nt + 3) / 4;
-    k_fill_u32<<<blocks_for(flag_words), WG, 0, st>>>(reinterpret_cast<uint32_t *>(d.xdirty), flag_words, 0x01010101u);
-    k_fill_u32<<<blocks_for(flag_words), WG, 0, st>>>(reinterpret_cast<uint32_t *>(d.sdirty), flag_words, 0x01010101u);
+    const unsigned nb = (unsigned)((dm.maxnt + 1 + WG - 1) / WG);
+    k_reset<<<dim3(nb, dm.ns), WG, 0, st>>>(ds);
     return hipGetLastError();
 }
 
-hipError_t launch_prep(const Grid &g, const Dev &d, const float *A, const float *f,
-                       const float *fdot, uint64_t n, hipStream_t st)
+hipError_t launch_prep(const Slot *ds, const Dims &dm, hipStream_t st)
 {
-    const unsigned nblk = (unsigned)((n + PREP_SRC - 1) / PREP_SRC);
-    if (n > 0) {
-        const unsigned na = blocks_for(n, AMAX_BLOCKS);
-        k_amax<<<na, WG, 0, st>>>(A, n, d);
-        k_amax_reduce<<<1, WG, 0, st>>>(d, (int)na);
-        k_prep_count<<<nblk, WG, 0, st>>>(g, d, A, f, fdot, n);
+    if (dm.prep_blocks > 0) {
+        k_amax<<<dim3(dm.amax_blocks, dm.ns), WG, 0, st>>>(ds);
+        k_amax_reduce<<<dim3(1, dm.ns), WG, 0, st>>>(ds, (int)dm.amax_blocks);
+        k_prep_count<<<dim3(dm.prep_blocks, dm.ns), WG, 0, st>>>(ds);
     }
-    k_prep_plan<<<1, WG, 0, st>>>(g, d);
-    if (n > 0) k_prep_scatter<<<nblk, WG, 0, st>>>(g, d, A, f, fdot, n);
-    k_accum<<<d.max_chunks, WG, 0, st>>>(g, d);
-    k_accum_reduce<<<g.nt * (g.tile / RED_BINS), RED_BINS, 0, st>>>(g, d);
-    k_dscan<<<1, WG, 0, st>>>(g, d);
+    k_prep_plan<<<dim3(1, dm.ns), WG, 0, st>>>(ds);
+    if (dm.prep_blocks > 0) k_prep_scatter<<<dim3(dm.prep_blocks, dm.ns), WG, 0, st>>>(ds);
+    k_accum<<<dim3(dm.accum_blocks, dm.ns), WG, 0, st>>>(ds);
+    k_accum_reduce<<<dim3(dm.maxnt * (dm.maxtile / RED_BINS), dm.ns), RED_BINS, 0, st>>>(ds);
+    k_dscan<<<dim3(1, dm.ns), WG, 0, st>>>(ds);
     return hipGetLastError();
 }
 
-hipError_t launch_xupdate(const Grid &g, const Dev &d, hipStream_t st)
+hipError_t launch_xupdate(const Slot *ds, const Dims &dm, hipStream_t st)
 {
-    k_xupdate<<<g.nt, WG, 0, st>>>(g, d);
+    k_xupdate<<<dim3(dm.maxnt, dm.ns), WG, 0, st>>>(ds);
     return hipGetLastError();
 }
 
-hipError_t launch_median(const Grid &g, const Dev &d, hipStream_t st)
+hipError_t launch_median(const Slot *ds, const Dims &dm, hipStream_t st)
 {
-    k_median<<<g.nt, WG, 0, st>>>(g, d);
-    k_med_tail<<<1, WG, 0, st>>>(g, d);
+    k_median<<<dim3(dm.maxnt, dm.ns), WG, 0, st>>>(ds);
+    k_med_tail<<<dim3(1, dm.ns), WG, 0, st>>>(ds);
     return hipGetLastError();
 }
 
-hipError_t launch_snr(const Grid &g, const Dev &d, int t, hipStream_t st)
+hipError_t launch_snr(const Slot *ds, const Dims &dm, hipStream_t st)
 {
-    k_snr<<<SNR_BLOCKS, WG, 0, st>>>(g, d, t);
-    k_snr_tail<<<1, WG, 0, st>>>(g, d, t, SNR_BLOCKS);
+    k_snr<<<dim3(SNR_BLOCKS, dm.ns), WG, 0, st>>>(ds);
+    k_snr_tail<<<dim3(1, dm.ns), WG, 0, st>>>(ds, SNR_BLOCKS);
     return hipGetLastError();
 }
 
-hipError_t launch_outputs(const Grid &g, const Dev &d, const uint32_t *ids, hipStream_t st)
+hipError_t launch_outputs(const Slot *ds, const Dims &dm, hipStream_t st)
 {
-    (void)g;
-    k_cand_ids<<<SNR_BLOCKS, WG, 0, st>>>(d, ids);
+    k_cand_ids<<<dim3(SNR_BLOCKS, dm.ns), WG, 0, st>>>(ds);
     return hipGetLastError();
 }
 

@@ -24,7 +24,10 @@ SPEC_SN, SPEC_X_RESIDUAL, SPEC_S_GAL, SPEC_S_INSTR = 0, 1, 2, 3
 
 EXPORTS = ["gbsub_default_config", "gbsub_create", "gbsub_workspace_size", "gbsub_run",
            "gbsub_spectrum", "gbsub_resolved", "gbsub_destroy", "gbsub_status_str",
-           "gbsub_set_profiling", "gbsub_kernel_stats"]
+           "gbsub_set_profiling", "gbsub_kernel_stats", "gbsub_batch_table_size",
+           "gbsub_batch_create", "gbsub_batch_admit", "gbsub_batch_step", "gbsub_batch_poll",
+           "gbsub_batch_retire", "gbsub_batch_destroy"]
+SLOT_RUNNING, SLOT_SETTLED, SLOT_MAXITER, SLOT_INVALID, SLOT_FREE = 0, 1, 2, 3, 255
 
 
 class GbsubError(RuntimeError):
@@ -93,8 +96,20 @@ def load(path: str | None = None):
     L.gbsub_status_str.restype = C.c_char_p
     L.gbsub_set_profiling.argtypes = [C.c_void_p, C.c_int]
     L.gbsub_kernel_stats.argtypes = [C.c_void_p, C.c_void_p, C.c_uint32, C.POINTER(C.c_uint32)]
+    L.gbsub_batch_table_size.argtypes = [C.c_uint32, C.POINTER(C.c_uint64)]
+    L.gbsub_batch_create.argtypes = [C.c_uint32, C.c_void_p, C.c_uint64, C.POINTER(C.c_void_p)]
+    L.gbsub_batch_admit.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(CatalogStruct), C.c_void_p,
+                                    C.c_uint64, C.c_void_p, C.POINTER(C.c_uint32)]
+    L.gbsub_batch_step.argtypes = [C.c_void_p, C.c_uint32, C.c_void_p]
+    L.gbsub_batch_poll.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32,
+                                   C.POINTER(C.c_uint32)]
+    L.gbsub_batch_retire.argtypes = [C.c_void_p, C.c_uint32, C.c_void_p, C.POINTER(SummaryStruct)]
+    L.gbsub_batch_destroy.argtypes = [C.c_void_p]
+    L.gbsub_batch_destroy.restype = None
     for name in ("gbsub_create", "gbsub_workspace_size", "gbsub_run", "gbsub_spectrum",
-                 "gbsub_resolved", "gbsub_set_profiling", "gbsub_kernel_stats"):
+                 "gbsub_resolved", "gbsub_set_profiling", "gbsub_kernel_stats",
+                 "gbsub_batch_table_size", "gbsub_batch_create", "gbsub_batch_admit",
+                 "gbsub_batch_step", "gbsub_batch_poll", "gbsub_batch_retire"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -270,6 +285,85 @@ class Context:
         if st != OK:
             raise GbsubError(st, "gbsub_resolved")
         return ids, it
+
+
+def _summary(s: SummaryStruct) -> Summary:
+    return Summary(s.n_iter, s.n_bins, s.n_candidates, s.n_resolved, s.n_near_threshold,
+                   s.min_rel_margin)
+
+
+class Batch:
+    """Continuous batch of catalogs sharing every loop launch (gbsub_batch_*).
+
+    Each admitted catalog keeps its own :class:`Context` (configuration and,
+    after retirement, results) and its own workspace tensor; the catalog
+    tensors must stay alive until the slot is retired."""
+
+    def __init__(self, max_slots: int, device="cuda"):
+        torch = _torch()
+        self._L = load()
+        need = C.c_uint64()
+        st = self._L.gbsub_batch_table_size(int(max_slots), C.byref(need))
+        if st != OK:
+            raise GbsubError(st, "gbsub_batch_table_size")
+        self.table = torch.empty(need.value + 256, dtype=torch.uint8, device=device)
+        p = (self.table.data_ptr() + 255) & ~255
+        h = C.c_void_p()
+        st = self._L.gbsub_batch_create(int(max_slots), C.c_void_p(p), need.value, C.byref(h))
+        if st != OK:
+            raise GbsubError(st, "gbsub_batch_create")
+        self.h = h
+        self.max_slots = int(max_slots)
+        self.slots = {}        # slot -> (ctx, catalog, workspace)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self._L.gbsub_batch_destroy(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def admit(self, ctx: "Context", cat: DeviceCatalog, ws=None, stream=None) -> int:
+        torch = _torch()
+        ws = ctx.ensure_workspace(cat.n) if ws is None else ws
+        ptr, nbytes = ctx._ws_ptr(ws)
+        sp = (stream or torch.cuda.current_stream()).cuda_stream
+        k = C.c_uint32()
+        cs = cat.struct()
+        st = self._L.gbsub_batch_admit(self.h, ctx.h, C.byref(cs), C.c_void_p(ptr), nbytes,
+                                       C.c_void_p(sp), C.byref(k))
+        if st != OK:
+            raise GbsubError(st, "gbsub_batch_admit")
+        self.slots[k.value] = (ctx, cat, ws)
+        return k.value
+
+    def step(self, n_bodies: int, stream=None):
+        torch = _torch()
+        sp = (stream or torch.cuda.current_stream()).cuda_stream
+        st = self._L.gbsub_batch_step(self.h, int(n_bodies), C.c_void_p(sp))
+        if st != OK:
+            raise GbsubError(st, "gbsub_batch_step")
+
+    def poll(self, stream=None):
+        """(state array uint8 [max_slots], number of running slots)."""
+        torch = _torch()
+        sp = (stream or torch.cuda.current_stream()).cuda_stream
+        state = np.empty(self.max_slots, np.uint8)
+        nr = C.c_uint32()
+        st = self._L.gbsub_batch_poll(self.h, C.c_void_p(sp), state.ctypes.data, self.max_slots,
+                                      C.byref(nr))
+        if st != OK:
+            raise GbsubError(st, "gbsub_batch_poll")
+        return state, nr.value
+
+    def retire(self, slot: int, stream=None):
+        """(status, Summary); the slot's context then holds its results."""
+        torch = _torch()
+        sp = (stream or torch.cuda.current_stream()).cuda_stream
+        s = SummaryStruct()
+        st = self._L.gbsub_batch_retire(self.h, int(slot), C.c_void_p(sp), C.byref(s))
+        self.slots.pop(slot, None)
+        return st, _summary(s)
 
 
 def subtract(cat, run, **kw):
