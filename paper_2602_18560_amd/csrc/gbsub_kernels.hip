@@ -1085,6 +1085,80 @@ __global__ __launch_bounds__(WG) void k_median(const Slot *S)
                 ro[r] = (ws != wp) ? sm.rank[wp] : 0xFFFFFFFFu;
                 ri[r] = (ws != wp) ? sm.rank[wp + W] : 0xFFFFFFFFu;
             }
+            // Moving the pointer to the next active element (position inside
+            // the window [ws, ws + W)).  Equal values sit in position order,
+            // so the inactive members of a run of equal values (a plateau of
+            // X, common where wide tracks overlap or bins are empty) form the
+            // run's two ends; those are passed by a galloping search instead
+            // of one dependent LDS read per element.
+            auto vbits = [&](uint32_t e) -> uint64_t {
+                return (uint64_t)__double_as_longlong(sm.xv[e & 0xFFFu]);
+            };
+            auto next_up = [&](int jj, int ws) -> int {
+                for (;;) {
+                    if (jj >= M - 1) return M - 1;
+                    ++jj;
+                    const uint32_t e = sw[jj];
+                    const uint32_t p = e & 0xFFFu;
+                    if (p - (uint32_t)ws < (uint32_t)W) return jj;
+                    if (jj >= M - 1) return M - 1;
+                    const uint32_t key = e >> POSBITS;
+                    const uint64_t v = vbits(e);
+                    const bool right = p >= (uint32_t)ws;          // inactive: beyond the window's end
+                    // true on a prefix of [jj, M): same value, and still inactive
+                    auto stay = [&](int i) -> bool {
+                        const uint32_t x = sw[i];
+                        return (x >> POSBITS) == key && vbits(x) == v && (right || (x & 0xFFFu) < (uint32_t)ws);
+                    };
+                    if (!stay(jj + 1)) continue;
+                    int a = jj + 1, b = M, s = 1;
+                    for (;;) {
+                        const int c = a + s;
+                        if (c >= M) break;
+                        if (!stay(c)) { b = c; break; }
+                        a = c;
+                        s <<= 1;
+                    }
+                    while (b - a > 1) {
+                        const int c = (a + b) >> 1;
+                        if (stay(c)) a = c; else b = c;
+                    }
+                    jj = a;                                      // [jj .. a] all inactive
+                }
+            };
+            auto next_down = [&](int jj, int ws) -> int {
+                for (;;) {
+                    if (jj <= 0) return 0;
+                    --jj;
+                    const uint32_t e = sw[jj];
+                    const uint32_t p = e & 0xFFFu;
+                    if (p - (uint32_t)ws < (uint32_t)W) return jj;
+                    if (jj <= 0) return 0;
+                    const uint32_t key = e >> POSBITS;
+                    const uint64_t v = vbits(e);
+                    const bool left = p < (uint32_t)ws;            // inactive: before the window's start
+                    // true on a suffix of [0, jj]: same value, and still inactive
+                    auto stay = [&](int i) -> bool {
+                        const uint32_t x = sw[i];
+                        return (x >> POSBITS) == key && vbits(x) == v &&
+                               (left || (x & 0xFFFu) >= (uint32_t)(ws + W));
+                    };
+                    if (!stay(jj - 1)) continue;
+                    int a = jj - 1, b = -1, s = 1;
+                    for (;;) {
+                        const int c = a - s;
+                        if (c < 0) break;
+                        if (!stay(c)) { b = c; break; }
+                        a = c;
+                        s <<= 1;
+                    }
+                    while (a - b > 1) {
+                        const int c = (a + b) >> 1;
+                        if (stay(c)) a = c; else b = c;
+                    }
+                    jj = a;
+                }
+            };
             int js[8];
             js[0] = j;
 #pragma unroll
@@ -1099,11 +1173,8 @@ __global__ __launch_bounds__(WG) void k_median(const Slot *S)
                         if (rout == j) dir = (rin < j) ? -1 : 1;
                         else if (below == h + 1) dir = -1;
                         else if (below == h - 1) dir = 1;
-                        if (dir < 0) {
-                            do { --j; } while (j > 0 && (sw[j] & 0xFFFu) - (uint32_t)ws >= (uint32_t)W);
-                        } else if (dir > 0) {
-                            do { ++j; } while (j < M - 1 && (sw[j] & 0xFFFu) - (uint32_t)ws >= (uint32_t)W);
-                        }
+                        if (dir < 0) j = next_down(j, ws);
+                        else if (dir > 0) j = next_up(j, ws);
                     }
                 }
                 js[r] = j;

@@ -187,3 +187,27 @@ def config5_jobs(n_jobs: int = 2000, rate_hz: float = 1.0, n_lo: float = 1e5, n_
                         window_bins=WINDOW_FOR_YEARS[years])
         jobs.append(Job(j, t, pop, run))
     return jobs
+
+
+def _draw_one(pop: Population):
+    c = draw_catalog(pop)
+    return c.A, c.f, c.fdot, c.id
+
+
+def draw_catalogs(pops, workers: int | None = None):
+    """Draws several catalogs in a pool of processes (same results as
+    ``draw_catalog`` one by one; order follows ``pops``).  Start it before
+    the calling process touches a GPU."""
+    import multiprocessing as mp
+    import os
+    pops = list(pops)
+    workers = max(1, min(workers or min(16, os.cpu_count() or 1), len(pops)))
+    if workers == 1:
+        return [draw_catalog(p) for p in pops]
+    order = sorted(range(len(pops)), key=lambda j: -pops[j].n)     # largest first
+    with mp.get_context("fork").Pool(workers) as pool:
+        res = pool.map(_draw_one, [pops[j] for j in order], chunksize=1)
+    out = [None] * len(pops)
+    for j, (A, f, fd, ids) in zip(order, res):
+        out[j] = Catalog(A, f, fd, ids, pops[j])
+    return out
