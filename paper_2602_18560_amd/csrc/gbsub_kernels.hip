@@ -898,7 +898,7 @@ __global__ __launch_bounds__(WG) void k_median(const Slot *S)
         if (p < M) {
             sm.xv[p] = xr[i];
             const uint64_t b = (uint64_t)__double_as_longlong(xr[i]);
-            mn = b < mn ? b : mn;
+            mn = (b != 0 && b < mn) ? b : mn;          // smallest positive value
             mx = b > mx ? b : mx;
         }
     }
@@ -919,15 +919,20 @@ __global__ __launch_bounds__(WG) void k_median(const Slot *S)
         mn = sm.red[w] < mn ? sm.red[w] : mn;
         mx = sm.red[WG / 64 + w] > mx ? sm.red[WG / 64 + w] : mx;
     }
-    const uint64_t span = mx - mn;
+    // order key: 0 for an empty bin, 1 + (bits - smallest positive bits) >> shift
+    // otherwise (X >= 0, so the fp64 bit patterns are in value order); empty
+    // bins do not stretch the key range of the occupied ones
+    const uint64_t span = mx > mn ? mx - mn : 0;
     const int span_bits = span ? 64 - __clzll(span) : 0;
-    const int shift = span_bits > KEYBITS ? span_bits - KEYBITS : 0;
-    const int passes = (span_bits - shift + 3) / 4;
+    const int shift = span_bits > KEYBITS - 1 ? span_bits - (KEYBITS - 1) : 0;
+    const uint32_t kmax = mx ? 1u + (uint32_t)(span >> shift) : 0u;
+    const int passes = ((kmax ? 32 - __clz(kmax) : 0) + 3) / 4;
 #pragma unroll
     for (int i = 0; i < MCH; ++i) {
         const int p = tid + i * WG;
         if (p < M) {
-            const uint32_t key = (uint32_t)(((uint64_t)__double_as_longlong(xr[i]) - mn) >> shift);
+            const uint64_t b = (uint64_t)__double_as_longlong(xr[i]);
+            const uint32_t key = b ? 1u + (uint32_t)((b - mn) >> shift) : 0u;
             sm.kp[0][p] = (key << POSBITS) | (uint32_t)p;
         }
     }
