@@ -231,21 +231,28 @@ __global__ __launch_bounds__(WG) void k_inv_prefix(const Slot *S)
     if (threadIdx.x == 0) tsum[tile] = tot;
 }
 
-// Exclusive prefix over the tile sums (single block).
+// Exclusive prefix over the tile sums (single block).  Each thread owns a
+// contiguous run of ceil(n / WG) entries: its loads are all issued at once
+// (no chain of per-chunk scans waiting on memory), one block scan combines
+// the run totals, and a second pass over the (cached) run writes the prefix.
 template <typename T>
 DEVI void block_scan_array(const T *in, T *out, int n)
 {
     __shared__ T sh[WG / 64];
-    T carry = zero_t<T>();
-    for (int base = 0; base < n; base += WG) {
-        const int i = base + threadIdx.x;
-        T x = (i < n) ? in[i] : zero_t<T>();
-        T tot;
-        T ex = block_excl_scan(x, sh, &tot);
-        if (i < n) out[i] = add_t(carry, ex);
-        carry = add_t(carry, tot);
+    const int per = (n + WG - 1) / WG;
+    const int b = min((int)threadIdx.x * per, n), e = min(b + per, n);
+    T s = zero_t<T>();
+#pragma unroll 8
+    for (int i = b; i < e; ++i) s = add_t(s, in[i]);
+    T tot;
+    T run = block_excl_scan(s, sh, &tot);
+#pragma unroll 8
+    for (int i = b; i < e; ++i) {
+        const T x = in[i];
+        out[i] = run;
+        run = add_t(run, x);
     }
-    if (threadIdx.x == 0) out[n] = carry;
+    if (threadIdx.x == 0) out[n] = tot;
 }
 
 __global__ __launch_bounds__(WG) void k_sx_scan(const Slot *S)
@@ -701,10 +708,16 @@ __global__ __launch_bounds__(WG) void k_dscan(const Slot *S)
 
 // ------------------------------------------------------------------ X update
 
-// X[k] = 2^L * (Xn[k] + prefix(D)[k]) for the tiles whose X changed.
+// X[k] = 2^L * (Xn[k] + prefix(D)[k]) for the tiles whose X changed.  D and
+// Xn are read and X written in coalesced order; the in-tile prefix runs over
+// thread-contiguous runs staged in LDS (one pad entry per 8 against bank
+// conflicts).
+DEVI int xpad(int i) { return i + (i >> 3); }
+
 __global__ __launch_bounds__(WG) void k_xupdate(const Slot *S)
 {
     __shared__ I128 sh[WG / 64];
+    __shared__ I128 stage[TILE_MAX + TILE_MAX / 8];
     const Slot &sl = S[blockIdx.y];
     if (!sl.active) return;
     const Grid g = sl.g;
@@ -713,25 +726,29 @@ __global__ __launch_bounds__(WG) void k_xupdate(const Slot *S)
     const int tile = blockIdx.x;
     if (tile >= g.nt || !d.xdirty[tile]) return;
     const int L = fx_exp(d.ctl->amax_bits, g.T);
+    const int t0 = tile * g.tile;
+    const int n = min(g.tile, g.B - t0);
     const int R = g.tile / WG;
-    const int base = tile * g.tile + threadIdx.x * R;
-    I128 loc[8];
+    for (int i = threadIdx.x; i < n; i += WG) stage[xpad(i)] = d.D[t0 + i];
+    __syncthreads();
+    const int b = (int)threadIdx.x * R;
     I128 s = zero_t<I128>();
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
-        const int k = base + r;
-        if (r < R && k < g.B) s = i128_add(s, d.D[k]);
-        loc[r] = s;
+        if (r < R && b + r < n) {
+            s = i128_add(s, stage[xpad(b + r)]);
+            stage[xpad(b + r)] = s;
+        }
     }
     I128 tot;
     I128 ex = block_excl_scan(s, sh, &tot);
     ex = i128_add(ex, d.Dcarry[tile]);
 #pragma unroll
-    for (int r = 0; r < 8; ++r) {
-        const int k = base + r;
-        if (r < R && k < g.B)
-            d.X[k] = ldexp(i128_to_double(i128_add(i128_add(ex, loc[r]), d.Xn[k])), L);
-    }
+    for (int r = 0; r < 8; ++r)
+        if (r < R && b + r < n) stage[xpad(b + r)] = i128_add(stage[xpad(b + r)], ex);
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += WG)
+        d.X[t0 + i] = ldexp(i128_to_double(i128_add(stage[xpad(i)], d.Xn[t0 + i])), L);
 }
 
 // ------------------------------------------------------------------ running median
@@ -1354,28 +1371,33 @@ __global__ __launch_bounds__(WG) void k_snr_tail(const Slot *S, int nblocks)
     }
     __syncthreads();
     block_scan_array<I128>(d.Dtile, d.Dcarry, g.nt);
-    uint32_t cx = 0, cs = 0;
+    // dirty flags: prefix sums of the per-tile change counters (difference
+    // arrays), each thread over its own contiguous run of tiles
+    const int per = (g.nt + WG - 1) / WG;
+    const int rb = min((int)threadIdx.x * per, g.nt), re = min(rb + per, g.nt);
+    uint32_t px = 0, ps = 0;
+#pragma unroll 8
+    for (int i = rb; i < re; ++i) {
+        px += (uint32_t)d.chgx[i];
+        ps += (uint32_t)d.chgs[i];
+    }
+    uint32_t tx, ts;
+    uint32_t cx = block_excl_scan(px, shx, &tx);
+    uint32_t cs = block_excl_scan(ps, shs, &ts);
     uint64_t ux = 0, us = 0;
-    for (int base = 0; base < g.nt; base += WG) {
-        const int i = base + threadIdx.x;
-        const int vx = (i < g.nt) ? d.chgx[i] : 0;
-        const int vs = (i < g.nt) ? d.chgs[i] : 0;
-        uint32_t tx, ts;
-        const uint32_t ex = block_excl_scan((uint32_t)vx, shx, &tx);
-        const uint32_t es = block_excl_scan((uint32_t)vs, shs, &ts);
-        if (i < g.nt) {
-            const bool dx = (int32_t)(cx + ex + (uint32_t)vx) > 0;
-            const bool ds = (int32_t)(cs + es + (uint32_t)vs) > 0;
-            d.xdirty[i] = dx;
-            d.sdirty[i] = ds;
-            const int width = min(g.tile, g.B - i * g.tile);
-            ux += dx ? width : 0;
-            us += ds ? width : 0;
-            d.chgx[i] = 0;
-            d.chgs[i] = 0;
-        }
-        cx += tx;
-        cs += ts;
+#pragma unroll 8
+    for (int i = rb; i < re; ++i) {
+        cx += (uint32_t)d.chgx[i];
+        cs += (uint32_t)d.chgs[i];
+        const bool dx = (int32_t)cx > 0;
+        const bool ds = (int32_t)cs > 0;
+        d.xdirty[i] = dx;
+        d.sdirty[i] = ds;
+        const int width = min(g.tile, g.B - i * g.tile);
+        ux += dx ? width : 0;
+        us += ds ? width : 0;
+        d.chgx[i] = 0;
+        d.chgs[i] = 0;
     }
     for (int s = 32; s >= 1; s >>= 1) {
         ux += (uint64_t)__shfl_xor((long long)ux, s, 64);
