@@ -111,7 +111,7 @@ DEVI T wave_incl_scan(T x)
 
 // Exclusive scan across the WG threads of a block; *total gets the block sum.
 // `sh` must hold WG/64 elements.  Contains __syncthreads().
-template <typename T>
+template <typename T, int NT = WG>
 DEVI T block_excl_scan(T x, T *sh, T *total)
 {
     const int lane = lane_id(), wave = threadIdx.x >> 6;
@@ -120,7 +120,7 @@ DEVI T block_excl_scan(T x, T *sh, T *total)
     __syncthreads();
     T pre = zero_t<T>(), tot = zero_t<T>();
 #pragma unroll
-    for (int w = 0; w < WG / 64; ++w) {
+    for (int w = 0; w < NT / 64; ++w) {
         if (w < wave) pre = add_t(pre, sh[w]);
         tot = add_t(tot, sh[w]);
     }
@@ -759,13 +759,16 @@ __global__ __launch_bounds__(WG) void k_xupdate(const Slot *S)
 // (tile + W - 1 bins) is loaded once into LDS and sorted there: a stable LSD
 // radix sort on a per-tile 20-bit order key (the fp64 bit pattern minus the
 // tile minimum, shifted), then an exact repair that orders equal keys by
-// the full fp64 value.  Each thread owns R = tile/256 consecutive outputs: it
+// the full fp64 value.  Each of the 512 threads owns R = tile/512 (at most
+// 4) consecutive outputs: it
 // locates the median of its first window through a 2-D count table
 // (positions x sorted ranks) and slides the window one bin at a time,
 // moving the median pointer along the sorted order when the count of active
 // elements below it changes.  Selection is exact: no arithmetic touches X.
 
-constexpr int MCH = MMAX / WG;             // union elements per thread in the sort
+constexpr int MWG = 512;                    // threads of a median block
+constexpr int RMAX = TILE_MAX / MWG;        // outputs per thread, at most
+constexpr int MCH = MMAX / MWG;             // union elements per thread in the sort
 constexpr int NCMAX = MMAX / CHP;          // start-table rows (+1)
 constexpr int NBMAX = MMAX / RBS;          // start-table columns (+1)
 constexpr int TLD = NBMAX + 1;             // start-table row stride (u16)
@@ -776,12 +779,13 @@ struct MedianSmem {
     uint32_t kp[2][MMAX];                  // sort words: key << POSBITS | position
     uint16_t rank[MMAX];                   // sorted index of each position
     union {
-        uint16_t off[16 * WG];             // radix: per-thread digit offsets
+        uint16_t off[16 * MWG];             // radix: per-thread digit offsets
         uint16_t tbl[(NCMAX + 1) * TLD];   // start table
+        double stage[TILE_MAX];            // outputs, for coalesced stores
     } u;
-    uint32_t wsc[(WG / 64) * TWORDS];      // cross-wave scan exchange
-    uint64_t red[2 * (WG / 64)];
-    double dsh[WG / 64];
+    uint32_t wsc[(MWG / 64 + 1) * TWORDS];  // cross-wave scan exchange
+    uint64_t red[2 * (MWG / 64)];
+    double dsh[MWG / 64];
     int flag;
 };
 
@@ -799,11 +803,15 @@ DEVI uint32_t wave_scan_u32(uint32_t v)
 }
 
 // Block-wide exclusive scan of NW words per thread (fields must not
-// overflow); tot[] receives the block totals.  Contains two barriers.
+// overflow); tot[] receives the block totals.  The per-wave totals are
+// combined by NW threads (one word each), so a thread keeps only its own
+// words in registers.  Contains two barriers; `wsc` holds (MWG/64 + 1) * NW
+// words and may be rewritten only after a further barrier.
 template <int NW>
 DEVI void block_scan_words(const uint32_t (&w)[NW], uint32_t (&ex)[NW], uint32_t (&tot)[NW],
                            uint32_t *wsc)
 {
+    constexpr int NV = MWG / 64;
     const int lane = lane_id(), wave = threadIdx.x >> 6;
     uint32_t inc[NW];
 #pragma unroll
@@ -813,19 +821,23 @@ DEVI void block_scan_words(const uint32_t (&w)[NW], uint32_t (&ex)[NW], uint32_t
         for (int j = 0; j < NW; ++j) wsc[wave * NW + j] = inc[j];
     }
     __syncthreads();
+    if ((int)threadIdx.x < NW) {
+        const int j = threadIdx.x;
+        uint32_t run = 0;
 #pragma unroll
-    for (int j = 0; j < NW; ++j) {
-        uint32_t pre = 0, t = 0;
-#pragma unroll
-        for (int v = 0; v < WG / 64; ++v) {
+        for (int v = 0; v < NV; ++v) {
             const uint32_t x = wsc[v * NW + j];
-            pre += (v < wave) ? x : 0u;
-            t += x;
+            wsc[v * NW + j] = run;
+            run += x;
         }
-        ex[j] = pre + inc[j] - w[j];
-        tot[j] = t;
+        wsc[NV * NW + j] = run;
     }
     __syncthreads();
+#pragma unroll
+    for (int j = 0; j < NW; ++j) {
+        ex[j] = wsc[wave * NW + j] + inc[j] - w[j];
+        tot[j] = wsc[NV * NW + j];
+    }
 }
 
 // Stable LSD radix sort of the M words in sm.kp[0] by bits [POSBITS,
@@ -835,7 +847,7 @@ DEVI void block_scan_words(const uint32_t (&w)[NW], uint32_t (&ex)[NW], uint32_t
 DEVI int radix_sort_tile(MedianSmem &sm, int M, int passes)
 {
     const int tid = threadIdx.x;
-    const int CH = (M + WG - 1) / WG;
+    const int CH = (M + MWG - 1) / MWG;
     const int beg = tid * CH;
     int in = 0;
     for (int ps = 0; ps < passes; ++ps) {
@@ -863,9 +875,9 @@ DEVI int radix_sort_tile(MedianSmem &sm, int M, int passes)
         uint32_t run = 0;
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
-            sm.u.off[(2 * j) * WG + tid] = (uint16_t)(run + (ex[j] & 0xFFFFu));
+            sm.u.off[(2 * j) * MWG + tid] = (uint16_t)(run + (ex[j] & 0xFFFFu));
             run += tot[j] & 0xFFFFu;
-            sm.u.off[(2 * j + 1) * WG + tid] = (uint16_t)(run + (ex[j] >> 16));
+            sm.u.off[(2 * j + 1) * MWG + tid] = (uint16_t)(run + (ex[j] >> 16));
             run += tot[j] >> 16;
         }
         // offsets are private to the thread: no barrier before reading them
@@ -873,7 +885,7 @@ DEVI int radix_sort_tile(MedianSmem &sm, int M, int passes)
         for (int i = 0; i < MCH; ++i) {
             if (i < CH && beg + i < M) {
                 const uint32_t dg = (e[i] >> sh) & 15u;
-                kout[sm.u.off[dg * WG + tid] + lr[i]] = e[i];
+                kout[sm.u.off[dg * MWG + tid] + lr[i]] = e[i];
             }
         }
         __syncthreads();
@@ -882,7 +894,7 @@ DEVI int radix_sort_tile(MedianSmem &sm, int M, int passes)
     return in;
 }
 
-__global__ __launch_bounds__(WG) void k_median(const Slot *S)
+__global__ __launch_bounds__(MWG, 2) void k_median(const Slot *S)
 {
     __shared__ MedianSmem sm;
     const Slot &sl = S[blockIdx.y];
@@ -905,13 +917,13 @@ __global__ __launch_bounds__(WG) void k_median(const Slot *S)
     double xr[MCH];
 #pragma unroll
     for (int i = 0; i < MCH; ++i) {
-        const int p = tid + i * WG;
+        const int p = tid + i * MWG;
         xr[i] = p < M ? d.X[u0 + p] : 0.0;
     }
     uint64_t mn = ~0ull, mx = 0;
 #pragma unroll
     for (int i = 0; i < MCH; ++i) {
-        const int p = tid + i * WG;
+        const int p = tid + i * MWG;
         if (p < M) {
             sm.xv[p] = xr[i];
             const uint64_t b = (uint64_t)__double_as_longlong(xr[i]);
@@ -927,14 +939,14 @@ __global__ __launch_bounds__(WG) void k_median(const Slot *S)
     }
     if (lane_id() == 0) {
         sm.red[tid >> 6] = mn;
-        sm.red[(WG / 64) + (tid >> 6)] = mx;
+        sm.red[(MWG / 64) + (tid >> 6)] = mx;
     }
     __syncthreads();
     mn = sm.red[0];
-    mx = sm.red[WG / 64];
-    for (int w = 1; w < WG / 64; ++w) {
+    mx = sm.red[MWG / 64];
+    for (int w = 1; w < MWG / 64; ++w) {
         mn = sm.red[w] < mn ? sm.red[w] : mn;
-        mx = sm.red[WG / 64 + w] > mx ? sm.red[WG / 64 + w] : mx;
+        mx = sm.red[MWG / 64 + w] > mx ? sm.red[MWG / 64 + w] : mx;
     }
     // order key: 0 for an empty bin, 1 + (bits - smallest positive bits) >> shift
     // otherwise (X >= 0, so the fp64 bit patterns are in value order); empty
@@ -946,7 +958,7 @@ __global__ __launch_bounds__(WG) void k_median(const Slot *S)
     const int passes = ((kmax ? 32 - __clz(kmax) : 0) + 3) / 4;
 #pragma unroll
     for (int i = 0; i < MCH; ++i) {
-        const int p = tid + i * WG;
+        const int p = tid + i * MWG;
         if (p < M) {
             const uint64_t b = (uint64_t)__double_as_longlong(xr[i]);
             const uint32_t key = b ? 1u + (uint32_t)((b - mn) >> shift) : 0u;
@@ -966,7 +978,7 @@ __global__ __launch_bounds__(WG) void k_median(const Slot *S)
             __syncthreads();
             int swapped = 0;
             for (int par = 0; par < 2; ++par) {
-                for (int i = par + 2 * tid; i + 1 < M; i += 2 * WG) {
+                for (int i = par + 2 * tid; i + 1 < M; i += 2 * MWG) {
                     const uint32_t a = sw[i], b = sw[i + 1];
                     if ((a >> POSBITS) != (b >> POSBITS)) continue;
                     const uint32_t pa = a & 0xFFFu, pb = b & 0xFFFu;
@@ -987,17 +999,17 @@ __global__ __launch_bounds__(WG) void k_median(const Slot *S)
             if (!any) break;
         }
     }
-    for (int i = tid; i < M; i += WG) sm.rank[sw[i] & 0xFFFu] = (uint16_t)i;
+    for (int i = tid; i < M; i += MWG) sm.rank[sw[i] & 0xFFFu] = (uint16_t)i;
     __syncthreads();
 
-    const int R = g.tile / WG;
+    const int R = (g.tile + MWG - 1) / MWG;
     const int kb = t0 + tid * R;
     const int ke = min(kb + R, t1);
-    double med[8];
+    double med[RMAX];
     if (whole) {
         const double m = sm.xv[sw[(B + 1) / 2 - 1] & 0xFFFu];
 #pragma unroll
-        for (int r = 0; r < 8; ++r) med[r] = m;
+        for (int r = 0; r < RMAX; ++r) med[r] = m;
     } else {
         // ---- start table: tbl[c][b] = #{p < c*CHP : rank[p] < b*RBS}
         const int NC = (M + CHP - 1) / CHP, NB = (M + RBS - 1) / RBS;
@@ -1098,9 +1110,9 @@ __global__ __launch_bounds__(WG) void k_median(const Slot *S)
             }
             if (j > M - 1) j = M - 1;          // guards a broken invariant only
             // rank of the element leaving / entering at each step
-            uint32_t ro[8], ri[8];
+            uint32_t ro[RMAX], ri[RMAX];
 #pragma unroll
-            for (int r = 1; r < 8; ++r) {
+            for (int r = 1; r < RMAX; ++r) {
                 const int k = kb + r;
                 const int ws = k < ke ? win_start(k, B, W, h) - u0 : w0;
                 const int wp = k < ke ? win_start(k - 1, B, W, h) - u0 : w0;
@@ -1181,10 +1193,10 @@ __global__ __launch_bounds__(WG) void k_median(const Slot *S)
                     jj = a;
                 }
             };
-            int js[8];
+            int js[RMAX];
             js[0] = j;
 #pragma unroll
-            for (int r = 1; r < 8; ++r) {
+            for (int r = 1; r < RMAX; ++r) {
                 const int k = kb + r;
                 if (k < ke) {
                     const int ws = win_start(k, B, W, h) - u0;
@@ -1202,33 +1214,39 @@ __global__ __launch_bounds__(WG) void k_median(const Slot *S)
                 js[r] = j;
             }
 #pragma unroll
-            for (int r = 0; r < 8; ++r) med[r] = (kb + r < ke) ? sm.xv[sw[js[r]] & 0xFFFu] : 0.0;
+            for (int r = 0; r < RMAX; ++r) med[r] = (kb + r < ke) ? sm.xv[sw[js[r]] & 0xFFFu] : 0.0;
         }
     }
 
-    // ---- S = C med + S_instr on the thread's own outputs; in-tile prefix
-    // of 1/S and the tile sum
-    {
-        double loc[8], s = 0.0;
+    // ---- S = C med + S_instr; in-tile prefix of 1/S and the tile sum.  The
+    // outputs pass through LDS so that global loads and stores are coalesced.
+    __syncthreads();                       // the start table is dead: reuse it
+    double *st = sm.u.stage;
+    const int n = t1 - t0;
 #pragma unroll
-        for (int r = 0; r < 8; ++r) {
-            const int k = kb + r;
-            if (r < R && k < ke) {
-                const double Sk = g.C * med[r] + d.sx[k];
-                d.S[k] = Sk;
-                s += 1.0 / Sk;
-            }
-            loc[r] = s;
-        }
-        double tot;
-        const double ex = block_excl_scan(s, sm.dsh, &tot);
-#pragma unroll
-        for (int r = 0; r < 8; ++r) {
-            const int k = kb + r;
-            if (r < R && k < ke) d.is_pre[k] = ex + loc[r];
-        }
-        if (tid == 0) d.is_tsum[tile] = tot;
+    for (int r = 0; r < RMAX; ++r)
+        if (kb + r < ke) st[kb + r - t0] = med[r];
+    __syncthreads();
+    for (int i = tid; i < n; i += MWG) {
+        const double Sk = g.C * st[i] + d.sx[t0 + i];
+        d.S[t0 + i] = Sk;
+        st[i] = 1.0 / Sk;
     }
+    __syncthreads();
+    double loc[RMAX], s = 0.0;
+#pragma unroll
+    for (int r = 0; r < RMAX; ++r) {
+        if (kb + r < ke) s += st[kb + r - t0];
+        loc[r] = s;
+    }
+    double tot;
+    const double ex = block_excl_scan<double, MWG>(s, sm.dsh, &tot);
+#pragma unroll
+    for (int r = 0; r < RMAX; ++r)
+        if (kb + r < ke) st[kb + r - t0] = ex + loc[r];
+    __syncthreads();
+    for (int i = tid; i < n; i += MWG) d.is_pre[t0 + i] = st[i];
+    if (tid == 0) d.is_tsum[tile] = tot;
 }
 
 // Exclusive prefix of the tile sums of 1/S (one block).
@@ -1494,7 +1512,7 @@ hipError_t launch_xupdate(const Slot *ds, const Dims &dm, hipStream_t st)
 
 hipError_t launch_median(const Slot *ds, const Dims &dm, hipStream_t st)
 {
-    k_median<<<dim3(dm.maxnt, dm.ns), WG, 0, st>>>(ds);
+    k_median<<<dim3(dm.maxnt, dm.ns), MWG, 0, st>>>(ds);
     k_med_tail<<<dim3(1, dm.ns), WG, 0, st>>>(ds);
     return hipGetLastError();
 }
