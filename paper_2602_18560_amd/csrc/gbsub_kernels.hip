@@ -1128,21 +1128,31 @@ __global__ __launch_bounds__(MWG, 2) void k_median(const Slot *S)
             auto vbits = [&](uint32_t e) -> uint64_t {
                 return (uint64_t)__double_as_longlong(sm.xv[e & 0xFFFu]);
             };
+            // Elements are examined four at a time (independent LDS reads);
+            // after four inactive ones, a plateau continuing past them is
+            // crossed by galloping.
             auto next_up = [&](int jj, int ws) -> int {
                 for (;;) {
                     if (jj >= M - 1) return M - 1;
-                    ++jj;
-                    const uint32_t e = sw[jj];
-                    const uint32_t p = e & 0xFFFu;
-                    if (p - (uint32_t)ws < (uint32_t)W) return jj;
+                    uint32_t v[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) v[q] = (jj + 1 + q < M) ? sw[jj + 1 + q] : 0u;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        if (jj + 1 + q >= M) return M - 1;
+                        if ((v[q] & 0xFFFu) - (uint32_t)ws < (uint32_t)W) return jj + 1 + q;
+                    }
+                    jj += 4;                                     // v[3] = sw[jj], inactive
                     if (jj >= M - 1) return M - 1;
+                    const uint32_t e = v[3];
+                    const uint32_t p = e & 0xFFFu;
                     const uint32_t key = e >> POSBITS;
-                    const uint64_t v = vbits(e);
-                    const bool right = p >= (uint32_t)ws;          // inactive: beyond the window's end
+                    const bool right = p >= (uint32_t)ws;          // beyond the window's end
                     // true on a prefix of [jj, M): same value, and still inactive
                     auto stay = [&](int i) -> bool {
                         const uint32_t x = sw[i];
-                        return (x >> POSBITS) == key && vbits(x) == v && (right || (x & 0xFFFu) < (uint32_t)ws);
+                        return (x >> POSBITS) == key && vbits(x) == vbits(e) &&
+                               (right || (x & 0xFFFu) < (uint32_t)ws);
                     };
                     if (!stay(jj + 1)) continue;
                     int a = jj + 1, b = M, s = 1;
@@ -1163,18 +1173,24 @@ __global__ __launch_bounds__(MWG, 2) void k_median(const Slot *S)
             auto next_down = [&](int jj, int ws) -> int {
                 for (;;) {
                     if (jj <= 0) return 0;
-                    --jj;
-                    const uint32_t e = sw[jj];
-                    const uint32_t p = e & 0xFFFu;
-                    if (p - (uint32_t)ws < (uint32_t)W) return jj;
+                    uint32_t v[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) v[q] = (jj - 1 - q >= 0) ? sw[jj - 1 - q] : 0u;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        if (jj - 1 - q < 0) return 0;
+                        if ((v[q] & 0xFFFu) - (uint32_t)ws < (uint32_t)W) return jj - 1 - q;
+                    }
+                    jj -= 4;                                     // v[3] = sw[jj], inactive
                     if (jj <= 0) return 0;
+                    const uint32_t e = v[3];
+                    const uint32_t p = e & 0xFFFu;
                     const uint32_t key = e >> POSBITS;
-                    const uint64_t v = vbits(e);
-                    const bool left = p < (uint32_t)ws;            // inactive: before the window's start
+                    const bool left = p < (uint32_t)ws;            // before the window's start
                     // true on a suffix of [0, jj]: same value, and still inactive
                     auto stay = [&](int i) -> bool {
                         const uint32_t x = sw[i];
-                        return (x >> POSBITS) == key && vbits(x) == v &&
+                        return (x >> POSBITS) == key && vbits(x) == vbits(e) &&
                                (left || (x & 0xFFFu) >= (uint32_t)(ws + W));
                     };
                     if (!stay(jj - 1)) continue;
