@@ -778,6 +778,8 @@ struct MedianSmem {
     double xv[MMAX];                       // X over the union, position order
     uint32_t kp[2][MMAX];                  // sort words: key << POSBITS | position
     uint16_t rank[MMAX];                   // sorted index of each position
+    uint64_t bm1[MMAX / 16];               // position chunks present in each 16 sorted elements
+    uint64_t bm2[MMAX / 256];              // ... in each 256 sorted elements
     union {
         uint16_t off[16 * MWG];             // radix: per-thread digit offsets
         uint16_t tbl[(NCMAX + 1) * TLD];   // start table
@@ -1000,6 +1002,22 @@ __global__ __launch_bounds__(MWG, 2) void k_median(const Slot *S)
         }
     }
     for (int i = tid; i < M; i += MWG) sm.rank[sw[i] & 0xFFFu] = (uint16_t)i;
+    // skip masks for the walks: bit c of bm1[b] is set iff one of the sorted
+    // elements 16b .. 16b+15 lies in position chunk c (chunks of CW bins)
+    const int CW = (M + 63) / 64;
+    for (int b = tid; b < (M + 15) / 16; b += MWG) {
+        uint64_t m = 0;
+        const int e = min(16 * b + 16, M);
+        for (int i = 16 * b; i < e; ++i) m |= 1ull << ((sw[i] & 0xFFFu) / CW);
+        sm.bm1[b] = m;
+    }
+    __syncthreads();
+    for (int b = tid; b < (M + 255) / 256; b += MWG) {
+        uint64_t m = 0;
+        const int e = min(16 * b + 16, (M + 15) / 16);
+        for (int i = 16 * b; i < e; ++i) m |= sm.bm1[i];
+        sm.bm2[b] = m;
+    }
     __syncthreads();
 
     const int R = (g.tile + MWG - 1) / MWG;
@@ -1120,93 +1138,53 @@ __global__ __launch_bounds__(MWG, 2) void k_median(const Slot *S)
                 ri[r] = (ws != wp) ? sm.rank[wp + W] : 0xFFFFFFFFu;
             }
             // Moving the pointer to the next active element (position inside
-            // the window [ws, ws + W)).  Equal values sit in position order,
-            // so the inactive members of a run of equal values (a plateau of
-            // X, common where wide tracks overlap or bins are empty) form the
-            // run's two ends; those are passed by a galloping search instead
-            // of one dependent LDS read per element.
-            auto vbits = [&](uint32_t e) -> uint64_t {
-                return (uint64_t)__double_as_longlong(sm.xv[e & 0xFFFu]);
+            // the window [ws, ws + W)).  Runs of inactive elements can be
+            // long (where X is piecewise constant, values near the median
+            // come in blocks of neighbouring positions), so blocks of 256
+            // and 16 sorted elements whose positions avoid every chunk the
+            // window touches are skipped whole; otherwise up to four
+            // elements are examined with independent LDS reads.
+            auto wmask = [&](int ws) -> uint64_t {
+                const int clo = ws / CW, chi = (ws + W - 1) / CW;
+                const uint64_t hi = chi >= 63 ? ~0ull : ((1ull << (chi + 1)) - 1);
+                return hi & ~((1ull << clo) - 1);
             };
-            // Elements are examined four at a time (independent LDS reads);
-            // after four inactive ones, a plateau continuing past them is
-            // crossed by galloping.
             auto next_up = [&](int jj, int ws) -> int {
+                const uint64_t wm = wmask(ws);
                 for (;;) {
-                    if (jj >= M - 1) return M - 1;
+                    const int i = jj + 1;
+                    if (i >= M) return M - 1;
+                    const uint64_t m2 = sm.bm2[i >> 8], m1 = sm.bm1[i >> 4];
+                    const int e4 = min(i | 3, M - 1);
                     uint32_t v[4];
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) v[q] = (jj + 1 + q < M) ? sw[jj + 1 + q] : 0u;
+                    for (int q = 0; q < 4; ++q) v[q] = (i + q <= e4) ? sw[i + q] : 0u;
+                    if (!(m2 & wm)) { jj = min(i | 255, M - 1); continue; }
+                    if (!(m1 & wm)) { jj = min(i | 15, M - 1); continue; }
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        if (jj + 1 + q >= M) return M - 1;
-                        if ((v[q] & 0xFFFu) - (uint32_t)ws < (uint32_t)W) return jj + 1 + q;
-                    }
-                    jj += 4;                                     // v[3] = sw[jj], inactive
-                    if (jj >= M - 1) return M - 1;
-                    const uint32_t e = v[3];
-                    const uint32_t p = e & 0xFFFu;
-                    const uint32_t key = e >> POSBITS;
-                    const bool right = p >= (uint32_t)ws;          // beyond the window's end
-                    // true on a prefix of [jj, M): same value, and still inactive
-                    auto stay = [&](int i) -> bool {
-                        const uint32_t x = sw[i];
-                        return (x >> POSBITS) == key && vbits(x) == vbits(e) &&
-                               (right || (x & 0xFFFu) < (uint32_t)ws);
-                    };
-                    if (!stay(jj + 1)) continue;
-                    int a = jj + 1, b = M, s = 1;
-                    for (;;) {
-                        const int c = a + s;
-                        if (c >= M) break;
-                        if (!stay(c)) { b = c; break; }
-                        a = c;
-                        s <<= 1;
-                    }
-                    while (b - a > 1) {
-                        const int c = (a + b) >> 1;
-                        if (stay(c)) a = c; else b = c;
-                    }
-                    jj = a;                                      // [jj .. a] all inactive
+                    for (int q = 0; q < 4; ++q)
+                        if (i + q <= e4 && (v[q] & 0xFFFu) - (uint32_t)ws < (uint32_t)W) return i + q;
+                    if (e4 == M - 1) return M - 1;
+                    jj = e4;
                 }
             };
             auto next_down = [&](int jj, int ws) -> int {
+                const uint64_t wm = wmask(ws);
                 for (;;) {
-                    if (jj <= 0) return 0;
+                    const int i = jj - 1;
+                    if (i < 0) return 0;
+                    const uint64_t m2 = sm.bm2[i >> 8], m1 = sm.bm1[i >> 4];
+                    const int e4 = i & ~3;
                     uint32_t v[4];
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) v[q] = (jj - 1 - q >= 0) ? sw[jj - 1 - q] : 0u;
+                    for (int q = 0; q < 4; ++q) v[q] = (i - q >= e4) ? sw[i - q] : 0u;
+                    if (!(m2 & wm)) { jj = i & ~255; if (jj == 0) return 0; continue; }
+                    if (!(m1 & wm)) { jj = i & ~15; if (jj == 0) return 0; continue; }
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        if (jj - 1 - q < 0) return 0;
-                        if ((v[q] & 0xFFFu) - (uint32_t)ws < (uint32_t)W) return jj - 1 - q;
-                    }
-                    jj -= 4;                                     // v[3] = sw[jj], inactive
-                    if (jj <= 0) return 0;
-                    const uint32_t e = v[3];
-                    const uint32_t p = e & 0xFFFu;
-                    const uint32_t key = e >> POSBITS;
-                    const bool left = p < (uint32_t)ws;            // before the window's start
-                    // true on a suffix of [0, jj]: same value, and still inactive
-                    auto stay = [&](int i) -> bool {
-                        const uint32_t x = sw[i];
-                        return (x >> POSBITS) == key && vbits(x) == vbits(e) &&
-                               (left || (x & 0xFFFu) >= (uint32_t)(ws + W));
-                    };
-                    if (!stay(jj - 1)) continue;
-                    int a = jj - 1, b = -1, s = 1;
-                    for (;;) {
-                        const int c = a - s;
-                        if (c < 0) break;
-                        if (!stay(c)) { b = c; break; }
-                        a = c;
-                        s <<= 1;
-                    }
-                    while (a - b > 1) {
-                        const int c = (a + b) >> 1;
-                        if (stay(c)) a = c; else b = c;
-                    }
-                    jj = a;
+                    for (int q = 0; q < 4; ++q)
+                        if (i - q >= e4 && (v[q] & 0xFFFu) - (uint32_t)ws < (uint32_t)W) return i - q;
+                    if (e4 == 0) return 0;
+                    jj = e4;
                 }
             };
             int js[RMAX];
