@@ -114,8 +114,8 @@ uint64_t carve(const Grid &g, uint64_t n, char *base, Dev *d)
     t.X = (double *)take(B * 8);
     t.S = (double *)take(B * 8);
     t.is_pre = (double *)take(B * 8);
-    t.is_tsum = (double *)take(nt * 8);
-    t.is_tile = (double *)take((nt + 1) * 8);
+    t.is_psum = (double *)take((uint64_t)g.nparts * 8);
+    t.is_part = (double *)take(((uint64_t)g.nparts + 1) * 8);
     t.chgx = (int32_t *)take((nt + 1) * 4);
     t.chgs = (int32_t *)take((nt + 1) * 4);
     t.xdirty = (uint8_t *)take(align_up(nt));
@@ -174,13 +174,19 @@ gbsub_status validate(const gbsub_config *c, Grid *g)
     r.B = (int32_t)((int64_t)b - (int64_t)a + 1);
     r.W = (int32_t)c->window_bins;
     r.h = (r.W - 1) / 2;
-    // tile: outputs + W - 1 must fit the median kernel's LDS union
-    int tile = ((MMAX - (r.W - 1)) / WG) * WG;
-    if (tile > TILE_MAX) tile = TILE_MAX;
-    if (tile < WG) return GBSUB_E_INVALID;
+    // tile: the largest power of two (256 .. TILE_MAX) with outputs + W - 1
+    // inside the median kernel's LDS union; parts of at most PART_MAX bins
+    const int room = MMAX - (r.W - 1);
+    if (room < WG) return GBSUB_E_INVALID;
+    int tile = TILE_MAX;
+    while (tile > room) tile >>= 1;
     r.tile = tile;
     r.nt = (r.B + tile - 1) / tile;
     if (r.nt > NBK_MAX) return GBSUB_E_INVALID;
+    r.part = tile < PART_MAX ? tile : PART_MAX;
+    r.np = tile / r.part;
+    r.nparts = (r.B + r.part - 1) / r.part;
+    r.split_tiles = (uint32_t)(SPLIT_BLOCKS / r.np);
     r.track_single = c->track_model == GBSUB_TRACK_SINGLE;
     r.T = c->t_obs_s;
     r.C = c->median_scale;
@@ -225,6 +231,7 @@ Dims dims_of(const Slot &sl)
     dm.maxB = sl.g.B;
     dm.maxnt = sl.g.nt;
     dm.maxtile = sl.g.tile;
+    dm.maxparts = sl.g.nparts;
     dm.prep_blocks = (uint32_t)((sl.n + PREP_SRC - 1) / PREP_SRC);
     dm.accum_blocks = sl.d.max_chunks;
     dm.amax_blocks = blocks_for(sl.n, AMAX_BLOCKS);
@@ -236,6 +243,7 @@ void widen(Dims &a, const Dims &b)
     a.maxB = std::max(a.maxB, b.maxB);
     a.maxnt = std::max(a.maxnt, b.maxnt);
     a.maxtile = std::max(a.maxtile, b.maxtile);
+    a.maxparts = std::max(a.maxparts, b.maxparts);
     a.prep_blocks = std::max(a.prep_blocks, b.prep_blocks);
     a.accum_blocks = std::max(a.accum_blocks, b.accum_blocks);
     a.amax_blocks = std::max(a.amax_blocks, b.amax_blocks);
@@ -560,7 +568,8 @@ struct gbsub_batch {
 namespace {
 bool same_dims(const Dims &a, const Dims &b)
 {
-    return a.ns == b.ns && a.maxB == b.maxB && a.maxnt == b.maxnt && a.maxtile == b.maxtile;
+    return a.ns == b.ns && a.maxB == b.maxB && a.maxnt == b.maxnt && a.maxtile == b.maxtile &&
+           a.maxparts == b.maxparts;
 }
 
 void drop_graph(gbsub_batch *b)
@@ -655,6 +664,9 @@ gbsub_status gbsub_batch_admit(gbsub_batch *b, gbsub_ctx *c, const gbsub_catalog
     Dev d;
     carve(c->g, cat->n, (char *)ws, &d);
     b->host_table[k] = make_slot(c->g, d, cat);
+    // the median splits tiles only while the whole batch would still fit
+    // SPLIT_BLOCKS blocks
+    b->host_table[k].g.split_tiles = (uint32_t)(SPLIT_BLOCKS / (c->g.np * b->max_slots));
     const Dims one = dims_of(b->host_table[k]);
     Slot *ds = b->table + k;
     hipError_t e = hipMemcpyAsync(ds, &b->host_table[k], sizeof(Slot), hipMemcpyHostToDevice, st);

@@ -22,6 +22,8 @@ constexpr int KEYBITS = 20;        // bits of the per-tile order key of the medi
 constexpr int POSBITS = 12;        // sort word = key << 12 | position (MMAX <= 4096)
 constexpr int CHP = 16;            // median start table: positions per row
 constexpr int RBS = 64;            // median start table: sorted ranks per column
+constexpr int PART_MAX = 512;      // outputs of a median block in split mode (prefix-of-1/S granule)
+constexpr int SPLIT_BLOCKS = 512;  // split the median into parts while dirty tiles x parts fit this
 
 // Signed 128-bit fixed-point accumulator (two's complement: hi*2^64 + lo).
 // Every power is accumulated as an exact integer multiple of 2^L, so sums
@@ -49,7 +51,7 @@ struct Ctl {
     uint64_t units_med;      // median outputs computed by k_median
     uint64_t units_snr;      // candidate evaluations by k_snr
     uint32_t status;         // 0 running/settled, 6 = max_iter reached with sources still resolving
-    uint32_t pad1;
+    uint32_t med_split;      // next median launch: one block per part (1) or per tile (0)
 };
 
 // Kernels that the profiling mode times separately.
@@ -59,9 +61,14 @@ struct Grid {
     int32_t B;               // bins
     int32_t W;               // window (odd)
     int32_t h;               // (W-1)/2
-    int32_t tile;            // bins per tile (multiple of WG)
+    int32_t tile;            // bins per tile (power of two, 256 .. TILE_MAX)
     int32_t nt;              // tiles = ceil(B / tile)
+    int32_t part;            // bins per part: min(tile, PART_MAX)
+    int32_t np;              // parts per tile
+    int32_t nparts;          // parts = ceil(B / part)
+    uint32_t split_tiles;    // median in split mode while at most this many tiles are dirty
     int32_t track_single;    // 1: every source occupies one bin
+    int32_t pad0;
     int64_t k0;              // first grid index
     double T;                // observation time
     double C;                // median scale
@@ -87,9 +94,9 @@ struct Dev {
     I128 *Dcarry;            // [nt+1] exclusive prefix of Dtile
     double *X;               // [B]    X^t
     double *S;               // [B]    S^t
-    double *is_pre;          // [B]    inclusive prefix of 1/S^t inside each tile
-    double *is_tsum;         // [nt]   tile sums of 1/S^t
-    double *is_tile;         // [nt+1] exclusive prefix of the tile sums
+    double *is_pre;          // [B]    inclusive prefix of 1/S^t inside each part
+    double *is_psum;         // [nparts]   part sums of 1/S^t
+    double *is_part;         // [nparts+1] exclusive prefix of the part sums
     int32_t *chgx;           // [nt+1] tiles whose X changes (difference counters)
     int32_t *chgs;           // [nt+1] tiles whose S must be recomputed
     uint8_t *xdirty;         // [nt]
@@ -140,7 +147,7 @@ struct Slot {
 // Launch extents: the largest per-slot block counts of a set of slots.
 struct Dims {
     int ns;                  // slots (gridDim.y)
-    int maxB, maxnt, maxtile;
+    int maxB, maxnt, maxtile, maxparts;
     uint32_t prep_blocks, accum_blocks, amax_blocks;
 };
 

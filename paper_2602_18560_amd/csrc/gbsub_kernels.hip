@@ -292,6 +292,7 @@ __global__ __launch_bounds__(WG) void k_reset(const Slot *S)
         c->units_med = (uint64_t)g.B;
         c->units_snr = 0;
         c->status = 0;
+        c->med_split = (uint32_t)g.nt <= g.split_tiles;   // every tile is dirty
     }
     for (int i = blockIdx.x * WG + threadIdx.x; i <= g.nt; i += gridDim.x * WG) {
         if (i < g.nt) {
@@ -904,12 +905,18 @@ __global__ __launch_bounds__(MWG, 2) void k_median(const Slot *S)
     const Grid g = sl.g;
     const Dev d = sl.d;
     if (d.ctl->done || d.ctl->bad) return;
-    const int tile = blockIdx.x, tid = threadIdx.x;
+    const int tid = threadIdx.x;
     const int B = g.B, W = g.W, h = g.h;
-    if (tile >= g.nt || !d.sdirty[tile]) return;
+    // One block per tile, or (split mode, chosen by the previous body's tail
+    // when few tiles are dirty) one block per part: more, shorter blocks.
+    const bool split = d.ctl->med_split != 0;
+    const int span = split ? g.part : g.tile;
+    const int blk = blockIdx.x;
+    const int tile = split ? blk / g.np : blk;
+    if (tile >= g.nt || blk * span >= B || !d.sdirty[tile]) return;
 
-    const int t0 = tile * g.tile;
-    const int t1 = min(t0 + g.tile, B);
+    const int t0 = blk * span;
+    const int t1 = min(t0 + span, B);
     const bool whole = B < W;
     const int u0 = whole ? 0 : win_start(t0, B, W, h);
     const int u1 = whole ? B - 1 : win_start(t1 - 1, B, W, h) + W - 1;
@@ -953,10 +960,10 @@ __global__ __launch_bounds__(MWG, 2) void k_median(const Slot *S)
     // order key: 0 for an empty bin, 1 + (bits - smallest positive bits) >> shift
     // otherwise (X >= 0, so the fp64 bit patterns are in value order); empty
     // bins do not stretch the key range of the occupied ones
-    const uint64_t span = mx > mn ? mx - mn : 0;
-    const int span_bits = span ? 64 - __clzll(span) : 0;
+    const uint64_t vspan = mx > mn ? mx - mn : 0;
+    const int span_bits = vspan ? 64 - __clzll(vspan) : 0;
     const int shift = span_bits > KEYBITS - 1 ? span_bits - (KEYBITS - 1) : 0;
-    const uint32_t kmax = mx ? 1u + (uint32_t)(span >> shift) : 0u;
+    const uint32_t kmax = mx ? 1u + (uint32_t)(vspan >> shift) : 0u;
     const int passes = ((kmax ? 32 - __clz(kmax) : 0) + 3) / 4;
 #pragma unroll
     for (int i = 0; i < MCH; ++i) {
@@ -1020,7 +1027,7 @@ __global__ __launch_bounds__(MWG, 2) void k_median(const Slot *S)
     }
     __syncthreads();
 
-    const int R = (g.tile + MWG - 1) / MWG;
+    const int R = (span + MWG - 1) / MWG;
     const int kb = t0 + tid * R;
     const int ke = min(kb + R, t1);
     double med[RMAX];
@@ -1233,14 +1240,32 @@ __global__ __launch_bounds__(MWG, 2) void k_median(const Slot *S)
         if (kb + r < ke) s += st[kb + r - t0];
         loc[r] = s;
     }
-    double tot;
-    const double ex = block_excl_scan<double, MWG>(s, sm.dsh, &tot);
+    // exclusive scan restarted at every part (part / R threads, whole waves)
+    const int lane = lane_id(), wave = tid >> 6;
+    const int segw = (g.part / R) >> 6;
+    const double inc = wave_incl_scan(s);
+    double exw = shfl_up_t(inc, 1);
+    if (lane == 0) exw = 0.0;
+    if (lane == 63) sm.dsh[wave] = inc;
+    __syncthreads();
+    const int ws0 = (wave / segw) * segw;
+    double pre = 0.0, tot = 0.0;
+#pragma unroll
+    for (int w = 0; w < MWG / 64; ++w) {
+        const double x = sm.dsh[w];
+        if (w >= ws0 && w < wave) pre += x;
+        if (w >= ws0 && w < ws0 + segw) tot += x;
+    }
+    const double ex = pre + exw;
 #pragma unroll
     for (int r = 0; r < RMAX; ++r)
         if (kb + r < ke) st[kb + r - t0] = ex + loc[r];
+    if ((tid & (segw * 64 - 1)) == 0) {
+        const int p0 = t0 + (tid / (segw * 64)) * g.part;
+        if (p0 < t1) d.is_psum[p0 / g.part] = tot;
+    }
     __syncthreads();
     for (int i = tid; i < n; i += MWG) d.is_pre[t0 + i] = st[i];
-    if (tid == 0) d.is_tsum[tile] = tot;
 }
 
 // Exclusive prefix of the tile sums of 1/S (one block).
@@ -1252,7 +1277,7 @@ __global__ __launch_bounds__(WG) void k_med_tail(const Slot *S)
     const Dev d = sl.d;
 
     if (d.ctl->done || d.ctl->bad) return;
-    block_scan_array<double>(d.is_tsum, d.is_tile, g.nt);
+    block_scan_array<double>(d.is_psum, d.is_part, g.nparts);
 }
 
 // ------------------------------------------------------------------ SNR, decisions, subtraction
@@ -1282,7 +1307,7 @@ __global__ __launch_bounds__(WG) void k_snr(const Slot *S)
         ++evals;
         const int glo = d.c_glo[j], ghi = d.c_ghi[j];
         const double q = d.c_q[j];
-        const double r2 = (4.0 * q) * range_inv_sum(d.S, d.is_pre, d.is_tile, glo, ghi, g.tile);
+        const double r2 = (4.0 * q) * range_inv_sum(d.S, d.is_pre, d.is_part, glo, ghi, g.part);
         d.c_rho2[j] = r2;
         const double rel = fabs(sqrt(r2) / g.rth - 1.0);
         minm = fmin(minm, rel);
@@ -1397,6 +1422,7 @@ __global__ __launch_bounds__(WG) void k_snr_tail(const Slot *S, int nblocks)
     uint32_t cx = block_excl_scan(px, shx, &tx);
     uint32_t cs = block_excl_scan(ps, shs, &ts);
     uint64_t ux = 0, us = 0;
+    uint32_t nds = 0;
 #pragma unroll 8
     for (int i = rb; i < re; ++i) {
         cx += (uint32_t)d.chgx[i];
@@ -1408,25 +1434,30 @@ __global__ __launch_bounds__(WG) void k_snr_tail(const Slot *S, int nblocks)
         const int width = min(g.tile, g.B - i * g.tile);
         ux += dx ? width : 0;
         us += ds ? width : 0;
+        nds += ds ? 1u : 0u;
         d.chgx[i] = 0;
         d.chgs[i] = 0;
     }
     for (int s = 32; s >= 1; s >>= 1) {
         ux += (uint64_t)__shfl_xor((long long)ux, s, 64);
         us += (uint64_t)__shfl_xor((long long)us, s, 64);
+        nds += (uint32_t)__shfl_xor((int)nds, s, 64);
     }
     __syncthreads();
     if (lane_id() == 0) {
         s64[w] = ux;
         s64[WG / 64 + w] = us;
+        shu[w] = nds;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        ux = 0; us = 0;
+        ux = 0; us = 0; nds = 0;
         for (int v = 0; v < WG / 64; ++v) {
             ux += s64[v];
             us += s64[WG / 64 + v];
+            nds += shu[v];
         }
+        d.ctl->med_split = nds <= g.split_tiles;
         d.chgx[g.nt] = 0;
         d.chgs[g.nt] = 0;
         Ctl *c = d.ctl;
@@ -1506,7 +1537,7 @@ hipError_t launch_xupdate(const Slot *ds, const Dims &dm, hipStream_t st)
 
 hipError_t launch_median(const Slot *ds, const Dims &dm, hipStream_t st)
 {
-    k_median<<<dim3(dm.maxnt, dm.ns), MWG, 0, st>>>(ds);
+    k_median<<<dim3(dm.maxparts, dm.ns), MWG, 0, st>>>(ds);
     k_med_tail<<<dim3(1, dm.ns), WG, 0, st>>>(ds);
     return hipGetLastError();
 }
