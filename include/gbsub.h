@@ -147,24 +147,42 @@ gbsub_status gbsub_spectrum(const gbsub_ctx *ctx, uint32_t kind, double *out, ui
 gbsub_status gbsub_resolved(const gbsub_ctx *ctx, uint32_t *ids, int32_t *iter_of, uint64_t cap,
                             uint64_t *n, int out_on_device);
 
+/* Kernel families of the profiling mode (bit k of the mask selects family k). */
+enum {
+    GBSUB_KF_TABLES = 0,         /* S_instr and its prefix tables (first run on a workspace) */
+    GBSUB_KF_RESET = 1,          /* per-run state */
+    GBSUB_KF_PREP = 2,           /* candidate cut, binning, fixed-point accumulation */
+    GBSUB_KF_XUPDATE = 3,        /* X from the fixed-point accumulators */
+    GBSUB_KF_MEDIAN = 4,         /* running median and S = C med + S_instr */
+    GBSUB_KF_MEDIAN_TAIL = 5,    /* prefix of the part sums of 1/S */
+    GBSUB_KF_SNR = 6,            /* rho^2, decisions, subtraction */
+    GBSUB_KF_SNR_TAIL = 7,       /* counts, settle test, dirty tiles */
+    GBSUB_KF_OUTPUT = 8,         /* candidate ids */
+    GBSUB_KF_COUNT = 9
+};
+#define GBSUB_PROFILE_ALL 0x1FFu
+
 /* Per-kernel timing of the runs made while profiling is enabled. */
 typedef struct {
     char     name[24];           /* kernel family: "tables", "reset", "prep", "xupdate",
-                                    "median", "snr", "output" */
+                                    "median", "median_tail", "snr", "snr_tail", "output" */
     uint64_t launches;           /* launches that did work (bodies past the settled one excluded) */
     double   total_ms;           /* sum of HIP-event durations on the run's stream */
     double   units;              /* work units processed by those launches */
-    char     unit[16];           /* "bins", "sources", "candidates" */
+    char     unit[16];           /* "bins", "sources", "candidates", "tiles" */
 } gbsub_kernel_stat;
 
-/* Enables (1) or disables (0) profiling and clears the accumulated stats.
- * While enabled, gbsub_run brackets every kernel launch with HIP events on
- * its stream (host-side events only; no device memory). */
-gbsub_status gbsub_set_profiling(gbsub_ctx *ctx, int enable);
+/* Selects the kernel families to time (a mask of 1u << GBSUB_KF_*, 0 = off,
+ * GBSUB_PROFILE_ALL = every family) and clears the accumulated stats.  While
+ * a family is selected, gbsub_run brackets each of its launches with HIP
+ * events on its stream (host-side events only; no device memory); the
+ * events cost some microseconds per launch, so time a run with only the
+ * families of interest selected.  Batched runs are not timed. */
+gbsub_status gbsub_set_profiling(gbsub_ctx *ctx, uint32_t families);
 
 /* Copies up to `cap` accumulated kernel stats into out[] (host pointer);
- * *n (host) receives the number of kernel families (7).  TRUNCATED if
- * cap < 7. */
+ * *n (host) receives the number of kernel families (GBSUB_KF_COUNT).
+ * TRUNCATED if cap < GBSUB_KF_COUNT. */
 gbsub_status gbsub_kernel_stats(const gbsub_ctx *ctx, gbsub_kernel_stat *out, uint32_t cap,
                                 uint32_t *n);
 

@@ -37,8 +37,8 @@ struct gbsub_ctx {
     Ctl *host_ctl;     // pinned
     Slot *host_slot;   // pinned staging of the one-slot table
     int batch_slot;    // slot held in a batch, -1 if none
-    // profiling
-    bool profiling;
+    // profiling: bit k of `profiling` selects kernel family k
+    uint32_t profiling;
     struct Rec { int kid; int64_t t; hipEvent_t a, b; };
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used;
@@ -61,7 +61,7 @@ struct gbsub_ctx {
     template <typename F>
     hipError_t timed(int kid, int64_t t, hipStream_t st, F fn)
     {
-        if (!profiling) return fn();
+        if (!(profiling >> kid & 1u)) return fn();
         hipEvent_t a = next_event(), b = next_event();
         if (!a || !b) return hipErrorOutOfMemory;
         hipError_t e = hipEventRecord(a, st);
@@ -340,7 +340,7 @@ gbsub_status gbsub_create(const gbsub_config *cfg, gbsub_ctx **out)
     c->host_ctl = nullptr;
     c->host_slot = nullptr;
     c->batch_slot = -1;
-    c->profiling = false;
+    c->profiling = 0;
     c->ev_used = 0;
     c->clear_stats();
     if (hipHostMalloc((void **)&c->host_ctl, sizeof(Ctl), hipHostMallocDefault) != hipSuccess ||
@@ -406,7 +406,9 @@ gbsub_status gbsub_run(gbsub_ctx *c, const gbsub_catalog *cat, void *ws, uint64_
             const int64_t ti = (int64_t)(t + i);
             e = c->timed(K_XUPDATE, ti, st, [&] { return launch_xupdate(ds, dm, st); });
             if (e == hipSuccess) e = c->timed(K_MEDIAN, ti, st, [&] { return launch_median(ds, dm, st); });
+            if (e == hipSuccess) e = c->timed(K_MEDTAIL, ti, st, [&] { return launch_med_tail(ds, dm, st); });
             if (e == hipSuccess) e = c->timed(K_SNR, ti, st, [&] { return launch_snr(ds, dm, st); });
+            if (e == hipSuccess) e = c->timed(K_SNRTAIL, ti, st, [&] { return launch_snr_tail(ds, dm, st); });
         }
         t += chunk;
         if (e == hipSuccess) e = hipMemcpyAsync(c->host_ctl, d.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st);
@@ -434,12 +436,16 @@ gbsub_status gbsub_run(gbsub_ctx *c, const gbsub_catalog *cat, void *ws, uint64_
             c->k_launches[r.kid] += 1;
             if (r.kid == K_TABLES) c->k_units[K_TABLES] += (double)g.B;
         }
-        c->k_units[K_PREP] += (double)cat->n;
-        c->k_units[K_RESET] += (double)g.B;
-        c->k_units[K_XUPDATE] += (double)h.units_x;
-        c->k_units[K_MEDIAN] += (double)h.units_med;
-        c->k_units[K_SNR] += (double)h.units_snr;
-        c->k_units[K_OUTPUT] += (double)h.n_cand;
+        const uint32_t m = c->profiling;
+        const double body_tiles = (double)g.nt * (double)h.n_iter;
+        if (m >> K_PREP & 1u) c->k_units[K_PREP] += (double)cat->n;
+        if (m >> K_RESET & 1u) c->k_units[K_RESET] += (double)g.B;
+        if (m >> K_XUPDATE & 1u) c->k_units[K_XUPDATE] += (double)h.units_x;
+        if (m >> K_MEDIAN & 1u) c->k_units[K_MEDIAN] += (double)h.units_med;
+        if (m >> K_MEDTAIL & 1u) c->k_units[K_MEDTAIL] += body_tiles;
+        if (m >> K_SNR & 1u) c->k_units[K_SNR] += (double)h.units_snr;
+        if (m >> K_SNRTAIL & 1u) c->k_units[K_SNRTAIL] += body_tiles;
+        if (m >> K_OUTPUT & 1u) c->k_units[K_OUTPUT] += (double)h.n_cand;
     }
     const gbsub_summary s = summary_of(g, h);
     if (out) *out = s;
@@ -516,10 +522,10 @@ gbsub_status gbsub_resolved(const gbsub_ctx *c, uint32_t *ids, int32_t *iter_of,
     return dev_err(e);
 }
 
-gbsub_status gbsub_set_profiling(gbsub_ctx *c, int enable)
+gbsub_status gbsub_set_profiling(gbsub_ctx *c, uint32_t families)
 {
     if (!c) return GBSUB_E_INVALID;
-    c->profiling = enable != 0;
+    c->profiling = families & ((1u << K_COUNT) - 1u);
     c->clear_stats();
     return GBSUB_OK;
 }
@@ -527,9 +533,10 @@ gbsub_status gbsub_set_profiling(gbsub_ctx *c, int enable)
 gbsub_status gbsub_kernel_stats(const gbsub_ctx *c, gbsub_kernel_stat *out, uint32_t cap, uint32_t *n)
 {
     if (!c || !n) return GBSUB_E_INVALID;
-    static const char *names[K_COUNT] = {"tables", "reset", "prep", "xupdate", "median", "snr", "output"};
-    static const char *units[K_COUNT] = {"bins", "bins", "sources", "bins", "bins", "candidates",
-                                         "candidates"};
+    static const char *names[K_COUNT] = {"tables", "reset", "prep", "xupdate", "median", "median_tail",
+                                         "snr", "snr_tail", "output"};
+    static const char *units[K_COUNT] = {"bins", "bins", "sources", "bins", "bins", "tiles",
+                                         "candidates", "tiles", "candidates"};
     *n = K_COUNT;
     if (cap < (uint32_t)K_COUNT) return GBSUB_E_TRUNCATED;
     if (!out) return GBSUB_E_INVALID;
@@ -586,7 +593,9 @@ hipError_t enqueue_bodies(const Slot *ds, const Dims &dm, uint32_t n, hipStream_
     for (uint32_t i = 0; i < n && e == hipSuccess; ++i) {
         e = launch_xupdate(ds, dm, st);
         if (e == hipSuccess) e = launch_median(ds, dm, st);
+        if (e == hipSuccess) e = launch_med_tail(ds, dm, st);
         if (e == hipSuccess) e = launch_snr(ds, dm, st);
+        if (e == hipSuccess) e = launch_snr_tail(ds, dm, st);
     }
     return e;
 }

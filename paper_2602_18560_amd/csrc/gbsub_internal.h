@@ -8,9 +8,12 @@
 namespace gbs {
 
 constexpr int WG = 256;            // threads per workgroup for every tiled kernel
+constexpr int TWG = 1024;          // threads of the one-block tail kernels
 constexpr int MMAX = 3072;         // median tile: outputs + W - 1 must fit
 constexpr int TILE_MAX = 2048;     // bins per tile (also the binning bucket)
 constexpr int NBK_MAX = 8192;      // tiles the prep histogram can hold (B <= 8192 tiles)
+constexpr int SWG = 512;           // threads of the SNR tail kernel
+constexpr int SPER = NBK_MAX / SWG;   // tiles per thread of the SNR tail kernel
 constexpr int NARROW = 16;         // tracks of <= NARROW bins: SNR summed bin by bin
 constexpr int SNR_BLOCKS = 1024;   // fixed grid of the per-candidate kernels
 constexpr int PREP_SRC = 8192;     // sources per prep block
@@ -55,7 +58,8 @@ struct Ctl {
 };
 
 // Kernels that the profiling mode times separately.
-enum KernelId { K_TABLES = 0, K_RESET, K_PREP, K_XUPDATE, K_MEDIAN, K_SNR, K_OUTPUT, K_COUNT };
+enum KernelId { K_TABLES = 0, K_RESET, K_PREP, K_XUPDATE, K_MEDIAN, K_MEDTAIL, K_SNR, K_SNRTAIL, K_OUTPUT,
+                K_COUNT };
 
 struct Grid {
     int32_t B;               // bins
@@ -158,7 +162,9 @@ hipError_t launch_reset(const Slot *ds, const Dims &dm, hipStream_t st);
 hipError_t launch_prep(const Slot *ds, const Dims &dm, hipStream_t st);
 hipError_t launch_xupdate(const Slot *ds, const Dims &dm, hipStream_t st);
 hipError_t launch_median(const Slot *ds, const Dims &dm, hipStream_t st);
+hipError_t launch_med_tail(const Slot *ds, const Dims &dm, hipStream_t st);
 hipError_t launch_snr(const Slot *ds, const Dims &dm, hipStream_t st);
+hipError_t launch_snr_tail(const Slot *ds, const Dims &dm, hipStream_t st);
 hipError_t launch_outputs(const Slot *ds, const Dims &dm, hipStream_t st);
 
 }  // namespace gbs

@@ -235,17 +235,17 @@ __global__ __launch_bounds__(WG) void k_inv_prefix(const Slot *S)
 // contiguous run of ceil(n / WG) entries: its loads are all issued at once
 // (no chain of per-chunk scans waiting on memory), one block scan combines
 // the run totals, and a second pass over the (cached) run writes the prefix.
-template <typename T>
+template <typename T, int NT = WG>
 DEVI void block_scan_array(const T *in, T *out, int n)
 {
-    __shared__ T sh[WG / 64];
-    const int per = (n + WG - 1) / WG;
+    __shared__ T sh[NT / 64];
+    const int per = (n + NT - 1) / NT;
     const int b = min((int)threadIdx.x * per, n), e = min(b + per, n);
     T s = zero_t<T>();
 #pragma unroll 8
     for (int i = b; i < e; ++i) s = add_t(s, in[i]);
     T tot;
-    T run = block_excl_scan(s, sh, &tot);
+    T run = block_excl_scan<T, NT>(s, sh, &tot);
 #pragma unroll 8
     for (int i = b; i < e; ++i) {
         const T x = in[i];
@@ -1269,7 +1269,7 @@ __global__ __launch_bounds__(MWG, 2) void k_median(const Slot *S)
 }
 
 // Exclusive prefix of the tile sums of 1/S (one block).
-__global__ __launch_bounds__(WG) void k_med_tail(const Slot *S)
+__global__ __launch_bounds__(TWG) void k_med_tail(const Slot *S)
 {
     const Slot &sl = S[blockIdx.y];
     if (!sl.active) return;
@@ -1277,7 +1277,7 @@ __global__ __launch_bounds__(WG) void k_med_tail(const Slot *S)
     const Dev d = sl.d;
 
     if (d.ctl->done || d.ctl->bad) return;
-    block_scan_array<double>(d.is_psum, d.is_part, g.nparts);
+    block_scan_array<double, TWG>(d.is_psum, d.is_part, g.nparts);
 }
 
 // ------------------------------------------------------------------ SNR, decisions, subtraction
@@ -1365,21 +1365,37 @@ __global__ __launch_bounds__(WG) void k_snr(const Slot *S)
 
 // One block: combines the per-block counts, carries of D, dirty tiles of
 // the next body, loop control.
-__global__ __launch_bounds__(WG) void k_snr_tail(const Slot *S, int nblocks)
+__global__ __launch_bounds__(SWG) void k_snr_tail(const Slot *S, int nblocks)
 {
-    __shared__ uint32_t shu[WG / 64], shx[WG / 64], shs[WG / 64];
-    __shared__ uint64_t s64[2 * (WG / 64)];
-    __shared__ double sd[WG / 64];
+    constexpr int NV = SWG / 64;
+    __shared__ uint32_t shu[NV], shx[NV], shs[NV];
+    __shared__ uint64_t s64[2 * NV];
+    __shared__ double sd[NV];
+    __shared__ I128 shi[NV];
     const Slot &sl = S[blockIdx.y];
     if (!sl.active) return;
     const Grid g = sl.g;
     const Dev d = sl.d;
     if (d.ctl->done || d.ctl->bad) return;
     const int t = (int)d.ctl->iter;
+    const int tid = threadIdx.x, lane = lane_id(), w = tid >> 6;
+    // every load first: per-block SNR partials, and this thread's run of
+    // tiles (Dtile sums, change counters)
+    const int per = (g.nt + SWG - 1) / SWG;             // <= SPER
+    const int rb = min(tid * per, g.nt), re = min(rb + per, g.nt);
+    I128 sdt = zero_t<I128>();
+    int32_t vx[SPER], vs[SPER];
+#pragma unroll
+    for (int q = 0; q < SPER; ++q) {
+        const bool in = rb + q < re;
+        if (in) sdt = i128_add(sdt, d.Dtile[rb + q]);
+        vx[q] = in ? d.chgx[rb + q] : 0;
+        vs[q] = in ? d.chgs[rb + q] : 0;
+    }
     uint32_t nw = 0;
     uint64_t near = 0, evals = 0;
     double minm = INFINITY;
-    for (int i = threadIdx.x; i < nblocks; i += WG) {
+    for (int i = tid; i < nblocks; i += SWG) {
         nw += d.b_new[i];
         near += d.b_near[i];
         evals += d.b_evals[i];
@@ -1391,52 +1407,60 @@ __global__ __launch_bounds__(WG) void k_snr_tail(const Slot *S, int nblocks)
         evals += (uint64_t)__shfl_xor((long long)evals, s, 64);
         minm = fmin(minm, __shfl_xor(minm, s, 64));
     }
-    const int w = threadIdx.x >> 6;
-    if (lane_id() == 0) {
+    if (lane == 0) {
         shu[w] = nw;
         s64[w] = near;
-        s64[WG / 64 + w] = evals;
+        s64[NV + w] = evals;
         sd[w] = minm;
     }
     __syncthreads();
     nw = 0; near = 0; evals = 0; minm = INFINITY;
-    for (int v = 0; v < WG / 64; ++v) {
+    for (int v = 0; v < NV; ++v) {
         nw += shu[v];
         near += s64[v];
-        evals += s64[WG / 64 + v];
+        evals += s64[NV + v];
         minm = fmin(minm, sd[v]);
     }
     __syncthreads();
-    block_scan_array<I128>(d.Dtile, d.Dcarry, g.nt);
-    // dirty flags: prefix sums of the per-tile change counters (difference
-    // arrays), each thread over its own contiguous run of tiles
-    const int per = (g.nt + WG - 1) / WG;
-    const int rb = min((int)threadIdx.x * per, g.nt), re = min(rb + per, g.nt);
+    // exclusive prefix of the tile sums of D (exact)
     uint32_t px = 0, ps = 0;
-#pragma unroll 8
-    for (int i = rb; i < re; ++i) {
-        px += (uint32_t)d.chgx[i];
-        ps += (uint32_t)d.chgs[i];
+#pragma unroll
+    for (int q = 0; q < SPER; ++q) {
+        px += (uint32_t)vx[q];
+        ps += (uint32_t)vs[q];
     }
+    I128 dtot;
+    I128 run = block_excl_scan<I128, SWG>(sdt, shi, &dtot);
+    for (int i = rb; i < re; ++i) {           // second pass: the run is in cache
+        const I128 x = d.Dtile[i];
+        d.Dcarry[i] = run;
+        run = i128_add(run, x);
+    }
+    if (tid == 0) d.Dcarry[g.nt] = dtot;
+    // dirty flags: prefix sums of the per-tile change counters (difference
+    // arrays)
     uint32_t tx, ts;
-    uint32_t cx = block_excl_scan(px, shx, &tx);
-    uint32_t cs = block_excl_scan(ps, shs, &ts);
+    uint32_t cx = block_excl_scan<uint32_t, SWG>(px, shx, &tx);
+    uint32_t cs = block_excl_scan<uint32_t, SWG>(ps, shs, &ts);
     uint64_t ux = 0, us = 0;
     uint32_t nds = 0;
-#pragma unroll 8
-    for (int i = rb; i < re; ++i) {
-        cx += (uint32_t)d.chgx[i];
-        cs += (uint32_t)d.chgs[i];
-        const bool dx = (int32_t)cx > 0;
-        const bool ds = (int32_t)cs > 0;
-        d.xdirty[i] = dx;
-        d.sdirty[i] = ds;
-        const int width = min(g.tile, g.B - i * g.tile);
-        ux += dx ? width : 0;
-        us += ds ? width : 0;
-        nds += ds ? 1u : 0u;
-        d.chgx[i] = 0;
-        d.chgs[i] = 0;
+#pragma unroll
+    for (int q = 0; q < SPER; ++q) {
+        const int i = rb + q;
+        if (i < re) {
+            cx += (uint32_t)vx[q];
+            cs += (uint32_t)vs[q];
+            const bool dx = (int32_t)cx > 0;
+            const bool ds = (int32_t)cs > 0;
+            d.xdirty[i] = dx;
+            d.sdirty[i] = ds;
+            const int width = min(g.tile, g.B - i * g.tile);
+            ux += dx ? width : 0;
+            us += ds ? width : 0;
+            nds += ds ? 1u : 0u;
+            d.chgx[i] = 0;
+            d.chgs[i] = 0;
+        }
     }
     for (int s = 32; s >= 1; s >>= 1) {
         ux += (uint64_t)__shfl_xor((long long)ux, s, 64);
@@ -1444,17 +1468,17 @@ __global__ __launch_bounds__(WG) void k_snr_tail(const Slot *S, int nblocks)
         nds += (uint32_t)__shfl_xor((int)nds, s, 64);
     }
     __syncthreads();
-    if (lane_id() == 0) {
+    if (lane == 0) {
         s64[w] = ux;
-        s64[WG / 64 + w] = us;
+        s64[NV + w] = us;
         shu[w] = nds;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
         ux = 0; us = 0; nds = 0;
-        for (int v = 0; v < WG / 64; ++v) {
+        for (int v = 0; v < NV; ++v) {
             ux += s64[v];
-            us += s64[WG / 64 + v];
+            us += s64[NV + v];
             nds += shu[v];
         }
         d.ctl->med_split = nds <= g.split_tiles;
@@ -1538,14 +1562,24 @@ hipError_t launch_xupdate(const Slot *ds, const Dims &dm, hipStream_t st)
 hipError_t launch_median(const Slot *ds, const Dims &dm, hipStream_t st)
 {
     k_median<<<dim3(dm.maxparts, dm.ns), MWG, 0, st>>>(ds);
-    k_med_tail<<<dim3(1, dm.ns), WG, 0, st>>>(ds);
+    return hipGetLastError();
+}
+
+hipError_t launch_med_tail(const Slot *ds, const Dims &dm, hipStream_t st)
+{
+    k_med_tail<<<dim3(1, dm.ns), TWG, 0, st>>>(ds);
     return hipGetLastError();
 }
 
 hipError_t launch_snr(const Slot *ds, const Dims &dm, hipStream_t st)
 {
     k_snr<<<dim3(SNR_BLOCKS, dm.ns), WG, 0, st>>>(ds);
-    k_snr_tail<<<dim3(1, dm.ns), WG, 0, st>>>(ds, SNR_BLOCKS);
+    return hipGetLastError();
+}
+
+hipError_t launch_snr_tail(const Slot *ds, const Dims &dm, hipStream_t st)
+{
+    k_snr_tail<<<dim3(1, dm.ns), SWG, 0, st>>>(ds, SNR_BLOCKS);
     return hipGetLastError();
 }
 

@@ -28,6 +28,9 @@ EXPORTS = ["gbsub_default_config", "gbsub_create", "gbsub_workspace_size", "gbsu
            "gbsub_batch_create", "gbsub_batch_admit", "gbsub_batch_step", "gbsub_batch_poll",
            "gbsub_batch_retire", "gbsub_batch_destroy"]
 SLOT_RUNNING, SLOT_SETTLED, SLOT_MAXITER, SLOT_INVALID, SLOT_FREE = 0, 1, 2, 3, 255
+(KF_TABLES, KF_RESET, KF_PREP, KF_XUPDATE, KF_MEDIAN, KF_MEDIAN_TAIL, KF_SNR, KF_SNR_TAIL,
+ KF_OUTPUT) = range(9)
+PROFILE_ALL = 0x1FF
 
 
 class GbsubError(RuntimeError):
@@ -94,7 +97,7 @@ def load(path: str | None = None):
     L.gbsub_destroy.restype = None
     L.gbsub_status_str.argtypes = [C.c_int]
     L.gbsub_status_str.restype = C.c_char_p
-    L.gbsub_set_profiling.argtypes = [C.c_void_p, C.c_int]
+    L.gbsub_set_profiling.argtypes = [C.c_void_p, C.c_uint32]
     L.gbsub_kernel_stats.argtypes = [C.c_void_p, C.c_void_p, C.c_uint32, C.POINTER(C.c_uint32)]
     L.gbsub_batch_table_size.argtypes = [C.c_uint32, C.POINTER(C.c_uint64)]
     L.gbsub_batch_create.argtypes = [C.c_uint32, C.c_void_p, C.c_uint64, C.POINTER(C.c_void_p)]
@@ -256,8 +259,11 @@ class Context:
             raise GbsubError(st, "gbsub_spectrum")
         return buf
 
-    def set_profiling(self, on: bool = True):
-        st = self._L.gbsub_set_profiling(self.h, 1 if on else 0)
+    def set_profiling(self, on=True):
+        """True: time every kernel family; False: off; an int: a mask of
+        1 << KF_* (the families to time)."""
+        mask = PROFILE_ALL if on is True else (0 if on is False else int(on))
+        st = self._L.gbsub_set_profiling(self.h, mask)
         if st != OK:
             raise GbsubError(st, "gbsub_set_profiling")
 
