@@ -104,6 +104,7 @@ uint64_t carve(const Grid &g, uint64_t n, char *base, Dev *d)
     t.max_chunks = (uint32_t)(ev_chunks + nt);
     t.max_slots = (uint32_t)(2 * ev_chunks + 2);
     t.sx = (double *)take(B * 8);
+    t.isx = (double *)take(B * 8);
     t.isx_pre = (double *)take(B * 8);
     t.isx_tsum = (double *)take(nt * 8);
     t.isx_tile = (double *)take((nt + 1) * 8);
@@ -130,6 +131,7 @@ uint64_t carve(const Grid &g, uint64_t n, char *base, Dev *d)
     t.ev_val = (int64_t *)take((max_events ? max_events : 1) * 8);
     t.partial = (I128 *)take((uint64_t)t.max_slots * 2 * (uint64_t)g.tile * 16);
     t.amax_part = (uint32_t *)take((uint64_t)AMAX_BLOCKS * 4);
+    t.cbits = (uint64_t *)take(((nn + 63) / 64) * 8);
     t.c_src = (uint32_t *)take(nn * 4);
     t.c_id = (uint32_t *)take(nn * 4);
     t.c_glo = (int32_t *)take(nn * 4);

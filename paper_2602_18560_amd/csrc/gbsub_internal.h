@@ -88,6 +88,7 @@ struct Grid {
 struct Dev {
     // grid tables (kept across runs with the same workspace and grid)
     double *sx;              // [B]    S_instr
+    double *isx;             // [B]    1 / S_instr
     double *isx_pre;         // [B]    inclusive prefix of 1/S_instr inside each tile
     double *isx_tsum;        // [nt]   tile sums of 1/S_instr
     double *isx_tile;        // [nt+1] exclusive prefix of the tile sums
@@ -116,6 +117,7 @@ struct Dev {
     int64_t *ev_val;         // [2n]   signed fixed-point power
     I128 *partial;           // [slots][2][tile] partial sums of the hot tiles
     uint32_t *amax_part;     // [AMAX_BLOCKS]
+    uint64_t *cbits;         // [ceil(n/64)] candidate flags of the sources (count pass)
     // candidates (capacity: all sources)
     uint32_t *c_src;         // source index
     uint32_t *c_id;          // its id (written at the end of a run)

@@ -197,7 +197,9 @@ __global__ __launch_bounds__(WG) void k_sinstr(const Slot *S)
     const int k = blockIdx.x * WG + threadIdx.x;
     if (k >= g.B) return;
     const double f = (double)(g.k0 + k) / g.T;
-    d.sx[k] = sinstr_dev(f, g.oms_pm, g.tm_fm, g.arm_m);
+    const double v = sinstr_dev(f, g.oms_pm, g.tm_fm, g.arm_m);
+    d.sx[k] = v;
+    d.isx[k] = 1.0 / v;
 }
 
 // In-tile inclusive prefix of 1/v and the tile sums (one block per tile).
@@ -327,7 +329,8 @@ struct Trk {
     uint64_t qfx;
 };
 
-DEVI Trk track_of(const Grid &g, const Dev &d, float Af, float Ff, float FDf, int L)
+// Track and per-bin power of one source (no candidate test).
+DEVI Trk track_geom(const Grid &g, float Af, float Ff, float FDf, int L)
 {
     Trk t;
     t.ok = false;
@@ -357,10 +360,26 @@ DEVI Trk track_of(const Grid &g, const Dev &d, float Af, float Ff, float FDf, in
     t.live = true;
     t.glo = (int)gl;
     t.ghi = (int)gh;
-    const double r2 = (4.0 * t.q) * range_inv_sum(d.sx, d.isx_pre, d.isx_tile, t.glo, t.ghi, g.tile);
-    t.cand = r2 >= g.cut2;
     t.qfx = to_fx(t.q, L);
     return t;
+}
+
+// rho_0^2 >= (kappa rho_th)^2 against S_instr.  Short tracks sum the stored
+// reciprocals 1/S_instr bin by bin in ascending order (the same values and
+// order as summing 1/S_instr directly), longer ones use the prefix tables.
+DEVI bool cand_test(const Grid &g, const Dev &d, const Trk &t)
+{
+    if (!t.live) return false;
+    double sum;
+    if (t.glo == t.ghi) {
+        sum = d.isx[t.glo];
+    } else if (t.ghi - t.glo + 1 <= NARROW) {
+        sum = 0.0;
+        for (int k = t.glo; k <= t.ghi; ++k) sum += d.isx[k];
+    } else {
+        sum = range_inv_sum(d.sx, d.isx_pre, d.isx_tile, t.glo, t.ghi, g.tile);
+    }
+    return (4.0 * t.q) * sum >= g.cut2;
 }
 
 // Largest amplitude (fixed-point scale) and validation of A: per-block
@@ -425,19 +444,43 @@ DEVI void k_prep_count_body(Grid g, Dev d, const float *A, const float *F, const
     const int L = fx_exp(d.ctl->amax_bits, g.T);
     const uint64_t base = (uint64_t)blockIdx.x * PREP_SRC;
     uint32_t cc = 0, bad = 0;
-    for (int r = 0; r < PREP_SRC / WG; ++r) {
-        const uint64_t i = base + (uint64_t)r * WG + threadIdx.x;
-        if (i >= n) break;
-        const Trk t = track_of(g, d, A[i], F[i], FD[i], L);
-        if (!t.ok) {
-            bad = 1;
-            continue;
+    // four sources per thread in flight: loads first, then the tracks and
+    // the S_instr gathers of the candidate tests
+    for (int r0 = 0; r0 < PREP_SRC / WG; r0 += 4) {
+        float a[4], f[4], fd[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint64_t i = base + (uint64_t)(r0 + q) * WG + threadIdx.x;
+            const bool in = i < n;
+            a[q] = in ? A[i] : 0.0f;
+            f[q] = in ? F[i] : 1.0f;
+            fd[q] = in ? FD[i] : 0.0f;
         }
-        if (t.live && t.qfx) {
-            atomicAdd(&hist[tile_of(t.glo, g.tile)], 1u);
-            if (t.glo != t.ghi && t.ghi + 1 < g.B) atomicAdd(&hist[tile_of(t.ghi + 1, g.tile)], 1u);
+        Trk t[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) t[q] = track_geom(g, a[q], f[q], fd[q], L);
+        bool cand[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) cand[q] = cand_test(g, d, t[q]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint64_t i = base + (uint64_t)(r0 + q) * WG + threadIdx.x;
+            const bool in = i < n;
+            const bool c = in && t[q].ok && cand[q];
+            const uint64_t m = (uint64_t)__ballot(c);
+            const uint64_t w0 = i - (uint64_t)lane_id();       // first source of this wave
+            if (lane_id() == 0 && w0 < n) d.cbits[w0 >> 6] = m;
+            if (!in) continue;
+            if (!t[q].ok) {
+                bad = 1;
+                continue;
+            }
+            if (t[q].live && t[q].qfx) {
+                atomicAdd(&hist[tile_of(t[q].glo, g.tile)], 1u);
+                if (t[q].glo != t[q].ghi && t[q].ghi + 1 < g.B) atomicAdd(&hist[tile_of(t[q].ghi + 1, g.tile)], 1u);
+            }
+            cc += c;
         }
-        cc += t.cand;
     }
     for (int s = 32; s >= 1; s >>= 1) cc += (uint32_t)__shfl_xor((int)cc, s, 64);
     if (lane_id() == 0 && cc) atomicAdd(&scand, cc);
@@ -515,17 +558,30 @@ DEVI void k_prep_scatter_body(Grid g, Dev d, const float *A, const float *F, con
     __syncthreads();
     const int L = fx_exp(d.ctl->amax_bits, g.T);
     const uint64_t base = (uint64_t)blockIdx.x * PREP_SRC;
+    auto is_cand = [&](uint64_t i) -> bool { return (d.cbits[i >> 6] >> (i & 63)) & 1ull; };
     uint32_t cc = 0;
-    for (int r = 0; r < PREP_SRC / WG; ++r) {
-        const uint64_t i = base + (uint64_t)r * WG + threadIdx.x;
-        if (i >= n) break;
-        const Trk t = track_of(g, d, A[i], F[i], FD[i], L);
-        if (!t.ok) continue;
-        if (t.live && t.qfx) {
-            atomicAdd(&cur[tile_of(t.glo, g.tile)], 1u);
-            if (t.glo != t.ghi && t.ghi + 1 < g.B) atomicAdd(&cur[tile_of(t.ghi + 1, g.tile)], 1u);
+    for (int r0 = 0; r0 < PREP_SRC / WG; r0 += 4) {
+        float a[4], f[4], fd[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint64_t i = base + (uint64_t)(r0 + q) * WG + threadIdx.x;
+            const bool in = i < n;
+            a[q] = in ? A[i] : 0.0f;
+            f[q] = in ? F[i] : 1.0f;
+            fd[q] = in ? FD[i] : 0.0f;
         }
-        cc += t.cand;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint64_t i = base + (uint64_t)(r0 + q) * WG + threadIdx.x;
+            if (i >= n) continue;
+            const Trk t = track_geom(g, a[q], f[q], fd[q], L);
+            if (!t.ok) continue;
+            if (t.live && t.qfx) {
+                atomicAdd(&cur[tile_of(t.glo, g.tile)], 1u);
+                if (t.glo != t.ghi && t.ghi + 1 < g.B) atomicAdd(&cur[tile_of(t.ghi + 1, g.tile)], 1u);
+            }
+            cc += is_cand(i);
+        }
     }
     for (int s = 32; s >= 1; s >>= 1) cc += (uint32_t)__shfl_xor((int)cc, s, 64);
     if (lane_id() == 0 && cc) atomicAdd(&scand, cc);
@@ -537,35 +593,47 @@ DEVI void k_prep_scatter_body(Grid g, Dev d, const float *A, const float *F, con
         scand = 0;
     }
     __syncthreads();
-    for (int r = 0; r < PREP_SRC / WG; ++r) {
-        const uint64_t i = base + (uint64_t)r * WG + threadIdx.x;
-        if (i >= n) break;
-        const Trk t = track_of(g, d, A[i], F[i], FD[i], L);
-        if (!t.ok) continue;
-        if (t.live && t.qfx) {
-            if (t.glo == t.ghi) {
-                const uint32_t p = atomicAdd(&cur[tile_of(t.glo, g.tile)], 1u);
-                d.ev_key[p] = (uint32_t)t.glo;
-                d.ev_val[p] = (int64_t)t.qfx;
-            } else {
-                uint32_t p = atomicAdd(&cur[tile_of(t.glo, g.tile)], 1u);
-                d.ev_key[p] = (uint32_t)t.glo | 0x80000000u;
-                d.ev_val[p] = (int64_t)t.qfx;
-                if (t.ghi + 1 < g.B) {
-                    p = atomicAdd(&cur[tile_of(t.ghi + 1, g.tile)], 1u);
-                    d.ev_key[p] = (uint32_t)(t.ghi + 1) | 0x80000000u;
-                    d.ev_val[p] = -(int64_t)t.qfx;
+    for (int r0 = 0; r0 < PREP_SRC / WG; r0 += 4) {
+        float a[4], f[4], fd[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint64_t i = base + (uint64_t)(r0 + q) * WG + threadIdx.x;
+            const bool in = i < n;
+            a[q] = in ? A[i] : 0.0f;
+            f[q] = in ? F[i] : 1.0f;
+            fd[q] = in ? FD[i] : 0.0f;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint64_t i = base + (uint64_t)(r0 + q) * WG + threadIdx.x;
+            if (i >= n) continue;
+            const Trk t = track_geom(g, a[q], f[q], fd[q], L);
+            if (!t.ok) continue;
+            if (t.live && t.qfx) {
+                if (t.glo == t.ghi) {
+                    const uint32_t p = atomicAdd(&cur[tile_of(t.glo, g.tile)], 1u);
+                    d.ev_key[p] = (uint32_t)t.glo;
+                    d.ev_val[p] = (int64_t)t.qfx;
+                } else {
+                    uint32_t p = atomicAdd(&cur[tile_of(t.glo, g.tile)], 1u);
+                    d.ev_key[p] = (uint32_t)t.glo | 0x80000000u;
+                    d.ev_val[p] = (int64_t)t.qfx;
+                    if (t.ghi + 1 < g.B) {
+                        p = atomicAdd(&cur[tile_of(t.ghi + 1, g.tile)], 1u);
+                        d.ev_key[p] = (uint32_t)(t.ghi + 1) | 0x80000000u;
+                        d.ev_val[p] = -(int64_t)t.qfx;
+                    }
                 }
             }
-        }
-        if (t.cand) {
-            const uint32_t j = cbase + atomicAdd(&scand, 1u);
-            d.c_src[j] = (uint32_t)i;
-            d.c_glo[j] = t.glo;
-            d.c_ghi[j] = t.ghi;
-            d.c_q[j] = t.q;
-            d.c_qfx[j] = t.qfx;
-            d.c_iter[j] = -1;
+            if (is_cand(i)) {
+                const uint32_t j = cbase + atomicAdd(&scand, 1u);
+                d.c_src[j] = (uint32_t)i;
+                d.c_glo[j] = t.glo;
+                d.c_ghi[j] = t.ghi;
+                d.c_q[j] = t.q;
+                d.c_qfx[j] = t.qfx;
+                d.c_iter[j] = -1;
+            }
         }
     }
 }
@@ -598,11 +666,37 @@ DEVI void atomic_add_i128_full(I128 *p, I128 v)
     if (add_hi != 0) atomicAdd((unsigned long long *)&p->hi, (unsigned long long)add_hi);
 }
 
-// Accumulation: block c sums up to ACC_EV events of one tile in LDS.
+// Accumulation: block c sums up to ACC_EV events of one tile in LDS.  Each
+// 64-bit event value v = vh 2^32 + vl (vl in [0, 2^32)) goes into two 64-bit
+// LDS sums with non-returning atomics (no carry to propagate: at most ACC_EV
+// events per block, so |sum vh| < 2^47 and sum vl < 2^48); the exact
+// 128-bit total is sum_vh 2^32 + sum_vl.
+struct SplitAcc {
+    int64_t h[TILE_MAX];
+    uint64_t l[TILE_MAX];
+};
+
+DEVI void split_add(SplitAcc &a, int k, int64_t v)
+{
+    atomicAdd((unsigned long long *)&a.h[k], (unsigned long long)(v >> 32));
+    atomicAdd((unsigned long long *)&a.l[k], (unsigned long long)((uint64_t)v & 0xFFFFFFFFull));
+}
+
+DEVI I128 split_total(const SplitAcc &a, int k)
+{
+    const int64_t h = a.h[k];
+    I128 x;
+    x.lo = (uint64_t)h << 32;
+    x.hi = h >> 32;
+    I128 y;
+    y.lo = a.l[k];
+    y.hi = 0;
+    return i128_add(x, y);
+}
+
 __global__ __launch_bounds__(WG) void k_accum(const Slot *S)
 {
-    __shared__ I128 xn[TILE_MAX];
-    __shared__ I128 dd[TILE_MAX];
+    __shared__ SplitAcc xn, dd;
     __shared__ I128 sh[WG / 64];
     const Slot &sl = S[blockIdx.y];
     if (!sl.active) return;
@@ -623,15 +717,26 @@ __global__ __launch_bounds__(WG) void k_accum(const Slot *S)
     const uint32_t e1 = min(e0 + (uint32_t)ACC_EV, d.bbase[b + 1]);
     const int k0 = b * g.tile;
     for (int k = threadIdx.x; k < g.tile; k += WG) {
-        xn[k].lo = 0; xn[k].hi = 0;
-        dd[k].lo = 0; dd[k].hi = 0;
+        xn.h[k] = 0; xn.l[k] = 0;
+        dd.h[k] = 0; dd.l[k] = 0;
     }
     __syncthreads();
-    for (uint32_t e = e0 + threadIdx.x; e < e1; e += WG) {
-        const uint32_t key = d.ev_key[e];
-        const int64_t v = d.ev_val[e];
-        const int k = (int)(key & 0x7FFFFFFFu) - k0;
-        lds_add_i128((key >> 31) ? &dd[k] : &xn[k], v);
+    // four events per thread in flight
+    for (uint32_t e = e0 + threadIdx.x; e < e1; e += 4 * WG) {
+        uint32_t key[4];
+        int64_t v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint32_t ee = e + (uint32_t)(q * WG);
+            key[q] = ee < e1 ? d.ev_key[ee] : 0u;
+            v[q] = ee < e1 ? d.ev_val[ee] : 0;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (e + (uint32_t)(q * WG) >= e1) continue;
+            const int k = (int)(key[q] & 0x7FFFFFFFu) - k0;
+            split_add((key[q] >> 31) ? dd : xn, k, v[q]);
+        }
     }
     __syncthreads();
     const int nbin = min(g.tile, g.B - k0);
@@ -639,9 +744,10 @@ __global__ __launch_bounds__(WG) void k_accum(const Slot *S)
         I128 s = zero_t<I128>();
         for (int k = threadIdx.x; k < g.tile; k += WG) {
             if (k < nbin) {
-                d.Xn[k0 + k] = xn[k];
-                d.D[k0 + k] = dd[k];
-                s = i128_add(s, dd[k]);
+                const I128 dk = split_total(dd, k);
+                d.Xn[k0 + k] = split_total(xn, k);
+                d.D[k0 + k] = dk;
+                s = i128_add(s, dk);
             }
         }
         I128 tot;
@@ -650,8 +756,8 @@ __global__ __launch_bounds__(WG) void k_accum(const Slot *S)
     } else {
         I128 *slot = d.partial + (size_t)(d.slot_base[b] + ci) * 2 * g.tile;
         for (int k = threadIdx.x; k < g.tile; k += WG) {
-            slot[k] = xn[k];
-            slot[g.tile + k] = dd[k];
+            slot[k] = split_total(xn, k);
+            slot[g.tile + k] = split_total(dd, k);
         }
     }
 }

@@ -68,11 +68,12 @@ _lib = None
 
 
 def load(path: str | None = None):
-    """Load the HIP library (raises if it has not been built)."""
+    """Load the HIP library (raises if it has not been built).  The
+    environment variable GBSUB_LIB names another build of it."""
     global _lib
     if _lib is not None:
         return _lib
-    path = path or LIB_PATH
+    path = path or os.environ.get("GBSUB_LIB") or LIB_PATH
     if not os.path.exists(path):
         raise RuntimeError(f"libgbsub.so not built ({path}); run python -m paper_2602_18560_amd.build")
     # PyTorch ships its own HIP runtime (same soname as ROCm's).  Loading torch
