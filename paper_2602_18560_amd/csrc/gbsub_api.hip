@@ -130,7 +130,6 @@ uint64_t carve(const Grid &g, uint64_t n, char *base, Dev *d)
     t.ev_key = (uint32_t *)take((max_events ? max_events : 1) * 4);
     t.ev_val = (int64_t *)take((max_events ? max_events : 1) * 8);
     t.partial = (I128 *)take((uint64_t)t.max_slots * 2 * (uint64_t)g.tile * 16);
-    t.amax_part = (uint32_t *)take((uint64_t)AMAX_BLOCKS * 4);
     t.cbits = (uint64_t *)take(((nn + 63) / 64) * 8);
     t.c_src = (uint32_t *)take(nn * 4);
     t.c_id = (uint32_t *)take(nn * 4);
@@ -204,13 +203,6 @@ gbsub_status validate(const gbsub_config *c, Grid *g)
     return GBSUB_OK;
 }
 
-unsigned blocks_for(uint64_t n, unsigned cap)
-{
-    uint64_t b = (n + WG - 1) / WG;
-    if (b < 1) b = 1;
-    return (unsigned)(b > cap ? cap : b);
-}
-
 Slot make_slot(const Grid &g, const Dev &d, const gbsub_catalog *cat)
 {
     Slot sl{};
@@ -236,7 +228,6 @@ Dims dims_of(const Slot &sl)
     dm.maxparts = sl.g.nparts;
     dm.prep_blocks = (uint32_t)((sl.n + PREP_SRC - 1) / PREP_SRC);
     dm.accum_blocks = sl.d.max_chunks;
-    dm.amax_blocks = blocks_for(sl.n, AMAX_BLOCKS);
     return dm;
 }
 
@@ -248,7 +239,6 @@ void widen(Dims &a, const Dims &b)
     a.maxparts = std::max(a.maxparts, b.maxparts);
     a.prep_blocks = std::max(a.prep_blocks, b.prep_blocks);
     a.accum_blocks = std::max(a.accum_blocks, b.accum_blocks);
-    a.amax_blocks = std::max(a.amax_blocks, b.amax_blocks);
 }
 
 gbsub_status check_catalog(const gbsub_ctx *c, const gbsub_catalog *cat, void *ws, uint64_t ws_bytes)

@@ -19,7 +19,6 @@ constexpr int SNR_BLOCKS = 1024;   // fixed grid of the per-candidate kernels
 constexpr int PREP_SRC = 8192;     // sources per prep block
 constexpr int ACC_EV = 65536;      // binning events per accumulation block
 constexpr int RED_BINS = 256;      // bins per reduction block of the hot buckets
-constexpr int AMAX_BLOCKS = 1024;  // grid of the amplitude-maximum kernel
 constexpr int NEW_CAP = 1 << 16;   // per-iteration counters kept (iterations beyond: not recorded)
 constexpr int KEYBITS = 20;        // bits of the per-tile order key of the median sort
 constexpr int POSBITS = 12;        // sort word = key << 12 | position (MMAX <= 4096)
@@ -116,7 +115,6 @@ struct Dev {
     uint32_t *ev_key;        // [2n]   bin | (1<<31 for difference events)
     int64_t *ev_val;         // [2n]   signed fixed-point power
     I128 *partial;           // [slots][2][tile] partial sums of the hot tiles
-    uint32_t *amax_part;     // [AMAX_BLOCKS]
     uint64_t *cbits;         // [ceil(n/64)] candidate flags of the sources (count pass)
     // candidates (capacity: all sources)
     uint32_t *c_src;         // source index
@@ -154,7 +152,7 @@ struct Slot {
 struct Dims {
     int ns;                  // slots (gridDim.y)
     int maxB, maxnt, maxtile, maxparts;
-    uint32_t prep_blocks, accum_blocks, amax_blocks;
+    uint32_t prep_blocks, accum_blocks;
 };
 
 // Kernel launchers (gbsub_kernels.hip); all enqueue on `st` and return the

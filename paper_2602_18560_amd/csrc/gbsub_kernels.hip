@@ -2,10 +2,11 @@
 // subtraction.
 //
 // Data layout in HBM (all structure-of-arrays, see gbsub_internal.h):
-//   catalog     A, f, fdot fp32 [n]            read once by k_amax / k_prep
-//   S_instr     sx fp64 [B] + 1/S_instr prefix tables (per grid, cached)
-//   binned power D: 128-bit fixed-point difference array [B+1]; X = prefix(D)
-//   X, S, 1/S prefix: fp64 [B]; tile-level tables [nt+1]
+//   catalog     A, f, fdot fp32 [n]            read by the two prep passes
+//   S_instr     sx, 1/sx fp64 [B] + 1/S_instr prefix tables (per grid, cached)
+//   binned power Xn (one-bin tracks) and D (difference array of wider
+//               tracks): 128-bit fixed point [B], [B+1]; X = Xn + prefix(D)
+//   X, S, in-part prefix of 1/S: fp64 [B]; tile- and part-level tables
 //   candidates  SoA records (source, clipped track, q, q in fixed point, iter)
 //
 // Every per-bin power sum is exact integer arithmetic on multiples of 2^L
@@ -323,23 +324,20 @@ __global__ __launch_bounds__(WG) void k_reset(const Slot *S)
 // tile's bins, hot tiles through partial sums reduced by a last pass.
 
 struct Trk {
-    bool ok, live, cand;
+    bool ok, live;
     int glo, ghi;
     double q;
-    uint64_t qfx;
 };
 
 // Track and per-bin power of one source (no candidate test).
-DEVI Trk track_geom(const Grid &g, float Af, float Ff, float FDf, int L)
+DEVI Trk track_geom(const Grid &g, float Af, float Ff, float FDf)
 {
     Trk t;
     t.ok = false;
     t.live = false;
-    t.cand = false;
     t.glo = 0;
     t.ghi = -1;
     t.q = 0.0;
-    t.qfx = 0;
     const double a = (double)Af, f = (double)Ff, fd = (double)FDf;
     bool ok = isfinite(a) && a >= 0.0 && isfinite(f) && f > 0.0 && isfinite(fd);
     const double P = ((a * a) * g.T) * 0.5;
@@ -353,14 +351,13 @@ DEVI Trk track_geom(const Grid &g, float Af, float Ff, float FDf, int L)
     const int64_t nn = g.track_single ? 1 : 1 + (int64_t)floor(s);
     const int64_t lo = c - (nn - 1) / 2;
     const int64_t hi = lo + nn - 1;
-    t.q = P / (double)nn;
+    t.q = nn == 1 ? P : P / (double)nn;
     const int64_t gl = lo < 0 ? 0 : lo;
     const int64_t gh = hi > g.B - 1 ? g.B - 1 : hi;
     if (gl > gh) return t;
     t.live = true;
     t.glo = (int)gl;
     t.ghi = (int)gh;
-    t.qfx = to_fx(t.q, L);
     return t;
 }
 
@@ -382,68 +379,21 @@ DEVI bool cand_test(const Grid &g, const Dev &d, const Trk &t)
     return (4.0 * t.q) * sum >= g.cut2;
 }
 
-// Largest amplitude (fixed-point scale) and validation of A: per-block
-// maxima, then one block reduces them.
-__global__ __launch_bounds__(WG) void k_amax(const Slot *S)
-{
-    __shared__ uint32_t sm[WG / 64];
-    const Slot &sl = S[blockIdx.y];
-    if (!sl.active) return;
-    const Dev d = sl.d;
-    const float *A = sl.A;
-    const uint64_t n = sl.n;
-    uint32_t m = 0, bad = 0;
-    for (uint64_t i = (uint64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (uint64_t)gridDim.x * WG) {
-        const float a = A[i];
-        if (!(a >= 0.0f) || !isfinite(a)) bad = 1;
-        else if (a > 0.0f) m = max(m, __float_as_uint(a));
-    }
-    for (int s = 32; s >= 1; s >>= 1) {
-        m = max(m, (uint32_t)__shfl_xor((int)m, s, 64));
-        bad |= (uint32_t)__shfl_xor((int)bad, s, 64);
-    }
-    if (lane_id() == 0) sm[threadIdx.x >> 6] = m;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t r = sm[0];
-        for (int w = 1; w < WG / 64; ++w) r = max(r, sm[w]);
-        d.amax_part[blockIdx.x] = r;
-    }
-    if (bad && lane_id() == 0) atomicOr(&d.ctl->bad, 1u);
-}
-
-__global__ __launch_bounds__(WG) void k_amax_reduce(const Slot *S, int nparts)
-{
-    const Slot &sl = S[blockIdx.y];
-    if (!sl.active) return;
-    const Dev d = sl.d;
-    uint32_t m = 0;
-    for (int i = threadIdx.x; i < nparts; i += WG) m = max(m, d.amax_part[i]);
-    for (int s = 32; s >= 1; s >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, s, 64));
-    __shared__ uint32_t sm[WG / 64];
-    if (lane_id() == 0) sm[threadIdx.x >> 6] = m;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int w = 1; w < WG / 64; ++w) m = max(m, sm[w]);
-        d.ctl->amax_bits = max(sm[0], m);
-    }
-}
-
-// Binning events of one source: a one-bin track adds q to Xn at that bin; a
-// wider one adds +q at its first bin and -q after its last bin in D.
 DEVI int tile_of(int bin, int tile) { return bin / tile; }
 
 // Count pass: events per tile and candidates of this block.
 DEVI void k_prep_count_body(Grid g, Dev d, const float *A, const float *F, const float *FD, uint64_t n)
 {
     __shared__ uint32_t hist[NBK_MAX];
-    __shared__ uint32_t scand;
+    __shared__ uint32_t scand, samax;
     for (int b = threadIdx.x; b < g.nt; b += WG) hist[b] = 0;
-    if (threadIdx.x == 0) scand = 0;
+    if (threadIdx.x == 0) {
+        scand = 0;
+        samax = 0;
+    }
     __syncthreads();
-    const int L = fx_exp(d.ctl->amax_bits, g.T);
     const uint64_t base = (uint64_t)blockIdx.x * PREP_SRC;
-    uint32_t cc = 0, bad = 0;
+    uint32_t cc = 0, bad = 0, amax = 0;
     // four sources per thread in flight: loads first, then the tracks and
     // the S_instr gathers of the candidate tests
     for (int r0 = 0; r0 < PREP_SRC / WG; r0 += 4) {
@@ -458,7 +408,7 @@ DEVI void k_prep_count_body(Grid g, Dev d, const float *A, const float *F, const
         }
         Trk t[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) t[q] = track_geom(g, a[q], f[q], fd[q], L);
+        for (int q = 0; q < 4; ++q) t[q] = track_geom(g, a[q], f[q], fd[q]);
         bool cand[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) cand[q] = cand_test(g, d, t[q]);
@@ -475,16 +425,22 @@ DEVI void k_prep_count_body(Grid g, Dev d, const float *A, const float *F, const
                 bad = 1;
                 continue;
             }
-            if (t[q].live && t[q].qfx) {
+            amax = max(amax, __float_as_uint(a[q]));      // A >= 0: bit patterns in value order
+            if (t[q].live) {
                 atomicAdd(&hist[tile_of(t[q].glo, g.tile)], 1u);
                 if (t[q].glo != t[q].ghi && t[q].ghi + 1 < g.B) atomicAdd(&hist[tile_of(t[q].ghi + 1, g.tile)], 1u);
             }
             cc += c;
         }
     }
-    for (int s = 32; s >= 1; s >>= 1) cc += (uint32_t)__shfl_xor((int)cc, s, 64);
+    for (int s = 32; s >= 1; s >>= 1) {
+        cc += (uint32_t)__shfl_xor((int)cc, s, 64);
+        amax = max(amax, (uint32_t)__shfl_xor((int)amax, s, 64));
+    }
     if (lane_id() == 0 && cc) atomicAdd(&scand, cc);
+    if (lane_id() == 0 && amax) atomicMax(&samax, amax);
     __syncthreads();
+    if (threadIdx.x == 0 && samax) atomicMax(&d.ctl->amax_bits, samax);
     for (int b = threadIdx.x; b < g.nt; b += WG)
         if (hist[b]) atomicAdd(&d.btot[b], hist[b]);
     if (threadIdx.x == 0 && scand) atomicAdd(&d.ctl->n_cand, scand);
@@ -574,9 +530,9 @@ DEVI void k_prep_scatter_body(Grid g, Dev d, const float *A, const float *F, con
         for (int q = 0; q < 4; ++q) {
             const uint64_t i = base + (uint64_t)(r0 + q) * WG + threadIdx.x;
             if (i >= n) continue;
-            const Trk t = track_geom(g, a[q], f[q], fd[q], L);
+            const Trk t = track_geom(g, a[q], f[q], fd[q]);
             if (!t.ok) continue;
-            if (t.live && t.qfx) {
+            if (t.live) {
                 atomicAdd(&cur[tile_of(t.glo, g.tile)], 1u);
                 if (t.glo != t.ghi && t.ghi + 1 < g.B) atomicAdd(&cur[tile_of(t.ghi + 1, g.tile)], 1u);
             }
@@ -607,21 +563,22 @@ DEVI void k_prep_scatter_body(Grid g, Dev d, const float *A, const float *F, con
         for (int q = 0; q < 4; ++q) {
             const uint64_t i = base + (uint64_t)(r0 + q) * WG + threadIdx.x;
             if (i >= n) continue;
-            const Trk t = track_geom(g, a[q], f[q], fd[q], L);
+            const Trk t = track_geom(g, a[q], f[q], fd[q]);
             if (!t.ok) continue;
-            if (t.live && t.qfx) {
+            const uint64_t qfx = to_fx(t.q, L);
+            if (t.live) {                  // every live source, so the counts match
                 if (t.glo == t.ghi) {
                     const uint32_t p = atomicAdd(&cur[tile_of(t.glo, g.tile)], 1u);
                     d.ev_key[p] = (uint32_t)t.glo;
-                    d.ev_val[p] = (int64_t)t.qfx;
+                    d.ev_val[p] = (int64_t)qfx;
                 } else {
                     uint32_t p = atomicAdd(&cur[tile_of(t.glo, g.tile)], 1u);
                     d.ev_key[p] = (uint32_t)t.glo | 0x80000000u;
-                    d.ev_val[p] = (int64_t)t.qfx;
+                    d.ev_val[p] = (int64_t)qfx;
                     if (t.ghi + 1 < g.B) {
                         p = atomicAdd(&cur[tile_of(t.ghi + 1, g.tile)], 1u);
                         d.ev_key[p] = (uint32_t)(t.ghi + 1) | 0x80000000u;
-                        d.ev_val[p] = -(int64_t)t.qfx;
+                        d.ev_val[p] = -(int64_t)qfx;
                     }
                 }
             }
@@ -631,7 +588,7 @@ DEVI void k_prep_scatter_body(Grid g, Dev d, const float *A, const float *F, con
                 d.c_glo[j] = t.glo;
                 d.c_ghi[j] = t.ghi;
                 d.c_q[j] = t.q;
-                d.c_qfx[j] = t.qfx;
+                d.c_qfx[j] = qfx;
                 d.c_iter[j] = -1;
             }
         }
@@ -1647,8 +1604,6 @@ hipError_t launch_reset(const Slot *ds, const Dims &dm, hipStream_t st)
 hipError_t launch_prep(const Slot *ds, const Dims &dm, hipStream_t st)
 {
     if (dm.prep_blocks > 0) {
-        k_amax<<<dim3(dm.amax_blocks, dm.ns), WG, 0, st>>>(ds);
-        k_amax_reduce<<<dim3(1, dm.ns), WG, 0, st>>>(ds, (int)dm.amax_blocks);
         k_prep_count<<<dim3(dm.prep_blocks, dm.ns), WG, 0, st>>>(ds);
     }
     k_prep_plan<<<dim3(1, dm.ns), WG, 0, st>>>(ds);
