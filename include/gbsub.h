@@ -188,8 +188,10 @@ gbsub_status gbsub_kernel_stats(const gbsub_ctx *ctx, gbsub_kernel_stat *out, ui
 
 /* ---------------------------------------------------------------- batches
  * Many catalogs, possibly on different grids, share every kernel launch of
- * the loop: one launch covers all slots (one slot per catalog), and a slot
- * whose loop has settled does nothing.  Catalogs are admitted and retired
+ * the loop: one launch covers all running slots (one slot per catalog; the
+ * launches are sized for the running slots only, and a slot whose loop
+ * settles inside a step does nothing until the next poll drops it from the
+ * launches).  Catalogs are admitted and retired
  * between steps (continuous batching).  Each admitted slot uses its own
  * context (configuration, results) and its own workspace; the results of a
  * retired slot are read with gbsub_spectrum / gbsub_resolved on that context.
@@ -204,7 +206,8 @@ enum {                                   /* slot states reported by gbsub_batch_
     GBSUB_SLOT_FREE = 255
 };
 
-/* Bytes of DEVICE memory for the descriptor table of max_slots slots. */
+/* Bytes of DEVICE memory for the descriptor tables of max_slots slots (one
+ * entry per slot and a compacted copy of the running ones). */
 gbsub_status gbsub_batch_table_size(uint32_t max_slots, uint64_t *bytes);
 
 /* Creates a batch of up to max_slots (1..4096) slots on the current device.
@@ -222,9 +225,11 @@ gbsub_status gbsub_batch_create(uint32_t max_slots, void *table, uint64_t table_
 gbsub_status gbsub_batch_admit(gbsub_batch *b, gbsub_ctx *ctx, const gbsub_catalog *cat,
                                void *workspace, uint64_t ws_bytes, void *stream, uint32_t *slot);
 
-/* Enqueues n_bodies loop bodies for every slot on `stream` (captured once in
- * a HIP graph and replayed when `stream` is not the null stream); returns
- * at once. */
+/* Enqueues n_bodies loop bodies for every running slot on `stream`
+ * (captured in a HIP graph, replayed until the set of running slots changes,
+ * when `stream` is not the null stream); returns at once, except that after
+ * an admission or a poll that saw slots settle it first waits for `stream`
+ * to rewrite the compacted table. */
 gbsub_status gbsub_batch_step(gbsub_batch *b, uint32_t n_bodies, void *stream);
 
 /* Waits for `stream`, then writes the state of slot i to state[i] (host,
@@ -242,7 +247,8 @@ gbsub_status gbsub_batch_retire(gbsub_batch *b, uint32_t slot, void *stream, gbs
 /* Releases the batch (NULL is ignored); caller memory is not touched. */
 void gbsub_batch_destroy(gbsub_batch *b);
 
-/* Releases the context (NULL is ignored).  Does not touch caller memory. */
+/* Releases the context (NULL is ignored).  Does not touch caller memory.
+ * A context that holds a batch slot must be retired from the batch first. */
 void gbsub_destroy(gbsub_ctx *ctx);
 
 /* Static description of a status code; never NULL. */

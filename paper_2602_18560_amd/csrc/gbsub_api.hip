@@ -551,12 +551,15 @@ struct gbsub_batch {
     int device;
     Slot *table;                       // device
     Slot *host_table;                  // pinned staging, one entry per slot
+    Slot *run_table;                   // device: the running slots, compacted (loop launches)
+    Slot *host_run;                    // pinned staging of run_table
+    uint32_t n_run;                    // entries of run_table
+    bool run_dirty;                    // the running set changed since run_table was written
+    Dims run_dims;                     // launch extents of run_table
     Ctl *host_ctls;                    // pinned
     std::vector<gbsub_ctx *> owner;
     std::vector<void *> ws;            // each slot's workspace
     std::vector<uint8_t> state;
-    Dims dims;                         // covers every slot admitted so far
-    bool have_dims;
     hipGraph_t graph;
     hipGraphExec_t exec;
     uint32_t graph_bodies;
@@ -596,7 +599,7 @@ hipError_t enqueue_bodies(const Slot *ds, const Dims &dm, uint32_t n, hipStream_
 gbsub_status gbsub_batch_table_size(uint32_t max_slots, uint64_t *bytes)
 {
     if (!bytes || max_slots < 1 || max_slots > 4096) return GBSUB_E_INVALID;
-    *bytes = align_up((uint64_t)max_slots * sizeof(Slot));
+    *bytes = align_up(2 * (uint64_t)max_slots * sizeof(Slot));   // all slots, then the running ones
     return GBSUB_OK;
 }
 
@@ -615,17 +618,22 @@ gbsub_status gbsub_batch_create(uint32_t max_slots, void *table, uint64_t table_
     b->max_slots = max_slots;
     b->device = dev;
     b->table = (Slot *)table;
+    b->run_table = (Slot *)table + max_slots;
     b->host_table = nullptr;
+    b->host_run = nullptr;
+    b->n_run = 0;
+    b->run_dirty = false;
+    b->run_dims = Dims{};
     b->host_ctls = nullptr;
     b->owner.assign(max_slots, nullptr);
     b->ws.assign(max_slots, nullptr);
     b->state.assign(max_slots, (uint8_t)GBSUB_SLOT_FREE);
-    b->have_dims = false;
     b->graph = nullptr;
     b->exec = nullptr;
     b->graph_bodies = 0;
     b->graph_stream = nullptr;
     if (hipHostMalloc((void **)&b->host_table, sizeof(Slot) * max_slots, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&b->host_run, sizeof(Slot) * max_slots, hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void **)&b->host_ctls, sizeof(Ctl) * max_slots, hipHostMallocDefault) != hipSuccess) {
         gbsub_batch_destroy(b);
         return GBSUB_E_DEVICE;
@@ -646,6 +654,7 @@ void gbsub_batch_destroy(gbsub_batch *b)
     for (gbsub_ctx *c : b->owner)
         if (c) c->batch_slot = -1;
     if (b->host_table) (void)hipHostFree(b->host_table);
+    if (b->host_run) (void)hipHostFree(b->host_run);
     if (b->host_ctls) (void)hipHostFree(b->host_ctls);
     delete b;
 }
@@ -665,9 +674,6 @@ gbsub_status gbsub_batch_admit(gbsub_batch *b, gbsub_ctx *c, const gbsub_catalog
     Dev d;
     carve(c->g, cat->n, (char *)ws, &d);
     b->host_table[k] = make_slot(c->g, d, cat);
-    // the median splits tiles only while the whole batch would still fit
-    // SPLIT_BLOCKS blocks
-    b->host_table[k].g.split_tiles = (uint32_t)(SPLIT_BLOCKS / (c->g.np * b->max_slots));
     const Dims one = dims_of(b->host_table[k]);
     Slot *ds = b->table + k;
     hipError_t e = hipMemcpyAsync(ds, &b->host_table[k], sizeof(Slot), hipMemcpyHostToDevice, st);
@@ -686,13 +692,7 @@ gbsub_status gbsub_batch_admit(gbsub_batch *b, gbsub_ctx *c, const gbsub_catalog
     b->owner[k] = c;
     b->ws[k] = ws;
     b->state[k] = GBSUB_SLOT_RUNNING;
-    if (!b->have_dims) {
-        b->dims = one;
-        b->have_dims = true;
-    } else {
-        widen(b->dims, one);
-    }
-    b->dims.ns = (int)b->max_slots;
+    b->run_dirty = true;
     *slot = k;
     return GBSUB_OK;
 }
@@ -700,15 +700,37 @@ gbsub_status gbsub_batch_admit(gbsub_batch *b, gbsub_ctx *c, const gbsub_catalog
 gbsub_status gbsub_batch_step(gbsub_batch *b, uint32_t n, void *stream)
 {
     if (!b || n == 0) return GBSUB_E_INVALID;
-    if (!b->have_dims) return GBSUB_OK;
     if (use_device(b->device) != GBSUB_OK) return GBSUB_E_DEVICE;
     hipStream_t st = (hipStream_t)stream;
-    if (!st) return b->dims.ns ? (enqueue_bodies(b->table, b->dims, n, st) == hipSuccess ? GBSUB_OK : GBSUB_E_DEVICE) : GBSUB_OK;
-    if (!b->exec || b->graph_bodies != n || !same_dims(b->graph_dims, b->dims) || b->graph_stream != st) {
+    if (b->run_dirty) {
+        // loop launches cover the running slots only: a compact descriptor
+        // table, grids sized for them, and the median's split threshold
+        // shared among them
+        if (hipStreamSynchronize(st) != hipSuccess) return GBSUB_E_DEVICE;   // host_run is free
+        uint32_t m = 0;
+        for (uint32_t k = 0; k < b->max_slots; ++k)
+            if (b->owner[k] && b->state[k] == GBSUB_SLOT_RUNNING) b->host_run[m++] = b->host_table[k];
+        Dims rd{};
+        for (uint32_t i = 0; i < m; ++i) {
+            Slot &sl = b->host_run[i];
+            sl.g.split_tiles = (uint32_t)(SPLIT_BLOCKS / ((uint32_t)sl.g.np * m));
+            const Dims one = dims_of(sl);
+            if (i == 0) rd = one; else widen(rd, one);
+        }
+        rd.ns = (int)m;
+        if (m && hipMemcpyAsync(b->run_table, b->host_run, sizeof(Slot) * m, hipMemcpyHostToDevice, st) != hipSuccess)
+            return GBSUB_E_DEVICE;
+        b->n_run = m;
+        b->run_dims = rd;
+        b->run_dirty = false;
+    }
+    if (b->n_run == 0) return GBSUB_OK;
+    if (!st) return enqueue_bodies(b->run_table, b->run_dims, n, st) == hipSuccess ? GBSUB_OK : GBSUB_E_DEVICE;
+    if (!b->exec || b->graph_bodies != n || !same_dims(b->graph_dims, b->run_dims) || b->graph_stream != st) {
         drop_graph(b);
         hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
-            const hipError_t e1 = enqueue_bodies(b->table, b->dims, n, st);
+            const hipError_t e1 = enqueue_bodies(b->run_table, b->run_dims, n, st);
             e = hipStreamEndCapture(st, &b->graph);
             if (e1 != hipSuccess) e = e1;
         }
@@ -718,7 +740,7 @@ gbsub_status gbsub_batch_step(gbsub_batch *b, uint32_t n, void *stream)
             return GBSUB_E_DEVICE;
         }
         b->graph_bodies = n;
-        b->graph_dims = b->dims;
+        b->graph_dims = b->run_dims;
         b->graph_stream = st;
     }
     return hipGraphLaunch(b->exec, st) == hipSuccess ? GBSUB_OK : GBSUB_E_DEVICE;
@@ -739,9 +761,11 @@ gbsub_status gbsub_batch_poll(gbsub_batch *b, void *stream, uint8_t *state, uint
     for (uint32_t k = 0; k < b->max_slots; ++k) {
         if (b->owner[k]) {
             const Ctl &h = b->host_ctls[k];
+            const uint8_t was = b->state[k];
             b->state[k] = h.bad ? GBSUB_SLOT_INVALID
                         : !h.done ? GBSUB_SLOT_RUNNING
                         : h.status == 6 ? GBSUB_SLOT_MAXITER : GBSUB_SLOT_SETTLED;
+            if (was == GBSUB_SLOT_RUNNING && b->state[k] != GBSUB_SLOT_RUNNING) b->run_dirty = true;
             running += b->state[k] == GBSUB_SLOT_RUNNING;
         }
         state[k] = b->state[k];
