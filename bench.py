@@ -45,6 +45,22 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def measured_traffic(kernel: str):
+    """HBM bytes per working launch of `kernel` from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary, if it was taken on the current kernel
+    source (else None: the counters no longer describe this build)."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_1e7_traffic.json")
+    try:
+        with open(path) as fh:
+            js = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    from paper_2602_18560_amd.profile_summary import kernel_source_hash
+    if js.get("kernel") != kernel or js.get("source_sha256") != kernel_source_hash():
+        return None
+    return float(js["traffic_bytes_per_launch"])
+
+
 def cpu_baseline(cat, run, iters=3):
     """The FP64 oracle on the same catalog, first `iters` loop bodies only."""
     from oracle import oracle as O
@@ -292,7 +308,8 @@ def main():
                    "n_sources": cat.n, "n_bins": s.n_bins, "n_iter": s.n_iter,
                    "n_candidates": s.n_candidates, "n_resolved": s.n_resolved},
         "roofline": {"bound": "hbm", "kernel": fam, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic("k_median"),
                      "avg_launch_ms": avg_ms, "algo_bytes_per_launch": bytes_per_launch},
         "run_level_hbm": {"algo_bytes_per_step": total_algo,
                           "achieved_GBs": total_algo / (ms * 1e-3) / 1e9,

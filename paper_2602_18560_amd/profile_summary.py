@@ -1,0 +1,107 @@
+"""Summaries of rocprofv3 output for the profiles/ folder.
+
+  python -m paper_2602_18560_amd.profile_summary stats DIR/ks_kernel_stats.csv "COMMAND"
+      -> markdown table of per-kernel calls / total / average duration
+
+  python -m paper_2602_18560_amd.profile_summary traffic FETCH.csv WRITE.csv \
+         COPY_FETCH.csv COPY_WRITE.csv COPY_BYTES KERNEL "COMMANDS"
+      -> markdown + json: per-dispatch HBM bytes of KERNEL from the FETCH_SIZE
+         and WRITE_SIZE counters, each scaled by what the counter reads for a
+         plain copy kernel that moves COPY_BYTES in and out.
+
+Reads only the CSV files it is given.
+"""
+from __future__ import annotations
+
+import collections
+import csv
+import hashlib
+import json
+import os
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCE = os.path.join(HERE, "csrc", "gbsub_kernels.hip")
+
+
+def kernel_source_hash() -> str:
+    with open(KERNEL_SOURCE, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()
+
+
+def short(name: str) -> str:
+    return name.split("(")[0].replace("gbs::", "")
+
+
+def stats(path: str, command: str) -> str:
+    rows = list(csv.DictReader(open(path)))
+    out = ["| kernel | calls | total ms | average us | share % |", "|---|---|---|---|---|"]
+    for r in rows:
+        out.append(f"| {short(r['Name'])} | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
+                   f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['Percentage']):.2f} |")
+    return f"Command:\n\n    {command}\n\n" + "\n".join(out) + "\n"
+
+
+def _per_dispatch(path: str):
+    acc = collections.defaultdict(list)
+    for r in csv.DictReader(open(path)):
+        acc[short(r["Kernel_Name"])].append(float(r["Counter_Value"]))
+    return acc
+
+
+def traffic(fetch, write, cfetch, cwrite, copy_bytes, kernel, commands):
+    f, w = _per_dispatch(fetch), _per_dispatch(write)
+    cf, cw = _per_dispatch(cfetch), _per_dispatch(cwrite)
+
+    def copy_kib(acc):   # the largest dispatches are the copy itself (fills are smaller)
+        vals = sorted(v for lst in acc.values() for v in lst)
+        return vals[-1]
+    kib = copy_bytes / 1024.0
+    ff = kib / copy_kib(cf)
+    fw = kib / copy_kib(cw)
+    rows = ["| kernel | dispatches | FETCH_SIZE KiB/dispatch | WRITE_SIZE KiB/dispatch | "
+            "HBM MB/dispatch (scaled) |", "|---|---|---|---|---|"]
+    for k in sorted(f):
+        fv = sum(f[k]) / len(f[k])
+        wv = sum(w.get(k, [0.0])) / max(len(w.get(k, [])), 1)
+        rows.append(f"| {k} | {len(f[k])} | {fv:.1f} | {wv:.1f} | {(fv * ff + wv * fw) * 1024 / 1e6:.3f} |")
+    kf, kw = f[kernel], w[kernel]
+    # dispatches that did work: a loop body enqueued after the loop settled
+    # exits at once and reads a few KiB of descriptors only
+    work = [(a, b) for a, b in zip(kf, kw) if a > 64.0]
+    fa = sum(a for a, _ in work) / len(work)
+    wa = sum(b for _, b in work) / len(work)
+    per = (fa * ff + wa * fw) * 1024
+    summary = {"kernel": kernel, "source_sha256": kernel_source_hash(),
+               "fetch_factor": ff, "write_factor": fw,
+               "working_dispatches": len(work), "all_dispatches": len(kf),
+               "fetch_kib_per_launch": fa, "write_kib_per_launch": wa,
+               "traffic_bytes_per_launch": per, "commands": commands}
+    md = (f"Commands:\n\n" + "\n".join(f"    {c}" for c in commands) + "\n\n"
+          f"Copy calibration: a {copy_bytes / 2**20:.0f} MiB read + {copy_bytes / 2**20:.0f} MiB write "
+          f"elementwise kernel reads FETCH_SIZE {copy_kib(cf):.0f} KiB and WRITE_SIZE {copy_kib(cw):.0f} KiB, "
+          f"so HBM read bytes = {ff:.3f} x FETCH_SIZE and written bytes = {fw:.3f} x WRITE_SIZE.\n\n"
+          + "\n".join(rows) + "\n\n"
+          f"{kernel}: {len(work)} working dispatches of {len(kf)}; "
+          f"{per / 1e6:.3f} MB of HBM traffic per working dispatch.\n")
+    return md, summary
+
+
+def main(argv):
+    if argv[0] == "stats":
+        sys.stdout.write(stats(argv[1], argv[2]))
+    elif argv[0] == "traffic":
+        md, js = traffic(argv[1], argv[2], argv[3], argv[4], float(argv[5]), argv[6], argv[7].split(" ;; "))
+        base = argv[8] if len(argv) > 8 else None
+        if base:
+            with open(base + ".md", "w") as fh:
+                fh.write(md)
+            with open(base + ".json", "w") as fh:
+                json.dump(js, fh, indent=1)
+        sys.stdout.write(md)
+    else:
+        raise SystemExit(__doc__)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:])
