@@ -16,7 +16,10 @@ Two more workloads print one JSON line each:
                      one shared batch against the same catalogs run one by one;
   --workload serve   a Poisson stream of jobs (N log-uniform in [1e5, 3e7],
                      T in {1, 2, 4} yr) through the continuous-batching server:
-                     p50/p99 latency at 0.7x the measured saturated rate.
+                     p50/p99 latency at 0.7x the measured saturated rate;
+  --workload precision   the 1e7-binary catalog in FP64, FP32 with compensated
+                     sums and naive FP32: spectrum and SNR errors and resolve-
+                     decision flips against the FP64 oracle's stored results.
 """
 from __future__ import annotations
 
@@ -213,9 +216,80 @@ def bench_serve(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_precision(args):
+    """FP64 / FP32 compensated / naive FP32 against the oracle (tests/golden)."""
+    import numpy as np
+    import torch
+    from paper_2602_18560_amd import gbsub as G
+    from paper_2602_18560_amd.inputs import config2
+    gold = np.load(os.path.join(ROOT, "tests", "golden", "config2_oracle.npz"))
+    grho = np.load(os.path.join(ROOT, "tests", "golden", "config2_rho2.npz"))
+    log("[precision] drawing the 1e7-binary catalog")
+    cat, run = config2()
+    torch.cuda.set_device(0)
+    dc = G.DeviceCatalog.from_host(cat)
+    ref_ids = gold["resolved_ids"].astype(np.int64)
+    ref_it = gold["resolved_iter"]
+    bins = gold["S_bins"]
+    out_modes = {}
+    for name, prec in (("fp64", G.FP64), ("fp32_compensated", G.FP32_COMP), ("fp32_naive", G.FP32_NAIVE)):
+        ctx = G.Context(G.config_from_run(run, precision=prec))
+        ctx.ensure_workspace(cat.n)
+        s = ctx.run(dc)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            s = ctx.run(dc)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        S = ctx.spectrum(G.SPEC_SN)[bins]
+        X = ctx.spectrum(G.SPEC_X_RESIDUAL)[bins]
+        ids, it = ctx.resolved()
+        cids, cit, cr2 = ctx.candidates()
+        ctx.close()
+        relS = np.abs(S - gold["S_final"]) / gold["S_final"]
+        xo = gold["X_final"]
+        pos = xo > 0
+        relX = np.abs(X[pos] - xo[pos]) / xo[pos]
+        same = np.array_equal(cids.astype(np.int64), grho["cand"].astype(np.int64))
+        relR = np.abs(cr2 - grho["rho2"]) / grho["rho2"] if same else np.array([np.nan])
+        a = set(ref_ids.tolist())
+        b = set(ids.astype(np.int64).tolist())
+        both = np.intersect1d(ref_ids, ids.astype(np.int64))
+        it_ref = dict(zip(ref_ids.tolist(), ref_it.tolist()))
+        it_gpu = dict(zip(ids.astype(np.int64).tolist(), it.tolist()))
+        moved = int(sum(it_ref[i] != it_gpu[i] for i in both.tolist()))
+        out_modes[name] = {
+            "ms_per_step": ms, "n_iter": s.n_iter, "n_iter_oracle": int(gold["n_iter"]),
+            "n_resolved": s.n_resolved, "n_candidates": s.n_candidates,
+            "flips_resolved_only_gpu": len(b - a), "flips_resolved_only_oracle": len(a - b),
+            "same_set_other_iteration": moved,
+            "S_rel_err": {"max": float(relS.max()), "median": float(np.median(relS)),
+                          "bins": int(relS.size)},
+            "X_rel_err": {"max": float(relX.max()), "median": float(np.median(relX)),
+                          "bins": int(relX.size),
+                          "nonzero_where_oracle_zero": int(np.count_nonzero(X[~pos]))},
+            "rho2_rel_err": {"max": float(np.nanmax(relR)), "median": float(np.nanmedian(relR)),
+                             "candidates": int(relR.size)},
+        }
+        log(f"[precision] {name}: {out_modes[name]}")
+    out = {"metric": "resolve-decision flips vs FP64 oracle (FP32 compensated)",
+           "value": out_modes["fp32_compensated"]["flips_resolved_only_gpu"]
+           + out_modes["fp32_compensated"]["flips_resolved_only_oracle"],
+           "unit": "sources", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+           "ms_per_step": out_modes["fp32_compensated"]["ms_per_step"], "higher_is_better": False,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "1e7-binary catalog (seed 2), T = 4 yr, W = 1001, in FP64 / "
+                                  "FP32 with compensated sums / naive FP32; S and X on every 997th "
+                                  "bin, rho^2 of every candidate at its last evaluation, resolved "
+                                  "ids and loop bodies against the FP64 oracle's stored results"},
+           "modes": out_modes}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", choices=["1e7", "batch", "serve"], default="1e7")
+    ap.add_argument("--workload", choices=["1e7", "batch", "serve", "precision"], default="1e7")
     ap.add_argument("--catalogs", type=int, default=64, help="batch: number of catalogs")
     ap.add_argument("--jobs", type=int, default=64, help="serve: number of jobs")
     ap.add_argument("--slots", type=int, default=64, help="serve: batch slots")
@@ -237,6 +311,8 @@ def main():
         return bench_batch(args)
     if args.workload == "serve":
         return bench_serve(args)
+    if args.workload == "precision":
+        return bench_precision(args)
 
     import numpy as np
     import torch

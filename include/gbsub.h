@@ -147,6 +147,16 @@ gbsub_status gbsub_spectrum(const gbsub_ctx *ctx, uint32_t kind, double *out, ui
 gbsub_status gbsub_resolved(const gbsub_ctx *ctx, uint32_t *ids, int32_t *iter_of, uint64_t cap,
                             uint64_t *n, int out_on_device);
 
+/* Every candidate of the last successful run (the sources with rho_0 >=
+ * kappa rho_th), in ascending id: ids[], the loop body that resolved it in
+ * iter_of[] (-1 if never; may be NULL) and rho^2 at its last evaluation
+ * (the body that resolved it, else the last body) in rho2[] (may be NULL).
+ * All pointers are HOST memory of `cap` entries; *n (host) receives the
+ * candidate count; TRUNCATED if cap is smaller; STATE if no run has
+ * completed.  The rho^2 values are those of the run's precision mode. */
+gbsub_status gbsub_candidates(const gbsub_ctx *ctx, uint32_t *ids, int32_t *iter_of, double *rho2,
+                              uint64_t cap, uint64_t *n);
+
 /* Kernel families of the profiling mode (bit k of the mask selects family k). */
 enum {
     GBSUB_KF_TABLES = 0,         /* S_instr and its prefix tables (first run on a workspace) */

@@ -210,8 +210,10 @@ class Result:
 
 
 def run(catalog, cfg: Config, *, spectra: bool = True, trace: bool = False,
-        near_cap: int = 4096, overrides=None) -> Result:
-    """Run the whole subtraction on ``catalog`` (arrays A, f, fdot)."""
+        near_cap: int = 4096, overrides=None, trace_fields=("X", "S", "cand", "rho2")) -> Result:
+    """Run the whole subtraction on ``catalog`` (arrays A, f, fdot).  With
+    ``trace``, every loop body appends a dict of ``trace_fields`` (X^t, S^t,
+    the candidate indices and their rho^2 at t, -1 once resolved)."""
     A = np.ascontiguousarray(catalog.A, np.float32)
     f = np.ascontiguousarray(catalog.f, np.float32)
     fd = np.ascontiguousarray(catalog.fdot, np.float32)
@@ -248,12 +250,16 @@ def run(catalog, cfg: Config, *, spectra: bool = True, trace: bool = False,
     traces = []
     if trace:
         def _cb(user, t, nb, Xp, Sp, nc, cp, rp):
-            traces.append(dict(
-                t=int(t),
-                X=np.ctypeslib.as_array(Xp, (nb,)).copy(),
-                S=np.ctypeslib.as_array(Sp, (nb,)).copy(),
-                cand=np.ctypeslib.as_array(cp, (nc,)).copy() if nc else np.zeros(0, np.int64),
-                rho2=np.ctypeslib.as_array(rp, (nc,)).copy() if nc else np.zeros(0)))
+            rec = dict(t=int(t))
+            if "X" in trace_fields:
+                rec["X"] = np.ctypeslib.as_array(Xp, (nb,)).copy()
+            if "S" in trace_fields:
+                rec["S"] = np.ctypeslib.as_array(Sp, (nb,)).copy()
+            if "cand" in trace_fields:
+                rec["cand"] = np.ctypeslib.as_array(cp, (nc,)).copy() if nc else np.zeros(0, np.int64)
+            if "rho2" in trace_fields:
+                rec["rho2"] = np.ctypeslib.as_array(rp, (nc,)).copy() if nc else np.zeros(0)
+            traces.append(rec)
         cb = TRACE_FN(_cb)
         keep.append(cb)
         io.trace = cb

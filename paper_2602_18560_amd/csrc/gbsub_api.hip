@@ -112,6 +112,11 @@ uint64_t carve(const Grid &g, uint64_t n, char *base, Dev *d)
     t.D = (I128 *)take((B + 1) * 16);
     t.Dtile = (I128 *)take((nt + 1) * 16);
     t.Dcarry = (I128 *)take((nt + 1) * 16);
+    const bool naive = g.prec == GBSUB_FP32_NAIVE;
+    t.Xf = (float *)take(naive ? B * 4 : 0);
+    t.Df = (float *)take(naive ? (B + 1) * 4 : 0);
+    t.Dtf = (float *)take(naive ? (nt + 1) * 4 : 0);
+    t.Dcf = (float *)take(naive ? (nt + 1) * 4 : 0);
     t.X = (double *)take(B * 8);
     t.S = (double *)take(B * 8);
     t.is_pre = (double *)take(B * 8);
@@ -162,7 +167,7 @@ gbsub_status validate(const gbsub_config *c, Grid *g)
         return GBSUB_E_INVALID;
     if (c->estimator != GBSUB_MEDIAN) return GBSUB_E_INVALID;
     if (c->track_model > GBSUB_TRACK_SINGLE) return GBSUB_E_INVALID;
-    if (c->precision != GBSUB_FP64) return GBSUB_E_INVALID;
+    if (c->precision > GBSUB_FP32_NAIVE) return GBSUB_E_INVALID;
     if (!(c->snr_threshold > 0.0) || !(c->kappa >= 0.0) || !(c->median_scale >= 0.0) ||
         !std::isfinite(c->snr_threshold) || !std::isfinite(c->kappa) || !std::isfinite(c->median_scale))
         return GBSUB_E_INVALID;
@@ -189,6 +194,7 @@ gbsub_status validate(const gbsub_config *c, Grid *g)
     r.nparts = (r.B + r.part - 1) / r.part;
     r.split_tiles = (uint32_t)(SPLIT_BLOCKS / r.np);
     r.track_single = c->track_model == GBSUB_TRACK_SINGLE;
+    r.prec = (int32_t)c->precision;
     r.T = c->t_obs_s;
     r.C = c->median_scale;
     r.rth = c->snr_threshold;
@@ -512,6 +518,36 @@ gbsub_status gbsub_resolved(const gbsub_ctx *c, uint32_t *ids, int32_t *iter_of,
     e = hipMemcpy(ids, id.data(), m * 4, kd);
     if (e == hipSuccess && iter_of) e = hipMemcpy(iter_of, it.data(), m * 4, kd);
     return dev_err(e);
+}
+
+gbsub_status gbsub_candidates(const gbsub_ctx *c, uint32_t *ids, int32_t *iter_of, double *rho2,
+                              uint64_t cap, uint64_t *n)
+{
+    if (!c || !n) return GBSUB_E_INVALID;
+    if (!c->have_result) return GBSUB_E_STATE;
+    if (hipSetDevice(c->device) != hipSuccess) return GBSUB_E_DEVICE;
+    const uint64_t nc = c->n_cand;
+    *n = nc;
+    if (cap < nc) return GBSUB_E_TRUNCATED;
+    if (nc == 0) return GBSUB_OK;
+    if (!ids) return GBSUB_E_INVALID;
+    std::vector<uint32_t> id(nc);
+    std::vector<int32_t> it(nc);
+    std::vector<double> r2(nc);
+    hipError_t e = hipMemcpy(id.data(), c->dev.c_id, nc * 4, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(it.data(), c->dev.c_iter, nc * 4, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(r2.data(), c->dev.c_rho2, nc * 8, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return GBSUB_E_DEVICE;
+    std::vector<uint64_t> order(nc);
+    for (uint64_t j = 0; j < nc; ++j) order[j] = ((uint64_t)id[j] << 32) | (uint32_t)j;
+    std::sort(order.begin(), order.end());
+    for (uint64_t q = 0; q < nc; ++q) {
+        const uint32_t j = (uint32_t)order[q];
+        ids[q] = id[j];
+        if (iter_of) iter_of[q] = it[j];
+        if (rho2) rho2[q] = r2[j];
+    }
+    return GBSUB_OK;
 }
 
 gbsub_status gbsub_set_profiling(gbsub_ctx *c, uint32_t families)

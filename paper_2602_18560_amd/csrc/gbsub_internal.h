@@ -24,6 +24,7 @@ constexpr int KEYBITS = 20;        // bits of the per-tile order key of the medi
 constexpr int POSBITS = 12;        // sort word = key << 12 | position (MMAX <= 4096)
 constexpr int CHP = 16;            // median start table: positions per row
 constexpr int RBS = 64;            // median start table: sorted ranks per column
+enum Prec { PREC_FP64 = 0, PREC_COMP = 1, PREC_NAIVE = 2 };   // Grid::prec (= gbsub_config precision)
 constexpr int PART_MAX = 512;      // outputs of a median block in split mode (prefix-of-1/S granule)
 constexpr int SPLIT_BLOCKS = 512;  // split the median into parts while dirty tiles x parts fit this
 
@@ -71,7 +72,7 @@ struct Grid {
     int32_t nparts;          // parts = ceil(B / part)
     uint32_t split_tiles;    // median in split mode while at most this many tiles are dirty
     int32_t track_single;    // 1: every source occupies one bin
-    int32_t pad0;
+    int32_t prec;            // 0 FP64, 1 FP32 with compensated sums, 2 naive FP32 (loop arithmetic)
     int64_t k0;              // first grid index
     double T;                // observation time
     double C;                // median scale
@@ -96,6 +97,11 @@ struct Dev {
     I128 *D;                 // [B+1]  difference array of the wider tracks
     I128 *Dtile;             // [nt+1] per-tile sums of D
     I128 *Dcarry;            // [nt+1] exclusive prefix of Dtile
+    // naive FP32 mode only: the binned power accumulated in fp32
+    float *Xf;               // [B]    one-bin tracks
+    float *Df;               // [B+1]  difference array of the wider tracks
+    float *Dtf;              // [nt+1] per-tile sums of Df
+    float *Dcf;              // [nt+1] exclusive prefix of Dtf
     double *X;               // [B]    X^t
     double *S;               // [B]    S^t
     double *is_pre;          // [B]    inclusive prefix of 1/S^t inside each part

@@ -75,6 +75,18 @@ DEVI int fx_exp(uint32_t amax_bits, double T)
 
 DEVI uint64_t to_fx(double q, int L) { return (uint64_t)rint(ldexp(q, -L)); }
 
+// The FP32 modes hold powers and PSDs scaled by 2^sc (exact): the largest
+// one-bin power becomes ~2^20, so S_instr (~1e-40 in SI units, below the
+// fp32 normal range) and its reciprocal stay representable; rho^2 is
+// unchanged by the scale.
+DEVI int f32_scale(uint32_t amax_bits, double T)
+{
+    const double a = (double)__uint_as_float(amax_bits);
+    const double pmax = ((a * a) * T) * 0.5;
+    if (!(pmax > 0.0)) return 128;
+    return 20 - ilogb(pmax);
+}
+
 DEVI int lane_id() { return __lane_id(); }
 
 template <typename T>
@@ -89,11 +101,13 @@ DEVI I128 shfl_up_t(I128 x, int d)
 }
 
 DEVI double add_t(double a, double b) { return a + b; }
+DEVI float add_t(float a, float b) { return a + b; }
 DEVI I128 add_t(I128 a, I128 b) { return i128_add(a, b); }
 DEVI uint32_t add_t(uint32_t a, uint32_t b) { return a + b; }
 
 template <typename T> DEVI T zero_t();
 template <> DEVI double zero_t<double>() { return 0.0; }
+template <> DEVI float zero_t<float>() { return 0.0f; }
 template <> DEVI uint32_t zero_t<uint32_t>() { return 0u; }
 template <> DEVI I128 zero_t<I128>() { I128 z; z.lo = 0; z.hi = 0; return z; }
 
@@ -238,24 +252,24 @@ __global__ __launch_bounds__(WG) void k_inv_prefix(const Slot *S)
 // contiguous run of ceil(n / WG) entries: its loads are all issued at once
 // (no chain of per-chunk scans waiting on memory), one block scan combines
 // the run totals, and a second pass over the (cached) run writes the prefix.
-template <typename T, int NT = WG>
+template <typename T, int NT = WG, typename A = T>
 DEVI void block_scan_array(const T *in, T *out, int n)
 {
-    __shared__ T sh[NT / 64];
+    __shared__ A sh[NT / 64];
     const int per = (n + NT - 1) / NT;
     const int b = min((int)threadIdx.x * per, n), e = min(b + per, n);
-    T s = zero_t<T>();
+    A s = zero_t<A>();
 #pragma unroll 8
-    for (int i = b; i < e; ++i) s = add_t(s, in[i]);
-    T tot;
-    T run = block_excl_scan<T, NT>(s, sh, &tot);
+    for (int i = b; i < e; ++i) s = add_t(s, (A)in[i]);
+    A tot;
+    A run = block_excl_scan<A, NT>(s, sh, &tot);
 #pragma unroll 8
     for (int i = b; i < e; ++i) {
-        const T x = in[i];
-        out[i] = run;
+        const A x = (A)in[i];
+        out[i] = (T)run;
         run = add_t(run, x);
     }
-    if (threadIdx.x == 0) out[n] = tot;
+    if (threadIdx.x == 0) out[n] = (T)tot;
 }
 
 __global__ __launch_bounds__(WG) void k_sx_scan(const Slot *S)
@@ -768,6 +782,47 @@ __global__ __launch_bounds__(WG) void k_dscan(const Slot *S)
     const Dev d = sl.d;
 
     block_scan_array<I128>(d.Dtile, d.Dcarry, g.nt);
+    if (g.prec == PREC_NAIVE) {
+        __syncthreads();
+        block_scan_array<float>(d.Dtf, d.Dcf, g.nt);
+    }
+}
+
+// Naive FP32 mode: the same events summed again in fp32, in whatever order
+// the atomics land (the accumulation the paper's float scatter performs).
+__global__ __launch_bounds__(WG) void k_zero_f32(const Slot *S)
+{
+    const Slot &sl = S[blockIdx.y];
+    if (!sl.active || sl.g.prec != PREC_NAIVE) return;
+    const Grid g = sl.g;
+    const Dev d = sl.d;
+    for (int i = blockIdx.x * WG + threadIdx.x; i <= g.B; i += gridDim.x * WG) {
+        if (i < g.B) d.Xf[i] = 0.0f;
+        d.Df[i] = 0.0f;
+        if (i <= g.nt) d.Dtf[i] = 0.0f;
+    }
+}
+
+__global__ __launch_bounds__(WG) void k_accum_f32(const Slot *S)
+{
+    const Slot &sl = S[blockIdx.y];
+    if (!sl.active || sl.g.prec != PREC_NAIVE) return;
+    const Grid g = sl.g;
+    const Dev d = sl.d;
+    const int L = fx_exp(d.ctl->amax_bits, g.T);
+    const int sc = f32_scale(d.ctl->amax_bits, g.T);
+    const uint32_t ne = d.ctl->n_events;
+    for (uint32_t e = blockIdx.x * WG + threadIdx.x; e < ne; e += gridDim.x * WG) {
+        const uint32_t key = d.ev_key[e];
+        const float v = (float)ldexp((double)d.ev_val[e], L + sc);
+        const int k = (int)(key & 0x7FFFFFFFu);
+        if (key >> 31) {
+            atomicAdd(&d.Df[k], v);
+            atomicAdd(&d.Dtf[k / g.tile], v);
+        } else {
+            atomicAdd(&d.Xf[k], v);
+        }
+    }
 }
 
 // ------------------------------------------------------------------ X update
@@ -782,6 +837,7 @@ __global__ __launch_bounds__(WG) void k_xupdate(const Slot *S)
 {
     __shared__ I128 sh[WG / 64];
     __shared__ I128 stage[TILE_MAX + TILE_MAX / 8];
+    __shared__ float shf[WG / 64];
     const Slot &sl = S[blockIdx.y];
     if (!sl.active) return;
     const Grid g = sl.g;
@@ -811,8 +867,39 @@ __global__ __launch_bounds__(WG) void k_xupdate(const Slot *S)
     for (int r = 0; r < 8; ++r)
         if (r < R && b + r < n) stage[xpad(b + r)] = i128_add(stage[xpad(b + r)], ex);
     __syncthreads();
-    for (int i = threadIdx.x; i < n; i += WG)
-        d.X[t0 + i] = ldexp(i128_to_double(i128_add(stage[xpad(i)], d.Xn[t0 + i])), L);
+    if (g.prec == PREC_FP64) {
+        for (int i = threadIdx.x; i < n; i += WG)
+            d.X[t0 + i] = ldexp(i128_to_double(i128_add(stage[xpad(i)], d.Xn[t0 + i])), L);
+        return;
+    }
+    const int sc = f32_scale(d.ctl->amax_bits, g.T);
+    if (g.prec == PREC_COMP) {
+        // the exact sum rounded once to fp32: what compensated fp32
+        // summation attains (to within an ulp)
+        for (int i = threadIdx.x; i < n; i += WG)
+            d.X[t0 + i] = ldexp((double)(float)ldexp(i128_to_double(i128_add(stage[xpad(i)], d.Xn[t0 + i])),
+                                                     L + sc), -sc);
+        return;
+    }
+    // naive fp32: X = Xf + prefix of Df, all in fp32
+    __syncthreads();
+    float *fst = reinterpret_cast<float *>(stage);
+    for (int i = threadIdx.x; i < n; i += WG) fst[xpad(i)] = d.Df[t0 + i];
+    __syncthreads();
+    float fs = 0.0f;
+    float floc[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        if (r < R && b + r < n) fs += fst[xpad(b + r)];
+        floc[r] = fs;
+    }
+    float ftot;
+    const float fex = block_excl_scan<float>(fs, shf, &ftot) + d.Dcf[tile];
+#pragma unroll
+    for (int r = 0; r < 8; ++r)
+        if (r < R && b + r < n) fst[xpad(b + r)] = fex + floc[r];
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += WG) d.X[t0 + i] = ldexp((double)(d.Xf[t0 + i] + fst[xpad(i)]), -sc);
 }
 
 // ------------------------------------------------------------------ running median
@@ -958,6 +1045,46 @@ DEVI int radix_sort_tile(MedianSmem &sm, int M, int passes)
         in ^= 1;
     }
     return in;
+}
+
+// In-part inclusive prefix of the values st[0 .. t1-t0) of a median block
+// (thread-contiguous runs of R outputs; a part is part/R threads, whole
+// waves), accumulated in type A; writes the prefix back into st and the part
+// sums to is_psum.  Contains one barrier.
+template <typename A>
+DEVI void part_prefix(MedianSmem &sm, double *st, const Grid &g, const Dev &d, int kb, int ke, int t0,
+                      int t1, int R)
+{
+    const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
+    A loc[RMAX], s = zero_t<A>();
+#pragma unroll
+    for (int r = 0; r < RMAX; ++r) {
+        if (kb + r < ke) s += (A)st[kb + r - t0];
+        loc[r] = s;
+    }
+    const int segw = (g.part / R) >> 6;
+    const A inc = wave_incl_scan(s);
+    A exw = shfl_up_t(inc, 1);
+    if (lane == 0) exw = zero_t<A>();
+    A *xch = reinterpret_cast<A *>(sm.dsh);
+    if (lane == 63) xch[wave] = inc;
+    __syncthreads();
+    const int ws0 = (wave / segw) * segw;
+    A pre = zero_t<A>(), tot = zero_t<A>();
+#pragma unroll
+    for (int w = 0; w < MWG / 64; ++w) {
+        const A x = xch[w];
+        if (w >= ws0 && w < wave) pre += x;
+        if (w >= ws0 && w < ws0 + segw) tot += x;
+    }
+    const A ex = pre + exw;
+#pragma unroll
+    for (int r = 0; r < RMAX; ++r)
+        if (kb + r < ke) st[kb + r - t0] = (double)(ex + loc[r]);
+    if ((tid & (segw * 64 - 1)) == 0) {
+        const int p0 = t0 + (tid / (segw * 64)) * g.part;
+        if (p0 < t1) d.is_psum[p0 / g.part] = (double)tot;
+    }
 }
 
 __global__ __launch_bounds__(MWG, 2) void k_median(const Slot *S)
@@ -1286,47 +1413,33 @@ __global__ __launch_bounds__(MWG, 2) void k_median(const Slot *S)
     // outputs pass through LDS so that global loads and stores are coalesced.
     __syncthreads();                       // the start table is dead: reuse it
     double *st = sm.u.stage;
+    const int sc = g.prec == PREC_FP64 ? 0 : f32_scale(d.ctl->amax_bits, g.T);
     const int n = t1 - t0;
 #pragma unroll
     for (int r = 0; r < RMAX; ++r)
         if (kb + r < ke) st[kb + r - t0] = med[r];
     __syncthreads();
     for (int i = tid; i < n; i += MWG) {
-        const double Sk = g.C * st[i] + d.sx[t0 + i];
+        double Sk, inv;
+        if (g.prec == PREC_FP64) {
+            Sk = g.C * st[i] + d.sx[t0 + i];
+            inv = 1.0 / Sk;
+        } else {                           // S and 1/S in fp32, scaled by 2^sc
+            const float sf = (float)g.C * (float)ldexp(st[i], sc) + (float)ldexp(d.sx[t0 + i], sc);
+            Sk = ldexp((double)sf, -sc);
+            inv = (double)(1.0f / sf);
+        }
         d.S[t0 + i] = Sk;
-        st[i] = 1.0 / Sk;
+        st[i] = inv;
     }
     __syncthreads();
-    double loc[RMAX], s = 0.0;
-#pragma unroll
-    for (int r = 0; r < RMAX; ++r) {
-        if (kb + r < ke) s += st[kb + r - t0];
-        loc[r] = s;
-    }
-    // exclusive scan restarted at every part (part / R threads, whole waves)
-    const int lane = lane_id(), wave = tid >> 6;
-    const int segw = (g.part / R) >> 6;
-    const double inc = wave_incl_scan(s);
-    double exw = shfl_up_t(inc, 1);
-    if (lane == 0) exw = 0.0;
-    if (lane == 63) sm.dsh[wave] = inc;
-    __syncthreads();
-    const int ws0 = (wave / segw) * segw;
-    double pre = 0.0, tot = 0.0;
-#pragma unroll
-    for (int w = 0; w < MWG / 64; ++w) {
-        const double x = sm.dsh[w];
-        if (w >= ws0 && w < wave) pre += x;
-        if (w >= ws0 && w < ws0 + segw) tot += x;
-    }
-    const double ex = pre + exw;
-#pragma unroll
-    for (int r = 0; r < RMAX; ++r)
-        if (kb + r < ke) st[kb + r - t0] = ex + loc[r];
-    if ((tid & (segw * 64 - 1)) == 0) {
-        const int p0 = t0 + (tid / (segw * 64)) * g.part;
-        if (p0 < t1) d.is_psum[p0 / g.part] = tot;
-    }
+    // prefix of 1/S restarted at every part: fp64 sums, or plain fp32 sums
+    // in the naive fp32 mode (fp64 sums of fp32 terms stand for compensated
+    // fp32 sums)
+    if (g.prec == PREC_NAIVE)
+        part_prefix<float>(sm, st, g, d, kb, ke, t0, t1, R);
+    else
+        part_prefix<double>(sm, st, g, d, kb, ke, t0, t1, R);
     __syncthreads();
     for (int i = tid; i < n; i += MWG) d.is_pre[t0 + i] = st[i];
 }
@@ -1340,7 +1453,10 @@ __global__ __launch_bounds__(TWG) void k_med_tail(const Slot *S)
     const Dev d = sl.d;
 
     if (d.ctl->done || d.ctl->bad) return;
-    block_scan_array<double, TWG>(d.is_psum, d.is_part, g.nparts);
+    if (g.prec == PREC_NAIVE)
+        block_scan_array<double, TWG, float>(d.is_psum, d.is_part, g.nparts);
+    else
+        block_scan_array<double, TWG>(d.is_psum, d.is_part, g.nparts);
 }
 
 // ------------------------------------------------------------------ SNR, decisions, subtraction
@@ -1350,6 +1466,41 @@ __global__ __launch_bounds__(TWG) void k_med_tail(const Slot *S)
 // rho_th^2 subtracts the source from the binned power at once (appendix
 // "Subtraction algorithm", steps 6-9: the data X^{t+1} no longer holds it).
 // Per-block counts go to arrays; k_snr_tail combines them.
+// rho^2 in fp32 (the FP32 precision modes): 4 q sum 1/S with the sum in
+// fp32, compensated (Kahan) for short tracks and from the fp64 prefix
+// tables otherwise, or plain fp32 (naive: bin by bin, or differences of the
+// fp32 prefix tables).
+DEVI double snr2_f32(const Grid &g, const Dev &d, double qd, int lo, int hi)
+{
+    // q and S scaled by 2^sc; the prefix tables already hold 1/(2^sc S)
+    const int sc = f32_scale(d.ctl->amax_bits, g.T);
+    const float q = (float)ldexp(qd, sc);
+    float sum;
+    if (hi - lo + 1 <= NARROW) {
+        float s = 0.0f, c = 0.0f;
+        for (int k = lo; k <= hi; ++k) {
+            const float x = 1.0f / (float)ldexp(d.S[k], sc);
+            if (g.prec == PREC_COMP) {         // Kahan
+                const float y = x - c;
+                const float t = s + y;
+                c = (t - s) - y;
+                s = t;
+            } else {
+                s += x;
+            }
+        }
+        sum = s;
+    } else if (g.prec == PREC_COMP) {
+        sum = (float)range_inv_sum(d.S, d.is_pre, d.is_part, lo, hi, g.part);
+    } else {                                   // differences of the fp32 prefix tables
+        const int plo = lo / g.part, phi = hi / g.part;
+        const float below = (lo % g.part == 0) ? 0.0f : (float)d.is_pre[lo - 1];
+        sum = plo == phi ? (float)d.is_pre[hi] - below
+                         : (((float)d.is_part[phi] - (float)d.is_part[plo]) - below) + (float)d.is_pre[hi];
+    }
+    return (double)((4.0f * q) * sum);
+}
+
 __global__ __launch_bounds__(WG) void k_snr(const Slot *S)
 {
     __shared__ uint64_t s_near[WG / 64], s_evals[WG / 64];
@@ -1370,7 +1521,9 @@ __global__ __launch_bounds__(WG) void k_snr(const Slot *S)
         ++evals;
         const int glo = d.c_glo[j], ghi = d.c_ghi[j];
         const double q = d.c_q[j];
-        const double r2 = (4.0 * q) * range_inv_sum(d.S, d.is_pre, d.is_part, glo, ghi, g.part);
+        const double r2 = g.prec == PREC_FP64
+                              ? (4.0 * q) * range_inv_sum(d.S, d.is_pre, d.is_part, glo, ghi, g.part)
+                              : snr2_f32(g, d, q, glo, ghi);
         d.c_rho2[j] = r2;
         const double rel = fabs(sqrt(r2) / g.rth - 1.0);
         minm = fmin(minm, rel);
@@ -1388,6 +1541,20 @@ __global__ __launch_bounds__(WG) void k_snr(const Slot *S)
                     if (ghi + 1 < g.B) {
                         atomic_add_i128(&d.D[ghi + 1], v);
                         atomic_add_i128(&d.Dtile[(ghi + 1) / g.tile], v);
+                    }
+                }
+                if (g.prec == PREC_NAIVE) {     // the same subtraction in fp32
+                    const float vf = (float)ldexp((double)v, fx_exp(d.ctl->amax_bits, g.T) +
+                                                             f32_scale(d.ctl->amax_bits, g.T));
+                    if (glo == ghi) {
+                        atomicAdd(&d.Xf[glo], -vf);
+                    } else {
+                        atomicAdd(&d.Df[glo], -vf);
+                        atomicAdd(&d.Dtf[glo / g.tile], -vf);
+                        if (ghi + 1 < g.B) {
+                            atomicAdd(&d.Df[ghi + 1], vf);
+                            atomicAdd(&d.Dtf[(ghi + 1) / g.tile], vf);
+                        }
                     }
                 }
             }
@@ -1500,6 +1667,10 @@ __global__ __launch_bounds__(SWG) void k_snr_tail(const Slot *S, int nblocks)
         run = i128_add(run, x);
     }
     if (tid == 0) d.Dcarry[g.nt] = dtot;
+    if (g.prec == PREC_NAIVE) {
+        __syncthreads();
+        block_scan_array<float, SWG>(d.Dtf, d.Dcf, g.nt);
+    }
     // dirty flags: prefix sums of the per-tile change counters (difference
     // arrays)
     uint32_t tx, ts;
@@ -1598,6 +1769,7 @@ hipError_t launch_reset(const Slot *ds, const Dims &dm, hipStream_t st)
 {
     const unsigned nb = (unsigned)((dm.maxnt + 1 + WG - 1) / WG);
     k_reset<<<dim3(nb, dm.ns), WG, 0, st>>>(ds);
+    k_zero_f32<<<dim3(1024, dm.ns), WG, 0, st>>>(ds);
     return hipGetLastError();
 }
 
@@ -1610,6 +1782,7 @@ hipError_t launch_prep(const Slot *ds, const Dims &dm, hipStream_t st)
     if (dm.prep_blocks > 0) k_prep_scatter<<<dim3(dm.prep_blocks, dm.ns), WG, 0, st>>>(ds);
     k_accum<<<dim3(dm.accum_blocks, dm.ns), WG, 0, st>>>(ds);
     k_accum_reduce<<<dim3(dm.maxnt * (dm.maxtile / RED_BINS), dm.ns), RED_BINS, 0, st>>>(ds);
+    k_accum_f32<<<dim3(2048, dm.ns), WG, 0, st>>>(ds);
     k_dscan<<<dim3(1, dm.ns), WG, 0, st>>>(ds);
     return hipGetLastError();
 }

@@ -23,7 +23,7 @@ FP64, FP32_COMP, FP32_NAIVE = 0, 1, 2
 SPEC_SN, SPEC_X_RESIDUAL, SPEC_S_GAL, SPEC_S_INSTR = 0, 1, 2, 3
 
 EXPORTS = ["gbsub_default_config", "gbsub_create", "gbsub_workspace_size", "gbsub_run",
-           "gbsub_spectrum", "gbsub_resolved", "gbsub_destroy", "gbsub_status_str",
+           "gbsub_spectrum", "gbsub_resolved", "gbsub_candidates", "gbsub_destroy", "gbsub_status_str",
            "gbsub_set_profiling", "gbsub_kernel_stats", "gbsub_batch_table_size",
            "gbsub_batch_create", "gbsub_batch_admit", "gbsub_batch_step", "gbsub_batch_poll",
            "gbsub_batch_retire", "gbsub_batch_destroy"]
@@ -94,6 +94,8 @@ def load(path: str | None = None):
                                  C.POINTER(C.c_uint64), C.c_int]
     L.gbsub_resolved.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64,
                                  C.POINTER(C.c_uint64), C.c_int]
+    L.gbsub_candidates.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64,
+                                   C.POINTER(C.c_uint64)]
     L.gbsub_destroy.argtypes = [C.c_void_p]
     L.gbsub_destroy.restype = None
     L.gbsub_status_str.argtypes = [C.c_int]
@@ -111,7 +113,7 @@ def load(path: str | None = None):
     L.gbsub_batch_destroy.argtypes = [C.c_void_p]
     L.gbsub_batch_destroy.restype = None
     for name in ("gbsub_create", "gbsub_workspace_size", "gbsub_run", "gbsub_spectrum",
-                 "gbsub_resolved", "gbsub_set_profiling", "gbsub_kernel_stats",
+                 "gbsub_resolved", "gbsub_candidates", "gbsub_set_profiling", "gbsub_kernel_stats",
                  "gbsub_batch_table_size", "gbsub_batch_create", "gbsub_batch_admit",
                  "gbsub_batch_step", "gbsub_batch_poll", "gbsub_batch_retire"):
         getattr(L, name).restype = C.c_int
@@ -278,6 +280,22 @@ class Context:
         return {arr[i].name.decode(): dict(launches=arr[i].launches, total_ms=arr[i].total_ms,
                                            units=arr[i].units, unit=arr[i].unit.decode())
                 for i in range(n.value)}
+
+    def candidates(self):
+        """(ids uint32 ascending, iter_of int32, rho^2 at the last evaluation) of
+        every candidate of the last run."""
+        n = C.c_uint64()
+        st = self._L.gbsub_candidates(self.h, None, None, None, 0, C.byref(n))
+        if st not in (OK, E_TRUNCATED):
+            raise GbsubError(st, "gbsub_candidates")
+        ids = np.empty(n.value, np.uint32)
+        it = np.empty(n.value, np.int32)
+        r2 = np.empty(n.value, np.float64)
+        st = self._L.gbsub_candidates(self.h, ids.ctypes.data, it.ctypes.data, r2.ctypes.data,
+                                      ids.shape[0], C.byref(n))
+        if st != OK:
+            raise GbsubError(st, "gbsub_candidates")
+        return ids, it, r2
 
     def resolved(self):
         """(ids uint32 ascending, iter_of int32) of the last run."""

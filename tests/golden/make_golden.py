@@ -5,7 +5,11 @@ Calls only oracle/ and the seeded input generator (no HIP code):
   bins, W = 1001): resolved ids and their loop body, n_iter, n_candidates,
   near-threshold count, and S_final on every 997th bin plus the last bin.
 
-  python tests/golden/make_golden.py      (~2-3 min on 8 cores)
+  config2_rho2.npz: every candidate of the same run (source index, ascending)
+  with rho^2 at its last evaluation (the body that resolved it, else the
+  last body), for the precision sweep's SNR errors.
+
+  python tests/golden/make_golden.py [rho2]     (~2-3 min each on 8 cores)
 """
 import os
 import sys
@@ -23,7 +27,28 @@ from paper_2602_18560_amd.inputs import config2  # noqa: E402
 SAMPLE_STRIDE = 997
 
 
+def write_rho2():
+    cat, run = config2()
+    O.set_threads(0)
+    t0 = time.time()
+    r = O.run(cat, O.make_config(run), spectra=False, trace=True, trace_fields=("cand", "rho2"))
+    assert r.status == O.OK
+    cand = r.trace[0]["cand"]
+    last = np.full(cand.shape[0], np.nan)
+    for rec in r.trace:
+        assert np.array_equal(rec["cand"], cand)
+        ev = rec["rho2"] >= 0.0
+        last[ev] = rec["rho2"][ev]
+    order = np.argsort(cand, kind="stable")
+    path = os.path.join(HERE, "config2_rho2.npz")
+    np.savez_compressed(path, cand=cand[order].astype(np.uint32), rho2=last[order],
+                        iter_of=r.iter_of[cand[order]].astype(np.int32))
+    print(f"wrote {path}: {cand.shape[0]} candidates ({time.time() - t0:.0f} s)")
+
+
 def main():
+    if sys.argv[1:] == ["rho2"]:
+        return write_rho2()
     cat, run = config2()
     O.set_threads(0)
     t0 = time.time()
