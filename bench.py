@@ -87,8 +87,8 @@ def percentile(x, q):
 
 def bench_batch(args):
     """Batched against plain on the same device-resident catalogs."""
-    from paper_2602_18560_amd.inputs import config3_populations, draw_catalogs
-    pops, run = config3_populations(args.catalogs)
+    from paper_2602_18560_amd.inputs import batch_populations, draw_catalogs
+    pops, run = batch_populations(args.catalogs)
     log(f"[batch] drawing {len(pops)} catalogs, {sum(p.n for p in pops):.3e} sources")
     t0 = time.perf_counter()
     cats = draw_catalogs(pops)
@@ -164,8 +164,8 @@ def bench_batch(args):
 
 def bench_serve(args):
     """Continuous batching of a Poisson job stream (saturated run first)."""
-    from paper_2602_18560_amd.inputs import config5_jobs, draw_catalogs
-    jobs = config5_jobs(args.jobs, rate_hz=1.0)
+    from paper_2602_18560_amd.inputs import job_stream, draw_catalogs
+    jobs = job_stream(args.jobs, rate_hz=1.0)
     log(f"[serve] drawing {len(jobs)} catalogs, {sum(j.population.n for j in jobs):.3e} sources")
     t0 = time.perf_counter()
     cats = draw_catalogs([j.population for j in jobs])
@@ -221,11 +221,11 @@ def bench_precision(args):
     import numpy as np
     import torch
     from paper_2602_18560_amd import gbsub as G
-    from paper_2602_18560_amd.inputs import config2
-    gold = np.load(os.path.join(ROOT, "tests", "golden", "config2_oracle.npz"))
-    grho = np.load(os.path.join(ROOT, "tests", "golden", "config2_rho2.npz"))
+    from paper_2602_18560_amd.inputs import catalog_1e7
+    gold = np.load(os.path.join(ROOT, "tests", "golden", "catalog1e7_oracle.npz"))
+    grho = np.load(os.path.join(ROOT, "tests", "golden", "catalog1e7_rho2.npz"))
     log("[precision] drawing the 1e7-binary catalog")
-    cat, run = config2()
+    cat, run = catalog_1e7()
     torch.cuda.set_device(0)
     dc = G.DeviceCatalog.from_host(cat)
     ref_ids = gold["resolved_ids"].astype(np.int64)
@@ -296,6 +296,9 @@ def main():
     ap.add_argument("--budget-gb", type=float, default=200.0, help="serve: device memory budget")
     ap.add_argument("--load", type=float, default=0.7, help="serve: arrival rate / saturated rate")
     ap.add_argument("--chunk", type=int, default=4, help="loop bodies per batch step")
+    ap.add_argument("--estimator", choices=["median", "mean"], default="median",
+                    help="1e7 workload: running median (default) or running mean")
+    ap.add_argument("--window", type=int, default=0, help="1e7 workload: window bins (default 1001)")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
@@ -318,13 +321,16 @@ def main():
     import torch
 
     from paper_2602_18560_amd import gbsub as G
-    from paper_2602_18560_amd.inputs import config2
+    from paper_2602_18560_amd.inputs import catalog_1e7
 
     log("[bench] drawing the 1e7-binary catalog")
-    cat, run = config2(args.n)
+    cat, run = catalog_1e7(args.n)
+    overrides = {"estimator": G.MEAN if args.estimator == "mean" else G.MEDIAN}
+    if args.window:
+        overrides["window_bins"] = args.window
     torch.cuda.set_device(0)
     dc = G.DeviceCatalog.from_host(cat)
-    ctx = G.Context(G.config_from_run(run))
+    ctx = G.Context(G.config_from_run(run, **overrides))
     ctx.ensure_workspace(cat.n)
     torch.cuda.synchronize()
 
@@ -378,14 +384,14 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "config 2: 1e7-binary catalog (seed 2), f in [0.1, 30] mHz, "
-                               "T_obs = 4 yr, 3,774,290 bins of 1/T, running-median window 1001, "
-                               "rho_th = 7; catalog resident in HBM",
+        "config": {"workload": f"1e7-binary catalog (seed 2), f in [0.1, 30] mHz, T_obs = 4 yr, "
+                               f"3,774,290 bins of 1/T, running-{args.estimator} window "
+                               f"{args.window or 1001}, rho_th = 7; catalog resident in HBM",
                    "n_sources": cat.n, "n_bins": s.n_bins, "n_iter": s.n_iter,
                    "n_candidates": s.n_candidates, "n_resolved": s.n_resolved},
-        "roofline": {"bound": "hbm", "kernel": fam, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic("k_median"),
+        "roofline": {"bound": "hbm", "kernel": "k_" + args.estimator, "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic("k_median") if args.estimator == "median" else None,
                      "avg_launch_ms": avg_ms, "algo_bytes_per_launch": bytes_per_launch},
         "run_level_hbm": {"algo_bytes_per_step": total_algo,
                           "achieved_GBs": total_algo / (ms * 1e-3) / 1e9,

@@ -71,7 +71,8 @@ typedef struct {
     double   f_min_hz;         /* grid start, > 0 */
     double   f_max_hz;         /* grid end, f_min < f_max < c/(2 arm_m) */
     uint32_t window_bins;      /* odd W, 1 <= W <= 2817 */
-    uint32_t estimator;        /* GBSUB_MEDIAN (GBSUB_MEAN: not supported, returns INVALID) */
+    uint32_t estimator;        /* GBSUB_MEDIAN: S = C med_W(X) + S_instr; GBSUB_MEAN:
+                                  S = (1/W) sum_window (X + S_instr) (FP64 only) */
     double   snr_threshold;    /* rho_th, default 7 */
     double   kappa;            /* candidate cut, default 1/rho_th */
     double   median_scale;     /* C, default 729/512 = (1 - 2/18)^-3 */

@@ -165,7 +165,8 @@ gbsub_status validate(const gbsub_config *c, Grid *g)
     if (!(c->arm_m > 0.0) || !(c->f_max_hz < C_LIGHT / (2.0 * c->arm_m))) return GBSUB_E_INVALID;
     if (c->window_bins < 1 || (c->window_bins % 2) == 0 || c->window_bins > (uint32_t)(MMAX - WG + 1))
         return GBSUB_E_INVALID;
-    if (c->estimator != GBSUB_MEDIAN) return GBSUB_E_INVALID;
+    if (c->estimator > GBSUB_MEAN) return GBSUB_E_INVALID;
+    if (c->estimator == GBSUB_MEAN && c->precision != GBSUB_FP64) return GBSUB_E_INVALID;
     if (c->track_model > GBSUB_TRACK_SINGLE) return GBSUB_E_INVALID;
     if (c->precision > GBSUB_FP32_NAIVE) return GBSUB_E_INVALID;
     if (!(c->snr_threshold > 0.0) || !(c->kappa >= 0.0) || !(c->median_scale >= 0.0) ||
@@ -195,6 +196,7 @@ gbsub_status validate(const gbsub_config *c, Grid *g)
     r.split_tiles = (uint32_t)(SPLIT_BLOCKS / r.np);
     r.track_single = c->track_model == GBSUB_TRACK_SINGLE;
     r.prec = (int32_t)c->precision;
+    r.est = (int32_t)c->estimator;
     r.T = c->t_obs_s;
     r.C = c->median_scale;
     r.rth = c->snr_threshold;
@@ -232,6 +234,7 @@ Dims dims_of(const Slot &sl)
     dm.maxnt = sl.g.nt;
     dm.maxtile = sl.g.tile;
     dm.maxparts = sl.g.nparts;
+    dm.est_mask = 1u << sl.g.est;
     dm.prep_blocks = (uint32_t)((sl.n + PREP_SRC - 1) / PREP_SRC);
     dm.accum_blocks = sl.d.max_chunks;
     return dm;
@@ -243,6 +246,7 @@ void widen(Dims &a, const Dims &b)
     a.maxnt = std::max(a.maxnt, b.maxnt);
     a.maxtile = std::max(a.maxtile, b.maxtile);
     a.maxparts = std::max(a.maxparts, b.maxparts);
+    a.est_mask |= b.est_mask;
     a.prep_blocks = std::max(a.prep_blocks, b.prep_blocks);
     a.accum_blocks = std::max(a.accum_blocks, b.accum_blocks);
 }
@@ -607,7 +611,7 @@ namespace {
 bool same_dims(const Dims &a, const Dims &b)
 {
     return a.ns == b.ns && a.maxB == b.maxB && a.maxnt == b.maxnt && a.maxtile == b.maxtile &&
-           a.maxparts == b.maxparts;
+           a.maxparts == b.maxparts && a.est_mask == b.est_mask;
 }
 
 void drop_graph(gbsub_batch *b)

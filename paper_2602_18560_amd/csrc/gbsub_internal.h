@@ -73,6 +73,8 @@ struct Grid {
     uint32_t split_tiles;    // median in split mode while at most this many tiles are dirty
     int32_t track_single;    // 1: every source occupies one bin
     int32_t prec;            // 0 FP64, 1 FP32 with compensated sums, 2 naive FP32 (loop arithmetic)
+    int32_t est;             // 0 running median, 1 running mean
+    int32_t pad1;
     int64_t k0;              // first grid index
     double T;                // observation time
     double C;                // median scale
@@ -158,6 +160,7 @@ struct Slot {
 struct Dims {
     int ns;                  // slots (gridDim.y)
     int maxB, maxnt, maxtile, maxparts;
+    uint32_t est_mask;       // bit e: some slot uses estimator e
     uint32_t prep_blocks, accum_blocks;
 };
 

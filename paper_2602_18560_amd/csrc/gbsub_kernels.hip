@@ -1052,7 +1052,7 @@ DEVI int radix_sort_tile(MedianSmem &sm, int M, int passes)
 // waves), accumulated in type A; writes the prefix back into st and the part
 // sums to is_psum.  Contains one barrier.
 template <typename A>
-DEVI void part_prefix(MedianSmem &sm, double *st, const Grid &g, const Dev &d, int kb, int ke, int t0,
+DEVI void part_prefix(double *dsh, double *st, const Grid &g, const Dev &d, int kb, int ke, int t0,
                       int t1, int R)
 {
     const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
@@ -1066,7 +1066,7 @@ DEVI void part_prefix(MedianSmem &sm, double *st, const Grid &g, const Dev &d, i
     const A inc = wave_incl_scan(s);
     A exw = shfl_up_t(inc, 1);
     if (lane == 0) exw = zero_t<A>();
-    A *xch = reinterpret_cast<A *>(sm.dsh);
+    A *xch = reinterpret_cast<A *>(dsh);
     if (lane == 63) xch[wave] = inc;
     __syncthreads();
     const int ws0 = (wave / segw) * segw;
@@ -1091,7 +1091,7 @@ __global__ __launch_bounds__(MWG, 2) void k_median(const Slot *S)
 {
     __shared__ MedianSmem sm;
     const Slot &sl = S[blockIdx.y];
-    if (!sl.active) return;
+    if (!sl.active || sl.g.est != 0) return;
     const Grid g = sl.g;
     const Dev d = sl.d;
     if (d.ctl->done || d.ctl->bad) return;
@@ -1437,11 +1437,88 @@ __global__ __launch_bounds__(MWG, 2) void k_median(const Slot *S)
     // in the naive fp32 mode (fp64 sums of fp32 terms stand for compensated
     // fp32 sums)
     if (g.prec == PREC_NAIVE)
-        part_prefix<float>(sm, st, g, d, kb, ke, t0, t1, R);
+        part_prefix<float>(sm.dsh, st, g, d, kb, ke, t0, t1, R);
     else
-        part_prefix<double>(sm, st, g, d, kb, ke, t0, t1, R);
+        part_prefix<double>(sm.dsh, st, g, d, kb, ke, t0, t1, R);
     __syncthreads();
     for (int i = tid; i < n; i += MWG) d.is_pre[t0 + i] = st[i];
+}
+
+// ------------------------------------------------------------------ running mean
+//
+// S[k] = (1/W) sum_{j in window(k)} (X[j] + S_instr[j])   (the mean form of the
+// PSD estimate, as printed: S_instr inside the sum).  Same tiles, parts,
+// dirty flags and outputs as the median; the window sums are differences of
+// an in-LDS prefix over the block's union, so no sum runs across the grid.
+
+struct MeanSmem {
+    double v[MMAX];                        // X + S_instr over the union, then its inclusive prefix
+    double stage[TILE_MAX];                // outputs, for coalesced stores
+    double dsh[MWG / 64];
+};
+
+__global__ __launch_bounds__(MWG) void k_mean(const Slot *S)
+{
+    __shared__ MeanSmem sm;
+    const Slot &sl = S[blockIdx.y];
+    if (!sl.active || sl.g.est != 1) return;
+    const Grid g = sl.g;
+    const Dev d = sl.d;
+    if (d.ctl->done || d.ctl->bad) return;
+    const int tid = threadIdx.x;
+    const int B = g.B, W = g.W, h = g.h;
+    const bool split = d.ctl->med_split != 0;
+    const int span = split ? g.part : g.tile;
+    const int blk = blockIdx.x;
+    const int tile = split ? blk / g.np : blk;
+    if (tile >= g.nt || blk * span >= B || !d.sdirty[tile]) return;
+    const int t0 = blk * span;
+    const int t1 = min(t0 + span, B);
+    const bool whole = B < W;
+    const int u0 = whole ? 0 : win_start(t0, B, W, h);
+    const int u1 = whole ? B - 1 : win_start(t1 - 1, B, W, h) + W - 1;
+    const int M = u1 - u0 + 1;
+
+    for (int p = tid; p < M; p += MWG) sm.v[p] = d.X[u0 + p] + d.sx[u0 + p];
+    __syncthreads();
+    // inclusive prefix over the union: thread-contiguous runs
+    const int ch = (M + MWG - 1) / MWG;
+    const int pb = tid * ch;
+    double loc[MCH], s = 0.0;
+#pragma unroll
+    for (int i = 0; i < MCH; ++i) {
+        if (i < ch && pb + i < M) s += sm.v[pb + i];
+        loc[i] = s;
+    }
+    double tot;
+    const double ex = block_excl_scan<double, MWG>(s, sm.dsh, &tot);
+#pragma unroll
+    for (int i = 0; i < MCH; ++i)
+        if (i < ch && pb + i < M) sm.v[pb + i] = ex + loc[i];
+    __syncthreads();
+    const int n = t1 - t0;
+    for (int i = tid; i < n; i += MWG) {
+        const int k = t0 + i;
+        double sum, len;
+        if (whole) {
+            sum = sm.v[M - 1];
+            len = (double)B;
+        } else {
+            const int a = win_start(k, B, W, h) - u0;
+            sum = sm.v[a + W - 1] - (a > 0 ? sm.v[a - 1] : 0.0);
+            len = (double)W;
+        }
+        const double Sk = sum / len;
+        d.S[k] = Sk;
+        sm.stage[i] = 1.0 / Sk;
+    }
+    __syncthreads();
+    const int R = (span + MWG - 1) / MWG;
+    const int kb = t0 + tid * R;
+    const int ke = min(kb + R, t1);
+    part_prefix<double>(sm.dsh, sm.stage, g, d, kb, ke, t0, t1, R);
+    __syncthreads();
+    for (int i = tid; i < n; i += MWG) d.is_pre[t0 + i] = sm.stage[i];
 }
 
 // Exclusive prefix of the tile sums of 1/S (one block).
@@ -1795,7 +1872,8 @@ hipError_t launch_xupdate(const Slot *ds, const Dims &dm, hipStream_t st)
 
 hipError_t launch_median(const Slot *ds, const Dims &dm, hipStream_t st)
 {
-    k_median<<<dim3(dm.maxparts, dm.ns), MWG, 0, st>>>(ds);
+    if (dm.est_mask & 1u) k_median<<<dim3(dm.maxparts, dm.ns), MWG, 0, st>>>(ds);
+    if (dm.est_mask & 2u) k_mean<<<dim3(dm.maxparts, dm.ns), MWG, 0, st>>>(ds);
     return hipGetLastError();
 }
 

@@ -125,14 +125,14 @@ def draw_catalog(pop: Population, chunk: int = 1 << 21) -> Catalog:
 # seeds are fixed so every run draws the same catalogs.
 # --------------------------------------------------------------------------
 
-def config1():
+def catalog_1e4():
     """N=1e4, f in [0.3, 10] mHz, T = 1 yr, median window 251 bins, seed 0."""
     pop = Population(n=10_000, seed=0, f_lo=3e-4, f_hi=1e-2)
     run = RunConfig(t_obs_s=1 * YEAR_S, f_min_hz=3e-4, f_max_hz=1e-2, window_bins=251)
     return draw_catalog(pop), run
 
 
-def config2(n: int = 10_000_000):
+def catalog_1e7(n: int = 10_000_000):
     """N=1e7, f in [0.1, 30] mHz, T = 4 yr, median window 1001 bins, seed 2."""
     pop = Population(n=n, seed=2, f_lo=1e-4, f_hi=3e-2)
     run = RunConfig(t_obs_s=4 * YEAR_S, f_min_hz=1e-4, f_max_hz=3e-2, window_bins=1001)
@@ -145,7 +145,7 @@ def _meta_population(rng, n: int, seed: int, f_lo=1e-4, f_hi=3e-2) -> Population
                       theta=float(rng.uniform(1.0, 4.0)), rho=float(rng.uniform(0.0, 0.8)))
 
 
-def config3_populations(n_catalogs: int = 64, n_lo: float = 1e5, n_hi: float = 2e7):
+def batch_populations(n_catalogs: int = 64, n_lo: float = 1e5, n_hi: float = 2e7):
     """64 catalogs, N log-uniform in [1e5, 2e7], per-catalog hyperparameters
     uniform (gamma in [2,4], Gamma shape in [1,3], scale in [1,4], rho in
     [0,0.8]); T = 4 yr, W = 1001 on the [0.1, 30] mHz grid.  Meta seed 3,
@@ -170,7 +170,7 @@ class Job:
     run: RunConfig
 
 
-def config5_jobs(n_jobs: int = 2000, rate_hz: float = 1.0, n_lo: float = 1e5, n_hi: float = 3e7):
+def job_stream(n_jobs: int = 2000, rate_hz: float = 1.0, n_lo: float = 1e5, n_hi: float = 3e7):
     """Poisson stream of subtraction jobs: N log-uniform in [1e5, 3e7], T in
     {1, 2, 4} yr uniform, W = 251/501/1001 for 1/2/4 yr (about 7.9 uHz),
     hyperparameters as for the batched catalogs.  Meta seed 5, job j seed

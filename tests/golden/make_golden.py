@@ -1,11 +1,11 @@
 """Writes the oracle's results on the full-size workloads to tests/golden/.
 
 Calls only oracle/ and the seeded input generator (no HIP code):
-  config2_oracle.npz: the 1e7-binary catalog (seed 2, T = 4 yr, 3,774,290
+  catalog1e7_oracle.npz: the 1e7-binary catalog (seed 2, T = 4 yr, 3,774,290
   bins, W = 1001): resolved ids and their loop body, n_iter, n_candidates,
   near-threshold count, and S_final on every 997th bin plus the last bin.
 
-  config2_rho2.npz: every candidate of the same run (source index, ascending)
+  catalog1e7_rho2.npz: every candidate of the same run (source index, ascending)
   with rho^2 at its last evaluation (the body that resolved it, else the
   last body), for the precision sweep's SNR errors.
 
@@ -22,13 +22,13 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 sys.path.insert(0, ROOT)
 
 from oracle import oracle as O  # noqa: E402
-from paper_2602_18560_amd.inputs import config2  # noqa: E402
+from paper_2602_18560_amd.inputs import catalog_1e7  # noqa: E402
 
 SAMPLE_STRIDE = 997
 
 
 def write_rho2():
-    cat, run = config2()
+    cat, run = catalog_1e7()
     O.set_threads(0)
     t0 = time.time()
     r = O.run(cat, O.make_config(run), spectra=False, trace=True, trace_fields=("cand", "rho2"))
@@ -40,7 +40,7 @@ def write_rho2():
         ev = rec["rho2"] >= 0.0
         last[ev] = rec["rho2"][ev]
     order = np.argsort(cand, kind="stable")
-    path = os.path.join(HERE, "config2_rho2.npz")
+    path = os.path.join(HERE, "catalog1e7_rho2.npz")
     np.savez_compressed(path, cand=cand[order].astype(np.uint32), rho2=last[order],
                         iter_of=r.iter_of[cand[order]].astype(np.int32))
     print(f"wrote {path}: {cand.shape[0]} candidates ({time.time() - t0:.0f} s)")
@@ -49,7 +49,7 @@ def write_rho2():
 def main():
     if sys.argv[1:] == ["rho2"]:
         return write_rho2()
-    cat, run = config2()
+    cat, run = catalog_1e7()
     O.set_threads(0)
     t0 = time.time()
     r = O.run(cat, O.make_config(run), spectra=True)
@@ -58,7 +58,7 @@ def main():
     ids = cat.id[sel]
     order = np.argsort(ids, kind="stable")
     bins = np.unique(np.r_[np.arange(0, r.n_bins, SAMPLE_STRIDE), r.n_bins - 1])
-    path = os.path.join(HERE, "config2_oracle.npz")
+    path = os.path.join(HERE, "catalog1e7_oracle.npz")
     np.savez_compressed(path, resolved_ids=ids[order].astype(np.uint32),
                         resolved_iter=r.iter_of[sel][order].astype(np.int32),
                         n_iter=r.n_iter, n_candidates=r.n_candidates, n_near=r.n_near,

@@ -11,7 +11,7 @@ import pytest
 
 from oracle import oracle as O
 from paper_2602_18560_amd import gbsub as G
-from paper_2602_18560_amd.inputs import Population, RunConfig, YEAR_S, draw_catalog, config1
+from paper_2602_18560_amd.inputs import Population, RunConfig, YEAR_S, draw_catalog, catalog_1e4
 from tests.helpers import amp_for_power, bin_freq, catalog, small_run
 from tests.test_oracle_pins import cascade_catalog
 
@@ -99,9 +99,9 @@ def test_three_iteration_cascade():
     assert s.n_iter == 3
 
 
-def test_config1_full():
-    cat, run = config1()
-    assert_parity(cat, run, "config1")
+def test_1e4_catalog_full():
+    cat, run = catalog_1e4()
+    assert_parity(cat, run, "catalog_1e4")
 
 
 @pytest.mark.parametrize("n,flo,fhi,W,T,scale,seed", [
@@ -142,8 +142,8 @@ def test_wide_tracks_and_clipping():
 
 
 def test_single_bin_track_model():
-    cat, run = config1()
-    assert_parity(cat, run, "config1 single-bin", track_model=G.TRACK_SINGLE)
+    cat, run = catalog_1e4()
+    assert_parity(cat, run, "catalog_1e4 single-bin", track_model=G.TRACK_SINGLE)
 
 
 def test_kappa_zero_evaluates_everyone():
@@ -152,6 +152,32 @@ def test_kappa_zero_evaluates_everyone():
     run = RunConfig(t_obs_s=YEAR_S, f_min_hz=1e-3, f_max_hz=1.3e-3, window_bins=51)
     ro, s, _ = assert_parity(cat, run, "kappa=0", kappa=0.0)
     assert s.n_candidates == cat.n
+
+
+# ----------------------------------------------------------------- running mean estimator
+
+@pytest.mark.parametrize("which,W", [("catalog_1e4", 251), ("dense", 2001), ("dense", 101), ("short", 1001)])
+def test_running_mean_estimator(which, W):
+    if which == "catalog_1e4":
+        cat, run = catalog_1e4()
+        run = RunConfig(**{**run.as_dict(), "window_bins": W})
+    elif which == "dense":
+        cat = draw_catalog(Population(n=200000, seed=4, f_lo=3e-4, f_hi=3e-3))
+        cat.A *= np.float32(3)
+        run = RunConfig(t_obs_s=2 * YEAR_S, f_min_hz=3e-4, f_max_hz=3e-3, window_bins=W)
+    else:                                   # B < W: the whole grid is the window
+        run, k0 = small_run(n_bins=700, W=W)
+        rng = np.random.default_rng(9)
+        f = (k0 + rng.uniform(0, 700, 3000)) / run.t_obs_s
+        Sx = O.sinstr(float(f.mean()))
+        cat = catalog(np.sqrt(2 * Sx * rng.exponential(30.0, 3000) / run.t_obs_s), f)
+    assert_parity(cat, run, f"mean {which} W={W}", estimator=G.MEAN)
+
+
+def test_mean_rejects_fp32_modes():
+    run, _ = small_run(n_bins=2000, W=21)
+    with pytest.raises(G.GbsubError):
+        G.Context(G.config_from_run(run, estimator=G.MEAN, precision=G.FP32_COMP))
 
 
 # ----------------------------------------------------------------- edge cases and errors
@@ -209,7 +235,7 @@ def test_results_before_run_and_truncation():
     import ctypes as C
     n = C.c_uint64()
     assert ctx._L.gbsub_spectrum(ctx.h, 0, None, 0, C.byref(n), 0) == G.E_STATE
-    ctx.run(G.DeviceCatalog.from_host(config1()[0].subset(np.arange(10))))
+    ctx.run(G.DeviceCatalog.from_host(catalog_1e4()[0].subset(np.arange(10))))
     assert ctx._L.gbsub_spectrum(ctx.h, 0, None, 0, C.byref(n), 0) == G.E_TRUNCATED
     assert n.value == 2000
     ctx.close()
@@ -229,14 +255,14 @@ def test_run_is_deterministic():
 
 # ----------------------------------------------------------------- full size
 
-def test_config2_full_size_against_oracle_golden():
+def test_1e7_full_size_against_oracle_golden():
     """The 1e7-binary workload in the configuration bench.py times, against
     the oracle's results stored by tests/golden/make_golden.py."""
     import os
-    from paper_2602_18560_amd.inputs import config2
-    gold = np.load(os.path.join(os.path.dirname(__file__), "golden", "config2_oracle.npz"))
-    say("[parity] config2 full size: drawing the catalog")
-    cat, run = config2()
+    from paper_2602_18560_amd.inputs import catalog_1e7
+    gold = np.load(os.path.join(os.path.dirname(__file__), "golden", "catalog1e7_oracle.npz"))
+    say("[parity] catalog_1e7 full size: drawing the catalog")
+    cat, run = catalog_1e7()
     st, s, S, X, ids, it = gpu_run(cat, run)
     assert st == G.OK
     assert int(gold["n_near"]) == 0

@@ -10,7 +10,7 @@ import pytest
 
 from oracle import oracle as O
 from paper_2602_18560_amd import gbsub as G
-from paper_2602_18560_amd.inputs import Population, RunConfig, YEAR_S, draw_catalog, config1
+from paper_2602_18560_amd.inputs import Population, RunConfig, YEAR_S, draw_catalog, catalog_1e4
 
 pytestmark = pytest.mark.gpu
 
@@ -40,9 +40,9 @@ def flips(ids, ro, cat):
     return len(ref ^ got)
 
 
-@pytest.mark.parametrize("which", ["config1", "dense"])
+@pytest.mark.parametrize("which", ["catalog_1e4", "dense"])
 def test_fp32_compensated_within_fp32_rounding(which):
-    cat, run = config1() if which == "config1" else dense()
+    cat, run = catalog_1e4() if which == "catalog_1e4" else dense()
     say(f"[precision] compensated fp32, {which}")
     ro = O.run(cat, O.make_config(run))
     s, S, (ids, it), (cids, cit, cr2) = gpu_run(cat, run, precision=G.FP32_COMP)
