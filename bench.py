@@ -299,6 +299,8 @@ def main():
     ap.add_argument("--estimator", choices=["median", "mean"], default="median",
                     help="1e7 workload: running median (default) or running mean")
     ap.add_argument("--window", type=int, default=0, help="1e7 workload: window bins (default 1001)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="1e7 workload: default schedule instead of the tuner's choice")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
@@ -330,7 +332,13 @@ def main():
         overrides["window_bins"] = args.window
     torch.cuda.set_device(0)
     dc = G.DeviceCatalog.from_host(cat)
-    ctx = G.Context(G.config_from_run(run, **overrides))
+    schedule = {"tile_bins": 0, "split_blocks": 0}
+    if not args.no_tune:
+        from paper_2602_18560_amd.autotune import tune
+        log("[bench] tuning the schedule (tile size, split budget)")
+        schedule, _ = tune(dc, {**run.as_dict(), **overrides}, log=log)
+        log(f"[bench] schedule {schedule}")
+    ctx = G.Context(G.config_from_run(run, **overrides, **schedule))
     ctx.ensure_workspace(cat.n)
     torch.cuda.synchronize()
 
@@ -388,7 +396,8 @@ def main():
                                f"3,774,290 bins of 1/T, running-{args.estimator} window "
                                f"{args.window or 1001}, rho_th = 7; catalog resident in HBM",
                    "n_sources": cat.n, "n_bins": s.n_bins, "n_iter": s.n_iter,
-                   "n_candidates": s.n_candidates, "n_resolved": s.n_resolved},
+                   "n_candidates": s.n_candidates, "n_resolved": s.n_resolved,
+                   "schedule": schedule},
         "roofline": {"bound": "hbm", "kernel": "k_" + args.estimator, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic("k_median") if args.estimator == "median" else None,

@@ -83,6 +83,13 @@ typedef struct {
     double   oms_pm;           /* SciRDv1 OMS level P, default 15 (pm/sqrt(Hz)) */
     double   tm_fm;            /* SciRDv1 test-mass level A, default 3 (fm/s^2/sqrt(Hz)) */
     double   arm_m;            /* arm length L, default 2.5e9 m */
+    /* Schedule (results are the same up to the association of the fp64 sums
+     * of 1/S, see the tuner in paper_2602_18560_amd/autotune.py): */
+    uint32_t tile_bins;        /* bins per tile: a power of two in [256, 2048] with
+                                  tile_bins + W - 1 <= 3072; 0 = the largest allowed */
+    uint32_t split_blocks;     /* the median runs one block per 512-bin part while
+                                  dirty tiles x parts per tile <= split_blocks (shared by
+                                  the running catalogs of a batch); 0 = 512, 1 = never */
 } gbsub_config;
 
 /* A catalog in structure-of-arrays form.  A, f, fdot, id are DEVICE

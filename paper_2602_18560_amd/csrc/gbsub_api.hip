@@ -181,19 +181,26 @@ gbsub_status validate(const gbsub_config *c, Grid *g)
     r.B = (int32_t)((int64_t)b - (int64_t)a + 1);
     r.W = (int32_t)c->window_bins;
     r.h = (r.W - 1) / 2;
-    // tile: the largest power of two (256 .. TILE_MAX) with outputs + W - 1
-    // inside the median kernel's LDS union; parts of at most PART_MAX bins
+    // tile: a power of two (256 .. TILE_MAX) with outputs + W - 1 inside the
+    // median kernel's LDS union (the largest such by default); parts of at
+    // most PART_MAX bins
     const int room = MMAX - (r.W - 1);
     if (room < WG) return GBSUB_E_INVALID;
     int tile = TILE_MAX;
     while (tile > room) tile >>= 1;
+    if (c->tile_bins) {
+        const uint32_t tb = c->tile_bins;
+        if (tb < (uint32_t)WG || tb > (uint32_t)tile || (tb & (tb - 1)) != 0) return GBSUB_E_INVALID;
+        tile = (int)tb;
+    }
     r.tile = tile;
     r.nt = (r.B + tile - 1) / tile;
     if (r.nt > NBK_MAX) return GBSUB_E_INVALID;
     r.part = tile < PART_MAX ? tile : PART_MAX;
     r.np = tile / r.part;
     r.nparts = (r.B + r.part - 1) / r.part;
-    r.split_tiles = (uint32_t)(SPLIT_BLOCKS / r.np);
+    r.split_blocks = c->split_blocks ? c->split_blocks : (uint32_t)SPLIT_BLOCKS;
+    r.split_tiles = r.split_blocks / (uint32_t)r.np;
     r.track_single = c->track_model == GBSUB_TRACK_SINGLE;
     r.prec = (int32_t)c->precision;
     r.est = (int32_t)c->estimator;
@@ -753,7 +760,7 @@ gbsub_status gbsub_batch_step(gbsub_batch *b, uint32_t n, void *stream)
         Dims rd{};
         for (uint32_t i = 0; i < m; ++i) {
             Slot &sl = b->host_run[i];
-            sl.g.split_tiles = (uint32_t)(SPLIT_BLOCKS / ((uint32_t)sl.g.np * m));
+            sl.g.split_tiles = sl.g.split_blocks / ((uint32_t)sl.g.np * m);
             const Dims one = dims_of(sl);
             if (i == 0) rd = one; else widen(rd, one);
         }

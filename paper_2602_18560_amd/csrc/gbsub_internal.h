@@ -71,6 +71,7 @@ struct Grid {
     int32_t np;              // parts per tile
     int32_t nparts;          // parts = ceil(B / part)
     uint32_t split_tiles;    // median in split mode while at most this many tiles are dirty
+    uint32_t split_blocks;   // the budget behind split_tiles (shared by a batch's running slots)
     int32_t track_single;    // 1: every source occupies one bin
     int32_t prec;            // 0 FP64, 1 FP32 with compensated sums, 2 naive FP32 (loop arithmetic)
     int32_t est;             // 0 running median, 1 running mean

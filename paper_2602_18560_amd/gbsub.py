@@ -45,7 +45,7 @@ class Config(C.Structure):
                 ("snr_threshold", C.c_double), ("kappa", C.c_double), ("median_scale", C.c_double),
                 ("track_model", C.c_uint32), ("precision", C.c_uint32), ("max_iter", C.c_uint32),
                 ("reserved0", C.c_uint32), ("oms_pm", C.c_double), ("tm_fm", C.c_double),
-                ("arm_m", C.c_double)]
+                ("arm_m", C.c_double), ("tile_bins", C.c_uint32), ("split_blocks", C.c_uint32)]
 
 
 class CatalogStruct(C.Structure):

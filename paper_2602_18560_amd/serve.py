@@ -113,6 +113,7 @@ class Server:
                 b.record(self.stream)
                 self.h2d_events.append((a, b, 16 * req.n))
                 ws = torch.empty(ctx.workspace_size(req.n) + 256, dtype=torch.uint8, device="cuda")
+            ctx.workspace = ws          # the results live there: the context keeps it
             dc = G.DeviceCatalog(*dev)
             k = self.batch.admit(ctx, dc, ws=ws, stream=self.stream)
             self.live[k] = (req, ctx, dc, need, self.now())

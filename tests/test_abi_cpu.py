@@ -31,7 +31,7 @@ def test_exports_every_declared_symbol():
 
 def test_struct_layouts_match_header():
     # sizes implied by the header's field order (no padding by construction)
-    assert C.sizeof(G.Config) == 96
+    assert C.sizeof(G.Config) == 104
     assert C.sizeof(G.CatalogStruct) == 40
     assert C.sizeof(G.SummaryStruct) == 48
     assert C.sizeof(G.KernelStat) == 64

@@ -1,0 +1,60 @@
+"""The continuous-batching server (paper_2602_18560_amd/serve.py): jobs of
+different sizes and observation times arrive while others run, are admitted
+as slots and memory free up, and each result equals the job run alone."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2602_18560_amd import gbsub as G
+from paper_2602_18560_amd import serve as SV
+from paper_2602_18560_amd.inputs import Population, RunConfig, YEAR_S, WINDOW_FOR_YEARS, draw_catalog
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def jobs():
+    out = []
+    for j, (n, years, seed, scale) in enumerate([(30000, 1, 1, 30), (80000, 2, 2, 10), (5000, 4, 3, 40),
+                                                 (120000, 1, 4, 5), (20000, 2, 5, 20), (60000, 4, 6, 8)]):
+        cat = draw_catalog(Population(n=n, seed=seed, f_lo=5e-4, f_hi=4e-3))
+        cat.A *= np.float32(scale)
+        run = RunConfig(t_obs_s=years * YEAR_S, f_min_hz=5e-4, f_max_hz=4e-3,
+                        window_bins=WINDOW_FOR_YEARS[years])
+        out.append((cat, run))
+    return out
+
+
+def alone(cat, run):
+    ctx = G.Context(G.config_from_run(run))
+    try:
+        s = ctx.run(G.DeviceCatalog.from_host(cat))
+        return s, ctx.spectrum(G.SPEC_SN), ctx.resolved()
+    finally:
+        ctx.close()
+
+
+@pytest.mark.parametrize("slots,budget_mb", [(3, 100000), (6, 60)])
+def test_server_results_equal_alone(slots, budget_mb):
+    js = jobs()
+    ref = [alone(c, r) for c, r in js]
+    reqs = [SV.Request(j, 0.002 * j, *SV.pin_catalog(c), run=r) for j, (c, r) in enumerate(js)]
+    say(f"[serve] {len(reqs)} jobs, {slots} slots, budget {budget_mb} MB")
+    done, srv = SV.serve(reqs, max_slots=slots, budget_bytes=budget_mb * 1e6, chunk=2,
+                         keep_contexts=True)
+    assert sorted(c.index for c in done) == list(range(len(js)))
+    for c in done:
+        s_ref, S_ref, (ids_ref, it_ref) = ref[c.index]
+        assert c.status == G.OK
+        assert c.summary.n_iter == s_ref.n_iter
+        np.testing.assert_array_equal(c.context.spectrum(G.SPEC_SN), S_ref)
+        ids, it = c.context.resolved()
+        np.testing.assert_array_equal(ids, ids_ref)
+        np.testing.assert_array_equal(it, it_ref)
+        assert c.done_s >= c.admit_s >= c.arrival_s - 1e-9
+        c.context.close()
+    srv.close()
