@@ -244,6 +244,41 @@ void orc_running_mean_psd(const double *X, const double *Sx, int64_t n_bins, int
     }
 }
 
+/* Coarse-graining: Sec. "Coarse-graining of the data".  Every grid sample is
+ * assigned to its logarithmic bin by comparing f_i with the edges; the
+ * spectrum and the frequencies are averaged over each bin in ascending i. */
+int orc_coarse(const double *S, int64_t k0, int64_t n_bins, double T, double f_lo, double f_hi,
+               int64_t n_out, double *f_out, double *s_out, int64_t *count)
+{
+    if (!(f_lo > 0.0) || !(f_hi > f_lo) || n_out < 1 || !(T > 0.0)) return ORC_E_INVALID;
+    double *edge = (double *)malloc((size_t)(n_out + 1) * sizeof(double));
+    if (!edge) return ORC_E_INVALID;
+    for (int64_t j = 0; j <= n_out; ++j) edge[j] = f_lo * pow(f_hi / f_lo, (double)j / (double)n_out);
+    edge[n_out] = f_hi;
+    for (int64_t k = 0; k < n_out; ++k) {
+        f_out[k] = 0.0;
+        s_out[k] = 0.0;
+        count[k] = 0;
+    }
+    for (int64_t i = 0; i < n_bins; ++i) {
+        const double fi = (double)(k0 + i) / T;
+        if (fi < edge[0] || fi > edge[n_out]) continue;
+        int64_t k = 0;
+        while (k + 1 < n_out && fi >= edge[k + 1]) ++k;
+        f_out[k] += fi;
+        s_out[k] += S[i];
+        count[k] += 1;
+    }
+    for (int64_t k = 0; k < n_out; ++k) {
+        if (count[k] > 0) {
+            f_out[k] /= (double)count[k];
+            s_out[k] /= (double)count[k];
+        }
+    }
+    free(edge);
+    return ORC_OK;
+}
+
 /* ---------------------------------------------------------------- the loop
  * Appendix "Subtraction algorithm":
  *   2. SNR of every source against S_instr;

@@ -106,6 +106,16 @@ double  orc_snr2(double q, int64_t glo, int64_t ghi, const double *S);
 void    orc_running_median(const double *X, int64_t n_bins, int64_t W, double *out);
 void    orc_running_mean_psd(const double *X, const double *Sx, int64_t n_bins, int64_t W, double *out);
 
+/* Coarse-graining (Sec. "Coarse-graining of the data", Eqs. "coarse graining
+ * spectrum" and "coarse graining frequencies"): n_out logarithmically spaced
+ * bins with edges e_j = f_lo (f_hi/f_lo)^(j/n_out); grid sample i (f_i =
+ * (k0+i)/T) belongs to bin k iff e_k <= f_i < e_{k+1} (the last bin also
+ * takes f_i = f_hi).  f_out[k] and s_out[k] are the means of f_i and S[i]
+ * over the bin; count[k] = N_k (means are 0 where N_k = 0).  Returns
+ * ORC_E_INVALID for bad arguments. */
+int     orc_coarse(const double *S, int64_t k0, int64_t n_bins, double T, double f_lo, double f_hi,
+                   int64_t n_out, double *f_out, double *s_out, int64_t *count);
+
 /* The whole subtraction.  Returns ORC_OK, ORC_E_INVALID or ORC_E_MAXITER. */
 int     orc_run(const orc_config *c, int64_t n, const float *A, const float *f, const float *fdot,
                 orc_io *io, orc_summary *sum);

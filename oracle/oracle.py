@@ -98,6 +98,9 @@ def lib():
         L.orc_running_median.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.c_void_p]
         L.orc_running_mean_psd.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64,
                                            C.c_void_p]
+        L.orc_coarse.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.c_double, C.c_double,
+                                 C.c_double, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.orc_coarse.restype = C.c_int
         L.orc_run.argtypes = [C.POINTER(Config), C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
                               C.POINTER(IO), C.POINTER(Summary)]
         L.orc_run.restype = C.c_int
@@ -174,6 +177,21 @@ def running_median(X: np.ndarray, W: int) -> np.ndarray:
     out = np.empty_like(X)
     lib().orc_running_median(X.ctypes.data, X.shape[0], int(W), out.ctypes.data)
     return out
+
+
+def coarse(S: np.ndarray, k0: int, T: float, f_lo: float = 1e-4, f_hi: float = 1e-2,
+           n_out: int = 100):
+    """(f_k, S_k, N_k) of the logarithmic coarse-graining of S on the grid
+    f_i = (k0+i)/T."""
+    S = np.ascontiguousarray(S, np.float64)
+    fo = np.zeros(n_out)
+    so = np.zeros(n_out)
+    cnt = np.zeros(n_out, np.int64)
+    rc = lib().orc_coarse(S.ctypes.data, int(k0), S.shape[0], float(T), float(f_lo), float(f_hi),
+                          int(n_out), fo.ctypes.data, so.ctypes.data, cnt.ctypes.data)
+    if rc != OK:
+        raise ValueError("invalid coarse-graining arguments")
+    return fo, so, cnt
 
 
 def running_mean_psd(X: np.ndarray, Sx: np.ndarray, W: int) -> np.ndarray:

@@ -444,3 +444,61 @@ def test_running_mean_lone_binary_closed_form():
         assert S[k] == pytest.approx(expect, rel=1e-14)
     interior = scipy.ndimage.uniform_filter(X + Sx, size=21, mode="nearest")
     np.testing.assert_allclose(S[10:290], interior[10:290], rtol=1e-12)
+
+
+# --------------------------------------------------------------------------- coarse-graining
+
+def _coarse_brute(S, k0, T, f_lo, f_hi, n_out):
+    """Independent statement: numpy log-space edges, searchsorted membership."""
+    f = (k0 + np.arange(S.shape[0])) / T
+    e = f_lo * (f_hi / f_lo) ** (np.arange(n_out + 1) / n_out)
+    e[-1] = f_hi
+    k = np.searchsorted(e, f, side="right") - 1
+    k[f == f_hi] = n_out - 1
+    keep = (f >= f_lo) & (f <= f_hi)
+    fo, so, cnt = np.zeros(n_out), np.zeros(n_out), np.zeros(n_out, np.int64)
+    for j in range(n_out):
+        m = keep & (k == j)
+        cnt[j] = m.sum()
+        if cnt[j]:
+            fo[j] = f[m].mean()
+            so[j] = S[m].mean()
+    return fo, so, cnt
+
+
+def test_coarse_constant_and_linear_spectra():
+    """A constant spectrum averages to itself; S = a f averages to a f_k, with
+    f_k the mean frequency of the bin, i.e. (first + last sample) / 2."""
+    T = YEAR_S
+    k0, B = O.grid(T, 1e-4, 1.2e-2)
+    f = (k0 + np.arange(B)) / T
+    fo, so, cnt = O.coarse(np.full(B, 3.5e-40), k0, T)
+    assert np.all(cnt > 0) and cnt.sum() == int(((f >= 1e-4) & (f <= 1e-2)).sum())
+    # recursive summation of N equal terms: relative error <= (N - 1) u
+    u = 2.0 ** -53
+    np.testing.assert_allclose(so, 3.5e-40, rtol=(cnt.max() + 1) * u)
+    fo2, so2, _ = O.coarse(2.0 * f, k0, T)
+    np.testing.assert_allclose(so2, 2.0 * fo2, rtol=4 * (cnt.max() + 1) * u)
+    # f_k is the mean of an arithmetic progression of step 1/T
+    e = 1e-4 * 100.0 ** (np.arange(101) / 100)
+    e[-1] = 1e-2
+    for j in (0, 37, 99):
+        sel = np.nonzero((f >= e[j]) & ((f < e[j + 1]) | ((j == 99) & (f <= e[j + 1]))))[0]
+        np.testing.assert_allclose(fo[j], 0.5 * (f[sel[0]] + f[sel[-1]]), rtol=(cnt.max() + 1) * u)
+
+
+def test_coarse_matches_brute_force_and_empty_bins():
+    rng = np.random.default_rng(3)
+    T = 0.2 * YEAR_S
+    for f_lo, f_hi, n_out in [(1e-4, 1e-2, 100), (2e-4, 6e-4, 17), (1e-3, 1.05e-3, 40)]:
+        k0, B = O.grid(T, 1e-4, 1.2e-2)
+        S = rng.lognormal(-90, 2, B)
+        got = O.coarse(S, k0, T, f_lo, f_hi, n_out)
+        ref = _coarse_brute(S, k0, T, f_lo, f_hi, n_out)
+        np.testing.assert_array_equal(got[2], ref[2])
+        np.testing.assert_allclose(got[0], ref[0], rtol=1e-12)
+        np.testing.assert_allclose(got[1], ref[1], rtol=1e-12)
+    # a grid narrower than the band: bins outside it are empty, with zero means
+    k0, B = O.grid(YEAR_S, 3e-4, 1e-2)
+    fo, so, cnt = O.coarse(np.ones(B), k0, YEAR_S)
+    assert cnt[0] == 0 and fo[0] == 0 and so[0] == 0 and cnt[-1] > 0
