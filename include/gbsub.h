@@ -155,6 +155,19 @@ gbsub_status gbsub_spectrum(const gbsub_ctx *ctx, uint32_t kind, double *out, ui
 gbsub_status gbsub_resolved(const gbsub_ctx *ctx, uint32_t *ids, int32_t *iter_of, uint64_t cap,
                             uint64_t *n, int out_on_device);
 
+/* Coarse-graining of a spectrum of the last successful run (Sec.
+ * "Coarse-graining of the data"): n_out (1..256) logarithmic bins with edges
+ * e_j = f_lo (f_hi/f_lo)^(j/n_out); grid sample f_i = (k0+i)/T belongs to bin
+ * k iff e_k <= f_i < e_{k+1} (the last bin also takes f_i = f_hi).  Writes,
+ * to HOST arrays of n_out entries, the mean frequency f_k and the mean
+ * spectrum of each bin (kind as in gbsub_spectrum), the characteristic
+ * strain sqrt(f_k S_k) (Eq. "characteristic strain"; S_n is already the
+ * response-rescaled PSD) to hc_out (may be NULL) and N_k to count (may be
+ * NULL); empty bins get 0.  The paper's setting is f_lo = 0.1 mHz,
+ * f_hi = 10 mHz, n_out = 100.  STATE if no run has completed. */
+gbsub_status gbsub_coarse(const gbsub_ctx *ctx, uint32_t kind, double f_lo, double f_hi, uint32_t n_out,
+                          double *f_out, double *s_out, double *hc_out, uint32_t *count);
+
 /* Every candidate of the last successful run (the sources with rho_0 >=
  * kappa rho_th), in ascending id: ids[], the loop body that resolved it in
  * iter_of[] (-1 if never; may be NULL) and rho^2 at its last evaluation

@@ -149,6 +149,7 @@ uint64_t carve(const Grid &g, uint64_t n, char *base, Dev *d)
     t.b_evals = (uint64_t *)take((uint64_t)SNR_BLOCKS * 8);
     t.b_minm = (double *)take((uint64_t)SNR_BLOCKS * 8);
     t.n_new = (uint32_t *)take((uint64_t)NEW_CAP * 4);
+    t.coarse = (double *)take(3 * COARSE_MAX * 8);
     t.ctl = (Ctl *)take(sizeof(Ctl));
     if (d) *d = t;
     return off;
@@ -492,6 +493,36 @@ gbsub_status gbsub_spectrum(const gbsub_ctx *c, uint32_t kind, double *out, uint
     for (uint64_t k = 0; k < B; ++k) s[k] -= x[k];
     return dev_err(hipMemcpy(out, s.data(), B * 8,
                              out_on_device ? hipMemcpyHostToDevice : hipMemcpyHostToHost));
+}
+
+gbsub_status gbsub_coarse(const gbsub_ctx *c, uint32_t kind, double f_lo, double f_hi, uint32_t n_out,
+                          double *f_out, double *s_out, double *hc_out, uint32_t *count)
+{
+    if (!c || !f_out || !s_out) return GBSUB_E_INVALID;
+    if (!c->have_result) return GBSUB_E_STATE;
+    if (kind > GBSUB_SPEC_S_INSTR || n_out < 1 || n_out > (uint32_t)COARSE_MAX || !(f_lo > 0.0) ||
+        !(f_hi > f_lo) || !std::isfinite(f_hi))
+        return GBSUB_E_INVALID;
+    if (hipSetDevice(c->device) != hipSuccess) return GBSUB_E_DEVICE;
+    CoarseEdges ed;
+    for (uint32_t j = 0; j <= n_out; ++j) ed.e[j] = f_lo * std::pow(f_hi / f_lo, (double)j / (double)n_out);
+    ed.e[n_out] = f_hi;
+    const Grid &g = c->g;
+    hipError_t e = launch_coarse(c->dev.S, c->dev.sx, c->dev.X, (int)kind, g.k0, g.B, g.T, ed, (int)n_out,
+                                 c->dev.coarse, nullptr);
+    std::vector<double> h(3 * (size_t)n_out);
+    if (e == hipSuccess) e = hipMemcpy(h.data(), c->dev.coarse, h.size() * 8, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return GBSUB_E_DEVICE;
+    for (uint32_t k = 0; k < n_out; ++k) {
+        const double cnt = h[3 * k + 2];
+        const double fm = cnt > 0 ? h[3 * k] / cnt : 0.0;
+        const double sm = cnt > 0 ? h[3 * k + 1] / cnt : 0.0;
+        f_out[k] = fm;
+        s_out[k] = sm;
+        if (hc_out) hc_out[k] = std::sqrt(fm * sm);
+        if (count) count[k] = (uint32_t)cnt;
+    }
+    return GBSUB_OK;
 }
 
 gbsub_status gbsub_resolved(const gbsub_ctx *c, uint32_t *ids, int32_t *iter_of, uint64_t cap,

@@ -25,6 +25,7 @@ constexpr int POSBITS = 12;        // sort word = key << 12 | position (MMAX <= 
 constexpr int CHP = 16;            // median start table: positions per row
 constexpr int RBS = 64;            // median start table: sorted ranks per column
 enum Prec { PREC_FP64 = 0, PREC_COMP = 1, PREC_NAIVE = 2 };   // Grid::prec (= gbsub_config precision)
+constexpr int COARSE_MAX = 256;    // coarse-graining bins at most
 constexpr int PART_MAX = 512;      // outputs of a median block in split mode (prefix-of-1/S granule)
 constexpr int SPLIT_BLOCKS = 512;  // split the median into parts while dirty tiles x parts fit this
 
@@ -139,6 +140,7 @@ struct Dev {
     uint64_t *b_evals;       // [SNR_BLOCKS]
     double *b_minm;          // [SNR_BLOCKS]
     uint32_t *n_new;         // [NEW_CAP] sources subtracted per loop body
+    double *coarse;          // [3 * COARSE_MAX] coarse-graining sums (f, value, count)
     Ctl *ctl;
     uint32_t max_slots;      // capacity of `partial`
     uint32_t max_chunks;     // grid of the accumulation kernel
@@ -176,5 +178,11 @@ hipError_t launch_med_tail(const Slot *ds, const Dims &dm, hipStream_t st);
 hipError_t launch_snr(const Slot *ds, const Dims &dm, hipStream_t st);
 hipError_t launch_snr_tail(const Slot *ds, const Dims &dm, hipStream_t st);
 hipError_t launch_outputs(const Slot *ds, const Dims &dm, hipStream_t st);
+
+struct CoarseEdges { double e[COARSE_MAX + 1]; };
+// Sums of f_i and of the chosen spectrum over each logarithmic bin
+// [e_k, e_{k+1}) (the last bin closed) into out[3k .. 3k+2] = (sum f, sum v, count).
+hipError_t launch_coarse(const double *S, const double *sx, const double *X, int kind, int64_t k0, int B,
+                         double T, const CoarseEdges &ed, int n_out, double *out, hipStream_t st);
 
 }  // namespace gbs

@@ -1895,6 +1895,59 @@ hipError_t launch_snr_tail(const Slot *ds, const Dims &dm, hipStream_t st)
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ coarse-graining
+//
+// Sec. "Coarse-graining of the data": the spectrum averaged over logarithmic
+// frequency bins, and the mean frequency of each bin.  One block per bin; the
+// bin is a contiguous range of grid samples, found by binary search on f_i.
+
+__global__ __launch_bounds__(WG) void k_coarse(const double *S, const double *sx, const double *X, int kind,
+                                               int64_t k0, int B, double T, CoarseEdges ed, int n_out,
+                                               double *out)
+{
+    __shared__ double sf[WG], sv[WG];
+    const int kb = blockIdx.x;
+    if (kb >= n_out) return;
+    auto first = [&](double x, bool strict) -> int {   // first i with f_i >= x (> x if strict)
+        int lo = 0, hi = B;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            const double f = (double)(k0 + mid) / T;
+            if (strict ? f > x : f >= x) hi = mid; else lo = mid + 1;
+        }
+        return lo;
+    };
+    const int i0 = first(ed.e[kb], false);
+    const int i1 = kb == n_out - 1 ? first(ed.e[n_out], true) : first(ed.e[kb + 1], false);
+    double af = 0.0, av = 0.0;
+    for (int i = i0 + (int)threadIdx.x; i < i1; i += WG) {
+        af += (double)(k0 + i) / T;
+        av += kind == 0 ? S[i] : kind == 1 ? X[i] : kind == 2 ? S[i] - sx[i] : sx[i];
+    }
+    sf[threadIdx.x] = af;
+    sv[threadIdx.x] = av;
+    __syncthreads();
+    for (int w = WG / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            sf[threadIdx.x] += sf[threadIdx.x + w];
+            sv[threadIdx.x] += sv[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[3 * kb] = sf[0];
+        out[3 * kb + 1] = sv[0];
+        out[3 * kb + 2] = (double)(i1 > i0 ? i1 - i0 : 0);
+    }
+}
+
+hipError_t launch_coarse(const double *S, const double *sx, const double *X, int kind, int64_t k0, int B,
+                         double T, const CoarseEdges &ed, int n_out, double *out, hipStream_t st)
+{
+    k_coarse<<<n_out, WG, 0, st>>>(S, sx, X, kind, k0, B, T, ed, n_out, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_outputs(const Slot *ds, const Dims &dm, hipStream_t st)
 {
     k_cand_ids<<<dim3(SNR_BLOCKS, dm.ns), WG, 0, st>>>(ds);

@@ -23,7 +23,8 @@ FP64, FP32_COMP, FP32_NAIVE = 0, 1, 2
 SPEC_SN, SPEC_X_RESIDUAL, SPEC_S_GAL, SPEC_S_INSTR = 0, 1, 2, 3
 
 EXPORTS = ["gbsub_default_config", "gbsub_create", "gbsub_workspace_size", "gbsub_run",
-           "gbsub_spectrum", "gbsub_resolved", "gbsub_candidates", "gbsub_destroy", "gbsub_status_str",
+           "gbsub_spectrum", "gbsub_resolved", "gbsub_candidates", "gbsub_coarse", "gbsub_destroy",
+           "gbsub_status_str",
            "gbsub_set_profiling", "gbsub_kernel_stats", "gbsub_batch_table_size",
            "gbsub_batch_create", "gbsub_batch_admit", "gbsub_batch_step", "gbsub_batch_poll",
            "gbsub_batch_retire", "gbsub_batch_destroy"]
@@ -94,6 +95,8 @@ def load(path: str | None = None):
                                  C.POINTER(C.c_uint64), C.c_int]
     L.gbsub_resolved.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64,
                                  C.POINTER(C.c_uint64), C.c_int]
+    L.gbsub_coarse.argtypes = [C.c_void_p, C.c_uint32, C.c_double, C.c_double, C.c_uint32,
+                               C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
     L.gbsub_candidates.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64,
                                    C.POINTER(C.c_uint64)]
     L.gbsub_destroy.argtypes = [C.c_void_p]
@@ -113,7 +116,8 @@ def load(path: str | None = None):
     L.gbsub_batch_destroy.argtypes = [C.c_void_p]
     L.gbsub_batch_destroy.restype = None
     for name in ("gbsub_create", "gbsub_workspace_size", "gbsub_run", "gbsub_spectrum",
-                 "gbsub_resolved", "gbsub_candidates", "gbsub_set_profiling", "gbsub_kernel_stats",
+                 "gbsub_resolved", "gbsub_candidates", "gbsub_coarse", "gbsub_set_profiling",
+                 "gbsub_kernel_stats",
                  "gbsub_batch_table_size", "gbsub_batch_create", "gbsub_batch_admit",
                  "gbsub_batch_step", "gbsub_batch_poll", "gbsub_batch_retire"):
         getattr(L, name).restype = C.c_int
@@ -280,6 +284,18 @@ class Context:
         return {arr[i].name.decode(): dict(launches=arr[i].launches, total_ms=arr[i].total_ms,
                                            units=arr[i].units, unit=arr[i].unit.decode())
                 for i in range(n.value)}
+
+    def coarse(self, kind: int = SPEC_SN, f_lo: float = 1e-4, f_hi: float = 1e-2, n_out: int = 100):
+        """(f_k, S_k, h_c, N_k) of the logarithmic coarse-graining of a spectrum."""
+        f = np.empty(n_out)
+        sp = np.empty(n_out)
+        hc = np.empty(n_out)
+        cnt = np.empty(n_out, np.uint32)
+        st = self._L.gbsub_coarse(self.h, kind, float(f_lo), float(f_hi), int(n_out), f.ctypes.data,
+                                  sp.ctypes.data, hc.ctypes.data, cnt.ctypes.data)
+        if st != OK:
+            raise GbsubError(st, "gbsub_coarse")
+        return f, sp, hc, cnt
 
     def candidates(self):
         """(ids uint32 ascending, iter_of int32, rho^2 at the last evaluation) of

@@ -279,3 +279,36 @@ def test_1e7_full_size_against_oracle_golden():
     # properties that hold at any size
     Sx = O.sinstr_table(O.make_config(run))
     assert np.all(S >= Sx * (1 - 1e-12))
+
+
+# ----------------------------------------------------------------- coarse-graining
+
+@pytest.mark.parametrize("which", ["1e4", "dense"])
+def test_coarse_graining_against_oracle(which):
+    if which == "1e4":
+        cat, run = catalog_1e4()
+    else:
+        cat = draw_catalog(Population(n=200000, seed=4, f_lo=1e-4, f_hi=1.2e-2))
+        run = RunConfig(t_obs_s=YEAR_S, f_min_hz=1e-4, f_max_hz=1.2e-2, window_bins=251)
+    say(f"[coarse] {which}")
+    ro = O.run(cat, O.make_config(run))
+    cfg = O.make_config(run)
+    k0, B = O.grid(cfg.t_obs_s, cfg.f_min_hz, cfg.f_max_hz)
+    Sx = O.sinstr_table(cfg)
+    ctx = G.Context(G.config_from_run(run))
+    try:
+        ctx.run(G.DeviceCatalog.from_host(cat))
+        for kind, ref_spec in ((G.SPEC_SN, ro.S_final), (G.SPEC_S_GAL, ro.S_final - Sx)):
+            fo, so, cnt = O.coarse(ref_spec, k0, run.t_obs_s)
+            f, s, hc, n = ctx.coarse(kind)
+            np.testing.assert_array_equal(n, cnt)
+            np.testing.assert_allclose(f, fo, rtol=1e-13)
+            nz = cnt > 0
+            if kind == G.SPEC_SN:
+                np.testing.assert_allclose(s[nz], so[nz], rtol=S_RTOL)
+                np.testing.assert_allclose(hc[nz], np.sqrt(fo[nz] * so[nz]), rtol=S_RTOL)
+            else:   # the foreground alone: absolute error relative to the total PSD
+                assert np.all(np.abs(s[nz] - so[nz]) <= S_RTOL * O.coarse(ro.S_final, k0, run.t_obs_s)[1][nz])
+            assert np.all(s[~nz] == 0) and np.all(f[~nz] == 0)
+    finally:
+        ctx.close()
