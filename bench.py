@@ -301,6 +301,8 @@ def main():
     ap.add_argument("--window", type=int, default=0, help="1e7 workload: window bins (default 1001)")
     ap.add_argument("--no-tune", action="store_true",
                     help="1e7 workload: default schedule instead of the tuner's choice")
+    ap.add_argument("--schedule", default="",
+                    help="1e7 workload: TILE,SPLIT fixed schedule (tile bins, split budget), no tuning")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
@@ -333,7 +335,10 @@ def main():
     torch.cuda.set_device(0)
     dc = G.DeviceCatalog.from_host(cat)
     schedule = {"tile_bins": 0, "split_blocks": 0}
-    if not args.no_tune:
+    if args.schedule:
+        tile, split = (int(v) for v in args.schedule.split(","))
+        schedule = {"tile_bins": tile, "split_blocks": split}
+    elif not args.no_tune:
         from paper_2602_18560_amd.autotune import tune
         log("[bench] tuning the schedule (tile size, split budget)")
         schedule, _ = tune(dc, {**run.as_dict(), **overrides}, log=log)
@@ -347,21 +352,29 @@ def main():
         s = ctx.run(dc)
     torch.cuda.synchronize()
 
-    # The timed region brackets only the dominant kernel (the running median)
-    # with HIP events: every event pair costs a few microseconds, so the
-    # per-family breakdown comes from a separate profiled pass below.
+    # Whole-run throughput: K runs with no events anywhere (an event on a
+    # dispatch leaves the GPU idle for a few microseconds on each side).
     fam = "median"
     log(f"[bench] timed x{args.steps}")
-    ctx.set_profiling(1 << G.KF_MEDIAN)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         s = ctx.run(dc)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    st = ctx.kernel_stats()[fam]
     ms = (t1 - t0) * 1e3 / args.steps
     value = cat.n * s.n_iter / (ms * 1e-3)
+    # The dominant kernel's launch durations: the same K runs again, with
+    # HIP events carried by every working median dispatch (on its stream).
+    log(f"[bench] median launch durations (HIP events) x{args.steps}")
+    ctx.set_profiling(1 << G.KF_MEDIAN)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.run(dc)
+    torch.cuda.synchronize()
+    ms_ev = (time.perf_counter() - t2) * 1e3 / args.steps
+    st = ctx.kernel_stats()[fam]
     avg_ms = st["total_ms"] / max(st["launches"], 1)
     bytes_per_launch = ALGO_BYTES[fam] * st["units"] / max(st["launches"], 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
@@ -401,7 +414,8 @@ def main():
         "roofline": {"bound": "hbm", "kernel": "k_" + args.estimator, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic("k_median") if args.estimator == "median" else None,
-                     "avg_launch_ms": avg_ms, "algo_bytes_per_launch": bytes_per_launch},
+                     "avg_launch_ms": avg_ms, "algo_bytes_per_launch": bytes_per_launch,
+                     "launches": st["launches"], "ms_per_step_with_events": ms_ev},
         "run_level_hbm": {"algo_bytes_per_step": total_algo,
                           "achieved_GBs": total_algo / (ms * 1e-3) / 1e9,
                           "frac": total_algo / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS},

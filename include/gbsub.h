@@ -184,31 +184,33 @@ enum {
     GBSUB_KF_RESET = 1,          /* per-run state */
     GBSUB_KF_PREP = 2,           /* candidate cut, binning, fixed-point accumulation */
     GBSUB_KF_XUPDATE = 3,        /* X from the fixed-point accumulators */
-    GBSUB_KF_MEDIAN = 4,         /* running median and S = C med + S_instr */
-    GBSUB_KF_MEDIAN_TAIL = 5,    /* prefix of the part sums of 1/S */
-    GBSUB_KF_SNR = 6,            /* rho^2, decisions, subtraction */
-    GBSUB_KF_SNR_TAIL = 7,       /* counts, settle test, dirty tiles */
-    GBSUB_KF_OUTPUT = 8,         /* candidate ids */
-    GBSUB_KF_COUNT = 9
+    GBSUB_KF_MEDIAN = 4,         /* running median, S = C med + S_instr, in-part prefix of 1/S */
+    GBSUB_KF_SNR = 5,            /* prefix of the part sums of 1/S, rho^2, decisions,
+                                    subtraction, dirty tiles, settle test */
+    GBSUB_KF_OUTPUT = 6,         /* candidate ids */
+    GBSUB_KF_COUNT = 7
 };
-#define GBSUB_PROFILE_ALL 0x1FFu
+#define GBSUB_PROFILE_ALL 0x7Fu
 
 /* Per-kernel timing of the runs made while profiling is enabled. */
 typedef struct {
     char     name[24];           /* kernel family: "tables", "reset", "prep", "xupdate",
-                                    "median", "median_tail", "snr", "snr_tail", "output" */
+                                    "median", "snr", "output" */
     uint64_t launches;           /* launches that did work (bodies past the settled one excluded) */
     double   total_ms;           /* sum of HIP-event durations on the run's stream */
     double   units;              /* work units processed by those launches */
-    char     unit[16];           /* "bins", "sources", "candidates", "tiles" */
+    char     unit[16];           /* "bins", "sources", "candidates" */
 } gbsub_kernel_stat;
 
 /* Selects the kernel families to time (a mask of 1u << GBSUB_KF_*, 0 = off,
  * GBSUB_PROFILE_ALL = every family) and clears the accumulated stats.  While
- * a family is selected, gbsub_run brackets each of its launches with HIP
- * events on its stream (host-side events only; no device memory); the
- * events cost some microseconds per launch, so time a run with only the
- * families of interest selected.  Batched runs are not timed. */
+ * a family is selected, gbsub_run times each of its launches with HIP
+ * events (host-side events only; no device memory): the loop-body kernels
+ * (xupdate, median, snr) carry the events on their dispatches, the
+ * once-per-run families are bracketed by events recorded on the stream.
+ * Either way an event costs some microseconds of idle time between
+ * launches, so time a run with only the families of interest selected.
+ * Batched runs are not timed. */
 gbsub_status gbsub_set_profiling(gbsub_ctx *ctx, uint32_t families);
 
 /* Copies up to `cap` accumulated kernel stats into out[] (host pointer);

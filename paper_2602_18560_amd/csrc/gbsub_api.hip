@@ -57,16 +57,28 @@ struct gbsub_ctx {
         return ev_pool[ev_used++];
     }
 
-    // Launches through `fn`, bracketed by events when profiling.
+    // Launches through `fn`, bracketed by events when profiling: the
+    // events are recorded on the stream around fn().
     template <typename F>
     hipError_t timed(int kid, int64_t t, hipStream_t st, F fn)
     {
-        if (!(profiling >> kid & 1u)) return fn();
+        return timed_ext(kid, t, [&](hipEvent_t a, hipEvent_t b) {
+            hipError_t e = a ? hipEventRecord(a, st) : hipSuccess;
+            if (e == hipSuccess) e = fn();
+            if (e == hipSuccess && b) e = hipEventRecord(b, st);
+            return e;
+        });
+    }
+
+    // Launches through fn(start, end); a loop-body launcher hands the
+    // events to its dispatch, which stamps them itself (no stream work).
+    template <typename F>
+    hipError_t timed_ext(int kid, int64_t t, F fn)
+    {
+        if (!(profiling >> kid & 1u)) return fn(nullptr, nullptr);
         hipEvent_t a = next_event(), b = next_event();
         if (!a || !b) return hipErrorOutOfMemory;
-        hipError_t e = hipEventRecord(a, st);
-        if (e == hipSuccess) e = fn();
-        if (e == hipSuccess) e = hipEventRecord(b, st);
+        const hipError_t e = fn(a, b);
         recs.push_back({kid, t, a, b});
         return e;
     }
@@ -112,6 +124,7 @@ uint64_t carve(const Grid &g, uint64_t n, char *base, Dev *d)
     t.D = (I128 *)take((B + 1) * 16);
     t.Dtile = (I128 *)take((nt + 1) * 16);
     t.Dcarry = (I128 *)take((nt + 1) * 16);
+    t.Dadj = (SplitSum *)take(nt * 16);
     const bool naive = g.prec == GBSUB_FP32_NAIVE;
     t.Xf = (float *)take(naive ? B * 4 : 0);
     t.Df = (float *)take(naive ? (B + 1) * 4 : 0);
@@ -122,10 +135,8 @@ uint64_t carve(const Grid &g, uint64_t n, char *base, Dev *d)
     t.is_pre = (double *)take(B * 8);
     t.is_psum = (double *)take((uint64_t)g.nparts * 8);
     t.is_part = (double *)take(((uint64_t)g.nparts + 1) * 8);
-    t.chgx = (int32_t *)take((nt + 1) * 4);
-    t.chgs = (int32_t *)take((nt + 1) * 4);
-    t.xdirty = (uint8_t *)take(align_up(nt));
-    t.sdirty = (uint8_t *)take(align_up(nt));
+    t.xstamp = (uint32_t *)take(nt * 4);
+    t.sstamp = (uint32_t *)take(nt * 4);
     t.btot = (uint32_t *)take(nt * 4);
     t.bbase = (uint32_t *)take((nt + 1) * 4);
     t.cursor = (uint32_t *)take(nt * 4);
@@ -144,10 +155,7 @@ uint64_t carve(const Grid &g, uint64_t n, char *base, Dev *d)
     t.c_q = (double *)take(nn * 8);
     t.c_qfx = (uint64_t *)take(nn * 8);
     t.c_rho2 = (double *)take(nn * 8);
-    t.b_new = (uint32_t *)take((uint64_t)SNR_BLOCKS * 4);
-    t.b_near = (uint64_t *)take((uint64_t)SNR_BLOCKS * 8);
-    t.b_evals = (uint64_t *)take((uint64_t)SNR_BLOCKS * 8);
-    t.b_minm = (double *)take((uint64_t)SNR_BLOCKS * 8);
+    t.b_part = (SnrPart *)take((uint64_t)SNR_BLOCKS * sizeof(SnrPart));
     t.n_new = (uint32_t *)take((uint64_t)NEW_CAP * 4);
     t.coarse = (double *)take(3 * COARSE_MAX * 8);
     t.ctl = (Ctl *)take(sizeof(Ctl));
@@ -243,6 +251,7 @@ Dims dims_of(const Slot &sl)
     dm.maxtile = sl.g.tile;
     dm.maxparts = sl.g.nparts;
     dm.est_mask = 1u << sl.g.est;
+    dm.naive = sl.g.prec == PREC_NAIVE;
     dm.prep_blocks = (uint32_t)((sl.n + PREP_SRC - 1) / PREP_SRC);
     dm.accum_blocks = sl.d.max_chunks;
     return dm;
@@ -255,6 +264,7 @@ void widen(Dims &a, const Dims &b)
     a.maxtile = std::max(a.maxtile, b.maxtile);
     a.maxparts = std::max(a.maxparts, b.maxparts);
     a.est_mask |= b.est_mask;
+    a.naive |= b.naive;
     a.prep_blocks = std::max(a.prep_blocks, b.prep_blocks);
     a.accum_blocks = std::max(a.accum_blocks, b.accum_blocks);
 }
@@ -414,11 +424,17 @@ gbsub_status gbsub_run(gbsub_ctx *c, const gbsub_catalog *cat, void *ws, uint64_
     for (;;) {
         for (uint64_t i = 0; i < chunk && e == hipSuccess; ++i) {
             const int64_t ti = (int64_t)(t + i);
-            e = c->timed(K_XUPDATE, ti, st, [&] { return launch_xupdate(ds, dm, st); });
-            if (e == hipSuccess) e = c->timed(K_MEDIAN, ti, st, [&] { return launch_median(ds, dm, st); });
-            if (e == hipSuccess) e = c->timed(K_MEDTAIL, ti, st, [&] { return launch_med_tail(ds, dm, st); });
-            if (e == hipSuccess) e = c->timed(K_SNR, ti, st, [&] { return launch_snr(ds, dm, st); });
-            if (e == hipSuccess) e = c->timed(K_SNRTAIL, ti, st, [&] { return launch_snr_tail(ds, dm, st); });
+            e = c->timed_ext(K_XUPDATE, ti, [&](hipEvent_t a, hipEvent_t b) {
+                return launch_xupdate(ds, dm, st, a, b);
+            });
+            if (e == hipSuccess)
+                e = c->timed_ext(K_MEDIAN, ti, [&](hipEvent_t a, hipEvent_t b) {
+                    return launch_median(ds, dm, st, a, b);
+                });
+            if (e == hipSuccess)
+                e = c->timed_ext(K_SNR, ti, [&](hipEvent_t a, hipEvent_t b) {
+                    return launch_snr(ds, dm, st, a, b);
+                });
         }
         t += chunk;
         if (e == hipSuccess) e = hipMemcpyAsync(c->host_ctl, d.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st);
@@ -447,14 +463,11 @@ gbsub_status gbsub_run(gbsub_ctx *c, const gbsub_catalog *cat, void *ws, uint64_
             if (r.kid == K_TABLES) c->k_units[K_TABLES] += (double)g.B;
         }
         const uint32_t m = c->profiling;
-        const double body_tiles = (double)g.nt * (double)h.n_iter;
         if (m >> K_PREP & 1u) c->k_units[K_PREP] += (double)cat->n;
         if (m >> K_RESET & 1u) c->k_units[K_RESET] += (double)g.B;
         if (m >> K_XUPDATE & 1u) c->k_units[K_XUPDATE] += (double)h.units_x;
         if (m >> K_MEDIAN & 1u) c->k_units[K_MEDIAN] += (double)h.units_med;
-        if (m >> K_MEDTAIL & 1u) c->k_units[K_MEDTAIL] += body_tiles;
         if (m >> K_SNR & 1u) c->k_units[K_SNR] += (double)h.units_snr;
-        if (m >> K_SNRTAIL & 1u) c->k_units[K_SNRTAIL] += body_tiles;
         if (m >> K_OUTPUT & 1u) c->k_units[K_OUTPUT] += (double)h.n_cand;
     }
     const gbsub_summary s = summary_of(g, h);
@@ -603,10 +616,9 @@ gbsub_status gbsub_set_profiling(gbsub_ctx *c, uint32_t families)
 gbsub_status gbsub_kernel_stats(const gbsub_ctx *c, gbsub_kernel_stat *out, uint32_t cap, uint32_t *n)
 {
     if (!c || !n) return GBSUB_E_INVALID;
-    static const char *names[K_COUNT] = {"tables", "reset", "prep", "xupdate", "median", "median_tail",
-                                         "snr", "snr_tail", "output"};
-    static const char *units[K_COUNT] = {"bins", "bins", "sources", "bins", "bins", "tiles",
-                                         "candidates", "tiles", "candidates"};
+    static const char *names[K_COUNT] = {"tables", "reset", "prep", "xupdate", "median", "snr", "output"};
+    static const char *units[K_COUNT] = {"bins", "bins", "sources", "bins", "bins", "candidates",
+                                         "candidates"};
     *n = K_COUNT;
     if (cap < (uint32_t)K_COUNT) return GBSUB_E_TRUNCATED;
     if (!out) return GBSUB_E_INVALID;
@@ -649,7 +661,7 @@ namespace {
 bool same_dims(const Dims &a, const Dims &b)
 {
     return a.ns == b.ns && a.maxB == b.maxB && a.maxnt == b.maxnt && a.maxtile == b.maxtile &&
-           a.maxparts == b.maxparts && a.est_mask == b.est_mask;
+           a.maxparts == b.maxparts && a.est_mask == b.est_mask && a.naive == b.naive;
 }
 
 void drop_graph(gbsub_batch *b)
@@ -666,9 +678,7 @@ hipError_t enqueue_bodies(const Slot *ds, const Dims &dm, uint32_t n, hipStream_
     for (uint32_t i = 0; i < n && e == hipSuccess; ++i) {
         e = launch_xupdate(ds, dm, st);
         if (e == hipSuccess) e = launch_median(ds, dm, st);
-        if (e == hipSuccess) e = launch_med_tail(ds, dm, st);
         if (e == hipSuccess) e = launch_snr(ds, dm, st);
-        if (e == hipSuccess) e = launch_snr_tail(ds, dm, st);
     }
     return e;
 }

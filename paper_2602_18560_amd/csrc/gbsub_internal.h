@@ -8,12 +8,10 @@
 namespace gbs {
 
 constexpr int WG = 256;            // threads per workgroup for every tiled kernel
-constexpr int TWG = 1024;          // threads of the one-block tail kernels
+constexpr int PWG = 1024;          // threads of the one-block scan of the part sums of 1/S
 constexpr int MMAX = 3072;         // median tile: outputs + W - 1 must fit
 constexpr int TILE_MAX = 2048;     // bins per tile (also the binning bucket)
 constexpr int NBK_MAX = 8192;      // tiles the prep histogram can hold (B <= 8192 tiles)
-constexpr int SWG = 512;           // threads of the SNR tail kernel
-constexpr int SPER = NBK_MAX / SWG;   // tiles per thread of the SNR tail kernel
 constexpr int NARROW = 16;         // tracks of <= NARROW bins: SNR summed bin by bin
 constexpr int SNR_BLOCKS = 1024;   // fixed grid of the per-candidate kernels
 constexpr int PREP_SRC = 8192;     // sources per prep block
@@ -22,8 +20,6 @@ constexpr int RED_BINS = 256;      // bins per reduction block of the hot bucket
 constexpr int NEW_CAP = 1 << 16;   // per-iteration counters kept (iterations beyond: not recorded)
 constexpr int KEYBITS = 20;        // bits of the per-tile order key of the median sort
 constexpr int POSBITS = 12;        // sort word = key << 12 | position (MMAX <= 4096)
-constexpr int CHP = 16;            // median start table: positions per row
-constexpr int RBS = 64;            // median start table: sorted ranks per column
 enum Prec { PREC_FP64 = 0, PREC_COMP = 1, PREC_NAIVE = 2 };   // Grid::prec (= gbsub_config precision)
 constexpr int COARSE_MAX = 256;    // coarse-graining bins at most
 constexpr int PART_MAX = 512;      // outputs of a median block in split mode (prefix-of-1/S granule)
@@ -35,6 +31,14 @@ constexpr int SPLIT_BLOCKS = 512;  // split the median into parts while dirty ti
 struct alignas(16) I128 {
     uint64_t lo;
     int64_t hi;
+};
+
+// Signed 128-bit sum kept as h 2^32 + l in two 64-bit words, so that adds
+// need no carry between the words: non-returning atomics, exact while fewer
+// than 2^32 terms have been added.
+struct alignas(16) SplitSum {
+    int64_t h;
+    uint64_t l;
 };
 
 // Device control block (lives in the workspace).
@@ -58,9 +62,17 @@ struct Ctl {
     uint32_t med_split;      // next median launch: one block per part (1) or per tile (0)
 };
 
+// Per-block partial results of k_snr (combined by k_snr_tail).
+struct SnrPart {
+    uint32_t n_new;          // sources subtracted
+    uint32_t pad;
+    uint64_t near;           // evaluations within 1e-6 of the threshold
+    uint64_t evals;          // candidate evaluations
+    double minm;             // min |rho/rho_th - 1|
+};
+
 // Kernels that the profiling mode times separately.
-enum KernelId { K_TABLES = 0, K_RESET, K_PREP, K_XUPDATE, K_MEDIAN, K_MEDTAIL, K_SNR, K_SNRTAIL, K_OUTPUT,
-                K_COUNT };
+enum KernelId { K_TABLES = 0, K_RESET, K_PREP, K_XUPDATE, K_MEDIAN, K_SNR, K_OUTPUT, K_COUNT };
 
 struct Grid {
     int32_t B;               // bins
@@ -99,22 +111,23 @@ struct Dev {
     // binned power: X = Xn + prefix(D), all exact 128-bit fixed point
     I128 *Xn;                // [B]    sources whose clipped track is one bin
     I128 *D;                 // [B+1]  difference array of the wider tracks
-    I128 *Dtile;             // [nt+1] per-tile sums of D
-    I128 *Dcarry;            // [nt+1] exclusive prefix of Dtile
+    I128 *Dtile;             // [nt+1] per-tile sums of D (binning)
+    I128 *Dcarry;            // [nt+1] sum of D before each tile, as binned
+    SplitSum *Dadj;          // [nt]   change of that sum by the subtractions so far
     // naive FP32 mode only: the binned power accumulated in fp32
     float *Xf;               // [B]    one-bin tracks
     float *Df;               // [B+1]  difference array of the wider tracks
-    float *Dtf;              // [nt+1] per-tile sums of Df
-    float *Dcf;              // [nt+1] exclusive prefix of Dtf
+    float *Dtf;              // [nt+1] per-tile sums of Df (binning)
+    float *Dcf;              // [nt+1] sum of Df before each tile
     double *X;               // [B]    X^t
     double *S;               // [B]    S^t
     double *is_pre;          // [B]    inclusive prefix of 1/S^t inside each part
     double *is_psum;         // [nparts]   part sums of 1/S^t
     double *is_part;         // [nparts+1] exclusive prefix of the part sums
-    int32_t *chgx;           // [nt+1] tiles whose X changes (difference counters)
-    int32_t *chgs;           // [nt+1] tiles whose S must be recomputed
-    uint8_t *xdirty;         // [nt]
-    uint8_t *sdirty;         // [nt]
+    // dirty tiles: a tile is converted (X) / filtered (S) in body t iff its
+    // stamp equals t; k_snr stamps t + 1 where a subtraction changes them
+    uint32_t *xstamp;        // [nt]
+    uint32_t *sstamp;        // [nt]
     // binning by tile (multisplit): events sorted by tile
     uint32_t *btot;          // [nt]   events per tile
     uint32_t *bbase;         // [nt+1] first event of each tile
@@ -134,11 +147,7 @@ struct Dev {
     double *c_q;             // per-bin power
     uint64_t *c_qfx;         // per-bin power in fixed point
     double *c_rho2;          // rho^2 at the last evaluation
-    // per-block partial results of k_snr
-    uint32_t *b_new;         // [SNR_BLOCKS]
-    uint64_t *b_near;        // [SNR_BLOCKS]
-    uint64_t *b_evals;       // [SNR_BLOCKS]
-    double *b_minm;          // [SNR_BLOCKS]
+    SnrPart *b_part;         // [SNR_BLOCKS] per-block partials of k_snr
     uint32_t *n_new;         // [NEW_CAP] sources subtracted per loop body
     double *coarse;          // [3 * COARSE_MAX] coarse-graining sums (f, value, count)
     Ctl *ctl;
@@ -164,6 +173,7 @@ struct Dims {
     int ns;                  // slots (gridDim.y)
     int maxB, maxnt, maxtile, maxparts;
     uint32_t est_mask;       // bit e: some slot uses estimator e
+    uint32_t naive;          // some slot runs in naive FP32
     uint32_t prep_blocks, accum_blocks;
 };
 
@@ -172,11 +182,14 @@ struct Dims {
 hipError_t launch_grid_tables(const Slot *ds, const Dims &dm, hipStream_t st);
 hipError_t launch_reset(const Slot *ds, const Dims &dm, hipStream_t st);
 hipError_t launch_prep(const Slot *ds, const Dims &dm, hipStream_t st);
-hipError_t launch_xupdate(const Slot *ds, const Dims &dm, hipStream_t st);
-hipError_t launch_median(const Slot *ds, const Dims &dm, hipStream_t st);
-hipError_t launch_med_tail(const Slot *ds, const Dims &dm, hipStream_t st);
-hipError_t launch_snr(const Slot *ds, const Dims &dm, hipStream_t st);
-hipError_t launch_snr_tail(const Slot *ds, const Dims &dm, hipStream_t st);
+// The loop body's launchers take optional events that the dispatch itself
+// stamps with its start and end (nullptr: none).
+hipError_t launch_xupdate(const Slot *ds, const Dims &dm, hipStream_t st, hipEvent_t ea = nullptr,
+                          hipEvent_t eb = nullptr);
+hipError_t launch_median(const Slot *ds, const Dims &dm, hipStream_t st, hipEvent_t ea = nullptr,
+                         hipEvent_t eb = nullptr);
+hipError_t launch_snr(const Slot *ds, const Dims &dm, hipStream_t st, hipEvent_t ea = nullptr,
+                      hipEvent_t eb = nullptr);
 hipError_t launch_outputs(const Slot *ds, const Dims &dm, hipStream_t st);
 
 struct CoarseEdges { double e[COARSE_MAX + 1]; };

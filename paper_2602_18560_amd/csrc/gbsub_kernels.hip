@@ -15,6 +15,7 @@
 // SNR and the median read fp64 values converted from it with one rounding.
 
 #include "gbsub_internal.h"
+#include <hip/hip_ext.h>
 
 #include <math.h>
 
@@ -61,6 +62,23 @@ DEVI double i128_to_double(I128 v)
     const uint64_t rest = v.lo << lz;
     top |= (uint64_t)(rest != 0);       // sticky bit keeps round-to-nearest exact
     return ldexp((double)top, 64 - lz);
+}
+
+DEVI void split_sum_add(SplitSum *p, int64_t v)
+{
+    atomicAdd((unsigned long long *)&p->h, (unsigned long long)(v >> 32));   // floor(v / 2^32)
+    atomicAdd((unsigned long long *)&p->l, (unsigned long long)((uint64_t)v & 0xFFFFFFFFull));
+}
+
+DEVI I128 split_sum_value(SplitSum s)
+{
+    I128 x;
+    x.lo = (uint64_t)s.h << 32;
+    x.hi = s.h >> 32;
+    I128 y;
+    y.lo = s.l;
+    y.hi = 0;
+    return i128_add(x, y);
 }
 
 // Fixed-point unit 2^L: every per-bin power q <= A_max^2 T / 2 maps to an
@@ -284,7 +302,7 @@ __global__ __launch_bounds__(WG) void k_sx_scan(const Slot *S)
 // ------------------------------------------------------------------ reset
 
 // Clears the per-run state of a slot: control block, tile counters, dirty
-// flags (every tile is dirty for the first loop body).
+// stamps (every tile is dirty for the first loop body, t = 0).
 __global__ __launch_bounds__(WG) void k_reset(const Slot *S)
 {
     const Slot &sl = S[blockIdx.y];
@@ -311,14 +329,12 @@ __global__ __launch_bounds__(WG) void k_reset(const Slot *S)
         c->status = 0;
         c->med_split = (uint32_t)g.nt <= g.split_tiles;   // every tile is dirty
     }
-    for (int i = blockIdx.x * WG + threadIdx.x; i <= g.nt; i += gridDim.x * WG) {
-        if (i < g.nt) {
-            d.btot[i] = 0;
-            d.xdirty[i] = 1;
-            d.sdirty[i] = 1;
-        }
-        d.chgx[i] = 0;
-        d.chgs[i] = 0;
+    for (int i = blockIdx.x * WG + threadIdx.x; i < g.nt; i += gridDim.x * WG) {
+        d.btot[i] = 0;
+        d.xstamp[i] = 0;          // body 0 converts and filters every tile
+        d.sstamp[i] = 0;
+        d.Dadj[i].h = 0;
+        d.Dadj[i].l = 0;
     }
 }
 
@@ -844,7 +860,7 @@ __global__ __launch_bounds__(WG) void k_xupdate(const Slot *S)
     const Dev d = sl.d;
     if (d.ctl->done || d.ctl->bad) return;
     const int tile = blockIdx.x;
-    if (tile >= g.nt || !d.xdirty[tile]) return;
+    if (tile >= g.nt || d.xstamp[tile] != d.ctl->iter) return;
     const int L = fx_exp(d.ctl->amax_bits, g.T);
     const int t0 = tile * g.tile;
     const int n = min(g.tile, g.B - t0);
@@ -862,7 +878,7 @@ __global__ __launch_bounds__(WG) void k_xupdate(const Slot *S)
     }
     I128 tot;
     I128 ex = block_excl_scan(s, sh, &tot);
-    ex = i128_add(ex, d.Dcarry[tile]);
+    ex = i128_add(ex, i128_add(d.Dcarry[tile], split_sum_value(d.Dadj[tile])));
 #pragma unroll
     for (int r = 0; r < 8; ++r)
         if (r < R && b + r < n) stage[xpad(b + r)] = i128_add(stage[xpad(b + r)], ex);
@@ -910,33 +926,44 @@ __global__ __launch_bounds__(WG) void k_xupdate(const Slot *S)
 // (tile + W - 1 bins) is loaded once into LDS and sorted there: a stable LSD
 // radix sort on a per-tile 20-bit order key (the fp64 bit pattern minus the
 // tile minimum, shifted), then an exact repair that orders equal keys by
-// the full fp64 value.  Each of the 512 threads owns R = tile/512 (at most
-// 4) consecutive outputs: it
-// locates the median of its first window through a 2-D count table
-// (positions x sorted ranks) and slides the window one bin at a time,
-// moving the median pointer along the sorted order when the count of active
-// elements below it changes.  Selection is exact: no arithmetic touches X.
+// the full fp64 value.  The sorted index (rank) of every union position
+// then goes into a wavelet matrix: one stable partition of the rank
+// sequence per rank bit, most significant first, down to buckets of 32
+// consecutive ranks, with the bit words and a zero count per 64 positions
+// kept in LDS.  The median of a window is the h-th smallest rank among its
+// W positions: descending the levels (two rank queries per level) gives its
+// bucket and its index there, and the bucket's 32 sorted elements are
+// tested against the window.  Each of the 512 threads answers its
+// R = tile/512 (at most 4) windows independently.  Selection is exact: no
+// arithmetic touches X.
 
 constexpr int MWG = 512;                    // threads of a median block
 constexpr int RMAX = TILE_MAX / MWG;        // outputs per thread, at most
 constexpr int MCH = MMAX / MWG;             // union elements per thread in the sort
-constexpr int NCMAX = MMAX / CHP;          // start-table rows (+1)
-constexpr int NBMAX = MMAX / RBS;          // start-table columns (+1)
-constexpr int TLD = NBMAX + 1;             // start-table row stride (u16)
-constexpr int TWORDS = (NBMAX + 2) / 2;    // 16-bit fields of a table row, two per word
+constexpr int WLB = 12;                     // wavelet levels, at most: ranks < MMAX <= 2^12
+constexpr int WWD = MMAX / 64 + 1;          // 64-position words per level (+1: the end position)
+
+// One 64-position word of a wavelet level: its bits and the zeros before it.
+struct alignas(16) WWord {
+    uint64_t bits;
+    uint32_t zpre;
+    uint32_t pad;
+};
 
 struct MedianSmem {
     double xv[MMAX];                       // X over the union, position order
     uint32_t kp[2][MMAX];                  // sort words: key << POSBITS | position
     uint16_t rank[MMAX];                   // sorted index of each position
-    uint64_t bm1[MMAX / 16];               // position chunks present in each 16 sorted elements
-    uint64_t bm2[MMAX / 256];              // ... in each 256 sorted elements
     union {
         uint16_t off[16 * MWG];             // radix: per-thread digit offsets
-        uint16_t tbl[(NCMAX + 1) * TLD];   // start table
+        struct {
+            WWord w[WLB][WWD];             // bits of the positions, level by level
+            uint32_t zt[WLB];              // zeros of the level
+            uint32_t zc[MCH * (MWG / 64)]; // zeros per (element chunk, wave)
+        } wm;                              // wavelet matrix of the ranks
         double stage[TILE_MAX];            // outputs, for coalesced stores
     } u;
-    uint32_t wsc[(MWG / 64 + 1) * TWORDS];  // cross-wave scan exchange
+    uint32_t wsc[(MWG / 64 + 1) * 8];       // cross-wave scan exchange of the radix sort
     uint64_t red[2 * (MWG / 64)];
     double dsh[MWG / 64];
     int flag;
@@ -1097,13 +1124,13 @@ __global__ __launch_bounds__(MWG, 2) void k_median(const Slot *S)
     if (d.ctl->done || d.ctl->bad) return;
     const int tid = threadIdx.x;
     const int B = g.B, W = g.W, h = g.h;
-    // One block per tile, or (split mode, chosen by the previous body's tail
-    // when few tiles are dirty) one block per part: more, shorter blocks.
+    // One block per tile, or (split mode, chosen by the previous body's SNR
+    // launch when few tiles are dirty) one block per part: more, shorter blocks.
     const bool split = d.ctl->med_split != 0;
     const int span = split ? g.part : g.tile;
     const int blk = blockIdx.x;
     const int tile = split ? blk / g.np : blk;
-    if (tile >= g.nt || blk * span >= B || !d.sdirty[tile]) return;
+    if (tile >= g.nt || blk * span >= B || d.sstamp[tile] != d.ctl->iter) return;
 
     const int t0 = blk * span;
     const int t1 = min(t0 + span, B);
@@ -1199,22 +1226,6 @@ __global__ __launch_bounds__(MWG, 2) void k_median(const Slot *S)
         }
     }
     for (int i = tid; i < M; i += MWG) sm.rank[sw[i] & 0xFFFu] = (uint16_t)i;
-    // skip masks for the walks: bit c of bm1[b] is set iff one of the sorted
-    // elements 16b .. 16b+15 lies in position chunk c (chunks of CW bins)
-    const int CW = (M + 63) / 64;
-    for (int b = tid; b < (M + 15) / 16; b += MWG) {
-        uint64_t m = 0;
-        const int e = min(16 * b + 16, M);
-        for (int i = 16 * b; i < e; ++i) m |= 1ull << ((sw[i] & 0xFFFu) / CW);
-        sm.bm1[b] = m;
-    }
-    __syncthreads();
-    for (int b = tid; b < (M + 255) / 256; b += MWG) {
-        uint64_t m = 0;
-        const int e = min(16 * b + 16, (M + 15) / 16);
-        for (int i = 16 * b; i < e; ++i) m |= sm.bm1[i];
-        sm.bm2[b] = m;
-    }
     __syncthreads();
 
     const int R = (span + MWG - 1) / MWG;
@@ -1226,192 +1237,146 @@ __global__ __launch_bounds__(MWG, 2) void k_median(const Slot *S)
 #pragma unroll
         for (int r = 0; r < RMAX; ++r) med[r] = m;
     } else {
-        // ---- start table: tbl[c][b] = #{p < c*CHP : rank[p] < b*RBS}
-        const int NC = (M + CHP - 1) / CHP, NB = (M + RBS - 1) / RBS;
-        {
-            // thread t counts chunk t (row t+1), columns as 8-bit fields
-            uint64_t hcol[(NBMAX + 8) / 8];
+        // ---- wavelet matrix of the rank sequence, levels LB-1 .. WB (the
+        // rank bits above the 32-rank buckets).  Element i of a level is
+        // handled by thread i % MWG (chunk j = i / MWG), so a wave's ballot
+        // is one 64-position word.
+        constexpr int NV = MWG / 64;
+        constexpr int WB = 5;                           // bucket: 2^WB consecutive ranks
+        const int lane = lane_id();
+        const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+        const int NJ = (M + MWG - 1) / MWG;
+        const int LB = M > 1 ? 32 - __clz((uint32_t)(M - 1)) : 1;
+        const uint64_t below = (1ull << lane) - 1ull;
+        uint16_t *src = sm.rank;
+        uint16_t *dst = reinterpret_cast<uint16_t *>(sm.kp[rb ^ 1]);   // free after the sort
+        uint64_t in[MCH];
 #pragma unroll
-            for (int j = 0; j < (NBMAX + 8) / 8; ++j) hcol[j] = 0;
-            if (tid < NC) {
+        for (int j = 0; j < MCH; ++j) in[j] = __ballot(j < NJ && j * MWG + tid < M);
+        for (int lvl = LB - 1; lvl >= WB; --lvl) {
+            uint32_t v[MCH];
+            uint64_t one[MCH];
 #pragma unroll
-                for (int i = 0; i < CHP; ++i) {
-                    const int p = tid * CHP + i;
-                    if (p < M) {
-                        const int col = sm.rank[p] / RBS + 1;   // counts ranks < b*RBS for b >= col
+            for (int j = 0; j < MCH; ++j) {
+                const int i = j * MWG + tid;
+                const bool ok = j < NJ && i < M;
+                v[j] = ok ? (uint32_t)src[i] : 0u;
+                one[j] = __ballot(ok && ((v[j] >> lvl) & 1u));
+                if (lane == 0 && j < NJ) sm.u.wm.zc[j * NV + wave] = (uint32_t)__popcll(in[j] & ~one[j]);
+            }
+            __syncthreads();
+            // exclusive prefix of the zero counts in element order
+            const uint32_t zv = lane < NJ * NV ? sm.u.wm.zc[lane] : 0u;
+            const uint32_t zinc = wave_scan_u32(zv);
+            const uint32_t zex = zinc - zv;
+            const uint32_t ztot = (uint32_t)__builtin_amdgcn_readlane((int)zinc, NJ * NV - 1);
 #pragma unroll
-                        for (int j = 0; j < (NBMAX + 8) / 8; ++j)
-                            hcol[j] += ((col >> 3) == j) ? (1ull << (8 * (col & 7))) : 0ull;
+            for (int j = 0; j < MCH; ++j) {
+                const uint32_t zw = (uint32_t)__builtin_amdgcn_readlane((int)zex, min(j, NJ - 1) * NV + wave);
+                const int i = j * MWG + tid;
+                if (j < NJ && i < M) {
+                    const uint32_t zb = zw + (uint32_t)__popcll(in[j] & ~one[j] & below);
+                    const bool bit = (v[j] >> lvl) & 1u;
+                    dst[bit ? ztot + (uint32_t)i - zb : zb] = (uint16_t)v[j];
+                    if (lane == 0) {
+                        WWord e;
+                        e.bits = one[j];
+                        e.zpre = zw;
+                        e.pad = 0;
+                        sm.u.wm.w[lvl][i >> 6] = e;
                     }
                 }
             }
-            // cumulative over columns (fields <= CHP, no overflow)
-            uint64_t carry = 0;
-#pragma unroll
-            for (int j = 0; j < (NBMAX + 8) / 8; ++j) {
-                uint64_t x = hcol[j];
-                x += x << 8;
-                x += x << 16;
-                x += x << 32;
-                x += carry * 0x0101010101010101ull;
-                carry = x >> 56;
-                hcol[j] = x;
-            }
-            // 16-bit fields, two per word; scan over threads (rows)
-            uint32_t w[TWORDS], ex[TWORDS], tot[TWORDS];
-#pragma unroll
-            for (int k = 0; k < TWORDS; ++k) {
-                const int b0 = 2 * k, b1 = 2 * k + 1;
-                const uint32_t v0 = (uint32_t)(hcol[b0 >> 3] >> (8 * (b0 & 7))) & 0xFFu;
-                const uint32_t v1 = (uint32_t)(hcol[b1 >> 3] >> (8 * (b1 & 7))) & 0xFFu;
-                w[k] = v0 | (v1 << 16);
-            }
-            block_scan_words<TWORDS>(w, ex, tot, sm.wsc);
-            if (tid < NC) {
-                uint16_t *row = sm.u.tbl + (tid + 1) * TLD;
-#pragma unroll
-                for (int k = 0; k < TWORDS; ++k) {
-                    const uint32_t inc = ex[k] + w[k];
-                    if (2 * k <= NB) row[2 * k] = (uint16_t)(inc & 0xFFFFu);
-                    if (2 * k + 1 <= NB) row[2 * k + 1] = (uint16_t)(inc >> 16);
+            if (tid == 0) {
+                sm.u.wm.zt[lvl] = ztot;
+                if ((M & 63) == 0) {
+                    WWord e;
+                    e.bits = 0;
+                    e.zpre = ztot;
+                    e.pad = 0;
+                    sm.u.wm.w[lvl][M >> 6] = e;
                 }
             }
-            if (tid <= NB) sm.u.tbl[tid] = 0;
             __syncthreads();
+            uint16_t *tmp = src;
+            src = dst;
+            dst = tmp;
         }
 
-        // ---- walks: thread owns outputs [kb, ke)
-        if (kb < ke) {
-            int w0 = win_start(kb, B, W, h) - u0;
-            const int cL = w0 / CHP, nl = w0 % CHP;
-            const int xr2 = w0 + W;
-            const int cR = xr2 / CHP, nr = xr2 % CHP;
-            uint32_t rl[CHP], rrr[CHP];
+        // ---- median of each window: the h-th smallest rank (0-based) among
+        // positions [a, a + W) of the union.  The levels give its bucket and
+        // its index among the window's elements in the bucket; the bucket's
+        // 32 sorted elements are then tested against the window.
+        auto rank0 = [&](int lvl, int x) -> int {      // zeros among positions < x
+            const WWord e = sm.u.wm.w[lvl][x >> 6];
+            const uint64_t m = ~e.bits & ((1ull << (x & 63)) - 1ull);
+            return (int)e.zpre + __popcll(m);
+        };
+        int qa[RMAX], qlo[RMAX], qhi[RMAX], qk[RMAX];
+        uint32_t qr[RMAX];
 #pragma unroll
-            for (int i = 0; i < CHP; ++i) {
-                rl[i] = (i < nl) ? sm.rank[cL * CHP + i] : 0xFFFFFFFFu;
-                rrr[i] = (i < nr) ? sm.rank[cR * CHP + i] : 0xFFFFFFFFu;
-            }
-            auto count = [&](int b) -> int {
-                const uint32_t lim = (uint32_t)(b * RBS);
-                int cnt = (int)sm.u.tbl[cR * TLD + b] - (int)sm.u.tbl[cL * TLD + b];
-#pragma unroll
-                for (int i = 0; i < CHP; ++i) cnt += (int)(rrr[i] < lim) - (int)(rl[i] < lim);
-                return cnt;
-            };
-            int lo = 1, hi2 = NB;
-            while (lo < hi2) {
-                const int mid = (lo + hi2) >> 1;
-                if (count(mid) >= h + 1) hi2 = mid; else lo = mid + 1;
-            }
-            int base = count(lo - 1);
-            int j = (lo - 1) * RBS;
-            // scan the rank block 8 at a time for the (h+1)-th active element
-            for (bool found = false; !found && j < M;) {
-                uint32_t v[8];
-#pragma unroll
-                for (int i = 0; i < 8; ++i) v[i] = (j + i < M) ? sw[j + i] : 0xFFFFFFFFu;
-#pragma unroll
-                for (int i = 0; i < 8; ++i) {
-                    if (!found) {
-                        const bool act = (j + i < M) && ((v[i] & 0xFFFu) - (uint32_t)w0 < (uint32_t)W);
-                        if (act && ++base == h + 1) {
-                            found = true;
-                            j += i;
-                        }
-                    }
-                }
-                if (!found) j += 8;
-            }
-            if (j > M - 1) j = M - 1;          // guards a broken invariant only
-            // rank of the element leaving / entering at each step
-            uint32_t ro[RMAX], ri[RMAX];
-#pragma unroll
-            for (int r = 1; r < RMAX; ++r) {
-                const int k = kb + r;
-                const int ws = k < ke ? win_start(k, B, W, h) - u0 : w0;
-                const int wp = k < ke ? win_start(k - 1, B, W, h) - u0 : w0;
-                ro[r] = (ws != wp) ? sm.rank[wp] : 0xFFFFFFFFu;
-                ri[r] = (ws != wp) ? sm.rank[wp + W] : 0xFFFFFFFFu;
-            }
-            // Moving the pointer to the next active element (position inside
-            // the window [ws, ws + W)).  Runs of inactive elements can be
-            // long (where X is piecewise constant, values near the median
-            // come in blocks of neighbouring positions), so blocks of 256
-            // and 16 sorted elements whose positions avoid every chunk the
-            // window touches are skipped whole; otherwise up to four
-            // elements are examined with independent LDS reads.
-            auto wmask = [&](int ws) -> uint64_t {
-                const int clo = ws / CW, chi = (ws + W - 1) / CW;
-                const uint64_t hi = chi >= 63 ? ~0ull : ((1ull << (chi + 1)) - 1);
-                return hi & ~((1ull << clo) - 1);
-            };
-            auto next_up = [&](int jj, int ws) -> int {
-                const uint64_t wm = wmask(ws);
-                for (;;) {
-                    const int i = jj + 1;
-                    if (i >= M) return M - 1;
-                    const uint64_t m2 = sm.bm2[i >> 8], m1 = sm.bm1[i >> 4];
-                    const int e4 = min(i | 3, M - 1);
-                    uint32_t v[4];
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) v[q] = (i + q <= e4) ? sw[i + q] : 0u;
-                    if (!(m2 & wm)) { jj = min(i | 255, M - 1); continue; }
-                    if (!(m1 & wm)) { jj = min(i | 15, M - 1); continue; }
-#pragma unroll
-                    for (int q = 0; q < 4; ++q)
-                        if (i + q <= e4 && (v[q] & 0xFFFu) - (uint32_t)ws < (uint32_t)W) return i + q;
-                    if (e4 == M - 1) return M - 1;
-                    jj = e4;
-                }
-            };
-            auto next_down = [&](int jj, int ws) -> int {
-                const uint64_t wm = wmask(ws);
-                for (;;) {
-                    const int i = jj - 1;
-                    if (i < 0) return 0;
-                    const uint64_t m2 = sm.bm2[i >> 8], m1 = sm.bm1[i >> 4];
-                    const int e4 = i & ~3;
-                    uint32_t v[4];
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) v[q] = (i - q >= e4) ? sw[i - q] : 0u;
-                    if (!(m2 & wm)) { jj = i & ~255; if (jj == 0) return 0; continue; }
-                    if (!(m1 & wm)) { jj = i & ~15; if (jj == 0) return 0; continue; }
-#pragma unroll
-                    for (int q = 0; q < 4; ++q)
-                        if (i - q >= e4 && (v[q] & 0xFFFu) - (uint32_t)ws < (uint32_t)W) return i - q;
-                    if (e4 == 0) return 0;
-                    jj = e4;
-                }
-            };
-            int js[RMAX];
-            js[0] = j;
-#pragma unroll
-            for (int r = 1; r < RMAX; ++r) {
-                const int k = kb + r;
-                if (k < ke) {
-                    const int ws = win_start(k, B, W, h) - u0;
-                    if (ro[r] != 0xFFFFFFFFu) {
-                        const int rout = (int)ro[r], rin = (int)ri[r];
-                        const int below = h - (rout < j) + (rin < j);
-                        int dir = 0;
-                        if (rout == j) dir = (rin < j) ? -1 : 1;
-                        else if (below == h + 1) dir = -1;
-                        else if (below == h - 1) dir = 1;
-                        if (dir < 0) j = next_down(j, ws);
-                        else if (dir > 0) j = next_up(j, ws);
-                    }
-                }
-                js[r] = j;
-            }
-#pragma unroll
-            for (int r = 0; r < RMAX; ++r) med[r] = (kb + r < ke) ? sm.xv[sw[js[r]] & 0xFFFu] : 0.0;
+        for (int r = 0; r < RMAX; ++r) {
+            const int k = min(kb + r, ke - 1);          // past the run: repeat its last window
+            const int a = kb < ke ? win_start(k, B, W, h) - u0 : 0;
+            qa[r] = a;
+            qlo[r] = a;
+            qhi[r] = a + W;
+            qk[r] = h;
+            qr[r] = 0;
         }
+        for (int lvl = LB - 1; lvl >= WB; --lvl) {
+            const int Z = (int)sm.u.wm.zt[lvl];
+#pragma unroll
+            for (int r = 0; r < RMAX; ++r) {
+                if (r >= R) break;                      // R is the same for the whole block
+                const int zl = rank0(lvl, qlo[r]), zh = rank0(lvl, qhi[r]);
+                const int zeros = zh - zl;
+                if (qk[r] < zeros) {
+                    qlo[r] = zl;
+                    qhi[r] = zh;
+                } else {
+                    qk[r] -= zeros;
+                    qlo[r] = Z + qlo[r] - zl;
+                    qhi[r] = Z + qhi[r] - zh;
+                    qr[r] |= 1u << lvl;
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < RMAX; ++r) {
+            if (r >= R) break;
+            const int base = (int)qr[r];                // first rank of the bucket (MMAX is a multiple of 32)
+            uint32_t mask = 0;
+#pragma unroll
+            for (int i0 = 0; i0 < 32; i0 += 4) {
+                const uint4 q4 = *reinterpret_cast<const uint4 *>(&sw[base + i0]);
+                const uint32_t qq[4] = {q4.x, q4.y, q4.z, q4.w};
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const bool act = base + i0 + c < M && (qq[c] & 0xFFFu) - (uint32_t)qa[r] < (uint32_t)W;
+                    mask |= (uint32_t)act << (i0 + c);
+                }
+            }
+            // position of the (qk+1)-th set bit
+            int k = qk[r], pos = 0;
+#pragma unroll
+            for (int wdt = 16; wdt >= 1; wdt >>= 1) {
+                const int c = __popc(mask & ((1u << wdt) - 1u));
+                if (k >= c) {
+                    k -= c;
+                    mask >>= wdt;
+                    pos += wdt;
+                }
+            }
+            qr[r] = (uint32_t)(base + pos);
+        }
+#pragma unroll
+        for (int r = 0; r < RMAX; ++r) med[r] = (kb + r < ke) ? sm.xv[sw[qr[r]] & 0xFFFu] : 0.0;
     }
 
     // ---- S = C med + S_instr; in-tile prefix of 1/S and the tile sum.  The
     // outputs pass through LDS so that global loads and stores are coalesced.
-    __syncthreads();                       // the start table is dead: reuse it
+    __syncthreads();                       // the wavelet matrix is dead: reuse it
     double *st = sm.u.stage;
     const int sc = g.prec == PREC_FP64 ? 0 : f32_scale(d.ctl->amax_bits, g.T);
     const int n = t1 - t0;
@@ -1471,7 +1436,7 @@ __global__ __launch_bounds__(MWG) void k_mean(const Slot *S)
     const int span = split ? g.part : g.tile;
     const int blk = blockIdx.x;
     const int tile = split ? blk / g.np : blk;
-    if (tile >= g.nt || blk * span >= B || !d.sdirty[tile]) return;
+    if (tile >= g.nt || blk * span >= B || d.sstamp[tile] != d.ctl->iter) return;
     const int t0 = blk * span;
     const int t1 = min(t0 + span, B);
     const bool whole = B < W;
@@ -1521,28 +1486,23 @@ __global__ __launch_bounds__(MWG) void k_mean(const Slot *S)
     for (int i = tid; i < n; i += MWG) d.is_pre[t0 + i] = sm.stage[i];
 }
 
-// Exclusive prefix of the tile sums of 1/S (one block).
-__global__ __launch_bounds__(TWG) void k_med_tail(const Slot *S)
+// ------------------------------------------------------------------ SNR, decisions, subtraction
+
+// Exclusive prefix of the part sums of 1/S (one block, after the median):
+// with the in-part prefixes it gives any track's sum of 1/S in O(1).
+__global__ __launch_bounds__(PWG) void k_part_scan(const Slot *S)
 {
     const Slot &sl = S[blockIdx.y];
     if (!sl.active) return;
     const Grid g = sl.g;
     const Dev d = sl.d;
-
     if (d.ctl->done || d.ctl->bad) return;
     if (g.prec == PREC_NAIVE)
-        block_scan_array<double, TWG, float>(d.is_psum, d.is_part, g.nparts);
+        block_scan_array<double, PWG, float>(d.is_psum, d.is_part, g.nparts);
     else
-        block_scan_array<double, TWG>(d.is_psum, d.is_part, g.nparts);
+        block_scan_array<double, PWG>(d.is_psum, d.is_part, g.nparts);
 }
 
-// ------------------------------------------------------------------ SNR, decisions, subtraction
-
-// rho^2 = 4 q sum_{k in track} 1/S^t[k] for every unsubtracted candidate
-// (Eq. "SNR inner product" in the sky-averaged power form); rho^2 >
-// rho_th^2 subtracts the source from the binned power at once (appendix
-// "Subtraction algorithm", steps 6-9: the data X^{t+1} no longer holds it).
-// Per-block counts go to arrays; k_snr_tail combines them.
 // rho^2 in fp32 (the FP32 precision modes): 4 q sum 1/S with the sum in
 // fp32, compensated (Kahan) for short tracks and from the fp64 prefix
 // tables otherwise, or plain fp32 (naive: bin by bin, or differences of the
@@ -1578,17 +1538,62 @@ DEVI double snr2_f32(const Grid &g, const Dev &d, double qd, int lo, int hi)
     return (double)((4.0f * q) * sum);
 }
 
+// Removes a resolved source's power from the exact accumulators: its one
+// bin of Xn, or the two entries of the difference array D plus the carries
+// into the tiles that start inside (glo, ghi + 1] (X = Xn + prefix of D,
+// with the prefix split into a carry per tile and a sum inside the tile).
+DEVI void subtract_track(const Grid &g, const Dev &d, int glo, int ghi, int64_t v)
+{
+    if (glo == ghi) {
+        atomic_add_i128(&d.Xn[glo], -v);
+        return;
+    }
+    atomic_add_i128(&d.D[glo], -v);
+    if (ghi + 1 < g.B) atomic_add_i128(&d.D[ghi + 1], v);
+    const int te = min((ghi + 1) / g.tile, g.nt - 1);
+    for (int tl = glo / g.tile + 1; tl <= te; ++tl) split_sum_add(&d.Dadj[tl], -v);
+}
+
+// The same subtraction in fp32 (naive FP32 mode), vf = the power as a float.
+DEVI void subtract_track_f32(const Grid &g, const Dev &d, int glo, int ghi, float vf)
+{
+    if (glo == ghi) {
+        atomicAdd(&d.Xf[glo], -vf);
+        return;
+    }
+    atomicAdd(&d.Df[glo], -vf);
+    if (ghi + 1 < g.B) atomicAdd(&d.Df[ghi + 1], vf);
+    const int te = min((ghi + 1) / g.tile, g.nt - 1);
+    for (int tl = glo / g.tile + 1; tl <= te; ++tl) atomicAdd(&d.Dcf[tl], -vf);
+}
+
+// Stamps tiles lo/tile .. hi/tile for body `nxt` (every writer stores the
+// same value, read after the launch ends; k_snr_tail counts the stamped
+// tiles).
+DEVI void stamp_tiles(uint32_t *stamp, const Grid &g, int lo, int hi, uint32_t nxt)
+{
+    for (int tl = lo / g.tile; tl <= hi / g.tile; ++tl) stamp[tl] = nxt;
+}
+
+// rho^2 = 4 q sum_{k in track} 1/S^t[k] for every unsubtracted candidate
+// (Eq. "SNR inner product" in the sky-averaged power form); rho^2 >
+// rho_th^2 subtracts the source from the binned power at once (appendix
+// "Subtraction algorithm", steps 6-9: the data X^{t+1} no longer holds it)
+// and stamps the tiles the next body must convert (the track) and filter
+// (the track widened by half a window).  Per-block counts go to b_part;
+// k_snr_tail combines them.
 __global__ __launch_bounds__(WG) void k_snr(const Slot *S)
 {
-    __shared__ uint64_t s_near[WG / 64], s_evals[WG / 64];
-    __shared__ uint32_t s_new[WG / 64];
-    __shared__ double s_min[WG / 64];
+    constexpr int NW = WG / 64;
+    __shared__ uint64_t s_red[3][NW];     // new, near, evals
+    __shared__ double s_min[NW];
     const Slot &sl = S[blockIdx.y];
     if (!sl.active) return;
     const Grid g = sl.g;
     const Dev d = sl.d;
     if (d.ctl->done || d.ctl->bad) return;
     const int t = (int)d.ctl->iter;
+    const uint32_t nxt = (uint32_t)t + 1;
     const uint32_t nc = d.ctl->n_cand;
     uint32_t my_new = 0;
     uint64_t near = 0, evals = 0;
@@ -1610,36 +1615,14 @@ __global__ __launch_bounds__(WG) void k_snr(const Slot *S)
             ++my_new;
             const int64_t v = (int64_t)d.c_qfx[j];
             if (v) {
-                if (glo == ghi) {
-                    atomic_add_i128(&d.Xn[glo], -v);
-                } else {
-                    atomic_add_i128(&d.D[glo], -v);
-                    atomic_add_i128(&d.Dtile[glo / g.tile], -v);
-                    if (ghi + 1 < g.B) {
-                        atomic_add_i128(&d.D[ghi + 1], v);
-                        atomic_add_i128(&d.Dtile[(ghi + 1) / g.tile], v);
-                    }
-                }
-                if (g.prec == PREC_NAIVE) {     // the same subtraction in fp32
-                    const float vf = (float)ldexp((double)v, fx_exp(d.ctl->amax_bits, g.T) +
-                                                             f32_scale(d.ctl->amax_bits, g.T));
-                    if (glo == ghi) {
-                        atomicAdd(&d.Xf[glo], -vf);
-                    } else {
-                        atomicAdd(&d.Df[glo], -vf);
-                        atomicAdd(&d.Dtf[glo / g.tile], -vf);
-                        if (ghi + 1 < g.B) {
-                            atomicAdd(&d.Df[ghi + 1], vf);
-                            atomicAdd(&d.Dtf[(ghi + 1) / g.tile], vf);
-                        }
-                    }
-                }
+                subtract_track(g, d, glo, ghi, v);
+                if (g.prec == PREC_NAIVE)
+                    subtract_track_f32(g, d, glo, ghi,
+                                       (float)ldexp((double)v, fx_exp(d.ctl->amax_bits, g.T) +
+                                                                   f32_scale(d.ctl->amax_bits, g.T)));
             }
-            atomicAdd(&d.chgx[glo / g.tile], 1);
-            atomicAdd(&d.chgx[ghi / g.tile + 1], -1);
-            const int slo = max(glo - g.h, 0), shi = min(ghi + g.h, g.B - 1);
-            atomicAdd(&d.chgs[slo / g.tile], 1);
-            atomicAdd(&d.chgs[shi / g.tile + 1], -1);
+            stamp_tiles(d.xstamp, g, glo, ghi, nxt);
+            stamp_tiles(d.sstamp, g, max(glo - g.h, 0), min(ghi + g.h, g.B - 1), nxt);
         }
     }
     for (int s = 32; s >= 1; s >>= 1) {
@@ -1650,171 +1633,102 @@ __global__ __launch_bounds__(WG) void k_snr(const Slot *S)
     }
     const int w = threadIdx.x >> 6;
     if (lane_id() == 0) {
-        s_new[w] = my_new;
-        s_near[w] = near;
-        s_evals[w] = evals;
+        s_red[0][w] = my_new;
+        s_red[1][w] = near;
+        s_red[2][w] = evals;
         s_min[w] = minm;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int v = 1; v < WG / 64; ++v) {
-            s_new[0] += s_new[v];
-            s_near[0] += s_near[v];
-            s_evals[0] += s_evals[v];
+        for (int v = 1; v < NW; ++v) {
+            for (int r = 0; r < 3; ++r) s_red[r][0] += s_red[r][v];
             s_min[0] = fmin(s_min[0], s_min[v]);
         }
-        d.b_new[blockIdx.x] = s_new[0];
-        d.b_near[blockIdx.x] = s_near[0];
-        d.b_evals[blockIdx.x] = s_evals[0];
-        d.b_minm[blockIdx.x] = s_min[0];
+        SnrPart p;
+        p.n_new = (uint32_t)s_red[0][0];
+        p.pad = 0;
+        p.near = s_red[1][0];
+        p.evals = s_red[2][0];
+        p.minm = s_min[0];
+        d.b_part[blockIdx.x] = p;
     }
 }
 
-// One block: combines the per-block counts, carries of D, dirty tiles of
-// the next body, loop control.
-__global__ __launch_bounds__(SWG) void k_snr_tail(const Slot *S, int nblocks)
+// One block of one thread per k_snr block: combines the partials, counts
+// the tiles stamped for the next body, takes the stop decision (nothing new
+// subtracted, or max_iter) and whether the next median runs in split mode.
+__global__ __launch_bounds__(SNR_BLOCKS) void k_snr_tail(const Slot *S)
 {
-    constexpr int NV = SWG / 64;
-    __shared__ uint32_t shu[NV], shx[NV], shs[NV];
-    __shared__ uint64_t s64[2 * NV];
-    __shared__ double sd[NV];
-    __shared__ I128 shi[NV];
+    constexpr int NW = SNR_BLOCKS / 64;
+    __shared__ uint64_t s_red[5][NW];     // new, near, evals, ux, us
+    __shared__ uint32_t s_nds[NW];
+    __shared__ double s_min[NW];
     const Slot &sl = S[blockIdx.y];
     if (!sl.active) return;
     const Grid g = sl.g;
     const Dev d = sl.d;
     if (d.ctl->done || d.ctl->bad) return;
-    const int t = (int)d.ctl->iter;
-    const int tid = threadIdx.x, lane = lane_id(), w = tid >> 6;
-    // every load first: per-block SNR partials, and this thread's run of
-    // tiles (Dtile sums, change counters)
-    const int per = (g.nt + SWG - 1) / SWG;             // <= SPER
-    const int rb = min(tid * per, g.nt), re = min(rb + per, g.nt);
-    I128 sdt = zero_t<I128>();
-    int32_t vx[SPER], vs[SPER];
-#pragma unroll
-    for (int q = 0; q < SPER; ++q) {
-        const bool in = rb + q < re;
-        if (in) sdt = i128_add(sdt, d.Dtile[rb + q]);
-        vx[q] = in ? d.chgx[rb + q] : 0;
-        vs[q] = in ? d.chgs[rb + q] : 0;
-    }
-    uint32_t nw = 0;
-    uint64_t near = 0, evals = 0;
-    double minm = INFINITY;
-    for (int i = tid; i < nblocks; i += SWG) {
-        nw += d.b_new[i];
-        near += d.b_near[i];
-        evals += d.b_evals[i];
-        minm = fmin(minm, d.b_minm[i]);
-    }
-    for (int s = 32; s >= 1; s >>= 1) {
-        nw += (uint32_t)__shfl_xor((int)nw, s, 64);
-        near += (uint64_t)__shfl_xor((long long)near, s, 64);
-        evals += (uint64_t)__shfl_xor((long long)evals, s, 64);
-        minm = fmin(minm, __shfl_xor(minm, s, 64));
-    }
-    if (lane == 0) {
-        shu[w] = nw;
-        s64[w] = near;
-        s64[NV + w] = evals;
-        sd[w] = minm;
-    }
-    __syncthreads();
-    nw = 0; near = 0; evals = 0; minm = INFINITY;
-    for (int v = 0; v < NV; ++v) {
-        nw += shu[v];
-        near += s64[v];
-        evals += s64[NV + v];
-        minm = fmin(minm, sd[v]);
-    }
-    __syncthreads();
-    // exclusive prefix of the tile sums of D (exact)
-    uint32_t px = 0, ps = 0;
-#pragma unroll
-    for (int q = 0; q < SPER; ++q) {
-        px += (uint32_t)vx[q];
-        ps += (uint32_t)vs[q];
-    }
-    I128 dtot;
-    I128 run = block_excl_scan<I128, SWG>(sdt, shi, &dtot);
-    for (int i = rb; i < re; ++i) {           // second pass: the run is in cache
-        const I128 x = d.Dtile[i];
-        d.Dcarry[i] = run;
-        run = i128_add(run, x);
-    }
-    if (tid == 0) d.Dcarry[g.nt] = dtot;
-    if (g.prec == PREC_NAIVE) {
-        __syncthreads();
-        block_scan_array<float, SWG>(d.Dtf, d.Dcf, g.nt);
-    }
-    // dirty flags: prefix sums of the per-tile change counters (difference
-    // arrays)
-    uint32_t tx, ts;
-    uint32_t cx = block_excl_scan<uint32_t, SWG>(px, shx, &tx);
-    uint32_t cs = block_excl_scan<uint32_t, SWG>(ps, shs, &ts);
-    uint64_t ux = 0, us = 0;
+    const uint32_t nxt = d.ctl->iter + 1;
+    const SnrPart p = d.b_part[threadIdx.x];
+    uint64_t nw = p.n_new, near = p.near, evals = p.evals, ux = 0, us = 0;
     uint32_t nds = 0;
-#pragma unroll
-    for (int q = 0; q < SPER; ++q) {
-        const int i = rb + q;
-        if (i < re) {
-            cx += (uint32_t)vx[q];
-            cs += (uint32_t)vs[q];
-            const bool dx = (int32_t)cx > 0;
-            const bool ds = (int32_t)cs > 0;
-            d.xdirty[i] = dx;
-            d.sdirty[i] = ds;
-            const int width = min(g.tile, g.B - i * g.tile);
-            ux += dx ? width : 0;
-            us += ds ? width : 0;
-            nds += ds ? 1u : 0u;
-            d.chgx[i] = 0;
-            d.chgs[i] = 0;
+    double minm = p.minm;
+    for (int tl = threadIdx.x; tl < g.nt; tl += SNR_BLOCKS) {
+        const uint64_t width = (uint64_t)min(g.tile, g.B - tl * g.tile);
+        if (d.xstamp[tl] == nxt) ux += width;
+        if (d.sstamp[tl] == nxt) {
+            us += width;
+            ++nds;
         }
     }
     for (int s = 32; s >= 1; s >>= 1) {
+        nw += (uint64_t)__shfl_xor((long long)nw, s, 64);
+        near += (uint64_t)__shfl_xor((long long)near, s, 64);
+        evals += (uint64_t)__shfl_xor((long long)evals, s, 64);
         ux += (uint64_t)__shfl_xor((long long)ux, s, 64);
         us += (uint64_t)__shfl_xor((long long)us, s, 64);
         nds += (uint32_t)__shfl_xor((int)nds, s, 64);
+        minm = fmin(minm, __shfl_xor(minm, s, 64));
+    }
+    const int w = threadIdx.x >> 6;
+    if (lane_id() == 0) {
+        s_red[0][w] = nw;
+        s_red[1][w] = near;
+        s_red[2][w] = evals;
+        s_red[3][w] = ux;
+        s_red[4][w] = us;
+        s_nds[w] = nds;
+        s_min[w] = minm;
     }
     __syncthreads();
-    if (lane == 0) {
-        s64[w] = ux;
-        s64[NV + w] = us;
-        shu[w] = nds;
+    if (threadIdx.x != 0) return;
+    for (int v = 1; v < NW; ++v) {
+        for (int r = 0; r < 5; ++r) s_red[r][0] += s_red[r][v];
+        s_nds[0] += s_nds[v];
+        s_min[0] = fmin(s_min[0], s_min[v]);
     }
-    __syncthreads();
-    if (tid == 0) {
-        ux = 0; us = 0; nds = 0;
-        for (int v = 0; v < NV; ++v) {
-            ux += s64[v];
-            us += s64[NV + v];
-            nds += shu[v];
-        }
-        d.ctl->med_split = nds <= g.split_tiles;
-        d.chgx[g.nt] = 0;
-        d.chgs[g.nt] = 0;
-        Ctl *c = d.ctl;
-        if (t < NEW_CAP) d.n_new[t] = nw;
-        c->n_resolved += nw;
-        c->n_near += near;
-        c->units_snr += evals;
-        if (minm < __longlong_as_double((long long)c->min_margin))
-            c->min_margin = (uint64_t)__double_as_longlong(minm);
-        const uint32_t mi = g.max_iter ? g.max_iter : c->n_cand + 1;
-        if (nw == 0) {
-            c->done = 1;
-            c->n_iter = (uint32_t)t + 1;
-        } else if ((uint32_t)t + 1 >= mi) {
-            c->done = 1;                 // the loop did not settle within max_iter bodies
-            c->status = 6;
-            c->n_iter = (uint32_t)t + 1;
-        } else {
-            c->iter = (uint32_t)t + 1;
-            c->units_x += ux;
-            c->units_med += us;
-        }
+    Ctl *c = d.ctl;
+    const int t = (int)c->iter;
+    const uint32_t n_new = (uint32_t)s_red[0][0];
+    c->med_split = s_nds[0] <= g.split_tiles;
+    if (t < NEW_CAP) d.n_new[t] = n_new;
+    c->n_resolved += n_new;
+    c->n_near += s_red[1][0];
+    c->units_snr += s_red[2][0];
+    if (s_min[0] < __longlong_as_double((long long)c->min_margin))
+        c->min_margin = (uint64_t)__double_as_longlong(s_min[0]);
+    const uint32_t mi = g.max_iter ? g.max_iter : c->n_cand + 1;
+    if (n_new == 0) {
+        c->done = 1;
+        c->n_iter = (uint32_t)t + 1;
+    } else if ((uint32_t)t + 1 >= mi) {
+        c->done = 1;                 // the loop did not settle within max_iter bodies
+        c->status = 6;
+        c->n_iter = (uint32_t)t + 1;
+    } else {
+        c->iter = (uint32_t)t + 1;
+        c->units_x += s_red[3][0];
+        c->units_med += s_red[4][0];
     }
 }
 
@@ -1844,9 +1758,9 @@ hipError_t launch_grid_tables(const Slot *ds, const Dims &dm, hipStream_t st)
 
 hipError_t launch_reset(const Slot *ds, const Dims &dm, hipStream_t st)
 {
-    const unsigned nb = (unsigned)((dm.maxnt + 1 + WG - 1) / WG);
+    const unsigned nb = (unsigned)((dm.maxnt + WG - 1) / WG);
     k_reset<<<dim3(nb, dm.ns), WG, 0, st>>>(ds);
-    k_zero_f32<<<dim3(1024, dm.ns), WG, 0, st>>>(ds);
+    if (dm.naive) k_zero_f32<<<dim3(1024, dm.ns), WG, 0, st>>>(ds);
     return hipGetLastError();
 }
 
@@ -1859,40 +1773,42 @@ hipError_t launch_prep(const Slot *ds, const Dims &dm, hipStream_t st)
     if (dm.prep_blocks > 0) k_prep_scatter<<<dim3(dm.prep_blocks, dm.ns), WG, 0, st>>>(ds);
     k_accum<<<dim3(dm.accum_blocks, dm.ns), WG, 0, st>>>(ds);
     k_accum_reduce<<<dim3(dm.maxnt * (dm.maxtile / RED_BINS), dm.ns), RED_BINS, 0, st>>>(ds);
-    k_accum_f32<<<dim3(2048, dm.ns), WG, 0, st>>>(ds);
+    if (dm.naive) k_accum_f32<<<dim3(2048, dm.ns), WG, 0, st>>>(ds);
     k_dscan<<<dim3(1, dm.ns), WG, 0, st>>>(ds);
     return hipGetLastError();
 }
 
-hipError_t launch_xupdate(const Slot *ds, const Dims &dm, hipStream_t st)
+// One kernel of the loop body; with events, the dispatch itself records its
+// start (ea) and end (eb), which adds no work to the stream.
+hipError_t go(const void *kernel, dim3 grid, dim3 block, hipStream_t st, hipEvent_t ea, hipEvent_t eb,
+              const Slot *ds)
 {
-    k_xupdate<<<dim3(dm.maxnt, dm.ns), WG, 0, st>>>(ds);
-    return hipGetLastError();
+    void *args[] = {(void *)&ds};
+    if (!ea && !eb) return hipLaunchKernel(kernel, grid, block, args, 0, st);
+    return hipExtLaunchKernel(kernel, grid, block, args, 0, st, ea, eb, 0);
 }
 
-hipError_t launch_median(const Slot *ds, const Dims &dm, hipStream_t st)
+hipError_t launch_xupdate(const Slot *ds, const Dims &dm, hipStream_t st, hipEvent_t ea, hipEvent_t eb)
 {
-    if (dm.est_mask & 1u) k_median<<<dim3(dm.maxparts, dm.ns), MWG, 0, st>>>(ds);
-    if (dm.est_mask & 2u) k_mean<<<dim3(dm.maxparts, dm.ns), MWG, 0, st>>>(ds);
-    return hipGetLastError();
+    return go((const void *)k_xupdate, dim3(dm.maxnt, dm.ns), dim3(WG), st, ea, eb, ds);
 }
 
-hipError_t launch_med_tail(const Slot *ds, const Dims &dm, hipStream_t st)
+hipError_t launch_median(const Slot *ds, const Dims &dm, hipStream_t st, hipEvent_t ea, hipEvent_t eb)
 {
-    k_med_tail<<<dim3(1, dm.ns), TWG, 0, st>>>(ds);
-    return hipGetLastError();
+    const bool med = dm.est_mask & 1u, mean = dm.est_mask & 2u;
+    hipError_t e = hipSuccess;
+    if (med) e = go((const void *)k_median, dim3(dm.maxparts, dm.ns), dim3(MWG), st, ea, mean ? nullptr : eb, ds);
+    if (mean && e == hipSuccess)
+        e = go((const void *)k_mean, dim3(dm.maxparts, dm.ns), dim3(MWG), st, med ? nullptr : ea, eb, ds);
+    return e;
 }
 
-hipError_t launch_snr(const Slot *ds, const Dims &dm, hipStream_t st)
+hipError_t launch_snr(const Slot *ds, const Dims &dm, hipStream_t st, hipEvent_t ea, hipEvent_t eb)
 {
-    k_snr<<<dim3(SNR_BLOCKS, dm.ns), WG, 0, st>>>(ds);
-    return hipGetLastError();
-}
-
-hipError_t launch_snr_tail(const Slot *ds, const Dims &dm, hipStream_t st)
-{
-    k_snr_tail<<<dim3(1, dm.ns), SWG, 0, st>>>(ds, SNR_BLOCKS);
-    return hipGetLastError();
+    hipError_t e = go((const void *)k_part_scan, dim3(1, dm.ns), dim3(PWG), st, ea, nullptr, ds);
+    if (e == hipSuccess) e = go((const void *)k_snr, dim3(SNR_BLOCKS, dm.ns), dim3(WG), st, nullptr, nullptr, ds);
+    if (e != hipSuccess) return e;
+    return go((const void *)k_snr_tail, dim3(1, dm.ns), dim3(SNR_BLOCKS), st, nullptr, eb, ds);
 }
 
 // ------------------------------------------------------------------ coarse-graining

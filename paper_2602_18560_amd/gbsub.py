@@ -29,9 +29,8 @@ EXPORTS = ["gbsub_default_config", "gbsub_create", "gbsub_workspace_size", "gbsu
            "gbsub_batch_create", "gbsub_batch_admit", "gbsub_batch_step", "gbsub_batch_poll",
            "gbsub_batch_retire", "gbsub_batch_destroy"]
 SLOT_RUNNING, SLOT_SETTLED, SLOT_MAXITER, SLOT_INVALID, SLOT_FREE = 0, 1, 2, 3, 255
-(KF_TABLES, KF_RESET, KF_PREP, KF_XUPDATE, KF_MEDIAN, KF_MEDIAN_TAIL, KF_SNR, KF_SNR_TAIL,
- KF_OUTPUT) = range(9)
-PROFILE_ALL = 0x1FF
+(KF_TABLES, KF_RESET, KF_PREP, KF_XUPDATE, KF_MEDIAN, KF_SNR, KF_OUTPUT) = range(7)
+PROFILE_ALL = 0x7F
 
 
 class GbsubError(RuntimeError):
