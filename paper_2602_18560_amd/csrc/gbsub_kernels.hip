@@ -940,6 +940,7 @@ __global__ __launch_bounds__(WG) void k_xupdate(const Slot *S)
 constexpr int MWG = 512;                    // threads of a median block
 constexpr int RMAX = TILE_MAX / MWG;        // outputs per thread, at most
 constexpr int MCH = MMAX / MWG;             // union elements per thread in the sort
+constexpr int REPAIR_ROUNDS = 16;           // tie-repair rounds after which the sort is refined
 constexpr int WLB = 12;                     // wavelet levels, at most: ranks < MMAX <= 2^12
 constexpr int WWD = MMAX / 64 + 1;          // 64-position words per level (+1: the end position)
 
@@ -1194,12 +1195,39 @@ __global__ __launch_bounds__(MWG, 2) void k_median(const Slot *S)
     __syncthreads();
 
     // ---- sort
-    const int rb = radix_sort_tile(sm, M, passes);
+    int rb = radix_sort_tile(sm, M, passes);
     uint32_t *sw = sm.kp[rb];
 
-    // ---- repair key ties: order equal keys by (fp64 value, position)
+    // ---- repair key ties: order equal keys by (fp64 value, position), by
+    // odd-even transposition inside runs of equal keys.  A run needs about
+    // as many rounds as its elements must travel; an outlier can stretch
+    // the key range until long runs of distinct values share a key, so past
+    // REPAIR_ROUNDS rounds the tile is sorted again by the KEYBITS bits below
+    // the key and then stably by the key, which leaves only short runs.
     if (shift > 0) {
-        for (;;) {
+        bool refined = false;
+        for (int round = 0;; ++round) {
+            if (round == REPAIR_ROUNDS && !refined) {
+                refined = true;
+                const int sh2 = shift > KEYBITS ? shift - KEYBITS : 0;
+                const uint64_t lmask = (1ull << (shift - sh2)) - 1ull;
+                for (int p = tid; p < M; p += MWG) {
+                    const uint64_t bp = (uint64_t)__double_as_longlong(sm.xv[p]);
+                    const uint32_t lk = bp ? (uint32_t)(((bp - mn) >> sh2) & lmask) : 0u;
+                    sm.kp[0][p] = (lk << POSBITS) | (uint32_t)p;
+                }
+                __syncthreads();
+                const int r2 = radix_sort_tile(sm, M, (shift - sh2 + 3) / 4);
+                for (int i = tid; i < M; i += MWG) {       // the key again, in the low-key order
+                    const uint32_t p = sm.kp[r2][i] & 0xFFFu;
+                    const uint64_t bp = (uint64_t)__double_as_longlong(sm.xv[p]);
+                    const uint32_t key = bp ? 1u + (uint32_t)((bp - mn) >> shift) : 0u;
+                    sm.kp[0][i] = (key << POSBITS) | p;
+                }
+                __syncthreads();
+                rb = radix_sort_tile(sm, M, passes);
+                sw = sm.kp[rb];
+            }
             if (tid == 0) sm.flag = 0;
             __syncthreads();
             int swapped = 0;
