@@ -147,6 +147,9 @@ uint64_t carve(const Grid &g, uint64_t n, char *base, Dev *d)
     t.ev_val = (int64_t *)take((max_events ? max_events : 1) * 8);
     t.partial = (I128 *)take((uint64_t)t.max_slots * 2 * (uint64_t)g.tile * 16);
     t.cbits = (uint64_t *)take(((nn + 63) / 64) * 8);
+    const uint64_t ncb = (nn + PREP_CNT - 1) / PREP_CNT;
+    t.blk_cand = (uint32_t *)take((ncb + 1) * 4);
+    t.blk_amax = (uint32_t *)take(ncb * 4);
     t.c_src = (uint32_t *)take(nn * 4);
     t.c_id = (uint32_t *)take(nn * 4);
     t.c_glo = (int32_t *)take(nn * 4);
@@ -253,6 +256,7 @@ Dims dims_of(const Slot &sl)
     dm.est_mask = 1u << sl.g.est;
     dm.naive = sl.g.prec == PREC_NAIVE;
     dm.prep_blocks = (uint32_t)((sl.n + PREP_SRC - 1) / PREP_SRC);
+    dm.count_blocks = (uint32_t)((sl.n + PREP_CNT - 1) / PREP_CNT);
     dm.accum_blocks = sl.d.max_chunks;
     return dm;
 }
@@ -266,6 +270,7 @@ void widen(Dims &a, const Dims &b)
     a.est_mask |= b.est_mask;
     a.naive |= b.naive;
     a.prep_blocks = std::max(a.prep_blocks, b.prep_blocks);
+    a.count_blocks = std::max(a.count_blocks, b.count_blocks);
     a.accum_blocks = std::max(a.accum_blocks, b.accum_blocks);
 }
 

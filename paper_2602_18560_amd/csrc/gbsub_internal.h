@@ -14,7 +14,8 @@ constexpr int TILE_MAX = 2048;     // bins per tile (also the binning bucket)
 constexpr int NBK_MAX = 8192;      // tiles the prep histogram can hold (B <= 8192 tiles)
 constexpr int NARROW = 16;         // tracks of <= NARROW bins: SNR summed bin by bin
 constexpr int SNR_BLOCKS = 1024;   // fixed grid of the per-candidate kernels
-constexpr int PREP_SRC = 8192;     // sources per prep block
+constexpr int PREP_SRC = 8192;     // sources per block of the prep scatter pass
+constexpr int PREP_CNT = 4096;     // sources per block of the prep count pass
 constexpr int ACC_EV = 65536;      // binning events per accumulation block
 constexpr int RED_BINS = 256;      // bins per reduction block of the hot buckets
 constexpr int NEW_CAP = 1 << 16;   // per-iteration counters kept (iterations beyond: not recorded)
@@ -139,6 +140,8 @@ struct Dev {
     int64_t *ev_val;         // [2n]   signed fixed-point power
     I128 *partial;           // [slots][2][tile] partial sums of the hot tiles
     uint64_t *cbits;         // [ceil(n/64)] candidate flags of the sources (count pass)
+    uint32_t *blk_cand;      // [count blocks + 1] candidates per count block, then their exclusive prefix
+    uint32_t *blk_amax;      // [count blocks] max fp32 bits of A per count block
     // candidates (capacity: all sources)
     uint32_t *c_src;         // source index
     uint32_t *c_id;          // its id (written at the end of a run)
@@ -174,7 +177,7 @@ struct Dims {
     int maxB, maxnt, maxtile, maxparts;
     uint32_t est_mask;       // bit e: some slot uses estimator e
     uint32_t naive;          // some slot runs in naive FP32
-    uint32_t prep_blocks, accum_blocks;
+    uint32_t prep_blocks, count_blocks, accum_blocks;
 };
 
 // Kernel launchers (gbsub_kernels.hip); all enqueue on `st` and return the

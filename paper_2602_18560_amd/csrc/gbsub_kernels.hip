@@ -107,6 +107,17 @@ DEVI int f32_scale(uint32_t amax_bits, double T)
 
 DEVI int lane_id() { return __lane_id(); }
 
+// x / p and x % p for x >= 0 and p a power of two (tile and part sizes).
+DEVI int div_p2(int x, int p) { return x >> __builtin_ctz((unsigned)p); }
+DEVI int mod_p2(int x, int p) { return x & (p - 1); }
+
+// Makes the compiler produce v here (an empty asm that reads it): loads
+// issued together stay together instead of being sunk into the branches
+// that use them, each with its own wait.
+DEVI void pin(float v) { asm volatile("" ::"v"(v)); }
+DEVI void pin(double v) { asm volatile("" ::"v"(v)); }
+DEVI void pin(uint64_t v) { asm volatile("" ::"v"(v)); }
+
 template <typename T>
 DEVI T shfl_up_t(T x, int d) { return __shfl_up(x, d, 64); }
 
@@ -189,8 +200,8 @@ DEVI double range_inv_sum(const double *v, const double *pre, const double *tl, 
         for (int k = lo; k <= hi; ++k) s += 1.0 / v[k];
         return s;
     }
-    const int tlo = lo / tile, thi = hi / tile;
-    const double below = (lo % tile == 0) ? 0.0 : pre[lo - 1];
+    const int tlo = div_p2(lo, tile), thi = div_p2(hi, tile);
+    const double below = mod_p2(lo, tile) == 0 ? 0.0 : pre[lo - 1];
     if (tlo == thi) return pre[hi] - below;
     return ((tl[thi] - tl[tlo]) - below) + pre[hi];
 }
@@ -377,13 +388,14 @@ DEVI Trk track_geom(const Grid &g, float Af, float Ff, float FDf)
     ok = ok && fabs(x) < 4503599627370496.0 && s < 2147483648.0;
     if (!ok) return t;
     t.ok = true;
-    const int64_t c = (int64_t)floor(x) - g.k0;
-    const int64_t nn = g.track_single ? 1 : 1 + (int64_t)floor(s);
-    const int64_t lo = c - (nn - 1) / 2;
-    const int64_t hi = lo + nn - 1;
-    t.q = nn == 1 ? P : P / (double)nn;
-    const int64_t gl = lo < 0 ? 0 : lo;
-    const int64_t gh = hi > g.B - 1 ? g.B - 1 : hi;
+    // integer-valued fp64 throughout (|values| < 2^53: exact)
+    const double c = floor(x) - (double)g.k0;
+    const double nn = g.track_single ? 1.0 : 1.0 + floor(s);
+    const double lo = c - floor((nn - 1.0) * 0.5);
+    const double hi = lo + (nn - 1.0);
+    t.q = nn == 1.0 ? P : P / nn;
+    const double gl = fmax(lo, 0.0);
+    const double gh = fmin(hi, (double)(g.B - 1));
     if (gl > gh) return t;
     t.live = true;
     t.glo = (int)gl;
@@ -394,56 +406,74 @@ DEVI Trk track_geom(const Grid &g, float Af, float Ff, float FDf)
 // rho_0^2 >= (kappa rho_th)^2 against S_instr.  Short tracks sum the stored
 // reciprocals 1/S_instr bin by bin in ascending order (the same values and
 // order as summing 1/S_instr directly), longer ones use the prefix tables.
-DEVI bool cand_test(const Grid &g, const Dev &d, const Trk &t)
+// x0 = 1/S_instr of the track's first bin, loaded by the caller.
+DEVI bool cand_test(const Grid &g, const Dev &d, const Trk &t, double x0)
 {
     if (!t.live) return false;
     double sum;
     if (t.glo == t.ghi) {
-        sum = d.isx[t.glo];
+        sum = x0;
     } else if (t.ghi - t.glo + 1 <= NARROW) {
-        sum = 0.0;
-        for (int k = t.glo; k <= t.ghi; ++k) sum += d.isx[k];
+        sum = x0;
+        for (int k = t.glo + 1; k <= t.ghi; ++k) sum += d.isx[k];
     } else {
         sum = range_inv_sum(d.sx, d.isx_pre, d.isx_tile, t.glo, t.ghi, g.tile);
     }
     return (4.0 * t.q) * sum >= g.cut2;
 }
 
-DEVI int tile_of(int bin, int tile) { return bin / tile; }
+DEVI int tile_of(int bin, int tile) { return div_p2(bin, tile); }
 
-// Count pass: events per tile and candidates of this block.
+// Count pass: events per tile and candidates of this block.  The per-tile
+// counts are 16-bit halves of LDS words (at most 2 PREP_CNT < 2^16 events
+// of a block fall in one tile), which keeps the block's LDS at 16 KB.
 DEVI void k_prep_count_body(Grid g, Dev d, const float *A, const float *F, const float *FD, uint64_t n)
 {
-    __shared__ uint32_t hist[NBK_MAX];
+    __shared__ uint32_t hist[NBK_MAX / 2];
     __shared__ uint32_t scand, samax;
-    for (int b = threadIdx.x; b < g.nt; b += WG) hist[b] = 0;
+    auto hadd = [&](int b) { atomicAdd(&hist[b >> 1], 1u << (16 * (b & 1))); };
+    for (int b = threadIdx.x; b < (g.nt + 1) / 2; b += WG) hist[b] = 0;
     if (threadIdx.x == 0) {
         scand = 0;
         samax = 0;
     }
     __syncthreads();
-    const uint64_t base = (uint64_t)blockIdx.x * PREP_SRC;
+    const uint64_t base = (uint64_t)blockIdx.x * PREP_CNT;
     uint32_t cc = 0, bad = 0, amax = 0;
-    // four sources per thread in flight: loads first, then the tracks and
+    constexpr int CB = 8;
+    // CB sources per thread in flight: loads first, then the tracks and
     // the S_instr gathers of the candidate tests
-    for (int r0 = 0; r0 < PREP_SRC / WG; r0 += 4) {
-        float a[4], f[4], fd[4];
+    for (int r0 = 0; r0 < PREP_CNT / WG; r0 += CB) {
+        float a[CB], f[CB], fd[CB];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < CB; ++q) {
             const uint64_t i = base + (uint64_t)(r0 + q) * WG + threadIdx.x;
             const bool in = i < n;
-            a[q] = in ? A[i] : 0.0f;
-            f[q] = in ? F[i] : 1.0f;
-            fd[q] = in ? FD[i] : 0.0f;
+            const uint64_t ic = in ? i : n - 1;        // unconditional loads: all in flight at once
+            const float av = A[ic], fv = F[ic], fdv = FD[ic];
+            a[q] = in ? av : 0.0f;
+            f[q] = in ? fv : 1.0f;
+            fd[q] = in ? fdv : 0.0f;
         }
-        Trk t[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) t[q] = track_geom(g, a[q], f[q], fd[q]);
-        bool cand[4];
+        for (int q = 0; q < CB; ++q) {
+            pin(a[q]);
+            pin(f[q]);
+            pin(fd[q]);
+        }
+        Trk t[CB];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) cand[q] = cand_test(g, d, t[q]);
+        for (int q = 0; q < CB; ++q) t[q] = track_geom(g, a[q], f[q], fd[q]);
+        double x0[CB];                            // first-bin gathers, all in flight
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < CB; ++q) x0[q] = d.isx[t[q].live ? t[q].glo : 0];
+#pragma unroll
+        for (int q = 0; q < CB; ++q) pin(x0[q]);
+        bool cand[CB];
+#pragma unroll
+        for (int q = 0; q < CB; ++q) cand[q] = cand_test(g, d, t[q], x0[q]);
+#pragma unroll
+        for (int q = 0; q < CB; ++q) {
             const uint64_t i = base + (uint64_t)(r0 + q) * WG + threadIdx.x;
             const bool in = i < n;
             const bool c = in && t[q].ok && cand[q];
@@ -457,8 +487,8 @@ DEVI void k_prep_count_body(Grid g, Dev d, const float *A, const float *F, const
             }
             amax = max(amax, __float_as_uint(a[q]));      // A >= 0: bit patterns in value order
             if (t[q].live) {
-                atomicAdd(&hist[tile_of(t[q].glo, g.tile)], 1u);
-                if (t[q].glo != t[q].ghi && t[q].ghi + 1 < g.B) atomicAdd(&hist[tile_of(t[q].ghi + 1, g.tile)], 1u);
+                hadd(tile_of(t[q].glo, g.tile));
+                if (t[q].glo != t[q].ghi && t[q].ghi + 1 < g.B) hadd(tile_of(t[q].ghi + 1, g.tile));
             }
             cc += c;
         }
@@ -470,17 +500,22 @@ DEVI void k_prep_count_body(Grid g, Dev d, const float *A, const float *F, const
     if (lane_id() == 0 && cc) atomicAdd(&scand, cc);
     if (lane_id() == 0 && amax) atomicMax(&samax, amax);
     __syncthreads();
-    if (threadIdx.x == 0 && samax) atomicMax(&d.ctl->amax_bits, samax);
-    for (int b = threadIdx.x; b < g.nt; b += WG)
-        if (hist[b]) atomicAdd(&d.btot[b], hist[b]);
-    if (threadIdx.x == 0 && scand) atomicAdd(&d.ctl->n_cand, scand);
+    // per-block results (k_prep_plan combines them: no atomics on one address)
+    if (threadIdx.x == 0) {
+        d.blk_cand[blockIdx.x] = scand;
+        d.blk_amax[blockIdx.x] = samax;
+    }
+    for (int b = threadIdx.x; b < g.nt; b += WG) {
+        const uint32_t c = (hist[b >> 1] >> (16 * (b & 1))) & 0xFFFFu;
+        if (c) atomicAdd(&d.btot[b], c);
+    }
     if (bad) atomicOr(&d.ctl->bad, 1u);
 }
 
 __global__ __launch_bounds__(WG) void k_prep_count(const Slot *S)
 {
     const Slot &sl = S[blockIdx.y];
-    if (!sl.active || (uint64_t)blockIdx.x * PREP_SRC >= sl.n) return;
+    if (!sl.active || (uint64_t)blockIdx.x * PREP_CNT >= sl.n) return;
     const Grid g = sl.g;
     const Dev d = sl.d;
     const float *A = sl.A, *F = sl.F, *FD = sl.FD;
@@ -498,6 +533,25 @@ __global__ __launch_bounds__(WG) void k_prep_plan(const Slot *S)
     if (!sl.active) return;
     const Grid g = sl.g;
     const Dev d = sl.d;
+
+    // largest A and the candidates of the count blocks: their exclusive
+    // prefix is each scatter block's first candidate slot
+    {
+        const int nb = (int)((sl.n + PREP_CNT - 1) / PREP_CNT);
+        uint32_t am = 0;
+        for (int b = threadIdx.x; b < nb; b += WG) am = max(am, d.blk_amax[b]);
+        for (int s = 32; s >= 1; s >>= 1) am = max(am, (uint32_t)__shfl_xor((int)am, s, 64));
+        if (lane_id() == 0) sh[threadIdx.x >> 6] = am;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int w = 1; w < WG / 64; ++w) am = max(am, sh[w]);
+            d.ctl->amax_bits = am;
+        }
+        __syncthreads();
+        block_scan_array<uint32_t>(d.blk_cand, d.blk_cand, nb);   // in place: each thread rereads its own run
+        if (threadIdx.x == 0) d.ctl->n_cand = d.blk_cand[nb];
+        __syncthreads();
+    }
 
     uint32_t carry_e = 0, carry_c = 0, carry_s = 0;
     for (int base = 0; base < g.nt; base += WG) {
@@ -544,20 +598,31 @@ DEVI void k_prep_scatter_body(Grid g, Dev d, const float *A, const float *F, con
     __syncthreads();
     const int L = fx_exp(d.ctl->amax_bits, g.T);
     const uint64_t base = (uint64_t)blockIdx.x * PREP_SRC;
-    auto is_cand = [&](uint64_t i) -> bool { return (d.cbits[i >> 6] >> (i & 63)) & 1ull; };
+    constexpr int SB = 8;                    // sources per thread in flight
     uint32_t cc = 0;
-    for (int r0 = 0; r0 < PREP_SRC / WG; r0 += 4) {
-        float a[4], f[4], fd[4];
+    for (int r0 = 0; r0 < PREP_SRC / WG; r0 += SB) {
+        float a[SB], f[SB], fd[SB];
+        uint64_t cw[SB];                         // candidate-flag words of the sources
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < SB; ++q) {
             const uint64_t i = base + (uint64_t)(r0 + q) * WG + threadIdx.x;
             const bool in = i < n;
-            a[q] = in ? A[i] : 0.0f;
-            f[q] = in ? F[i] : 1.0f;
-            fd[q] = in ? FD[i] : 0.0f;
+            const uint64_t ic = in ? i : n - 1;        // unconditional loads: all in flight at once
+            const float av = A[ic], fv = F[ic], fdv = FD[ic];
+            a[q] = in ? av : 0.0f;
+            f[q] = in ? fv : 1.0f;
+            fd[q] = in ? fdv : 0.0f;
+            cw[q] = d.cbits[ic >> 6];
         }
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < SB; ++q) {
+            pin(a[q]);
+            pin(f[q]);
+            pin(fd[q]);
+            pin(cw[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < SB; ++q) {
             const uint64_t i = base + (uint64_t)(r0 + q) * WG + threadIdx.x;
             if (i >= n) continue;
             const Trk t = track_geom(g, a[q], f[q], fd[q]);
@@ -566,7 +631,7 @@ DEVI void k_prep_scatter_body(Grid g, Dev d, const float *A, const float *F, con
                 atomicAdd(&cur[tile_of(t.glo, g.tile)], 1u);
                 if (t.glo != t.ghi && t.ghi + 1 < g.B) atomicAdd(&cur[tile_of(t.ghi + 1, g.tile)], 1u);
             }
-            cc += is_cand(i);
+            cc += (uint32_t)(cw[q] >> (i & 63)) & 1u;
         }
     }
     for (int s = 32; s >= 1; s >>= 1) cc += (uint32_t)__shfl_xor((int)cc, s, 64);
@@ -575,22 +640,33 @@ DEVI void k_prep_scatter_body(Grid g, Dev d, const float *A, const float *F, con
     for (int b = threadIdx.x; b < g.nt; b += WG)
         if (cur[b]) cur[b] = atomicAdd(&d.cursor[b], cur[b]);
     if (threadIdx.x == 0) {
-        cbase = scand ? atomicAdd(&d.ctl->cand_cursor, scand) : 0u;
+        cbase = d.blk_cand[blockIdx.x * (PREP_SRC / PREP_CNT)];
         scand = 0;
     }
     __syncthreads();
-    for (int r0 = 0; r0 < PREP_SRC / WG; r0 += 4) {
-        float a[4], f[4], fd[4];
+    for (int r0 = 0; r0 < PREP_SRC / WG; r0 += SB) {
+        float a[SB], f[SB], fd[SB];
+        uint64_t cw[SB];                         // candidate-flag words of the sources
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < SB; ++q) {
             const uint64_t i = base + (uint64_t)(r0 + q) * WG + threadIdx.x;
             const bool in = i < n;
-            a[q] = in ? A[i] : 0.0f;
-            f[q] = in ? F[i] : 1.0f;
-            fd[q] = in ? FD[i] : 0.0f;
+            const uint64_t ic = in ? i : n - 1;        // unconditional loads: all in flight at once
+            const float av = A[ic], fv = F[ic], fdv = FD[ic];
+            a[q] = in ? av : 0.0f;
+            f[q] = in ? fv : 1.0f;
+            fd[q] = in ? fdv : 0.0f;
+            cw[q] = d.cbits[ic >> 6];
         }
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < SB; ++q) {
+            pin(a[q]);
+            pin(f[q]);
+            pin(fd[q]);
+            pin(cw[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < SB; ++q) {
             const uint64_t i = base + (uint64_t)(r0 + q) * WG + threadIdx.x;
             if (i >= n) continue;
             const Trk t = track_geom(g, a[q], f[q], fd[q]);
@@ -612,7 +688,7 @@ DEVI void k_prep_scatter_body(Grid g, Dev d, const float *A, const float *F, con
                     }
                 }
             }
-            if (is_cand(i)) {
+            if ((cw[q] >> (i & 63)) & 1ull) {
                 const uint32_t j = cbase + atomicAdd(&scand, 1u);
                 d.c_src[j] = (uint32_t)i;
                 d.c_glo[j] = t.glo;
@@ -834,7 +910,7 @@ __global__ __launch_bounds__(WG) void k_accum_f32(const Slot *S)
         const int k = (int)(key & 0x7FFFFFFFu);
         if (key >> 31) {
             atomicAdd(&d.Df[k], v);
-            atomicAdd(&d.Dtf[k / g.tile], v);
+            atomicAdd(&d.Dtf[div_p2(k, g.tile)], v);
         } else {
             atomicAdd(&d.Xf[k], v);
         }
@@ -1111,7 +1187,7 @@ DEVI void part_prefix(double *dsh, double *st, const Grid &g, const Dev &d, int 
         if (kb + r < ke) st[kb + r - t0] = (double)(ex + loc[r]);
     if ((tid & (segw * 64 - 1)) == 0) {
         const int p0 = t0 + (tid / (segw * 64)) * g.part;
-        if (p0 < t1) d.is_psum[p0 / g.part] = (double)tot;
+        if (p0 < t1) d.is_psum[div_p2(p0, g.part)] = (double)tot;
     }
 }
 
@@ -1558,8 +1634,8 @@ DEVI double snr2_f32(const Grid &g, const Dev &d, double qd, int lo, int hi)
     } else if (g.prec == PREC_COMP) {
         sum = (float)range_inv_sum(d.S, d.is_pre, d.is_part, lo, hi, g.part);
     } else {                                   // differences of the fp32 prefix tables
-        const int plo = lo / g.part, phi = hi / g.part;
-        const float below = (lo % g.part == 0) ? 0.0f : (float)d.is_pre[lo - 1];
+        const int plo = div_p2(lo, g.part), phi = div_p2(hi, g.part);
+        const float below = mod_p2(lo, g.part) == 0 ? 0.0f : (float)d.is_pre[lo - 1];
         sum = plo == phi ? (float)d.is_pre[hi] - below
                          : (((float)d.is_part[phi] - (float)d.is_part[plo]) - below) + (float)d.is_pre[hi];
     }
@@ -1578,8 +1654,8 @@ DEVI void subtract_track(const Grid &g, const Dev &d, int glo, int ghi, int64_t 
     }
     atomic_add_i128(&d.D[glo], -v);
     if (ghi + 1 < g.B) atomic_add_i128(&d.D[ghi + 1], v);
-    const int te = min((ghi + 1) / g.tile, g.nt - 1);
-    for (int tl = glo / g.tile + 1; tl <= te; ++tl) split_sum_add(&d.Dadj[tl], -v);
+    const int te = min(div_p2(ghi + 1, g.tile), g.nt - 1);
+    for (int tl = div_p2(glo, g.tile) + 1; tl <= te; ++tl) split_sum_add(&d.Dadj[tl], -v);
 }
 
 // The same subtraction in fp32 (naive FP32 mode), vf = the power as a float.
@@ -1591,8 +1667,8 @@ DEVI void subtract_track_f32(const Grid &g, const Dev &d, int glo, int ghi, floa
     }
     atomicAdd(&d.Df[glo], -vf);
     if (ghi + 1 < g.B) atomicAdd(&d.Df[ghi + 1], vf);
-    const int te = min((ghi + 1) / g.tile, g.nt - 1);
-    for (int tl = glo / g.tile + 1; tl <= te; ++tl) atomicAdd(&d.Dcf[tl], -vf);
+    const int te = min(div_p2(ghi + 1, g.tile), g.nt - 1);
+    for (int tl = div_p2(glo, g.tile) + 1; tl <= te; ++tl) atomicAdd(&d.Dcf[tl], -vf);
 }
 
 // Stamps tiles lo/tile .. hi/tile for body `nxt` (every writer stores the
@@ -1600,7 +1676,7 @@ DEVI void subtract_track_f32(const Grid &g, const Dev &d, int glo, int ghi, floa
 // tiles).
 DEVI void stamp_tiles(uint32_t *stamp, const Grid &g, int lo, int hi, uint32_t nxt)
 {
-    for (int tl = lo / g.tile; tl <= hi / g.tile; ++tl) stamp[tl] = nxt;
+    for (int tl = div_p2(lo, g.tile); tl <= div_p2(hi, g.tile); ++tl) stamp[tl] = nxt;
 }
 
 // rho^2 = 4 q sum_{k in track} 1/S^t[k] for every unsubtracted candidate
@@ -1794,9 +1870,7 @@ hipError_t launch_reset(const Slot *ds, const Dims &dm, hipStream_t st)
 
 hipError_t launch_prep(const Slot *ds, const Dims &dm, hipStream_t st)
 {
-    if (dm.prep_blocks > 0) {
-        k_prep_count<<<dim3(dm.prep_blocks, dm.ns), WG, 0, st>>>(ds);
-    }
+    if (dm.count_blocks > 0) k_prep_count<<<dim3(dm.count_blocks, dm.ns), WG, 0, st>>>(ds);
     k_prep_plan<<<dim3(1, dm.ns), WG, 0, st>>>(ds);
     if (dm.prep_blocks > 0) k_prep_scatter<<<dim3(dm.prep_blocks, dm.ns), WG, 0, st>>>(ds);
     k_accum<<<dim3(dm.accum_blocks, dm.ns), WG, 0, st>>>(ds);
