@@ -118,8 +118,8 @@ struct Dev {
     // naive FP32 mode only: the binned power accumulated in fp32
     float *Xf;               // [B]    one-bin tracks
     float *Df;               // [B+1]  difference array of the wider tracks
-    float *Dtf;              // [nt+1] per-tile sums of Df (binning)
-    float *Dcf;              // [nt+1] sum of Df before each tile
+    float *Dtf;              // [nt+1] per-tile sums of Df (binning and subtractions)
+    float *Dcf;              // [nt+1] exclusive prefix of Dtf (rescanned every body)
     double *X;               // [B]    X^t
     double *S;               // [B]    S^t
     double *is_pre;          // [B]    inclusive prefix of 1/S^t inside each part

@@ -1658,7 +1658,9 @@ DEVI void subtract_track(const Grid &g, const Dev &d, int glo, int ghi, int64_t 
     for (int tl = div_p2(glo, g.tile) + 1; tl <= te; ++tl) split_sum_add(&d.Dadj[tl], -v);
 }
 
-// The same subtraction in fp32 (naive FP32 mode), vf = the power as a float.
+// The same subtraction in fp32 (naive FP32 mode), vf = the power as a float:
+// the fp32 difference array and its per-tile sums (k_snr_tail rescans the
+// tile sums into the carries in fp32 every body).
 DEVI void subtract_track_f32(const Grid &g, const Dev &d, int glo, int ghi, float vf)
 {
     if (glo == ghi) {
@@ -1666,9 +1668,11 @@ DEVI void subtract_track_f32(const Grid &g, const Dev &d, int glo, int ghi, floa
         return;
     }
     atomicAdd(&d.Df[glo], -vf);
-    if (ghi + 1 < g.B) atomicAdd(&d.Df[ghi + 1], vf);
-    const int te = min(div_p2(ghi + 1, g.tile), g.nt - 1);
-    for (int tl = div_p2(glo, g.tile) + 1; tl <= te; ++tl) atomicAdd(&d.Dcf[tl], -vf);
+    atomicAdd(&d.Dtf[div_p2(glo, g.tile)], -vf);
+    if (ghi + 1 < g.B) {
+        atomicAdd(&d.Df[ghi + 1], vf);
+        atomicAdd(&d.Dtf[div_p2(ghi + 1, g.tile)], vf);
+    }
 }
 
 // Stamps tiles lo/tile .. hi/tile for body `nxt` (every writer stores the
@@ -1772,6 +1776,7 @@ __global__ __launch_bounds__(SNR_BLOCKS) void k_snr_tail(const Slot *S)
     const Grid g = sl.g;
     const Dev d = sl.d;
     if (d.ctl->done || d.ctl->bad) return;
+    if (g.prec == PREC_NAIVE) block_scan_array<float, SNR_BLOCKS>(d.Dtf, d.Dcf, g.nt);
     const uint32_t nxt = d.ctl->iter + 1;
     const SnrPart p = d.b_part[threadIdx.x];
     uint64_t nw = p.n_new, near = p.near, evals = p.evals, ux = 0, us = 0;
