@@ -285,8 +285,31 @@ template <typename T, int NT = WG, typename A = T>
 DEVI void block_scan_array(const T *in, T *out, int n)
 {
     __shared__ A sh[NT / 64];
+    constexpr int RUN = 8;                 // runs this short stay in registers
     const int per = (n + NT - 1) / NT;
     const int b = min((int)threadIdx.x * per, n), e = min(b + per, n);
+    if (per <= RUN) {
+        // every load of the run issued before the first use (clamped
+        // indices, no branches around the loads)
+        A v[RUN];
+#pragma unroll
+        for (int r = 0; r < RUN; ++r) v[r] = (A)in[min(b + r, n - 1 < 0 ? 0 : n - 1)];
+        A s = zero_t<A>();
+#pragma unroll
+        for (int r = 0; r < RUN; ++r)
+            if (b + r < e) s = add_t(s, v[r]);
+        A tot;
+        A run = block_excl_scan<A, NT>(s, sh, &tot);
+#pragma unroll
+        for (int r = 0; r < RUN; ++r) {
+            if (b + r < e) {
+                out[b + r] = (T)run;
+                run = add_t(run, v[r]);
+            }
+        }
+        if (threadIdx.x == 0) out[n] = (T)tot;
+        return;
+    }
     A s = zero_t<A>();
 #pragma unroll 8
     for (int i = b; i < e; ++i) s = add_t(s, (A)in[i]);
