@@ -120,6 +120,34 @@ int     orc_coarse(const double *S, int64_t k0, int64_t n_bins, double T, double
 int     orc_run(const orc_config *c, int64_t n, const float *A, const float *f, const float *fdot,
                 orc_io *io, orc_summary *sum);
 
+/* ---------------------------------------------------------------- population model
+ * (population_oracle.c; Sec. "Population model", Table "priors", appendix
+ * "Copulas") */
+typedef struct {
+    double alpha_pl;            /* power-law index of f, alpha_PL != -1 */
+    double alpha_g, beta_g;     /* Gamma shape and rate of log10(fdot) - mu_Gamma */
+    double mu_g;                /* mu_Gamma */
+    double mu;                  /* mu of the rescaled log amplitude */
+    double sigma;               /* log-normal shape of the rescaled log amplitude */
+    double rho;                 /* Gaussian-copula correlation of (f, fdot), |rho| < 1 */
+    double f_lo_hz, f_hi_hz;    /* support of the power law */
+} orc_population;
+
+/* Philox4x32-10: out = the 10-round bijection of ctr under key. */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+/* Regularized lower incomplete gamma P(a, x). */
+double orc_gamma_p(double a, double x);
+/* Quantile of Gamma(shape, rate): x with P(shape, rate x) = p. */
+double orc_gamma_quantile(double shape, double rate, double p);
+/* (u, v) copula uniforms and w ~ N(0,1) -> f, fdot, A. */
+void orc_pop_transform(const orc_population *p, double u, double v, double w, double *f, double *fdot,
+                       double *A);
+/* Sources first .. first+n-1 of the catalog drawn with `seed` (fp32 A, f,
+ * fdot; id = source index; id may be NULL).  ORC_E_INVALID on bad
+ * parameters. */
+int orc_pop_draw(const orc_population *p, uint64_t seed, uint64_t first, int64_t n, float *A, float *f,
+                 float *fdot, uint32_t *id);
+
 #ifdef __cplusplus
 }
 #endif

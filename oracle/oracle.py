@@ -16,6 +16,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "gbsub_oracle.c")
+POP_SRC = os.path.join(HERE, "population_oracle.c")
 HDR = os.path.join(HERE, "gbsub_oracle.h")
 BUILD_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(BUILD_DIR, "libgbsub_oracle.so")
@@ -29,11 +30,11 @@ def build(force: bool = False) -> str:
     """Compile the oracle (gcc, -O2, no FMA contraction, OpenMP)."""
     os.makedirs(BUILD_DIR, exist_ok=True)
     if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= max(
-            os.path.getmtime(SRC), os.path.getmtime(HDR)):
+            os.path.getmtime(SRC), os.path.getmtime(POP_SRC), os.path.getmtime(HDR)):
         return LIB
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
-           "-fPIC", "-shared", "-Wall", "-o", tmp, SRC, "-lm"]
+           "-fPIC", "-shared", "-Wall", "-o", tmp, SRC, POP_SRC, "-lm"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
     return LIB
@@ -291,3 +292,72 @@ def run(catalog, cfg: Config, *, spectra: bool = True, trace: bool = False,
                   iter_of=iter_of[:n].copy(), is_candidate=is_c[:n].astype(bool),
                   rho0_sq=rho0[:n].copy(), S_final=S, X_final=X,
                   near=[(int(near_t[j]), int(near_i[j])) for j in range(nn)], trace=traces)
+
+
+# ---------------------------------------------------------------- population model
+
+class Population(C.Structure):
+    """Hyperparameters of the population model (Sec. "Population model",
+    Table "priors"); f_lo_hz / f_hi_hz bound the power law."""
+    _fields_ = [("alpha_pl", C.c_double), ("alpha_g", C.c_double), ("beta_g", C.c_double),
+                ("mu_g", C.c_double), ("mu", C.c_double), ("sigma", C.c_double), ("rho", C.c_double),
+                ("f_lo_hz", C.c_double), ("f_hi_hz", C.c_double)]
+
+
+def population(alpha_pl=-2.9, alpha_g=1.96, beta_g=1.8, mu_g=-21.0, mu=-22.0, sigma=0.18, rho=0.99,
+               f_lo_hz=1e-4, f_hi_hz=1e-2) -> Population:
+    return Population(alpha_pl, alpha_g, beta_g, mu_g, mu, sigma, rho, f_lo_hz, f_hi_hz)
+
+
+def _pop_lib():
+    L = lib()
+    if not getattr(L, "_pop_ready", False):
+        L.orc_philox4x32_10.argtypes = [C.POINTER(C.c_uint32 * 4), C.POINTER(C.c_uint32 * 2),
+                                        C.POINTER(C.c_uint32 * 4)]
+        L.orc_gamma_p.argtypes = [C.c_double, C.c_double]
+        L.orc_gamma_p.restype = C.c_double
+        L.orc_gamma_quantile.argtypes = [C.c_double, C.c_double, C.c_double]
+        L.orc_gamma_quantile.restype = C.c_double
+        L.orc_pop_transform.argtypes = [C.POINTER(Population), C.c_double, C.c_double, C.c_double,
+                                        C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                        C.POINTER(C.c_double)]
+        L.orc_pop_draw.argtypes = [C.POINTER(Population), C.c_uint64, C.c_uint64, C.c_int64,
+                                   C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.orc_pop_draw.restype = C.c_int
+        L._pop_ready = True
+    return L
+
+
+def philox4x32_10(ctr, key):
+    c = (C.c_uint32 * 4)(*ctr)
+    k = (C.c_uint32 * 2)(*key)
+    o = (C.c_uint32 * 4)()
+    _pop_lib().orc_philox4x32_10(C.byref(c), C.byref(k), C.byref(o))
+    return tuple(o)
+
+
+def gamma_p(a: float, x: float) -> float:
+    return _pop_lib().orc_gamma_p(a, x)
+
+
+def gamma_quantile(shape: float, rate: float, p: float) -> float:
+    return _pop_lib().orc_gamma_quantile(shape, rate, p)
+
+
+def pop_transform(pop: Population, u: float, v: float, w: float):
+    f, fd, A = C.c_double(), C.c_double(), C.c_double()
+    _pop_lib().orc_pop_transform(C.byref(pop), u, v, w, C.byref(f), C.byref(fd), C.byref(A))
+    return f.value, fd.value, A.value
+
+
+def pop_draw(pop: Population, seed: int, n: int, first: int = 0):
+    """(A, f, fdot, id) of sources first .. first+n-1, fp32 / uint32."""
+    A = np.empty(n, np.float32)
+    f = np.empty(n, np.float32)
+    fd = np.empty(n, np.float32)
+    ids = np.empty(n, np.uint32)
+    rc = _pop_lib().orc_pop_draw(C.byref(pop), seed, first, n, A.ctypes.data, f.ctypes.data,
+                                 fd.ctypes.data, ids.ctypes.data)
+    if rc != OK:
+        raise ValueError(f"orc_pop_draw: {rc}")
+    return A, f, fd, ids
