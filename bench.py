@@ -216,6 +216,50 @@ def bench_serve(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_generate(args):
+    """Catalogs drawn on the GPU from the population model (gbsub_generate):
+    generator throughput, then generation + subtraction of one catalog."""
+    import torch
+    from paper_2602_18560_amd import gbsub as G
+    from paper_2602_18560_amd.inputs import RunConfig, YEAR_S
+    torch.cuda.set_device(0)
+    n = int(args.n) if args.n != 10_000_000 else 7_500_000      # N_b of the paper's figure
+    pop = G.population(**G.PAPER_FIG_LAMBDA)
+    dc = G.generate(pop, 1, n)
+    torch.cuda.synchronize()
+    log(f"[generate] {n} sources x{args.steps}")
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        G.generate(pop, 100 + s, n, out=dc)
+    torch.cuda.synchronize()
+    gen_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    run = RunConfig(t_obs_s=4 * YEAR_S, f_min_hz=1e-4, f_max_hz=1e-2, window_bins=1001)
+    ctx = G.Context(G.config_from_run(run))
+    ctx.ensure_workspace(n)
+    G.generate(pop, 7, n, out=dc)
+    s = ctx.run(dc)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        G.generate(pop, 7, n, out=dc)
+        s = ctx.run(dc)
+    torch.cuda.synchronize()
+    e2e_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    ctx.close()
+    out = {"metric": "sources/s", "value": n / (gen_ms * 1e-3), "unit": "sources/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": 1, "ms_per_step": gen_ms, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"{n} sources drawn on the GPU from the population model with the "
+                                  "hyperparameters of the paper's population-model figure "
+                                  "(alpha_PL -2.9, alpha_G 1.96, beta_G 1.8, mu_G -21, mu -22, "
+                                  "sigma 0.18, rho 0.99) on [0.1, 10] mHz",
+                      "n_sources": n},
+           "generate_and_subtract": {"ms": e2e_ms, "t_obs_yr": 4, "window_bins": 1001,
+                                     "n_iter": s.n_iter, "n_resolved": s.n_resolved,
+                                     "n_candidates": s.n_candidates}}
+    print(json.dumps(out), flush=True)
+
+
 def bench_precision(args):
     """FP64 / FP32 compensated / naive FP32 against the oracle (tests/golden)."""
     import numpy as np
@@ -289,7 +333,7 @@ def bench_precision(args):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", choices=["1e7", "batch", "serve", "precision"], default="1e7")
+    ap.add_argument("--workload", choices=["1e7", "batch", "serve", "precision", "generate"], default="1e7")
     ap.add_argument("--catalogs", type=int, default=64, help="batch: number of catalogs")
     ap.add_argument("--jobs", type=int, default=64, help="serve: number of jobs")
     ap.add_argument("--slots", type=int, default=64, help="serve: batch slots")
@@ -320,6 +364,8 @@ def main():
         return bench_serve(args)
     if args.workload == "precision":
         return bench_precision(args)
+    if args.workload == "generate":
+        return bench_generate(args)
 
     import numpy as np
     import torch

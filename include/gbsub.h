@@ -178,6 +178,36 @@ gbsub_status gbsub_coarse(const gbsub_ctx *ctx, uint32_t kind, double f_lo, doub
 gbsub_status gbsub_candidates(const gbsub_ctx *ctx, uint32_t *ids, int32_t *iter_of, double *rho2,
                               uint64_t cap, uint64_t *n);
 
+/* ---------------------------------------------------------------- catalogs
+ * Population model of Sec. "Population model" (Table "priors", appendix
+ * "Copulas"): f ~ f^alpha_PL on [f_lo, f_hi]; log10(fdot) - mu_Gamma ~
+ * Gamma(alpha_Gamma, rate beta_Gamma); log10(f^(-2/3) A) - mu ~ log-normal
+ * with log-scale 0 and shape sigma; (f, fdot) joined by a Gaussian copula
+ * with correlation rho. */
+typedef struct {
+    double alpha_pl;     /* power-law index of f; != -1 (prior U(-4, -2)) */
+    double alpha_g;      /* Gamma shape, > 0 (prior U(1, 3)) */
+    double beta_g;       /* Gamma rate, > 0 (prior U(1, 3)) */
+    double mu_g;         /* mu_Gamma (prior U(-22, -20)) */
+    double mu;           /* amplitude offset mu (prior U(-23, -21)) */
+    double sigma;        /* log-normal shape, >= 0 (prior U(0.1, 0.3)) */
+    double rho;          /* copula correlation, |rho| < 1 (prior U(0, 1)) */
+    double f_lo_hz;      /* power-law support, 0 < f_lo < f_hi (the paper: 1e-4 .. 1e-2 Hz) */
+    double f_hi_hz;
+} gbsub_population;
+
+/* Draws sources first .. first+n-1 of the catalog defined by (pop, seed)
+ * into DEVICE arrays A, f, fdot (fp32, n entries each, caller-owned) and, if
+ * id is non-null, id[i] = first + i (uint32).  Source i is a function of
+ * (pop, seed, first + i) only: Philox4x32-10 with key = seed and counter =
+ * (index, block) gives its random numbers, so a catalog can be drawn in
+ * pieces, and the same catalog results on any launch shape.  Enqueued on
+ * `stream` (hipStream_t; NULL = default stream) on the current device;
+ * returns without waiting.  Allocates nothing.  Errors: INVALID for bad
+ * parameters or a NULL output with n > 0, DEVICE for a launch failure. */
+gbsub_status gbsub_generate(const gbsub_population *pop, uint64_t seed, uint64_t first, uint64_t n, float *A,
+                            float *f, float *fdot, uint32_t *id, void *stream);
+
 /* Kernel families of the profiling mode (bit k of the mask selects family k). */
 enum {
     GBSUB_KF_TABLES = 0,         /* S_instr and its prefix tables (first run on a workspace) */

@@ -543,6 +543,22 @@ gbsub_status gbsub_coarse(const gbsub_ctx *c, uint32_t kind, double f_lo, double
     return GBSUB_OK;
 }
 
+gbsub_status gbsub_generate(const gbsub_population *pop, uint64_t seed, uint64_t first, uint64_t n, float *A,
+                            float *f, float *fdot, uint32_t *id, void *stream)
+{
+    if (!pop) return GBSUB_E_INVALID;
+    const gbsub_population &p = *pop;
+    const double v[9] = {p.alpha_pl, p.alpha_g, p.beta_g, p.mu_g, p.mu, p.sigma, p.rho, p.f_lo_hz, p.f_hi_hz};
+    for (double x : v)
+        if (!std::isfinite(x)) return GBSUB_E_INVALID;
+    if (p.alpha_pl == -1.0 || !(p.alpha_g > 0.0) || !(p.beta_g > 0.0) || !(p.sigma >= 0.0) || !(p.rho > -1.0) ||
+        !(p.rho < 1.0) || !(p.f_lo_hz > 0.0) || !(p.f_hi_hz > p.f_lo_hz))
+        return GBSUB_E_INVALID;
+    if (n > 0 && (!A || !f || !fdot)) return GBSUB_E_INVALID;
+    const PopParams pp{p.alpha_pl, p.alpha_g, p.beta_g, p.mu_g, p.mu, p.sigma, p.rho, p.f_lo_hz, p.f_hi_hz};
+    return dev_err(launch_generate(pp, seed, first, n, A, f, fdot, id, (hipStream_t)stream));
+}
+
 gbsub_status gbsub_resolved(const gbsub_ctx *c, uint32_t *ids, int32_t *iter_of, uint64_t cap,
                             uint64_t *n, int out_on_device)
 {

@@ -196,6 +196,15 @@ hipError_t launch_snr(const Slot *ds, const Dims &dm, hipStream_t st, hipEvent_t
 hipError_t launch_outputs(const Slot *ds, const Dims &dm, hipStream_t st);
 
 struct CoarseEdges { double e[COARSE_MAX + 1]; };
+
+// Population hyperparameters of a generator launch (gbsub_population).
+struct PopParams {
+    double alpha_pl, alpha_g, beta_g, mu_g, mu, sigma, rho, f_lo_hz, f_hi_hz;
+};
+// Sources first .. first+n-1 of the catalog drawn with `seed` into the fp32
+// columns A, F, FD and (if non-null) the ids (gbsub_population.hip).
+hipError_t launch_generate(const PopParams &pp, uint64_t seed, uint64_t first, uint64_t n, float *A, float *F,
+                           float *FD, uint32_t *id, hipStream_t st);
 // Sums of f_i and of the chosen spectrum over each logarithmic bin
 // [e_k, e_{k+1}) (the last bin closed) into out[3k .. 3k+2] = (sum f, sum v, count).
 hipError_t launch_coarse(const double *S, const double *sx, const double *X, int kind, int64_t k0, int B,

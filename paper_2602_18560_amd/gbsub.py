@@ -27,7 +27,7 @@ EXPORTS = ["gbsub_default_config", "gbsub_create", "gbsub_workspace_size", "gbsu
            "gbsub_status_str",
            "gbsub_set_profiling", "gbsub_kernel_stats", "gbsub_batch_table_size",
            "gbsub_batch_create", "gbsub_batch_admit", "gbsub_batch_step", "gbsub_batch_poll",
-           "gbsub_batch_retire", "gbsub_batch_destroy"]
+           "gbsub_batch_retire", "gbsub_batch_destroy", "gbsub_generate"]
 SLOT_RUNNING, SLOT_SETTLED, SLOT_MAXITER, SLOT_INVALID, SLOT_FREE = 0, 1, 2, 3, 255
 (KF_TABLES, KF_RESET, KF_PREP, KF_XUPDATE, KF_MEDIAN, KF_SNR, KF_OUTPUT) = range(7)
 PROFILE_ALL = 0x7F
@@ -46,6 +46,13 @@ class Config(C.Structure):
                 ("track_model", C.c_uint32), ("precision", C.c_uint32), ("max_iter", C.c_uint32),
                 ("reserved0", C.c_uint32), ("oms_pm", C.c_double), ("tm_fm", C.c_double),
                 ("arm_m", C.c_double), ("tile_bins", C.c_uint32), ("split_blocks", C.c_uint32)]
+
+
+class PopulationStruct(C.Structure):
+    """gbsub_population: hyperparameters of the population model."""
+    _fields_ = [("alpha_pl", C.c_double), ("alpha_g", C.c_double), ("beta_g", C.c_double),
+                ("mu_g", C.c_double), ("mu", C.c_double), ("sigma", C.c_double), ("rho", C.c_double),
+                ("f_lo_hz", C.c_double), ("f_hi_hz", C.c_double)]
 
 
 class CatalogStruct(C.Structure):
@@ -114,11 +121,13 @@ def load(path: str | None = None):
     L.gbsub_batch_retire.argtypes = [C.c_void_p, C.c_uint32, C.c_void_p, C.POINTER(SummaryStruct)]
     L.gbsub_batch_destroy.argtypes = [C.c_void_p]
     L.gbsub_batch_destroy.restype = None
+    L.gbsub_generate.argtypes = [C.POINTER(PopulationStruct), C.c_uint64, C.c_uint64, C.c_uint64,
+                                 C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
     for name in ("gbsub_create", "gbsub_workspace_size", "gbsub_run", "gbsub_spectrum",
                  "gbsub_resolved", "gbsub_candidates", "gbsub_coarse", "gbsub_set_profiling",
                  "gbsub_kernel_stats",
                  "gbsub_batch_table_size", "gbsub_batch_create", "gbsub_batch_admit",
-                 "gbsub_batch_step", "gbsub_batch_poll", "gbsub_batch_retire"):
+                 "gbsub_batch_step", "gbsub_batch_poll", "gbsub_batch_retire", "gbsub_generate"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -404,6 +413,36 @@ class Batch:
         st = self._L.gbsub_batch_retire(self.h, int(slot), C.c_void_p(sp), C.byref(s))
         self.slots.pop(slot, None)
         return st, _summary(s)
+
+
+PAPER_FIG_LAMBDA = dict(alpha_pl=-2.9, alpha_g=1.96, beta_g=1.8, mu_g=-21.0, mu=-22.0, sigma=0.18,
+                        rho=0.99)   # the hyperparameters of the paper's population-model figure
+
+
+def population(alpha_pl=-2.9, alpha_g=1.96, beta_g=1.8, mu_g=-21.0, mu=-22.0, sigma=0.18, rho=0.99,
+               f_lo_hz=1e-4, f_hi_hz=1e-2) -> PopulationStruct:
+    return PopulationStruct(alpha_pl, alpha_g, beta_g, mu_g, mu, sigma, rho, f_lo_hz, f_hi_hz)
+
+
+def generate(pop: PopulationStruct, seed: int, n: int, first: int = 0, out: DeviceCatalog = None,
+             stream=None) -> DeviceCatalog:
+    """Sources first .. first+n-1 of the catalog (pop, seed), drawn on the GPU
+    into `out` (or new tensors) with ``gbsub_generate``; asynchronous on the
+    stream."""
+    torch = _torch()
+    L = load()
+    if out is None:
+        mk = lambda dt: torch.empty(n, dtype=dt, device="cuda")
+        out = DeviceCatalog(mk(torch.float32), mk(torch.float32), mk(torch.float32), mk(torch.int32))
+    elif out.n != n:
+        raise ValueError("out must hold n sources")
+    sp = (stream or torch.cuda.current_stream()).cuda_stream
+    st = L.gbsub_generate(C.byref(pop), int(seed), int(first), int(n), C.c_void_p(out.A.data_ptr()),
+                          C.c_void_p(out.f.data_ptr()), C.c_void_p(out.fdot.data_ptr()),
+                          C.c_void_p(out.id.data_ptr()), C.c_void_p(sp))
+    if st != OK:
+        raise GbsubError(st, "gbsub_generate")
+    return out
 
 
 def subtract(cat, run, **kw):

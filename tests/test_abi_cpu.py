@@ -52,3 +52,17 @@ def test_binding_refuses_without_gpu(monkeypatch):
         pytest.skip("a GPU is present")
     with pytest.raises(RuntimeError):
         G.Context(G.default_config())
+
+
+def test_generate_validates_parameters_without_launching():
+    """gbsub_generate checks its arguments before any device call; with
+    n = 0 there is nothing to launch."""
+    L = G.load()
+    ok = G.population()
+    assert C.sizeof(G.PopulationStruct) == 72
+    assert L.gbsub_generate(C.byref(ok), 1, 0, 0, None, None, None, None, None) == G.OK
+    for bad in (dict(rho=1.0), dict(rho=-1.0), dict(alpha_pl=-1.0), dict(alpha_g=0.0), dict(beta_g=-1.0),
+                dict(sigma=-0.1), dict(f_lo_hz=0.0), dict(f_hi_hz=1e-5), dict(mu=float("nan"))):
+        p = G.population(**bad)
+        assert L.gbsub_generate(C.byref(p), 1, 0, 0, None, None, None, None, None) == G.E_INVALID, bad
+    assert L.gbsub_generate(C.byref(ok), 1, 0, 10, None, None, None, None, None) == G.E_INVALID
