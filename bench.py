@@ -163,20 +163,31 @@ def bench_batch(args):
 
 
 def bench_serve(args):
-    """Continuous batching of a Poisson job stream (saturated run first)."""
-    from paper_2602_18560_amd.inputs import job_stream, draw_catalogs
-    jobs = job_stream(args.jobs, rate_hz=1.0)
-    log(f"[serve] drawing {len(jobs)} catalogs, {sum(j.population.n for j in jobs):.3e} sources")
-    t0 = time.perf_counter()
-    cats = draw_catalogs([j.population for j in jobs])
-    log(f"[serve] drawn in {time.perf_counter() - t0:.1f} s")
+    """Continuous batching of a Poisson job stream (saturated run first).
+    With --gpu-gen the jobs' catalogs come from the population model and are
+    drawn on the GPU at admission (inside the latency; no host catalog)."""
+    import dataclasses
+    if args.gpu_gen:
+        from paper_2602_18560_amd.inputs import model_job_stream
+        jobs = model_job_stream(args.jobs, rate_hz=1.0)
+        log(f"[serve] {len(jobs)} model jobs, {sum(j.n for j in jobs):.3e} sources drawn on the GPU")
+    else:
+        from paper_2602_18560_amd.inputs import job_stream, draw_catalogs
+        jobs = job_stream(args.jobs, rate_hz=1.0)
+        log(f"[serve] drawing {len(jobs)} catalogs, {sum(j.population.n for j in jobs):.3e} sources")
+        t0 = time.perf_counter()
+        cats = draw_catalogs([j.population for j in jobs])
+        log(f"[serve] drawn in {time.perf_counter() - t0:.1f} s")
     import torch
     from paper_2602_18560_amd import serve as SV
     torch.cuda.set_device(0)
-    pinned = [SV.pin_catalog(c) for c in cats]
-    del cats
+    if not args.gpu_gen:
+        pinned = [SV.pin_catalog(c) for c in cats]
+        del cats
 
     def requests(times):
+        if args.gpu_gen:
+            return [SV.model_request(dataclasses.replace(j, arrival_s=t)) for j, t in zip(jobs, times)]
         return [SV.Request(j.index, t, *p, run=j.run) for j, t, p in zip(jobs, times, pinned)]
 
     log("[serve] warmup")
@@ -201,10 +212,15 @@ def bench_serve(args):
         "steps": len(jobs), "warmup": 4, "ms_per_step": span2 / len(jobs) * 1e3,
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"{len(jobs)} jobs, Poisson arrivals at {args.load}x the saturated "
-                               "rate, N log-uniform in [1e5, 3e7], T in {1,2,4} yr with W = "
-                               "251/501/1001 (meta seed 5, job j seed 5000+j); catalogs drawn "
-                               "ahead into pinned host memory, H2D inside the latency",
+        "config": {"workload": (f"{len(jobs)} jobs, Poisson arrivals at {args.load}x the saturated "
+                                "rate, N log-uniform in [1e5, 3e7], T in {1,2,4} yr with W = "
+                                "251/501/1001 " + (
+                                    "(meta seed 7, job j generator seed 7000+j); catalogs drawn on "
+                                    "the GPU from the population model at admission, hyperparameters "
+                                    "uniform in the prior box, generation inside the latency"
+                                    if args.gpu_gen else
+                                    "(meta seed 5, job j seed 5000+j); catalogs drawn ahead into "
+                                    "pinned host memory, H2D inside the latency")),
                    "slots": args.slots, "budget_gb": args.budget_gb, "chunk": args.chunk},
         "latency_ms": {"p50": percentile(lat, 50) * 1e3, "p99": percentile(lat, 99) * 1e3,
                        "max": max(lat) * 1e3},
@@ -340,6 +356,8 @@ def main():
     ap.add_argument("--budget-gb", type=float, default=200.0, help="serve: device memory budget")
     ap.add_argument("--load", type=float, default=0.7, help="serve: arrival rate / saturated rate")
     ap.add_argument("--chunk", type=int, default=4, help="loop bodies per batch step")
+    ap.add_argument("--gpu-gen", action="store_true",
+                    help="serve: catalogs drawn on the GPU from the population model at admission")
     ap.add_argument("--estimator", choices=["median", "mean"], default="median",
                     help="1e7 workload: running median (default) or running mean")
     ap.add_argument("--window", type=int, default=0, help="1e7 workload: window bins (default 1001)")

@@ -95,7 +95,9 @@ typedef struct {
 /* A catalog in structure-of-arrays form.  A, f, fdot, id are DEVICE
  * pointers to n entries each, read-only, not retained after gbsub_run
  * returns.  Valid entries: finite A >= 0, finite f > 0, finite fdot,
- * |fdot|*T^2 < 2^31 and |(f + fdot*T/2)*T| < 2^52.  ids are opaque. */
+ * a source with |fdot|*T^2 or |(f + fdot*T/2)*T| at 2^52 or beyond puts no
+ * power on the grid (at most 2^-52 of it would fall in any bin).  ids are
+ * opaque. */
 typedef struct {
     uint64_t        n;
     const float    *A;

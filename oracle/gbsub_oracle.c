@@ -138,8 +138,16 @@ int orc_track(const orc_config *c, int64_t k0, int64_t n_bins, float Af, float f
     const double fbar = f + (fd * T) * 0.5;
     const double x = fbar * T + 0.5;
     const double s = (fabs(fd) * T) * T;
-    if (!(fabs(x) < 4503599627370496.0) || !(s < 2147483648.0))   /* 2^52, 2^31 */
-        return ORC_E_INVALID;
+    if (!(fabs(x) < 4503599627370496.0) || !(s < 4503599627370496.0)) {
+        /* 2^52 bins or more away, or long: at most 2^-52 of the power in
+         * any bin; no power on the grid (as for a source off the grid) */
+        *lo = 0;
+        *n = 0;
+        *q = 0.0;
+        *glo = 1;
+        *ghi = 0;
+        return ORC_OK;
+    }
     const int64_t cbin = (int64_t)floor(x) - k0;
     const int64_t nn = (c->track_model == ORC_TRACK_SINGLE) ? 1 : 1 + (int64_t)floor(s);
     const int64_t l = cbin - (nn - 1) / 2;

@@ -408,9 +408,11 @@ DEVI Trk track_geom(const Grid &g, float Af, float Ff, float FDf)
     const double fbar = f + (fd * g.T) * 0.5;
     const double x = fbar * g.T + 0.5;
     const double s = (fabs(fd) * g.T) * g.T;
-    ok = ok && fabs(x) < 4503599627370496.0 && s < 2147483648.0;
     if (!ok) return t;
     t.ok = true;
+    // 2^52 bins or more away, or long (beyond exact integers): at most 2^-52
+    // of the power in any bin; no power on the grid
+    if (!(fabs(x) < 4503599627370496.0 && s < 4503599627370496.0)) return t;
     // integer-valued fp64 throughout (|values| < 2^53: exact)
     const double c = floor(x) - (double)g.k0;
     const double nn = g.track_single ? 1.0 : 1.0 + floor(s);

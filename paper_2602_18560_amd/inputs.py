@@ -211,3 +211,42 @@ def draw_catalogs(pops, workers: int | None = None):
     for j, (A, f, fd, ids) in zip(order, res):
         out[j] = Catalog(A, f, fd, ids, pops[j])
     return out
+
+
+# Uniform prior box of the population model's hyperparameters (Table
+# "priors"): alpha_PL, alpha_Gamma, beta_Gamma, mu_Gamma, mu, sigma, rho.
+MODEL_PRIOR_BOX = {"alpha_pl": (-4.0, -2.0), "alpha_g": (1.0, 3.0), "beta_g": (1.0, 3.0),
+                   "mu_g": (-22.0, -20.0), "mu": (-23.0, -21.0), "sigma": (0.1, 0.3), "rho": (0.0, 1.0)}
+
+
+@dataclass(frozen=True)
+class ModelJob:
+    """A subtraction job whose catalog is drawn on the GPU from the
+    population model: hyperparameters, generator seed and size."""
+    index: int
+    arrival_s: float
+    model: dict
+    seed: int
+    n: int
+    run: RunConfig
+
+
+def model_job_stream(n_jobs: int = 64, rate_hz: float = 1.0, n_lo: float = 1e5, n_hi: float = 3e7):
+    """Poisson stream of jobs drawn from the model: hyperparameters uniform
+    in the prior box (rho below 0.999), N log-uniform in [n_lo, n_hi], T in
+    {1, 2, 4} yr with W = 251/501/1001, f in [0.1, 10] mHz (the model's
+    support).  Meta seed 7, job j generator seed 7000+j."""
+    rng = np.random.default_rng(7)
+    t = 0.0
+    jobs = []
+    for j in range(n_jobs):
+        t += float(rng.exponential(1.0 / rate_hz))
+        n = int(round(10 ** rng.uniform(math.log10(n_lo), math.log10(n_hi))))
+        years = int(rng.choice([1, 2, 4]))
+        lam = {k: float(rng.uniform(lo, hi)) for k, (lo, hi) in MODEL_PRIOR_BOX.items()}
+        lam["rho"] = min(lam["rho"], 0.999)
+        run = RunConfig(t_obs_s=years * YEAR_S, f_min_hz=1e-4, f_max_hz=1e-2,
+                        window_bins=WINDOW_FOR_YEARS[years])
+        jobs.append(ModelJob(j, t, lam, 7000 + j, n, run))
+    return jobs
+

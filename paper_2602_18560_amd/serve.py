@@ -1,7 +1,8 @@
 """Continuous-batching service of subtraction jobs on one GPU.
 
-Jobs (a catalog in pinned host memory plus its run configuration) are queued
-in arrival order.  A job is admitted into the shared gbsub batch as soon as a
+Jobs (a catalog in pinned host memory, or population-model hyperparameters
+and a seed to draw it on the GPU, plus its run configuration) are queued in
+arrival order.  A job is admitted into the shared gbsub batch as soon as a
 slot is free and its device footprint (catalog + workspace) fits the byte
 budget; admission copies the catalog host-to-device, runs its preparation and
 adds it to every following loop launch.  All running jobs advance together,
@@ -24,12 +25,21 @@ from . import gbsub as G
 class Request:
     index: int
     arrival_s: float
-    A: object            # pinned host tensors, fp32 (id: int32 view of uint32)
+    A: object            # pinned host tensors, fp32 (id: int32 view of uint32); None: drawn on the GPU
     f: object
     fdot: object
     ids: object
     run: object          # inputs.RunConfig
-    n: int = 0
+    n: int = 0           # sources (read from A when it is given)
+    model: object = None  # gbsub.PopulationStruct of a catalog drawn at admission
+    seed: int = 0
+
+
+def model_request(job) -> Request:
+    """Request of an inputs.ModelJob: its catalog is drawn on the GPU at
+    admission (no host catalog, no host-to-device copy)."""
+    return Request(job.index, job.arrival_s, None, None, None, None, run=job.run, n=job.n,
+                   model=G.population(**job.model), seed=job.seed)
 
 
 @dataclass
@@ -87,7 +97,8 @@ class Server:
         self.t0 = time.perf_counter()
 
     def submit(self, req: Request):
-        req.n = int(req.A.shape[0])
+        if req.A is not None:
+            req.n = int(req.A.shape[0])
         self.queue.append(req)
 
     def footprint(self, ctx: G.Context, n: int) -> int:
@@ -104,14 +115,19 @@ class Server:
                 return                      # first in, first served: wait for memory
             self.queue.popleft()
             with torch.cuda.stream(self.stream):
-                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                a.record(self.stream)
-                dev = [torch.empty(req.n, dtype=x.dtype, device="cuda") for x in
-                       (req.A, req.f, req.fdot, req.ids)]
-                for d, h in zip(dev, (req.A, req.f, req.fdot, req.ids)):
-                    d.copy_(h, non_blocking=True)
-                b.record(self.stream)
-                self.h2d_events.append((a, b, 16 * req.n))
+                if req.A is None:          # drawn on the GPU, on the serving stream
+                    dev = [torch.empty(req.n, dtype=dt, device="cuda") for dt in
+                           (torch.float32, torch.float32, torch.float32, torch.int32)]
+                    G.generate(req.model, req.seed, req.n, out=G.DeviceCatalog(*dev), stream=self.stream)
+                else:
+                    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    a.record(self.stream)
+                    dev = [torch.empty(req.n, dtype=x.dtype, device="cuda") for x in
+                           (req.A, req.f, req.fdot, req.ids)]
+                    for d, h in zip(dev, (req.A, req.f, req.fdot, req.ids)):
+                        d.copy_(h, non_blocking=True)
+                    b.record(self.stream)
+                    self.h2d_events.append((a, b, 16 * req.n))
                 ws = torch.empty(ctx.workspace_size(req.n) + 256, dtype=torch.uint8, device="cuda")
             ctx.workspace = ws          # the results live there: the context keeps it
             dc = G.DeviceCatalog(*dev)

@@ -312,3 +312,19 @@ def test_coarse_graining_against_oracle(which):
             assert np.all(s[~nz] == 0) and np.all(f[~nz] == 0)
     finally:
         ctx.close()
+
+
+def test_tracks_longer_than_two_to_the_31_bins():
+    """Sources whose track n = 1 + floor(|fdot| T^2) exceeds 2^31 bins, some
+    beyond 2^52 (no power on the grid), next to ordinary ones (the
+    population model's Gamma tail of log fdot)."""
+    run, k0 = small_run(n_bins=4000, W=21)
+    T = run.t_obs_s
+    rng = np.random.default_rng(8)
+    n = 3000
+    bins = rng.integers(0, 4000, n)
+    fd = np.where(rng.random(n) < 0.05, 2.0 ** rng.uniform(31, 60, n) / (T * T), rng.uniform(0, 20, n) / (T * T))
+    Sx = O.sinstr_table(O.make_config(run))
+    P = Sx[bins] * 10 ** rng.uniform(-1, 3, n)
+    cat = catalog([amp_for_power(p, T) for p in P], [bin_freq(k0, b, T) for b in bins], list(fd))
+    assert_parity(cat, run, "tracks beyond 2^31 bins")

@@ -58,3 +58,34 @@ def test_server_results_equal_alone(slots, budget_mb):
         assert c.done_s >= c.admit_s >= c.arrival_s - 1e-9
         c.context.close()
     srv.close()
+
+
+def test_server_with_catalogs_drawn_on_the_gpu():
+    """Jobs given as population-model hyperparameters and a seed: the server
+    draws each catalog on the GPU at admission; every result equals the
+    catalog drawn and run alone."""
+    from paper_2602_18560_amd.inputs import model_job_stream
+    jobs = model_job_stream(5, rate_hz=500.0, n_lo=2e4, n_hi=2e5)
+    ref = []
+    for j in jobs:
+        dc = G.generate(G.population(**j.model), j.seed, j.n)
+        ctx = G.Context(G.config_from_run(j.run))
+        try:
+            s = ctx.run(dc)
+            ref.append((s, ctx.spectrum(G.SPEC_SN), ctx.resolved()))
+        finally:
+            ctx.close()
+    say(f"[serve] {len(jobs)} model jobs, n = {[j.n for j in jobs]}")
+    done, srv = SV.serve([SV.model_request(j) for j in jobs], max_slots=2, budget_bytes=1e12, chunk=2,
+                         keep_contexts=True)
+    assert sorted(c.index for c in done) == list(range(len(jobs)))
+    for c in done:
+        s_ref, S_ref, (ids_ref, it_ref) = ref[c.index]
+        assert c.status == G.OK
+        assert c.summary.n_iter == s_ref.n_iter
+        np.testing.assert_array_equal(c.context.spectrum(G.SPEC_SN), S_ref)
+        ids, it = c.context.resolved()
+        np.testing.assert_array_equal(ids, ids_ref)
+        np.testing.assert_array_equal(it, it_ref)
+        c.context.close()
+    srv.close()

@@ -502,3 +502,37 @@ def test_coarse_matches_brute_force_and_empty_bins():
     k0, B = O.grid(YEAR_S, 3e-4, 1e-2)
     fo, so, cnt = O.coarse(np.ones(B), k0, YEAR_S)
     assert cnt[0] == 0 and fo[0] == 0 and so[0] == 0 and cnt[-1] > 0
+
+
+def test_track_longer_than_two_to_the_31_bins():
+    """n = 1 + floor(|fdot| T^2) bins far beyond 2^31 (the population model's
+    Gamma tail of log fdot reaches it): the upward sweep from the source's
+    bin runs past the grid's end, so every bin from it on holds q = P/n and
+    the bins below hold nothing (Sec. "Signal parametrization")."""
+    run, k0 = small_run(n_bins=60, W=5)
+    T = run.t_obs_s
+    fd = 2.0 ** 40 / (T * T)                     # |fdot| T^2 = 2^40
+    A = 1e-21
+    r = O.run(catalog([A], [bin_freq(k0, 30, T)], [fd]), O.make_config(run))
+    assert r.status == O.OK and r.n_candidates == 0
+    a = float(np.float32(A))
+    P = (a * a * T) * 0.5
+    n = 1 + math.floor((abs(float(np.float32(fd))) * T) * T)
+    assert n > 2 ** 31
+    np.testing.assert_array_equal(r.X_final[:30], 0.0)
+    np.testing.assert_allclose(r.X_final[30:], P / n, rtol=1e-12)
+
+
+def test_track_beyond_exact_integer_bins_puts_no_power_on_the_grid():
+    """|fdot| T^2 >= 2^52 (or a centre 2^52 bins away): at most 2^-52 of the
+    power per bin; the source is valid and leaves the grid empty."""
+    run, k0 = small_run(n_bins=60, W=5)
+    T = run.t_obs_s
+    for fd in (2.0 ** 53 / (T * T), -2.0 ** 60 / (T * T), 100.0):
+        r = O.run(catalog([1e-20, 1e-30], [bin_freq(k0, 30, T), bin_freq(k0, 2, T)], [fd, 0.0]),
+                  O.make_config(run))
+        assert r.status == O.OK and r.n_candidates == 0
+        expect = np.zeros(60)
+        expect[2] = (float(np.float32(1e-30)) ** 2 * T) * 0.5
+        np.testing.assert_allclose(r.X_final, expect, rtol=1e-12, atol=0)
+
