@@ -1542,7 +1542,7 @@ __global__ __launch_bounds__(MWG, 2) void k_median(const Slot *S)
 //
 // S[k] = (1/W) sum_{j in window(k)} (X[j] + S_instr[j])   (the mean form of the
 // PSD estimate, as printed: S_instr inside the sum).  Same tiles, parts,
-// dirty flags and outputs as the median; the window sums are differences of
+// dirty stamps and outputs as the median; the window sums are differences of
 // an in-LDS prefix over the block's union, so no sum runs across the grid.
 
 struct MeanSmem {
