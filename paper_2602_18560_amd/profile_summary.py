@@ -25,8 +25,15 @@ KERNEL_SOURCE = os.path.join(HERE, "csrc", "gbsub_kernels.hip")
 
 
 def kernel_source_hash() -> str:
-    with open(KERNEL_SOURCE, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()
+    """sha256 of the kernel source with comments and whitespace removed: the
+    counters describe the code, so an edit of a comment keeps them valid."""
+    import re
+    with open(KERNEL_SOURCE, encoding="utf-8") as fh:
+        src = fh.read()
+    src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", " ", src)
+    src = re.sub(r"\s+", " ", src).strip()
+    return hashlib.sha256(src.encode()).hexdigest()
 
 
 def short(name: str) -> str:
