@@ -19,7 +19,11 @@ Two more workloads print one JSON line each:
                      p50/p99 latency at 0.7x the measured saturated rate;
   --workload precision   the 1e7-binary catalog in FP64, FP32 with compensated
                      sums and naive FP32: spectrum and SNR errors and resolve-
-                     decision flips against the FP64 oracle's stored results.
+                     decision flips against the FP64 oracle's stored results;
+  --workload generate    catalogs drawn on the GPU from the population model;
+  --workload oracle      the FP64 oracle alone on the host cores (one thread
+                     and all threads, 1e4 and 1e7 catalogs, a subset of the
+                     64-catalog batch).
 """
 from __future__ import annotations
 
@@ -67,17 +71,115 @@ def measured_traffic(kernel: str):
 def cpu_baseline(cat, run, iters=3):
     """The FP64 oracle on the same catalog, first `iters` loop bodies only."""
     from oracle import oracle as O
-    threads = O.set_threads(0)
+    threads = O.set_threads(all_threads())
     cfg = O.make_config(run, max_iter=iters)
     t0 = time.perf_counter()
     r = O.run(cat, cfg, spectra=False)
     dt = time.perf_counter() - t0
     done = r.n_iter
     return {"value": cat.n * done / dt, "unit": "binary-iterations/s", "cores": threads,
-            "kind": "oracle",
+            "kind": "oracle", "host_cpu": host_cpu()["model"],
             "sample": f"the same {cat.n}-source catalog, first {done} loop bodies "
                       f"(prep + {done} x [binning, running median over all bins, SNR]), "
                       f"{dt:.1f} s on {threads} threads"}
+
+
+def host_cpu():
+    """CPU model and the cores this process may run on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "nproc": len(os.sched_getaffinity(0)), "cpu_count": os.cpu_count()}
+
+
+def all_threads():
+    """OpenMP threads for an all-core leg: OMP_NUM_THREADS if set, else the
+    cores this process may run on."""
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    return int(env) if env.isdigit() and int(env) > 0 else len(os.sched_getaffinity(0))
+
+
+def oracle_leg(cat, run, threads=0, max_iter=0):
+    """Time the oracle on one catalog: `threads` OpenMP threads (0 = all),
+    at most `max_iter` loop bodies (0 = the whole run)."""
+    from oracle import oracle as O
+    used = O.set_threads(threads if threads > 0 else all_threads())
+    cfg = O.make_config(run, max_iter=max_iter)
+    t0 = time.perf_counter()
+    r = O.run(cat, cfg, spectra=False)
+    dt = time.perf_counter() - t0
+    if r.status not in (0, -6):
+        raise RuntimeError(f"oracle run failed with status {r.status}")
+    return {"n": int(cat.n), "threads": used, "bodies": int(r.n_iter), "complete": r.status == 0,
+            "seconds": dt, "binary_iterations_per_s": cat.n * r.n_iter / dt}
+
+
+def bench_oracle(args):
+    """The FP64 oracle alone on the host cores: one thread on the 1e4 and 1e7
+    catalogs, all threads on the 1e7 catalog, and all threads on a subset of
+    the 64-catalog batch (the 8 smallest and the 2 largest, first loop bodies
+    only), extrapolated to whole runs with the loop-body counts the GPU finds
+    on the same catalogs."""
+    from paper_2602_18560_amd.inputs import batch_populations, catalog_1e4, catalog_1e7, draw_catalog
+    legs = {}
+    cat, run = catalog_1e4()
+    log("[oracle] 1e4 catalog, one thread, whole run")
+    legs["1e4_single_thread"] = oracle_leg(cat, run, threads=1)
+    log("[oracle] drawing the 1e7 catalog")
+    cat, run = catalog_1e7(args.n)
+    log(f"[oracle] 1e7 catalog, one thread, first {args.oracle_bodies_single} loop bodies")
+    legs["1e7_single_thread"] = oracle_leg(cat, run, threads=1, max_iter=args.oracle_bodies_single)
+    log(f"[oracle] 1e7 catalog, all threads, first {args.cpu_iters} loop bodies")
+    legs["1e7_all_threads"] = oracle_leg(cat, run, threads=0, max_iter=args.cpu_iters)
+    del cat
+    pops, brun = batch_populations(args.catalogs)
+    order = sorted(range(len(pops)), key=lambda j: pops[j].n)
+    subset = order[:8] + order[-2:]
+    bodies = args.oracle_bodies_batch
+    sub = []
+    n_iter_gpu = {}
+    import torch
+    ctx = None
+    if torch.cuda.is_available():
+        from paper_2602_18560_amd import gbsub as G
+        torch.cuda.set_device(0)
+        ctx = G.Context(G.config_from_run(brun))
+    for j in subset:
+        c = draw_catalog(pops[j])
+        log(f"[oracle] batch catalog {j} (N = {c.n}), all threads, first {bodies} loop bodies")
+        leg = oracle_leg(c, brun, threads=0, max_iter=bodies)
+        leg["catalog"] = j
+        if ctx is not None:
+            n_iter_gpu[j] = int(ctx.run(G.DeviceCatalog.from_host(c)).n_iter)
+            leg["n_iter"] = n_iter_gpu[j]
+        sub.append(leg)
+        del c
+    work = sum(l["n"] * l["bodies"] for l in sub)
+    secs = sum(l["seconds"] for l in sub)
+    rate = work / secs
+    batch = {"subset": subset, "legs": sub, "binary_iterations_per_s": rate, "seconds": secs}
+    if n_iter_gpu:
+        full_sub = sum(pops[j].n * n_iter_gpu[j] for j in subset)
+        mean_iter = full_sub / sum(pops[j].n for j in subset)
+        total = sum(p.n for p in pops)
+        batch["extrapolated"] = {
+            "subset_whole_runs_s": full_sub / rate,
+            "all_catalogs_s": total * mean_iter / rate,
+            "how": "measured rate on the subset's first loop bodies; whole runs take the GPU's "
+                   "loop-body counts on the same catalogs; the 64 catalogs take the subset's "
+                   "source-weighted mean count (an extrapolation, not a measurement)"}
+    out = {"metric": "oracle binary-iterations/s", "unit": "binary-iterations/s",
+           "host": host_cpu(), "legs": legs, "batch": batch,
+           "config": {"workload": "FP64 oracle on the host cores: 1e4 catalog (seed 0, T = 1 yr, "
+                                  "W = 251), 1e7 catalog (seed 2, T = 4 yr, W = 1001), and 10 of "
+                                  "the 64 batch catalogs (meta seed 3)"}}
+    print(json.dumps(out), flush=True)
 
 
 def percentile(x, q):
@@ -349,7 +451,8 @@ def bench_precision(args):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", choices=["1e7", "batch", "serve", "precision", "generate"], default="1e7")
+    ap.add_argument("--workload", choices=["1e7", "batch", "serve", "precision", "generate", "oracle"],
+                    default="1e7")
     ap.add_argument("--catalogs", type=int, default=64, help="batch: number of catalogs")
     ap.add_argument("--jobs", type=int, default=64, help="serve: number of jobs")
     ap.add_argument("--slots", type=int, default=64, help="serve: batch slots")
@@ -371,6 +474,10 @@ def main():
     ap.add_argument("--n", type=int, default=10_000_000, help="catalog size (default: 1e7)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=3)
+    ap.add_argument("--oracle-bodies-single", type=int, default=1,
+                    help="oracle workload: loop bodies of the one-thread 1e7 run")
+    ap.add_argument("--oracle-bodies-batch", type=int, default=2,
+                    help="oracle workload: loop bodies per batch catalog")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); catalogs are independent "
@@ -384,6 +491,8 @@ def main():
         return bench_precision(args)
     if args.workload == "generate":
         return bench_generate(args)
+    if args.workload == "oracle":
+        return bench_oracle(args)
 
     import numpy as np
     import torch

@@ -172,8 +172,9 @@ gbsub_status gbsub_coarse(const gbsub_ctx *ctx, uint32_t kind, double f_lo, doub
 
 /* Every candidate of the last successful run (the sources with rho_0 >=
  * kappa rho_th), in ascending id: ids[], the loop body that resolved it in
- * iter_of[] (-1 if never; may be NULL) and rho^2 at its last evaluation
- * (the body that resolved it, else the last body) in rho2[] (may be NULL).
+ * iter_of[] (-1 if never; may be NULL) and rho^2 in rho2[] (may be NULL):
+ * at the body that resolved it, else against the final spectrum (as last
+ * evaluated, in the latest body whose spectrum changed on its track).
  * All pointers are HOST memory of `cap` entries; *n (host) receives the
  * candidate count; TRUNCATED if cap is smaller; STATE if no run has
  * completed.  The rho^2 values are those of the run's precision mode. */

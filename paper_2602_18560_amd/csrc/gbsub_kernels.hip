@@ -1708,13 +1708,34 @@ DEVI void stamp_tiles(uint32_t *stamp, const Grid &g, int lo, int hi, uint32_t n
     for (int tl = div_p2(lo, g.tile); tl <= div_p2(hi, g.tile); ++tl) stamp[tl] = nxt;
 }
 
+// True when S^t may differ from S^{t-1} somewhere on tiles lo/tile ..
+// hi/tile: one of them was refiltered in body t (stamp t), or was stamped
+// for body t + 1 by a writer of this same launch, which may have replaced a
+// stamp t (every stamp is at most t + 1).  Tracks over more than SKIP_TILES
+// tiles count as changed without looking.
+constexpr int SKIP_TILES = 4;
+DEVI bool track_refiltered(const uint32_t *stamp, const Grid &g, int lo, int hi, uint32_t t)
+{
+    const int a = div_p2(lo, g.tile), b = div_p2(hi, g.tile);
+    if (b - a >= SKIP_TILES) return true;
+    bool r = false;
+    for (int tl = a; tl <= b; ++tl) {
+        const uint32_t s = stamp[tl];
+        r |= s == t || s == t + 1;
+    }
+    return r;
+}
+
 // rho^2 = 4 q sum_{k in track} 1/S^t[k] for every unsubtracted candidate
 // (Eq. "SNR inner product" in the sky-averaged power form); rho^2 >
 // rho_th^2 subtracts the source from the binned power at once (appendix
 // "Subtraction algorithm", steps 6-9: the data X^{t+1} no longer holds it)
 // and stamps the tiles the next body must convert (the track) and filter
-// (the track widened by half a window).  Per-block counts go to b_part;
-// k_snr_tail combines them.
+// (the track widened by half a window).  A candidate whose track lies in
+// tiles the median left alone this body sees the same S as at its last
+// evaluation, so its stored rho^2 stands (it was not above threshold then,
+// or it would have been subtracted); body 0 filters every tile.  Per-block
+// counts go to b_part; k_snr_tail combines them.
 __global__ __launch_bounds__(WG) void k_snr(const Slot *S)
 {
     constexpr int NW = WG / 64;
@@ -1733,13 +1754,17 @@ __global__ __launch_bounds__(WG) void k_snr(const Slot *S)
     double minm = INFINITY;
     for (uint32_t j = blockIdx.x * WG + threadIdx.x; j < nc; j += gridDim.x * WG) {
         if (d.c_iter[j] >= 0) continue;
-        ++evals;
         const int glo = d.c_glo[j], ghi = d.c_ghi[j];
-        const double q = d.c_q[j];
-        const double r2 = g.prec == PREC_FP64
-                              ? (4.0 * q) * range_inv_sum(d.S, d.is_pre, d.is_part, glo, ghi, g.part)
-                              : snr2_f32(g, d, q, glo, ghi);
-        d.c_rho2[j] = r2;
+        double r2;
+        if (t != 0 && !track_refiltered(d.sstamp, g, glo, ghi, (uint32_t)t)) {
+            r2 = d.c_rho2[j];
+        } else {
+            ++evals;
+            const double q = d.c_q[j];
+            r2 = g.prec == PREC_FP64 ? (4.0 * q) * range_inv_sum(d.S, d.is_pre, d.is_part, glo, ghi, g.part)
+                                     : snr2_f32(g, d, q, glo, ghi);
+            d.c_rho2[j] = r2;
+        }
         const double rel = fabs(sqrt(r2) / g.rth - 1.0);
         minm = fmin(minm, rel);
         near += rel <= 1e-6;
