@@ -419,26 +419,30 @@ gbsub_status gbsub_run(gbsub_ctx *c, const gbsub_catalog *cat, void *ws, uint64_
     }
     if (e == hipSuccess) e = c->timed(K_RESET, -1, st, [&] { return launch_reset(ds, dm, st); });
     if (e == hipSuccess) e = c->timed(K_PREP, -1, st, [&] { return launch_prep(ds, dm, st); });
+    if (e == hipSuccess)
+        e = c->timed_ext(K_XUPDATE, -1, [&](hipEvent_t a, hipEvent_t b) { return launch_xupdate(ds, dm, st, a, b); });
     if (e != hipSuccess) {
         c->tables_ws = nullptr;
         return GBSUB_E_DEVICE;
     }
-    // loop bodies in growing chunks; the device enforces max_iter
+    // loop bodies in growing chunks; the device enforces max_iter.  A body
+    // is median, SNR, then the X update of the next body, whose last block
+    // takes this body's stop decision.
     uint64_t t = 0, chunk = 4;
     const uint64_t guard = (uint64_t)cat->n + 2 + (c->cfg.max_iter ? c->cfg.max_iter : 0);
     for (;;) {
         for (uint64_t i = 0; i < chunk && e == hipSuccess; ++i) {
             const int64_t ti = (int64_t)(t + i);
-            e = c->timed_ext(K_XUPDATE, ti, [&](hipEvent_t a, hipEvent_t b) {
-                return launch_xupdate(ds, dm, st, a, b);
+            e = c->timed_ext(K_MEDIAN, ti, [&](hipEvent_t a, hipEvent_t b) {
+                return launch_median(ds, dm, st, a, b);
             });
-            if (e == hipSuccess)
-                e = c->timed_ext(K_MEDIAN, ti, [&](hipEvent_t a, hipEvent_t b) {
-                    return launch_median(ds, dm, st, a, b);
-                });
             if (e == hipSuccess)
                 e = c->timed_ext(K_SNR, ti, [&](hipEvent_t a, hipEvent_t b) {
                     return launch_snr(ds, dm, st, a, b);
+                });
+            if (e == hipSuccess)
+                e = c->timed_ext(K_XUPDATE, ti, [&](hipEvent_t a, hipEvent_t b) {
+                    return launch_xupdate(ds, dm, st, a, b);
                 });
         }
         t += chunk;
@@ -697,9 +701,9 @@ hipError_t enqueue_bodies(const Slot *ds, const Dims &dm, uint32_t n, hipStream_
 {
     hipError_t e = hipSuccess;
     for (uint32_t i = 0; i < n && e == hipSuccess; ++i) {
-        e = launch_xupdate(ds, dm, st);
-        if (e == hipSuccess) e = launch_median(ds, dm, st);
+        e = launch_median(ds, dm, st);
         if (e == hipSuccess) e = launch_snr(ds, dm, st);
+        if (e == hipSuccess) e = launch_xupdate(ds, dm, st);
     }
     return e;
 }
@@ -792,6 +796,7 @@ gbsub_status gbsub_batch_admit(gbsub_batch *b, gbsub_ctx *c, const gbsub_catalog
     }
     if (e == hipSuccess) e = launch_reset(ds, one, st);
     if (e == hipSuccess) e = launch_prep(ds, one, st);
+    if (e == hipSuccess) e = launch_xupdate(ds, one, st);
     if (e != hipSuccess) {
         c->tables_ws = nullptr;
         return GBSUB_E_DEVICE;

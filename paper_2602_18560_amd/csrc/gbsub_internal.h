@@ -61,9 +61,12 @@ struct Ctl {
     uint64_t units_snr;      // candidate evaluations by k_snr
     uint32_t status;         // 0 running/settled, 6 = max_iter reached with sources still resolving
     uint32_t med_split;      // next median launch: one block per part (1) or per tile (0)
+    uint32_t xupd;           // stamp of the tiles the next k_xupdate converts
+    uint32_t tail_due;       // k_snr has run; its partials await the tail
 };
 
-// Per-block partial results of k_snr (combined by k_snr_tail).
+// Per-block partial results of k_snr (combined by the tail: the last block
+// of the next k_xupdate, or k_snr_tail in the naive FP32 mode).
 struct SnrPart {
     uint32_t n_new;          // sources subtracted
     uint32_t pad;

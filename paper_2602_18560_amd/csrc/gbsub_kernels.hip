@@ -362,6 +362,8 @@ __global__ __launch_bounds__(WG) void k_reset(const Slot *S)
         c->units_snr = 0;
         c->status = 0;
         c->med_split = (uint32_t)g.nt <= g.split_tiles;   // every tile is dirty
+        c->xupd = 0;
+        c->tail_due = 0;
     }
     for (int i = blockIdx.x * WG + threadIdx.x; i < g.nt; i += gridDim.x * WG) {
         d.btot[i] = 0;
@@ -950,6 +952,11 @@ __global__ __launch_bounds__(WG) void k_accum_f32(const Slot *S)
 // conflicts).
 DEVI int xpad(int i) { return i + (i >> 3); }
 
+template <int NT> DEVI void snr_tail(const Slot &sl);
+
+// The last block of the grid is the tail of the previous k_snr (its
+// decisions touch neither the stamps nor the accumulators these blocks
+// read; a stop it takes leaves no tile stamped for conversion).
 __global__ __launch_bounds__(WG) void k_xupdate(const Slot *S)
 {
     __shared__ I128 sh[WG / 64];
@@ -957,11 +964,15 @@ __global__ __launch_bounds__(WG) void k_xupdate(const Slot *S)
     __shared__ float shf[WG / 64];
     const Slot &sl = S[blockIdx.y];
     if (!sl.active) return;
+    if (blockIdx.x == gridDim.x - 1) {
+        snr_tail<WG>(sl);
+        return;
+    }
     const Grid g = sl.g;
     const Dev d = sl.d;
     if (d.ctl->done || d.ctl->bad) return;
     const int tile = blockIdx.x;
-    if (tile >= g.nt || d.xstamp[tile] != d.ctl->iter) return;
+    if (tile >= g.nt || d.xstamp[tile] != d.ctl->xupd) return;
     const int L = fx_exp(d.ctl->amax_bits, g.T);
     const int t0 = tile * g.tile;
     const int n = min(g.tile, g.B - t0);
@@ -1701,7 +1712,7 @@ DEVI void subtract_track_f32(const Grid &g, const Dev &d, int glo, int ghi, floa
 }
 
 // Stamps tiles lo/tile .. hi/tile for body `nxt` (every writer stores the
-// same value, read after the launch ends; k_snr_tail counts the stamped
+// same value, read after the launch ends; the tail counts the stamped
 // tiles).
 DEVI void stamp_tiles(uint32_t *stamp, const Grid &g, int lo, int hi, uint32_t nxt)
 {
@@ -1735,7 +1746,7 @@ DEVI bool track_refiltered(const uint32_t *stamp, const Grid &g, int lo, int hi,
 // tiles the median left alone this body sees the same S as at its last
 // evaluation, so its stored rho^2 stands (it was not above threshold then,
 // or it would have been subtracted); body 0 filters every tile.  Per-block
-// counts go to b_part; k_snr_tail combines them.
+// counts go to b_part for the tail (snr_tail).
 __global__ __launch_bounds__(WG) void k_snr(const Slot *S)
 {
     constexpr int NW = WG / 64;
@@ -1798,6 +1809,10 @@ __global__ __launch_bounds__(WG) void k_snr(const Slot *S)
     }
     __syncthreads();
     if (threadIdx.x == 0) {
+        if (blockIdx.x == 0) {
+            d.ctl->xupd = nxt;
+            d.ctl->tail_due = 1;
+        }
         for (int v = 1; v < NW; ++v) {
             for (int r = 0; r < 3; ++r) s_red[r][0] += s_red[r][v];
             s_min[0] = fmin(s_min[0], s_min[v]);
@@ -1812,27 +1827,34 @@ __global__ __launch_bounds__(WG) void k_snr(const Slot *S)
     }
 }
 
-// One block of one thread per k_snr block: combines the partials, counts
-// the tiles stamped for the next body, takes the stop decision (nothing new
-// subtracted, or max_iter) and whether the next median runs in split mode.
-__global__ __launch_bounds__(SNR_BLOCKS) void k_snr_tail(const Slot *S)
+// The tail of a loop body, run by one block of NT threads once k_snr has
+// ended: combines the per-block partials, counts the tiles stamped for the
+// next body, takes the stop decision (nothing new subtracted, or max_iter)
+// and whether the next median runs in split mode.  It runs at most once per
+// k_snr (tail_due).
+template <int NT> DEVI void snr_tail(const Slot &sl)
 {
-    constexpr int NW = SNR_BLOCKS / 64;
+    constexpr int NW = NT / 64;
     __shared__ uint64_t s_red[5][NW];     // new, near, evals, ux, us
     __shared__ uint32_t s_nds[NW];
     __shared__ double s_min[NW];
-    const Slot &sl = S[blockIdx.y];
-    if (!sl.active) return;
     const Grid g = sl.g;
     const Dev d = sl.d;
-    if (d.ctl->done || d.ctl->bad) return;
-    if (g.prec == PREC_NAIVE) block_scan_array<float, SNR_BLOCKS>(d.Dtf, d.Dcf, g.nt);
-    const uint32_t nxt = d.ctl->iter + 1;
-    const SnrPart p = d.b_part[threadIdx.x];
-    uint64_t nw = p.n_new, near = p.near, evals = p.evals, ux = 0, us = 0;
+    Ctl *c = d.ctl;
+    if (!c->tail_due || c->done || c->bad) return;
+    if (g.prec == PREC_NAIVE) block_scan_array<float, NT>(d.Dtf, d.Dcf, g.nt);
+    const uint32_t nxt = c->iter + 1;
+    uint64_t nw = 0, near = 0, evals = 0, ux = 0, us = 0;
     uint32_t nds = 0;
-    double minm = p.minm;
-    for (int tl = threadIdx.x; tl < g.nt; tl += SNR_BLOCKS) {
+    double minm = INFINITY;
+    for (int i = threadIdx.x; i < SNR_BLOCKS; i += NT) {
+        const SnrPart p = d.b_part[i];
+        nw += p.n_new;
+        near += p.near;
+        evals += p.evals;
+        minm = fmin(minm, p.minm);
+    }
+    for (int tl = threadIdx.x; tl < g.nt; tl += NT) {
         const uint64_t width = (uint64_t)min(g.tile, g.B - tl * g.tile);
         if (d.xstamp[tl] == nxt) ux += width;
         if (d.sstamp[tl] == nxt) {
@@ -1866,9 +1888,9 @@ __global__ __launch_bounds__(SNR_BLOCKS) void k_snr_tail(const Slot *S)
         s_nds[0] += s_nds[v];
         s_min[0] = fmin(s_min[0], s_min[v]);
     }
-    Ctl *c = d.ctl;
     const int t = (int)c->iter;
     const uint32_t n_new = (uint32_t)s_red[0][0];
+    c->tail_due = 0;
     c->med_split = s_nds[0] <= g.split_tiles;
     if (t < NEW_CAP) d.n_new[t] = n_new;
     c->n_resolved += n_new;
@@ -1889,6 +1911,15 @@ __global__ __launch_bounds__(SNR_BLOCKS) void k_snr_tail(const Slot *S)
         c->units_x += s_red[3][0];
         c->units_med += s_red[4][0];
     }
+}
+
+// The tail as a kernel of its own, ahead of k_xupdate: the naive FP32 mode
+// rescans the fp32 tile sums into the carries that k_xupdate reads.
+__global__ __launch_bounds__(SNR_BLOCKS) void k_snr_tail(const Slot *S)
+{
+    const Slot &sl = S[blockIdx.y];
+    if (!sl.active) return;
+    snr_tail<SNR_BLOCKS>(sl);
 }
 
 // ------------------------------------------------------------------ outputs
@@ -1947,7 +1978,7 @@ hipError_t go(const void *kernel, dim3 grid, dim3 block, hipStream_t st, hipEven
 
 hipError_t launch_xupdate(const Slot *ds, const Dims &dm, hipStream_t st, hipEvent_t ea, hipEvent_t eb)
 {
-    return go((const void *)k_xupdate, dim3(dm.maxnt, dm.ns), dim3(WG), st, ea, eb, ds);
+    return go((const void *)k_xupdate, dim3(dm.maxnt + 1, dm.ns), dim3(WG), st, ea, eb, ds);
 }
 
 hipError_t launch_median(const Slot *ds, const Dims &dm, hipStream_t st, hipEvent_t ea, hipEvent_t eb)
@@ -1963,6 +1994,8 @@ hipError_t launch_median(const Slot *ds, const Dims &dm, hipStream_t st, hipEven
 hipError_t launch_snr(const Slot *ds, const Dims &dm, hipStream_t st, hipEvent_t ea, hipEvent_t eb)
 {
     hipError_t e = go((const void *)k_part_scan, dim3(1, dm.ns), dim3(PWG), st, ea, nullptr, ds);
+    if (!dm.naive) return e == hipSuccess ? go((const void *)k_snr, dim3(SNR_BLOCKS, dm.ns), dim3(WG), st, nullptr, eb, ds)
+                                          : e;
     if (e == hipSuccess) e = go((const void *)k_snr, dim3(SNR_BLOCKS, dm.ns), dim3(WG), st, nullptr, nullptr, ds);
     if (e != hipSuccess) return e;
     return go((const void *)k_snr_tail, dim3(1, dm.ns), dim3(SNR_BLOCKS), st, nullptr, eb, ds);
