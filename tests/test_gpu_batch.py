@@ -115,6 +115,46 @@ def test_batched_equals_plain_mixed_grids(kind):
     batch.close()
 
 
+@pytest.mark.parametrize("kind", [None, "graph"])
+def test_batched_equals_plain_mixed_precision(kind):
+    """FP64, compensated FP32 and naive FP32 slots in one batch: the naive
+    slot brings the loop-body tail back as a kernel of its own for every
+    slot, which must not change any slot's result."""
+    jobs = mixed_jobs()
+    picks = [(0, G.FP64), (1, G.FP32_COMP), (4, G.FP32_NAIVE), (5, G.FP32_COMP)]
+    say(f"[batch precision {kind}] plain runs")
+    ref = []
+    for j, prec in picks:
+        cat, run = jobs[j]
+        ctx = G.Context(G.config_from_run(run, precision=prec))
+        try:
+            s = ctx.run(G.DeviceCatalog.from_host(cat))
+            ref.append((s, ) + results_of(ctx))
+        finally:
+            ctx.close()
+    batch = G.Batch(max_slots=len(picks))
+    ctxs = []
+    st_ = side_stream(kind)
+    for j, prec in picks:
+        cat, run = jobs[j]
+        ctx = G.Context(G.config_from_run(run, precision=prec))
+        dc = G.DeviceCatalog.from_host(cat)
+        ctx.ensure_workspace(dc.n)
+        batch.admit(ctx, dc, stream=st_)
+        ctxs.append((ctx, dc))
+    say(f"[batch precision {kind}] stepping")
+    state = drain(batch, stream=st_)
+    assert np.all(state[:len(picks)] == G.SLOT_SETTLED)
+    for k, ((ctx, _), (s_ref, S_ref, X_ref, r_ref)) in enumerate(zip(ctxs, ref)):
+        st, s = batch.retire(k, st_)
+        assert st == G.OK
+        assert (s.n_iter, s.n_resolved) == (s_ref.n_iter, s_ref.n_resolved)
+        assert_same(results_of(ctx), (S_ref, X_ref, r_ref))
+    for ctx, _ in ctxs:
+        ctx.close()
+    batch.close()
+
+
 def test_continuous_batching_alone_equals_mixed():
     jobs = mixed_jobs()
     ref = [plain(cat, run) for cat, run in jobs]
