@@ -119,7 +119,9 @@ def test_batched_equals_plain_mixed_grids(kind):
 def test_batched_equals_plain_mixed_precision(kind):
     """FP64, compensated FP32 and naive FP32 slots in one batch: the naive
     slot brings the loop-body tail back as a kernel of its own for every
-    slot, which must not change any slot's result."""
+    slot, which must not change the other slots' results.  The naive slot
+    itself sums with fp32 atomics in arbitrary order, so no two of its runs
+    need agree bit for bit: it must settle on the same candidate set."""
     jobs = mixed_jobs()
     picks = [(0, G.FP64), (1, G.FP32_COMP), (4, G.FP32_NAIVE), (5, G.FP32_COMP)]
     say(f"[batch precision {kind}] plain runs")
@@ -148,6 +150,9 @@ def test_batched_equals_plain_mixed_precision(kind):
     for k, ((ctx, _), (s_ref, S_ref, X_ref, r_ref)) in enumerate(zip(ctxs, ref)):
         st, s = batch.retire(k, st_)
         assert st == G.OK
+        assert s.n_candidates == s_ref.n_candidates
+        if picks[k][1] == G.FP32_NAIVE:
+            continue
         assert (s.n_iter, s.n_resolved) == (s_ref.n_iter, s_ref.n_resolved)
         assert_same(results_of(ctx), (S_ref, X_ref, r_ref))
     for ctx, _ in ctxs:
