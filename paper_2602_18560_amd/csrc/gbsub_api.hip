@@ -5,19 +5,22 @@
 // memory and enqueues the kernels of gbsub_kernels.hip.  Kernels read the
 // descriptor of slot blockIdx.y, so a single catalog (gbsub_run, a one-slot
 // table inside its workspace) and a batch of catalogs (gbsub_batch_*, a table
-// in a caller buffer) use the same launches.  Loop bodies are enqueued in
-// chunks without waiting; every kernel of a body exits at once after the
-// slot's device-side "settled" flag is set, and the host reads the control
-// blocks once per chunk.
+// in a caller buffer) use the same launches.  gbsub_run keeps a couple of
+// loop bodies queued ahead of the GPU, paced by progress words that the loop
+// writes to pinned host memory; a batch step enqueues its bodies at once and
+// the host reads the control blocks at each poll.  Every kernel of a body
+// exits at once after the slot's device-side "settled" flag is set.
 
 #include "gbsub_internal.h"
 #include "gbsub.h"
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <thread>
 #include <vector>
 
 using namespace gbs;
@@ -36,6 +39,8 @@ struct gbsub_ctx {
     void *tables_ws;
     Ctl *host_ctl;     // pinned
     Slot *host_slot;   // pinned staging of the one-slot table
+    uint32_t *host_prog;   // pinned, device-mapped: bodies finished and settled flag, written by the tail
+    uint32_t *dev_prog;    // the same words as the kernels address them
     int batch_slot;    // slot held in a batch, -1 if none
     // profiling: bit k of `profiling` selects kernel family k
     uint32_t profiling;
@@ -364,13 +369,19 @@ gbsub_status gbsub_create(const gbsub_config *cfg, gbsub_ctx **out)
     c->tables_ws = nullptr;
     c->host_ctl = nullptr;
     c->host_slot = nullptr;
+    c->host_prog = nullptr;
+    c->dev_prog = nullptr;
     c->batch_slot = -1;
     c->profiling = 0;
     c->ev_used = 0;
     c->clear_stats();
     if (hipHostMalloc((void **)&c->host_ctl, sizeof(Ctl), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void **)&c->host_slot, sizeof(Slot), hipHostMallocDefault) != hipSuccess) {
+        hipHostMalloc((void **)&c->host_slot, sizeof(Slot), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&c->host_prog, 64, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
+        hipHostGetDevicePointer((void **)&c->dev_prog, c->host_prog, 0) != hipSuccess) {
         if (c->host_ctl) (void)hipHostFree(c->host_ctl);
+        if (c->host_slot) (void)hipHostFree(c->host_slot);
+        if (c->host_prog) (void)hipHostFree(c->host_prog);
         delete c;
         return GBSUB_E_DEVICE;
     }
@@ -383,6 +394,7 @@ void gbsub_destroy(gbsub_ctx *c)
     if (!c) return;
     if (c->host_ctl) (void)hipHostFree(c->host_ctl);
     if (c->host_slot) (void)hipHostFree(c->host_slot);
+    if (c->host_prog) (void)hipHostFree(c->host_prog);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     delete c;
 }
@@ -408,7 +420,13 @@ gbsub_status gbsub_run(gbsub_ctx *c, const gbsub_catalog *cat, void *ws, uint64_
     const Grid &g = c->g;
     Slot *ds = reinterpret_cast<Slot *>(ws);    // one-slot table at the start of the workspace
     *c->host_slot = make_slot(g, d, cat);
+    c->host_slot->prog = c->dev_prog;
     const Dims dm = dims_of(*c->host_slot);
+    // every kernel of an earlier run has ended (each return below follows a
+    // synchronization once loop bodies are in flight)
+    volatile uint32_t *prog = c->host_prog;
+    prog[0] = 0;
+    prog[1] = 0;
 
     c->ev_used = 0;
     c->recs.clear();
@@ -425,39 +443,72 @@ gbsub_status gbsub_run(gbsub_ctx *c, const gbsub_catalog *cat, void *ws, uint64_
         c->tables_ws = nullptr;
         return GBSUB_E_DEVICE;
     }
-    // loop bodies in growing chunks; the device enforces max_iter.  A body
-    // is median, SNR, then the X update of the next body, whose last block
-    // takes this body's stop decision.
-    uint64_t t = 0, chunk = 4;
+    // Loop bodies, paced by the progress words the tail writes to host
+    // memory: the host keeps AHEAD bodies queued beyond the last finished
+    // one and stops enqueuing once a body settles the loop, so the GPU never
+    // waits for the host and at most AHEAD bodies run past the settled one
+    // (their kernels exit at once).  The device enforces max_iter.  A body is
+    // median, SNR, then the X update of the next body, whose last block
+    // takes this body's stop decision.  Whenever the stream runs dry without
+    // a settled flag in sight, the control block in device memory decides.
+    constexpr uint64_t AHEAD = 2;
     const uint64_t guard = (uint64_t)cat->n + 2 + (c->cfg.max_iter ? c->cfg.max_iter : 0);
-    for (;;) {
-        for (uint64_t i = 0; i < chunk && e == hipSuccess; ++i) {
-            const int64_t ti = (int64_t)(t + i);
-            e = c->timed_ext(K_MEDIAN, ti, [&](hipEvent_t a, hipEvent_t b) {
-                return launch_median(ds, dm, st, a, b);
+    auto fail = [&](gbsub_status s) {
+        (void)hipStreamSynchronize(st);
+        return s;
+    };
+    auto body = [&](int64_t ti) {
+        hipError_t r = c->timed_ext(K_MEDIAN, ti, [&](hipEvent_t a, hipEvent_t b) {
+            return launch_median(ds, dm, st, a, b);
+        });
+        if (r == hipSuccess)
+            r = c->timed_ext(K_SNR, ti, [&](hipEvent_t a, hipEvent_t b) { return launch_snr(ds, dm, st, a, b); });
+        if (r == hipSuccess)
+            r = c->timed_ext(K_XUPDATE, ti, [&](hipEvent_t a, hipEvent_t b) {
+                return launch_xupdate(ds, dm, st, a, b);
             });
-            if (e == hipSuccess)
-                e = c->timed_ext(K_SNR, ti, [&](hipEvent_t a, hipEvent_t b) {
-                    return launch_snr(ds, dm, st, a, b);
-                });
-            if (e == hipSuccess)
-                e = c->timed_ext(K_XUPDATE, ti, [&](hipEvent_t a, hipEvent_t b) {
-                    return launch_xupdate(ds, dm, st, a, b);
-                });
+        return r;
+    };
+    uint64_t t = 0;                  // bodies enqueued
+    uint32_t seen_prev = 0;
+    auto quiet_since = std::chrono::steady_clock::now();
+    for (;;) {
+        if (prog[1]) break;
+        const uint32_t seen = prog[0];
+        if (t < (uint64_t)seen + AHEAD) {
+            if (t > guard) return fail(GBSUB_E_DEVICE);   // the loop must settle within n + 1 bodies
+            if (body((int64_t)t) != hipSuccess) return fail(GBSUB_E_DEVICE);
+            ++t;
+            continue;
         }
-        t += chunk;
-        if (e == hipSuccess) e = hipMemcpyAsync(c->host_ctl, d.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st);
+        const auto now = std::chrono::steady_clock::now();
+        if (seen != seen_prev) {
+            seen_prev = seen;
+            quiet_since = now;
+            continue;
+        }
+        if (now - quiet_since < std::chrono::microseconds(200)) {
+            std::this_thread::yield();
+            continue;
+        }
+        quiet_since = now;
+        const hipError_t q = hipStreamQuery(st);
+        if (q == hipErrorNotReady) continue;
+        if (q != hipSuccess) return fail(GBSUB_E_DEVICE);
+        // nothing in flight: read the control block itself
+        e = hipMemcpyAsync(c->host_ctl, d.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
-        if (e != hipSuccess) return GBSUB_E_DEVICE;
+        if (e != hipSuccess) return fail(GBSUB_E_DEVICE);
         if (c->host_ctl->bad) return GBSUB_E_INVALID;
         if (c->host_ctl->done) break;
-        if (t > guard) return GBSUB_E_DEVICE;   // the device loop must settle within n + 1 bodies
-        chunk = std::min<uint64_t>(chunk * 2, 32);
+        if (t > guard) return GBSUB_E_DEVICE;
+        if (body((int64_t)t) != hipSuccess) return fail(GBSUB_E_DEVICE);
+        ++t;
     }
     e = c->timed(K_OUTPUT, -1, st, [&] { return launch_outputs(ds, dm, st); });
     if (e == hipSuccess) e = hipMemcpyAsync(c->host_ctl, d.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e != hipSuccess) return GBSUB_E_DEVICE;
+    if (e != hipSuccess) return fail(GBSUB_E_DEVICE);
 
     const Ctl &h = *c->host_ctl;
     const gbsub_status status = h.status == 6 ? GBSUB_E_MAXITER : GBSUB_OK;

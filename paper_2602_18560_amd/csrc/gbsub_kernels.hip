@@ -1899,17 +1899,23 @@ template <int NT> DEVI void snr_tail(const Slot &sl)
     if (s_min[0] < __longlong_as_double((long long)c->min_margin))
         c->min_margin = (uint64_t)__double_as_longlong(s_min[0]);
     const uint32_t mi = g.max_iter ? g.max_iter : c->n_cand + 1;
+    uint32_t done = 0;
     if (n_new == 0) {
-        c->done = 1;
+        done = 1;
         c->n_iter = (uint32_t)t + 1;
     } else if ((uint32_t)t + 1 >= mi) {
-        c->done = 1;                 // the loop did not settle within max_iter bodies
+        done = 1;                    // the loop did not settle within max_iter bodies
         c->status = 6;
         c->n_iter = (uint32_t)t + 1;
     } else {
         c->iter = (uint32_t)t + 1;
         c->units_x += s_red[3][0];
         c->units_med += s_red[4][0];
+    }
+    c->done = done;
+    if (sl.prog) {                   // progress for the host that paces the launches
+        __hip_atomic_store(&sl.prog[0], (uint32_t)t + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&sl.prog[1], done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     }
 }
 
