@@ -135,7 +135,10 @@ gbsub_status gbsub_workspace_size(const gbsub_ctx *ctx, uint64_t n_sources, uint
  * device pointers).  `workspace` is a DEVICE pointer to at least
  * gbsub_workspace_size() bytes, 256-byte aligned, owned by the caller and
  * holding the results until the next run or destroy.  All work is enqueued
- * on `stream`; the call returns after it has completed.  *out (host
+ * on `stream`; the call returns after it has completed.  While it runs, the
+ * calling thread keeps a couple of loop bodies queued ahead of the GPU,
+ * polling (and yielding) on progress words that the loop writes to the
+ * context's pinned host memory.  *out (host
  * pointer, may be NULL) receives the summary.  INVALID for a bad catalog
  * entry or too small a workspace, MAXITER if the loop did not settle within
  * max_iter bodies, DEVICE on a HIP error. */
