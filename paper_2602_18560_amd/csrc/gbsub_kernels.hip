@@ -954,9 +954,15 @@ DEVI int xpad(int i) { return i + (i >> 3); }
 
 template <int NT> DEVI void snr_tail(const Slot &sl);
 
-// The last block of the grid is the tail of the previous k_snr (its
-// decisions touch neither the stamps nor the accumulators these blocks
-// read; a stop it takes leaves no tile stamped for conversion).
+// The last block of the grid is the tail of the previous k_snr; the other
+// blocks convert the tiles stamped with the value k_snr published.  The two
+// share no data: the tail writes only the control block (not the fields
+// read here) and the partials' consumers, and the converting blocks read
+// neither the settled flag nor anything else the tail writes.  Past the
+// settled body no k_snr runs and the accumulators stay as they are: a body
+// that settles the loop subtracted nothing and stamped nothing, and after a
+// max_iter stop the tiles of the last stamp are only converted again to the
+// same values.
 __global__ __launch_bounds__(WG) void k_xupdate(const Slot *S)
 {
     __shared__ I128 sh[WG / 64];
@@ -970,7 +976,7 @@ __global__ __launch_bounds__(WG) void k_xupdate(const Slot *S)
     }
     const Grid g = sl.g;
     const Dev d = sl.d;
-    if (d.ctl->done || d.ctl->bad) return;
+    if (d.ctl->bad) return;
     const int tile = blockIdx.x;
     if (tile >= g.nt || d.xstamp[tile] != d.ctl->xupd) return;
     const int L = fx_exp(d.ctl->amax_bits, g.T);
