@@ -955,10 +955,11 @@ DEVI int xpad(int i) { return i + (i >> 3); }
 template <int NT> DEVI void snr_tail(const Slot &sl);
 
 // The last block of the grid is the tail of the previous k_snr; the other
-// blocks convert the tiles stamped with the value k_snr published.  The two
-// share no data: the tail writes only the control block (not the fields
-// read here) and the partials' consumers, and the converting blocks read
-// neither the settled flag nor anything else the tail writes.  Past the
+// blocks convert the tiles stamped with the value k_snr published.  They
+// touch disjoint data: the tail reads the partials and the stamps and
+// writes the control block's counters and flags, while the converting
+// blocks read the accumulators, the stamps and the control fields set
+// before this launch (bad, xupd, amax_bits), never the settled flag.  Past the
 // settled body no k_snr runs and the accumulators stay as they are: a body
 // that settles the loop subtracted nothing and stamped nothing, and after a
 // max_iter stop the tiles of the last stamp are only converted again to the
