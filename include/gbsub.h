@@ -137,7 +137,7 @@ gbsub_status gbsub_workspace_size(const gbsub_ctx *ctx, uint64_t n_sources, uint
  * holding the results until the next run or destroy.  All work is enqueued
  * on `stream`; the call returns after it has completed.  While it runs, the
  * calling thread keeps a couple of loop bodies queued ahead of the GPU,
- * polling (and yielding) on progress words that the loop writes to the
+ * polling (and yielding) on a progress word that the loop writes to the
  * context's pinned host memory.  *out (host
  * pointer, may be NULL) receives the summary.  INVALID for a bad catalog
  * entry or too small a workspace, MAXITER if the loop did not settle within

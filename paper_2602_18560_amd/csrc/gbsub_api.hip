@@ -6,7 +6,7 @@
 // descriptor of slot blockIdx.y, so a single catalog (gbsub_run, a one-slot
 // table inside its workspace) and a batch of catalogs (gbsub_batch_*, a table
 // in a caller buffer) use the same launches.  gbsub_run keeps a couple of
-// loop bodies queued ahead of the GPU, paced by progress words that the loop
+// loop bodies queued ahead of the GPU, paced by a progress word that the loop
 // writes to pinned host memory; a batch step enqueues its bodies at once and
 // the host reads the control blocks at each poll.  Every kernel of a body
 // exits at once after the slot's device-side "settled" flag is set.
@@ -39,8 +39,8 @@ struct gbsub_ctx {
     void *tables_ws;
     Ctl *host_ctl;     // pinned
     Slot *host_slot;   // pinned staging of the one-slot table
-    uint32_t *host_prog;   // pinned, device-mapped: bodies finished and settled flag, written by the tail
-    uint32_t *dev_prog;    // the same words as the kernels address them
+    uint32_t *host_prog;   // pinned, device-mapped: bodies finished << 1 | settled, written by the tail
+    uint32_t *dev_prog;    // the same word as the kernels address it
     int batch_slot;    // slot held in a batch, -1 if none
     // profiling: bit k of `profiling` selects kernel family k
     uint32_t profiling;
@@ -425,8 +425,7 @@ gbsub_status gbsub_run(gbsub_ctx *c, const gbsub_catalog *cat, void *ws, uint64_
     // every kernel of an earlier run has ended (each return below follows a
     // synchronization once loop bodies are in flight)
     volatile uint32_t *prog = c->host_prog;
-    prog[0] = 0;
-    prog[1] = 0;
+    *prog = 0;
 
     c->ev_used = 0;
     c->recs.clear();
@@ -443,7 +442,7 @@ gbsub_status gbsub_run(gbsub_ctx *c, const gbsub_catalog *cat, void *ws, uint64_
         c->tables_ws = nullptr;
         return GBSUB_E_DEVICE;
     }
-    // Loop bodies, paced by the progress words the tail writes to host
+    // Loop bodies, paced by the progress word the tail writes to host
     // memory: the host keeps AHEAD bodies queued beyond the last finished
     // one and stops enqueuing once a body settles the loop, so the GPU never
     // waits for the host and at most AHEAD bodies run past the settled one
@@ -473,8 +472,9 @@ gbsub_status gbsub_run(gbsub_ctx *c, const gbsub_catalog *cat, void *ws, uint64_
     uint32_t seen_prev = 0;
     auto quiet_since = std::chrono::steady_clock::now();
     for (;;) {
-        if (prog[1]) break;
-        const uint32_t seen = prog[0];
+        const uint32_t w = *prog;
+        if (w & 1u) break;
+        const uint32_t seen = w >> 1;
         if (t < (uint64_t)seen + AHEAD) {
             if (t > guard) return fail(GBSUB_E_DEVICE);   // the loop must settle within n + 1 bodies
             if (body((int64_t)t) != hipSuccess) return fail(GBSUB_E_DEVICE);

@@ -172,7 +172,7 @@ struct Slot {
     uint64_t n;
     uint32_t active;
     uint32_t pad;
-    uint32_t *prog;          // host-mapped words of a single run: bodies finished, settled (null in batches)
+    uint32_t *prog;          // host-mapped word of a single run: bodies finished << 1 | settled (null in batches)
 };
 
 // Launch extents: the largest per-slot block counts of a set of slots.

@@ -1920,10 +1920,10 @@ template <int NT> DEVI void snr_tail(const Slot &sl)
         c->units_med += s_red[4][0];
     }
     c->done = done;
-    if (sl.prog) {                   // progress for the host that paces the launches
-        __hip_atomic_store(&sl.prog[0], (uint32_t)t + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-        __hip_atomic_store(&sl.prog[1], done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-    }
+    // progress for the host that paces the launches: bodies finished and the
+    // settled flag in one word, so that the host never sees one without the other
+    if (sl.prog)
+        __hip_atomic_store(sl.prog, ((uint32_t)t + 1) << 1 | done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // The tail as a kernel of its own, ahead of k_xupdate: the naive FP32 mode
