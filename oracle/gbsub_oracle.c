@@ -287,6 +287,62 @@ int orc_coarse(const double *S, int64_t k0, int64_t n_bins, double T, double f_l
     return ORC_OK;
 }
 
+/* ---------------------------------------------------------------- X^t and S^t
+ * The data "h_AET minus subtracted templates" in the power model: the
+ * per-bin power of every source not yet subtracted, summed in ascending
+ * source index (appendix "Subtraction algorithm", the subtraction step). */
+static void bin_unsubtracted(int64_t n, const int32_t *iter_of, const int64_t *glo, const int64_t *ghi,
+                             const double *q, int64_t B, double *X)
+{
+    for (int64_t k = 0; k < B; ++k) X[k] = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (iter_of[i] >= 0) continue;
+        for (int64_t k = glo[i]; k <= ghi[i]; ++k) X[k] += q[i];
+    }
+}
+
+/* The PSD estimate of the data X (Eqs. "running median" and "running
+ * mean"); med is scratch of B entries. */
+static void estimate_psd(const orc_config *c, const double *X, const double *Sx, int64_t B, double *med,
+                         double *S)
+{
+    if (c->estimator == ORC_MEAN) {
+        orc_running_mean_psd(X, Sx, B, c->window_bins, S);
+    } else {
+        orc_running_median(X, B, c->window_bins, med);
+        for (int64_t k = 0; k < B; ++k) S[k] = c->median_scale * med[k] + Sx[k];
+    }
+}
+
+int orc_spectra_after(const orc_config *c, int64_t n, const float *A, const float *f, const float *fdot,
+                      const uint8_t *subtracted, double *X, double *S)
+{
+    int64_t k0, B;
+    if (n < 0 || !(c->window_bins >= 1) || (c->window_bins % 2) == 0) return ORC_E_INVALID;
+    if (orc_grid(c->t_obs_s, c->f_min_hz, c->f_max_hz, &k0, &B) != ORC_OK) return ORC_E_INVALID;
+    const size_t nn = (size_t)(n > 0 ? n : 1);
+    int64_t *glo = (int64_t *)malloc(sizeof(int64_t) * nn);
+    int64_t *ghi = (int64_t *)malloc(sizeof(int64_t) * nn);
+    double *q = (double *)malloc(sizeof(double) * nn);
+    int32_t *iter_of = (int32_t *)malloc(sizeof(int32_t) * nn);
+    double *Sx = (double *)malloc(sizeof(double) * (size_t)B);
+    double *med = (double *)malloc(sizeof(double) * (size_t)B);
+    int rc = ORC_OK;
+    for (int64_t i = 0; i < n && rc == ORC_OK; ++i) {
+        int64_t lo, nb;
+        if (orc_track(c, k0, B, A[i], f[i], fdot[i], &lo, &nb, &q[i], &glo[i], &ghi[i]) != ORC_OK)
+            rc = ORC_E_INVALID;
+        iter_of[i] = subtracted[i] ? 0 : -1;
+    }
+    if (rc == ORC_OK) {
+        orc_sinstr_table(c, k0, B, Sx);
+        bin_unsubtracted(n, iter_of, glo, ghi, q, B, X);
+        estimate_psd(c, X, Sx, B, med, S);
+    }
+    free(glo); free(ghi); free(q); free(iter_of); free(Sx); free(med);
+    return rc;
+}
+
 /* ---------------------------------------------------------------- the loop
  * Appendix "Subtraction algorithm":
  *   2. SNR of every source against S_instr;
@@ -358,19 +414,9 @@ int orc_run(const orc_config *c, int64_t n, const float *A, const float *f, cons
     sum->min_rel_margin = INFINITY;
 
     for (int64_t t = 0;; ++t) {
-        /* X^t: every source not yet subtracted, ascending source index. */
-        for (int64_t k = 0; k < B; ++k) X[k] = 0.0;
-        for (int64_t i = 0; i < n; ++i) {
-            if (iter_of[i] >= 0) continue;
-            for (int64_t k = glo[i]; k <= ghi[i]; ++k) X[k] += q[i];
-        }
-        /* S^t */
-        if (c->estimator == ORC_MEAN) {
-            orc_running_mean_psd(X, Sx, B, c->window_bins, S);
-        } else {
-            orc_running_median(X, B, c->window_bins, med);
-            for (int64_t k = 0; k < B; ++k) S[k] = c->median_scale * med[k] + Sx[k];
-        }
+        /* X^t: every source not yet subtracted; S^t */
+        bin_unsubtracted(n, iter_of, glo, ghi, q, B, X);
+        estimate_psd(c, X, Sx, B, med, S);
         /* rho^2 of every unsubtracted candidate against S^t */
 #pragma omp parallel for schedule(static)
         for (int64_t j = 0; j < nc; ++j) {

@@ -116,6 +116,14 @@ void    orc_running_mean_psd(const double *X, const double *Sx, int64_t n_bins, 
 int     orc_coarse(const double *S, int64_t k0, int64_t n_bins, double T, double f_lo, double f_hi,
                    int64_t n_out, double *f_out, double *s_out, int64_t *count);
 
+/* X^t and S^t of the loop once exactly the sources with subtracted[i] != 0
+ * have been subtracted: the binned power of all others (ascending source
+ * index) and the PSD estimate over it, the same operations as a loop body.
+ * With the final resolved set this is the run's X_final and S_final.
+ * X and S have n_bins entries.  Returns ORC_OK or ORC_E_INVALID. */
+int     orc_spectra_after(const orc_config *c, int64_t n, const float *A, const float *f, const float *fdot,
+                          const uint8_t *subtracted, double *X, double *S);
+
 /* The whole subtraction.  Returns ORC_OK, ORC_E_INVALID or ORC_E_MAXITER. */
 int     orc_run(const orc_config *c, int64_t n, const float *A, const float *f, const float *fdot,
                 orc_io *io, orc_summary *sum);

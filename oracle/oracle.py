@@ -105,6 +105,9 @@ def lib():
         L.orc_run.argtypes = [C.POINTER(Config), C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
                               C.POINTER(IO), C.POINTER(Summary)]
         L.orc_run.restype = C.c_int
+        L.orc_spectra_after.argtypes = [C.POINTER(Config), C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
+                                        C.c_void_p, C.c_void_p, C.c_void_p]
+        L.orc_spectra_after.restype = C.c_int
         _lib = L
     return _lib
 
@@ -202,6 +205,25 @@ def running_mean_psd(X: np.ndarray, Sx: np.ndarray, W: int) -> np.ndarray:
     lib().orc_running_mean_psd(X.ctypes.data, Sx.ctypes.data, X.shape[0], int(W),
                                out.ctypes.data)
     return out
+
+
+def spectra_after(catalog, cfg: Config, subtracted) -> tuple[np.ndarray, np.ndarray]:
+    """(X, S) of a loop body once exactly the sources flagged in
+    ``subtracted`` (bool [n]) are subtracted; with the final resolved set
+    these are the run's X_final and S_final."""
+    A = np.ascontiguousarray(catalog.A, np.float32)
+    f = np.ascontiguousarray(catalog.f, np.float32)
+    fd = np.ascontiguousarray(catalog.fdot, np.float32)
+    m = np.ascontiguousarray(np.asarray(subtracted, bool).astype(np.uint8))
+    assert m.shape == A.shape
+    k0, B = grid(cfg.t_obs_s, cfg.f_min_hz, cfg.f_max_hz)
+    X = np.empty(B, np.float64)
+    S = np.empty(B, np.float64)
+    rc = lib().orc_spectra_after(C.byref(cfg), A.shape[0], A.ctypes.data, f.ctypes.data, fd.ctypes.data,
+                                 m.ctypes.data, X.ctypes.data, S.ctypes.data)
+    if rc != OK:
+        raise ValueError("invalid catalog or configuration")
+    return X, S
 
 
 @dataclass

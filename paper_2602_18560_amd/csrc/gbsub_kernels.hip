@@ -1726,6 +1726,18 @@ DEVI void stamp_tiles(uint32_t *stamp, const Grid &g, int lo, int hi, uint32_t n
     for (int tl = div_p2(lo, g.tile); tl <= div_p2(hi, g.tile); ++tl) stamp[tl] = nxt;
 }
 
+// Outputs whose window holds a bin of [lo, hi] (Eq. "running median" with the
+// window shifted inward at the grid edges): [lo - h, hi + h] in the interior;
+// every output of the lower edge (window [0, W-1]) once lo <= W-1, every
+// output of the upper edge (window [B-W, B-1]) once hi >= B-W, and the whole
+// grid when it is shorter than the window.
+DEVI void window_reach(const Grid &g, int lo, int hi, int *a, int *b)
+{
+    const bool whole = g.B < g.W;
+    *a = (whole || lo <= g.W - 1) ? 0 : lo - g.h;
+    *b = (whole || hi >= g.B - g.W) ? g.B - 1 : hi + g.h;
+}
+
 // True when S^t may differ from S^{t-1} somewhere on tiles lo/tile ..
 // hi/tile: one of them was refiltered in body t (stamp t), or was stamped
 // for body t + 1 by a writer of this same launch, which may have replaced a
@@ -1749,7 +1761,7 @@ DEVI bool track_refiltered(const uint32_t *stamp, const Grid &g, int lo, int hi,
 // rho_th^2 subtracts the source from the binned power at once (appendix
 // "Subtraction algorithm", steps 6-9: the data X^{t+1} no longer holds it)
 // and stamps the tiles the next body must convert (the track) and filter
-// (the track widened by half a window).  A candidate whose track lies in
+// (every output whose window holds a bin of the track, window_reach).  A candidate whose track lies in
 // tiles the median left alone this body sees the same S as at its last
 // evaluation, so its stored rho^2 stands (it was not above threshold then,
 // or it would have been subtracted); body 0 filters every tile.  Per-block
@@ -1798,7 +1810,9 @@ __global__ __launch_bounds__(WG) void k_snr(const Slot *S)
                                                                    f32_scale(d.ctl->amax_bits, g.T)));
             }
             stamp_tiles(d.xstamp, g, glo, ghi, nxt);
-            stamp_tiles(d.sstamp, g, max(glo - g.h, 0), min(ghi + g.h, g.B - 1), nxt);
+            int sa, sb;
+            window_reach(g, glo, ghi, &sa, &sb);
+            stamp_tiles(d.sstamp, g, sa, sb, nxt);
         }
     }
     for (int s = 32; s >= 1; s >>= 1) {

@@ -6,9 +6,11 @@ import sys
 import numpy as np
 import pytest
 
+from oracle import oracle as O
 from paper_2602_18560_amd import gbsub as G
 from paper_2602_18560_amd import serve as SV
 from paper_2602_18560_amd.inputs import Population, RunConfig, YEAR_S, WINDOW_FOR_YEARS, draw_catalog
+from tests import oracle_bar as OB
 
 pytestmark = pytest.mark.gpu
 
@@ -56,6 +58,37 @@ def test_server_results_equal_alone(slots, budget_mb):
         np.testing.assert_array_equal(ids, ids_ref)
         np.testing.assert_array_equal(it, it_ref)
         assert c.done_s >= c.admit_s >= c.arrival_s - 1e-9
+        # the served result against the oracle
+        cat, run = js[c.index]
+        OB.check(cat, O.make_config(run), c.summary, c.context.spectrum(G.SPEC_SN),
+                 c.context.spectrum(G.SPEC_X_RESIDUAL), ids, it)
+        c.context.close()
+    srv.close()
+
+
+def test_served_jobs_on_the_job_stream_grids_match_the_oracle():
+    """Jobs on the [0.1, 10] mHz grids of the model job stream at 1, 2 and 4
+    yr (W = 251 / 501 / 1001; the 2- and 4-yr grids end in tiles of 201 and
+    402 bins, at most h), catalogs of 2e4 .. 2e5 sources drawn on the host,
+    served two at a time: every result meets the oracle bar."""
+    js = []
+    for j, (n, years, seed, scale) in enumerate([(20000, 1, 51, 20), (200000, 2, 52, 3), (60000, 4, 53, 8),
+                                                 (120000, 4, 54, 4), (40000, 2, 55, 12)]):
+        cat = draw_catalog(Population(n=n, seed=seed, f_lo=1e-4, f_hi=1e-2))
+        cat.A *= np.float32(scale)
+        js.append((cat, RunConfig(t_obs_s=years * YEAR_S, f_min_hz=1e-4, f_max_hz=1e-2,
+                                  window_bins=WINDOW_FOR_YEARS[years])))
+    reqs = [SV.Request(j, 0.001 * j, *SV.pin_catalog(c), run=r) for j, (c, r) in enumerate(js)]
+    say(f"[serve] {len(reqs)} jobs on the job-stream grids, 2 slots")
+    done, srv = SV.serve(reqs, max_slots=2, budget_bytes=1e12, chunk=2, keep_contexts=True)
+    assert sorted(c.index for c in done) == list(range(len(js)))
+    for c in done:
+        assert c.status == G.OK
+        cat, run = js[c.index]
+        ids, it = c.context.resolved()
+        say(f"  job {c.index}: n={cat.n} bins={c.summary.n_bins} bodies={c.summary.n_iter}")
+        OB.check(cat, O.make_config(run), c.summary, c.context.spectrum(G.SPEC_SN),
+                 c.context.spectrum(G.SPEC_X_RESIDUAL), ids, it)
         c.context.close()
     srv.close()
 
