@@ -25,8 +25,9 @@
  *    usable.
  *  - "Device pointer" means memory on the GPU the context was created on
  *    (e.g. a torch CUDA tensor's data_ptr()); "host pointer" means ordinary
- *    host memory.  The library never allocates device memory: every device
- *    buffer (catalog, workspace, device-side outputs) belongs to the caller.
+ *    host memory.  The library allocates no device memory at run time: every
+ *    device buffer (catalog, workspace, device-side outputs) belongs to the
+ *    caller, except the fixed array behind gbsub_run_static.
  *  - ``stream`` is a hipStream_t passed as void* (NULL = the null stream).
  */
 #ifndef GBSUB_H
@@ -144,6 +145,26 @@ gbsub_status gbsub_workspace_size(const gbsub_ctx *ctx, uint64_t n_sources, uint
  * max_iter bodies, DEVICE on a HIP error. */
 gbsub_status gbsub_run(gbsub_ctx *ctx, const gbsub_catalog *cat, void *workspace,
                        uint64_t ws_bytes, void *stream, gbsub_summary *out);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * run as gbsub_run, with the workspace taken from an array of
+ * GBSUB_STATIC_WORKSPACE_BYTES bytes that the library holds on each GPU it
+ * runs on (from the first gbsub_create on that GPU until the process ends).
+ * The call allocates nothing; the caller still passes the catalog (device
+ * arrays, as for gbsub_run) and reads results with gbsub_spectrum /
+ * gbsub_resolved / gbsub_candidates / gbsub_coarse as after gbsub_run.
+ * Every context on one GPU shares that GPU's array: a context's results stay
+ * valid only until the next gbsub_run_static call on the same GPU (by any
+ * context), and calls that overlap in time on one GPU (several host threads
+ * or streams) race and must be serialised by the caller.  The grid tables
+ * are recomputed on every call.  Profiling is not applied to these runs.
+ * Errors: NOMEM if gbsub_workspace_size(ctx, cat->n) exceeds
+ * GBSUB_STATIC_WORKSPACE_BYTES (e.g. the 1-yr [0.3, 10] mHz grid fits up to
+ * ~5e5 sources, the 4-yr [0.1, 30] mHz grid does not fit); STATE while the
+ * context holds a batch slot; otherwise as gbsub_run. */
+#define GBSUB_STATIC_WORKSPACE_BYTES (64u << 20)
+gbsub_status gbsub_run_static(gbsub_ctx *ctx, const gbsub_catalog *cat, void *stream, gbsub_summary *out);
 
 /* Copies spectrum `kind` (GBSUB_SPEC_*) of the last successful run, B fp64
  * values in grid order, to `out` (host pointer if out_on_device == 0, device

@@ -19,6 +19,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <thread>
 #include <vector>
@@ -314,6 +315,36 @@ gbsub_summary summary_of(const Grid &g, const Ctl &h)
 
 }  // namespace
 
+// Workspace of gbsub_run_static, for callers that cannot allocate device
+// memory: one array per GPU the library runs on, held until the process
+// ends.  Host code never passes `scratch` itself (in host code the name is
+// a host-side stand-in, not a device address); it uses the address that
+// hipGetSymbolAddress returns on each device, cached by static_scratch().
+static __device__ __align__(256) unsigned char scratch[GBSUB_STATIC_WORKSPACE_BYTES];
+
+namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[MAX_DEVICES];
+
+// Device address of `scratch` on device `dev`, which must be current.  The
+// lookup runs once per device (at the first gbsub_create on it).
+gbsub_status static_scratch(int dev, void **out)
+{
+    if (dev < 0 || dev >= MAX_DEVICES) return GBSUB_E_DEVICE;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return GBSUB_E_DEVICE;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return GBSUB_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 void gbsub_default_config(gbsub_config *c)
@@ -383,6 +414,11 @@ gbsub_status gbsub_create(const gbsub_config *cfg, gbsub_ctx **out)
         if (c->host_slot) (void)hipHostFree(c->host_slot);
         if (c->host_prog) (void)hipHostFree(c->host_prog);
         delete c;
+        return GBSUB_E_DEVICE;
+    }
+    void *scr = nullptr;
+    if (static_scratch(dev, &scr) != GBSUB_OK) {
+        gbsub_destroy(c);
         return GBSUB_E_DEVICE;
     }
     *out = c;
@@ -539,6 +575,31 @@ gbsub_status gbsub_run(gbsub_ctx *c, const gbsub_catalog *cat, void *ws, uint64_
     c->n_cand = h.n_cand;
     c->have_result = true;
     return GBSUB_OK;
+}
+
+gbsub_status gbsub_run_static(gbsub_ctx *c, const gbsub_catalog *cat, void *stream, gbsub_summary *out)
+{
+    if (!c || !cat) return GBSUB_E_INVALID;
+    if (c->batch_slot >= 0) return GBSUB_E_STATE;
+    uint64_t need = 0;
+    if (cat->n >= (1ull << 31)) return GBSUB_E_INVALID;
+    need = carve(c->g, cat->n, nullptr, nullptr);
+    if (need > (uint64_t)GBSUB_STATIC_WORKSPACE_BYTES) return GBSUB_E_NOMEM;
+    if (use_device(c->device) != GBSUB_OK) return GBSUB_E_DEVICE;
+    void *ws = nullptr;
+    if (static_scratch(c->device, &ws) != GBSUB_OK) return GBSUB_E_DEVICE;
+    // Another context may have used the array since: the grid tables are
+    // always recomputed, and every other buffer is rewritten by the run
+    // (k_reset and prep start from arbitrary contents, as in a fresh
+    // caller workspace).  No timing: the profiling mode creates events and
+    // grows host-side records.
+    const uint32_t prof = c->profiling;
+    c->profiling = 0;
+    c->tables_ws = nullptr;
+    const gbsub_status st = gbsub_run(c, cat, ws, (uint64_t)GBSUB_STATIC_WORKSPACE_BYTES, stream, out);
+    c->tables_ws = nullptr;
+    c->profiling = prof;
+    return st;
 }
 
 gbsub_status gbsub_spectrum(const gbsub_ctx *c, uint32_t kind, double *out, uint64_t cap,

@@ -27,7 +27,8 @@ EXPORTS = ["gbsub_default_config", "gbsub_create", "gbsub_workspace_size", "gbsu
            "gbsub_status_str",
            "gbsub_set_profiling", "gbsub_kernel_stats", "gbsub_batch_table_size",
            "gbsub_batch_create", "gbsub_batch_admit", "gbsub_batch_step", "gbsub_batch_poll",
-           "gbsub_batch_retire", "gbsub_batch_destroy", "gbsub_generate"]
+           "gbsub_batch_retire", "gbsub_batch_destroy", "gbsub_generate", "gbsub_run_static"]
+STATIC_WORKSPACE_BYTES = 64 << 20   # GBSUB_STATIC_WORKSPACE_BYTES
 SLOT_RUNNING, SLOT_SETTLED, SLOT_MAXITER, SLOT_INVALID, SLOT_FREE = 0, 1, 2, 3, 255
 (KF_TABLES, KF_RESET, KF_PREP, KF_XUPDATE, KF_MEDIAN, KF_SNR, KF_OUTPUT) = range(7)
 PROFILE_ALL = 0x7F
@@ -97,6 +98,8 @@ def load(path: str | None = None):
     L.gbsub_workspace_size.argtypes = [C.c_void_p, C.c_uint64, C.POINTER(C.c_uint64)]
     L.gbsub_run.argtypes = [C.c_void_p, C.POINTER(CatalogStruct), C.c_void_p, C.c_uint64,
                             C.c_void_p, C.POINTER(SummaryStruct)]
+    L.gbsub_run_static.argtypes = [C.c_void_p, C.POINTER(CatalogStruct), C.c_void_p,
+                                   C.POINTER(SummaryStruct)]
     L.gbsub_spectrum.argtypes = [C.c_void_p, C.c_uint32, C.c_void_p, C.c_uint64,
                                  C.POINTER(C.c_uint64), C.c_int]
     L.gbsub_resolved.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64,
@@ -123,7 +126,7 @@ def load(path: str | None = None):
     L.gbsub_batch_destroy.restype = None
     L.gbsub_generate.argtypes = [C.POINTER(PopulationStruct), C.c_uint64, C.c_uint64, C.c_uint64,
                                  C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
-    for name in ("gbsub_create", "gbsub_workspace_size", "gbsub_run", "gbsub_spectrum",
+    for name in ("gbsub_create", "gbsub_workspace_size", "gbsub_run", "gbsub_run_static", "gbsub_spectrum",
                  "gbsub_resolved", "gbsub_candidates", "gbsub_coarse", "gbsub_set_profiling",
                  "gbsub_kernel_stats",
                  "gbsub_batch_table_size", "gbsub_batch_create", "gbsub_batch_admit",
@@ -254,6 +257,22 @@ class Context:
         st, s = self.run_raw(cat, ws, stream)
         if st != OK:
             raise GbsubError(st, "gbsub_run")
+        return s
+
+    def run_static_raw(self, cat: DeviceCatalog, stream=None) -> tuple[int, Summary]:
+        """gbsub_run_static: the run in the library's fixed per-GPU array
+        (no workspace; results valid until the next such run on this GPU)."""
+        torch = _torch()
+        s = SummaryStruct()
+        sp = (stream or torch.cuda.current_stream()).cuda_stream
+        cs = cat.struct()
+        st = self._L.gbsub_run_static(self.h, C.byref(cs), C.c_void_p(sp), C.byref(s))
+        return st, _summary(s)
+
+    def run_static(self, cat: DeviceCatalog, stream=None) -> Summary:
+        st, s = self.run_static_raw(cat, stream)
+        if st != OK:
+            raise GbsubError(st, "gbsub_run_static")
         return s
 
     def spectrum(self, kind: int = SPEC_SN, out=None) -> np.ndarray:
