@@ -41,7 +41,7 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 # Algorithmic bytes per work unit of each kernel family (what the method must
 # move, not what the implementation happens to move).
 ALGO_BYTES = {
-    "median": 32.0,    # per output bin: read X, S_instr; write S, in-tile prefix of 1/S
+    "median": 24.0,    # per output bin: read X and S_instr, write S
     "xupdate": 24.0,   # per bin: read the 128-bit difference entry, write X
     "prep": 28.0,      # per source: read A, f, fdot; two 8-byte accumulator updates
     "snr": 36.0,       # per candidate evaluation: track, q, state, one S gather, write rho^2
@@ -464,8 +464,10 @@ def main():
     ap.add_argument("--estimator", choices=["median", "mean"], default="median",
                     help="1e7 workload: running median (default) or running mean")
     ap.add_argument("--window", type=int, default=0, help="1e7 workload: window bins (default 1001)")
-    ap.add_argument("--no-tune", action="store_true",
-                    help="1e7 workload: default schedule instead of the tuner's choice")
+    ap.add_argument("--tune", action="store_true",
+                    help="1e7 workload: run the schedule tuner first (default: the library's default "
+                         "schedule, tile 2048 and split budget 512, the one the committed profiles use)")
+    ap.add_argument("--no-tune", action="store_true", help="(the default; kept for old command lines)")
     ap.add_argument("--schedule", default="",
                     help="1e7 workload: TILE,SPLIT fixed schedule (tile bins, split budget), no tuning")
     ap.add_argument("--gpus", type=int, default=1)
@@ -511,7 +513,7 @@ def main():
     if args.schedule:
         tile, split = (int(v) for v in args.schedule.split(","))
         schedule = {"tile_bins": tile, "split_blocks": split}
-    elif not args.no_tune:
+    elif args.tune:
         from paper_2602_18560_amd.autotune import tune
         log("[bench] tuning the schedule (tile size, split budget)")
         schedule, _ = tune(dc, {**run.as_dict(), **overrides}, log=log)
@@ -552,6 +554,31 @@ def main():
     bytes_per_launch = ALGO_BYTES[fam] * st["units"] / max(st["launches"], 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
 
+    # The first body filters every bin (full grid); later bodies only the
+    # tiles a subtraction touched.  The first launch alone: runs stopped
+    # after one body (max_iter = 1), median events only.
+    ctx1 = G.Context(G.config_from_run(run, **overrides, **schedule, max_iter=1))
+    ctx1.ensure_workspace(cat.n)
+    ctx1.set_profiling(1 << G.KF_MEDIAN)
+    for _ in range(args.steps):
+        st1, _ = ctx1.run_raw(dc)
+        if st1 not in (G.OK, G.E_MAXITER):
+            raise G.GbsubError(st1, "gbsub_run (first body)")
+    torch.cuda.synchronize()
+    st_first = ctx1.kernel_stats()[fam]
+    ctx1.close()
+    first_ms = st_first["total_ms"] / max(st_first["launches"], 1)
+    first_units = st_first["units"] / max(st_first["launches"], 1)
+    late_launches = st["launches"] - st_first["launches"]
+    late_ms = (st["total_ms"] - st_first["total_ms"]) / max(late_launches, 1)
+    late_units = (st["units"] - st_first["units"]) / max(late_launches, 1)
+    launch_split = {
+        "first_body": {"avg_launch_ms": first_ms, "bins_per_launch": first_units,
+                       "achieved_GBs": ALGO_BYTES[fam] * first_units / (first_ms * 1e-3) / 1e9},
+        "later_bodies": {"avg_launch_ms": late_ms, "bins_per_launch": late_units,
+                         "achieved_GBs": ALGO_BYTES[fam] * late_units / (late_ms * 1e-3) / 1e9},
+    }
+
     nprof = min(args.steps, 5)
     log(f"[bench] per-family breakdown (profiled, untimed) x{nprof}")
     ctx.set_profiling(True)
@@ -588,7 +615,8 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic("k_median") if args.estimator == "median" else None,
                      "avg_launch_ms": avg_ms, "algo_bytes_per_launch": bytes_per_launch,
-                     "launches": st["launches"], "ms_per_step_with_events": ms_ev},
+                     "launches": st["launches"], "ms_per_step_with_events": ms_ev,
+                     "bytes_per_bin": ALGO_BYTES[fam], "launch_split": launch_split},
         "run_level_hbm": {"algo_bytes_per_step": total_algo,
                           "achieved_GBs": total_algo / (ms * 1e-3) / 1e9,
                           "frac": total_algo / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS},

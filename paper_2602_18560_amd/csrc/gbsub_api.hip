@@ -140,7 +140,6 @@ uint64_t carve(const Grid &g, uint64_t n, char *base, Dev *d)
     t.S = (double *)take(B * 8);
     t.is_pre = (double *)take(B * 8);
     t.is_psum = (double *)take((uint64_t)g.nparts * 8);
-    t.is_part = (double *)take(((uint64_t)g.nparts + 1) * 8);
     t.xstamp = (uint32_t *)take(nt * 4);
     t.sstamp = (uint32_t *)take(nt * 4);
     t.btot = (uint32_t *)take(nt * 4);

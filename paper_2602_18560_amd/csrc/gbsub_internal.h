@@ -8,12 +8,12 @@
 namespace gbs {
 
 constexpr int WG = 256;            // threads per workgroup for every tiled kernel
-constexpr int PWG = 1024;          // threads of the one-block scan of the part sums of 1/S
 constexpr int MMAX = 3072;         // median tile: outputs + W - 1 must fit
 constexpr int TILE_MAX = 2048;     // bins per tile (also the binning bucket)
 constexpr int NBK_MAX = 8192;      // tiles the prep histogram can hold (B <= 8192 tiles)
 constexpr int NARROW = 16;         // tracks of <= NARROW bins: SNR summed bin by bin
 constexpr int SNR_BLOCKS = 1024;   // fixed grid of the per-candidate kernels
+constexpr int COOP_PARTS = 8;      // tracks over more parts: the part sums are added by the whole wave
 constexpr int PREP_SRC = 8192;     // sources per block of the prep scatter pass
 constexpr int PREP_CNT = 4096;     // sources per block of the prep count pass
 constexpr int ACC_EV = 65536;      // binning events per accumulation block
@@ -126,8 +126,7 @@ struct Dev {
     double *X;               // [B]    X^t
     double *S;               // [B]    S^t
     double *is_pre;          // [B]    inclusive prefix of 1/S^t inside each part
-    double *is_psum;         // [nparts]   part sums of 1/S^t
-    double *is_part;         // [nparts+1] exclusive prefix of the part sums
+    double *is_psum;         // [nparts] part sums of 1/S^t
     // dirty tiles: a tile is converted (X) / filtered (S) in body t iff its
     // stamp equals t; k_snr stamps t + 1 where a subtraction changes them
     uint32_t *xstamp;        // [nt]

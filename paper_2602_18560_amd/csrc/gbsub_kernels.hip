@@ -1635,26 +1635,26 @@ __global__ __launch_bounds__(MWG) void k_mean(const Slot *S)
 
 // ------------------------------------------------------------------ SNR, decisions, subtraction
 
-// Exclusive prefix of the part sums of 1/S (one block, after the median):
-// with the in-part prefixes it gives any track's sum of 1/S in O(1).
-__global__ __launch_bounds__(PWG) void k_part_scan(const Slot *S)
+// Sum of 1/S over bins lo..hi from the in-part prefixes of 1/S and `mid`,
+// the sum of the part sums of the parts plo .. phi-1 (plo, phi: the parts
+// of lo and hi); short tracks are summed bin by bin in ascending order.
+DEVI double track_inv_sum(const double *v, const double *pre, int lo, int hi, int part, double mid)
 {
-    const Slot &sl = S[blockIdx.y];
-    if (!sl.active) return;
-    const Grid g = sl.g;
-    const Dev d = sl.d;
-    if (d.ctl->done || d.ctl->bad) return;
-    if (g.prec == PREC_NAIVE)
-        block_scan_array<double, PWG, float>(d.is_psum, d.is_part, g.nparts);
-    else
-        block_scan_array<double, PWG>(d.is_psum, d.is_part, g.nparts);
+    if (hi - lo + 1 <= NARROW) {
+        double s = 0.0;
+        for (int k = lo; k <= hi; ++k) s += 1.0 / v[k];
+        return s;
+    }
+    const double below = mod_p2(lo, part) == 0 ? 0.0 : pre[lo - 1];
+    if (div_p2(lo, part) == div_p2(hi, part)) return pre[hi] - below;
+    return (mid - below) + pre[hi];
 }
 
 // rho^2 in fp32 (the FP32 precision modes): 4 q sum 1/S with the sum in
-// fp32, compensated (Kahan) for short tracks and from the fp64 prefix
-// tables otherwise, or plain fp32 (naive: bin by bin, or differences of the
-// fp32 prefix tables).
-DEVI double snr2_f32(const Grid &g, const Dev &d, double qd, int lo, int hi)
+// fp32, compensated (Kahan) for short tracks and from fp64 sums of the
+// fp32 reciprocals otherwise, or plain fp32 (naive: bin by bin, or the fp32
+// in-part prefixes and an fp32 sum of the part sums).
+DEVI double snr2_f32(const Grid &g, const Dev &d, double qd, int lo, int hi, double mid)
 {
     // q and S scaled by 2^sc; the prefix tables already hold 1/(2^sc S)
     const int sc = f32_scale(d.ctl->amax_bits, g.T);
@@ -1675,12 +1675,11 @@ DEVI double snr2_f32(const Grid &g, const Dev &d, double qd, int lo, int hi)
         }
         sum = s;
     } else if (g.prec == PREC_COMP) {
-        sum = (float)range_inv_sum(d.S, d.is_pre, d.is_part, lo, hi, g.part);
-    } else {                                   // differences of the fp32 prefix tables
-        const int plo = div_p2(lo, g.part), phi = div_p2(hi, g.part);
+        sum = (float)track_inv_sum(d.S, d.is_pre, lo, hi, g.part, mid);
+    } else {
         const float below = mod_p2(lo, g.part) == 0 ? 0.0f : (float)d.is_pre[lo - 1];
-        sum = plo == phi ? (float)d.is_pre[hi] - below
-                         : (((float)d.is_part[phi] - (float)d.is_part[plo]) - below) + (float)d.is_pre[hi];
+        sum = div_p2(lo, g.part) == div_p2(hi, g.part) ? (float)d.is_pre[hi] - below
+                                                         : ((float)mid - below) + (float)d.is_pre[hi];
     }
     return (double)((4.0f * q) * sum);
 }
@@ -1779,22 +1778,66 @@ __global__ __launch_bounds__(WG) void k_snr(const Slot *S)
     const int t = (int)d.ctl->iter;
     const uint32_t nxt = (uint32_t)t + 1;
     const uint32_t nc = d.ctl->n_cand;
+    const bool naive = g.prec == PREC_NAIVE;
+    const int lane = lane_id();
     uint32_t my_new = 0;
     uint64_t near = 0, evals = 0;
     double minm = INFINITY;
-    for (uint32_t j = blockIdx.x * WG + threadIdx.x; j < nc; j += gridDim.x * WG) {
-        if (d.c_iter[j] >= 0) continue;
-        const int glo = d.c_glo[j], ghi = d.c_ghi[j];
-        double r2;
-        if (t != 0 && !track_refiltered(d.sstamp, g, glo, ghi, (uint32_t)t)) {
-            r2 = d.c_rho2[j];
-        } else {
+    // the wave walks its candidates together (uniform trip count), so that
+    // all its lanes can sum the part sums under a wide track
+    const uint32_t stride = gridDim.x * WG;
+    for (uint32_t jb = blockIdx.x * WG + (threadIdx.x & ~63u); jb < nc; jb += stride) {
+        const uint32_t j = jb + (uint32_t)lane;
+        const bool live = j < nc && d.c_iter[j] < 0;
+        int glo = 0, ghi = 0;
+        bool eval = false;
+        double r2 = 0.0;
+        if (live) {
+            glo = d.c_glo[j];
+            ghi = d.c_ghi[j];
+            eval = t == 0 || track_refiltered(d.sstamp, g, glo, ghi, (uint32_t)t);
+            if (!eval) r2 = d.c_rho2[j];
+        }
+        // sum of the part sums of 1/S over the parts strictly before the
+        // track's last part: a loop for tracks over a few parts, all lanes
+        // of the wave together for wider ones, one track at a time
+        const int plo = div_p2(glo, g.part), phi = div_p2(ghi, g.part);
+        const bool need = eval && ghi - glo + 1 > NARROW && phi > plo;
+        const bool wide = need && phi - plo > COOP_PARTS;
+        double mid = 0.0;
+        if (need && !wide) {
+            if (naive) {
+                float m = 0.0f;
+                for (int pp = plo; pp < phi; ++pp) m += (float)d.is_psum[pp];
+                mid = (double)m;
+            } else {
+                for (int pp = plo; pp < phi; ++pp) mid += d.is_psum[pp];
+            }
+        }
+        for (uint64_t wm = (uint64_t)__ballot(wide); wm; wm &= wm - 1) {
+            const int L = __builtin_ctzll(wm);
+            const int a = __builtin_amdgcn_readlane(plo, L), b = __builtin_amdgcn_readlane(phi, L);
+            double sum;
+            if (naive) {
+                float m = 0.0f;
+                for (int pp = a + lane; pp < b; pp += 64) m += (float)d.is_psum[pp];
+                for (int o = 32; o >= 1; o >>= 1) m += __shfl_xor(m, o, 64);
+                sum = (double)m;
+            } else {
+                double m = 0.0;
+                for (int pp = a + lane; pp < b; pp += 64) m += d.is_psum[pp];
+                sum = wave_sum(m);
+            }
+            if (lane == L) mid = sum;
+        }
+        if (eval) {
             ++evals;
             const double q = d.c_q[j];
-            r2 = g.prec == PREC_FP64 ? (4.0 * q) * range_inv_sum(d.S, d.is_pre, d.is_part, glo, ghi, g.part)
-                                     : snr2_f32(g, d, q, glo, ghi);
+            r2 = g.prec == PREC_FP64 ? (4.0 * q) * track_inv_sum(d.S, d.is_pre, glo, ghi, g.part, mid)
+                                     : snr2_f32(g, d, q, glo, ghi, mid);
             d.c_rho2[j] = r2;
         }
+        if (!live) continue;
         const double rel = fabs(sqrt(r2) / g.rth - 1.0);
         minm = fmin(minm, rel);
         near += rel <= 1e-6;
@@ -1804,7 +1847,7 @@ __global__ __launch_bounds__(WG) void k_snr(const Slot *S)
             const int64_t v = (int64_t)d.c_qfx[j];
             if (v) {
                 subtract_track(g, d, glo, ghi, v);
-                if (g.prec == PREC_NAIVE)
+                if (naive)
                     subtract_track_f32(g, d, glo, ghi,
                                        (float)ldexp((double)v, fx_exp(d.ctl->amax_bits, g.T) +
                                                                    f32_scale(d.ctl->amax_bits, g.T)));
@@ -2020,10 +2063,8 @@ hipError_t launch_median(const Slot *ds, const Dims &dm, hipStream_t st, hipEven
 
 hipError_t launch_snr(const Slot *ds, const Dims &dm, hipStream_t st, hipEvent_t ea, hipEvent_t eb)
 {
-    hipError_t e = go((const void *)k_part_scan, dim3(1, dm.ns), dim3(PWG), st, ea, nullptr, ds);
-    if (!dm.naive) return e == hipSuccess ? go((const void *)k_snr, dim3(SNR_BLOCKS, dm.ns), dim3(WG), st, nullptr, eb, ds)
-                                          : e;
-    if (e == hipSuccess) e = go((const void *)k_snr, dim3(SNR_BLOCKS, dm.ns), dim3(WG), st, nullptr, nullptr, ds);
+    if (!dm.naive) return go((const void *)k_snr, dim3(SNR_BLOCKS, dm.ns), dim3(WG), st, ea, eb, ds);
+    hipError_t e = go((const void *)k_snr, dim3(SNR_BLOCKS, dm.ns), dim3(WG), st, ea, nullptr, ds);
     if (e != hipSuccess) return e;
     return go((const void *)k_snr_tail, dim3(1, dm.ns), dim3(SNR_BLOCKS), st, nullptr, eb, ds);
 }
