@@ -126,6 +126,7 @@ uint64_t carve(const Grid &g, uint64_t n, char *base, Dev *d)
     t.isx_pre = (double *)take(B * 8);
     t.isx_tsum = (double *)take(nt * 8);
     t.isx_tile = (double *)take((nt + 1) * 8);
+    t.isx_seg = (double2 *)take(((B + SEG_BINS - 1) / SEG_BINS) * 16);
     t.Xn = (I128 *)take(B * 16);
     t.D = (I128 *)take((B + 1) * 16);
     t.Dtile = (I128 *)take((nt + 1) * 16);
@@ -143,8 +144,10 @@ uint64_t carve(const Grid &g, uint64_t n, char *base, Dev *d)
     t.xstamp = (uint32_t *)take(nt * 4);
     t.sstamp = (uint32_t *)take(nt * 4);
     t.btot = (uint32_t *)take(nt * 4);
+    const uint64_t npb = (nn + PREP_SRC - 1) / PREP_SRC;
+    t.bhist = (uint32_t *)take(npb * ((nt + 1) / 2) * 4);
+    t.boff = (uint32_t *)take(npb * nt * 4);
     t.bbase = (uint32_t *)take((nt + 1) * 4);
-    t.cursor = (uint32_t *)take(nt * 4);
     t.nch = (uint32_t *)take(nt * 4);
     t.chunk_base = (uint32_t *)take((nt + 1) * 4);
     t.slot_base = (uint32_t *)take(nt * 4);
@@ -152,7 +155,7 @@ uint64_t carve(const Grid &g, uint64_t n, char *base, Dev *d)
     t.ev_val = (int64_t *)take((max_events ? max_events : 1) * 8);
     t.partial = (I128 *)take((uint64_t)t.max_slots * 2 * (uint64_t)g.tile * 16);
     t.cbits = (uint64_t *)take(((nn + 63) / 64) * 8);
-    const uint64_t ncb = (nn + PREP_CNT - 1) / PREP_CNT;
+    const uint64_t ncb = npb;
     t.blk_cand = (uint32_t *)take((ncb + 1) * 4);
     t.blk_amax = (uint32_t *)take(ncb * 4);
     t.c_src = (uint32_t *)take(nn * 4);
@@ -261,7 +264,6 @@ Dims dims_of(const Slot &sl)
     dm.est_mask = 1u << sl.g.est;
     dm.naive = sl.g.prec == PREC_NAIVE;
     dm.prep_blocks = (uint32_t)((sl.n + PREP_SRC - 1) / PREP_SRC);
-    dm.count_blocks = (uint32_t)((sl.n + PREP_CNT - 1) / PREP_CNT);
     dm.accum_blocks = sl.d.max_chunks;
     return dm;
 }
@@ -275,7 +277,6 @@ void widen(Dims &a, const Dims &b)
     a.est_mask |= b.est_mask;
     a.naive |= b.naive;
     a.prep_blocks = std::max(a.prep_blocks, b.prep_blocks);
-    a.count_blocks = std::max(a.count_blocks, b.count_blocks);
     a.accum_blocks = std::max(a.accum_blocks, b.accum_blocks);
 }
 

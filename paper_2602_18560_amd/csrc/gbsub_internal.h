@@ -14,8 +14,9 @@ constexpr int NBK_MAX = 8192;      // tiles the prep histogram can hold (B <= 81
 constexpr int NARROW = 16;         // tracks of <= NARROW bins: SNR summed bin by bin
 constexpr int SNR_BLOCKS = 1024;   // fixed grid of the per-candidate kernels
 constexpr int COOP_PARTS = 8;      // tracks over more parts: the part sums are added by the whole wave
-constexpr int PREP_SRC = 8192;     // sources per block of the prep scatter pass
-constexpr int PREP_CNT = 4096;     // sources per block of the prep count pass
+constexpr int PREP_SRC = 4096;     // sources per block of the prep passes (count and scatter)
+constexpr int SEG_BINS = 128;      // bins per segment of the 1/S_instr bounds of the candidate test
+constexpr int CS_WG = 1024;        // threads of a column-pass block (64 tiles, 16 waves over the blocks)
 constexpr int ACC_EV = 65536;      // binning events per accumulation block
 constexpr int RED_BINS = 256;      // bins per reduction block of the hot buckets
 constexpr int NEW_CAP = 1 << 16;   // per-iteration counters kept (iterations beyond: not recorded)
@@ -112,6 +113,7 @@ struct Dev {
     double *isx_pre;         // [B]    inclusive prefix of 1/S_instr inside each tile
     double *isx_tsum;        // [nt]   tile sums of 1/S_instr
     double *isx_tile;        // [nt+1] exclusive prefix of the tile sums
+    double2 *isx_seg;        // [ceil(B/SEG_BINS)] (min, max) of 1/S_instr over each segment
     // binned power: X = Xn + prefix(D), all exact 128-bit fixed point
     I128 *Xn;                // [B]    sources whose clipped track is one bin
     I128 *D;                 // [B+1]  difference array of the wider tracks
@@ -133,8 +135,9 @@ struct Dev {
     uint32_t *sstamp;        // [nt]
     // binning by tile (multisplit): events sorted by tile
     uint32_t *btot;          // [nt]   events per tile
+    uint32_t *bhist;         // [prep blocks][(nt+1)/2] events per (block, tile), two 16-bit counts a word
+    uint32_t *boff;          // [prep blocks][nt] events of the blocks before, per tile
     uint32_t *bbase;         // [nt+1] first event of each tile
-    uint32_t *cursor;        // [nt]   scatter cursors
     uint32_t *nch;           // [nt]   accumulation blocks per tile
     uint32_t *chunk_base;    // [nt+1]
     uint32_t *slot_base;     // [nt]   partial-sum slots of tiles with several blocks
@@ -180,7 +183,7 @@ struct Dims {
     int maxB, maxnt, maxtile, maxparts;
     uint32_t est_mask;       // bit e: some slot uses estimator e
     uint32_t naive;          // some slot runs in naive FP32
-    uint32_t prep_blocks, count_blocks, accum_blocks;
+    uint32_t prep_blocks, accum_blocks;
 };
 
 // Kernel launchers (gbsub_kernels.hip); all enqueue on `st` and return the

@@ -333,6 +333,31 @@ __global__ __launch_bounds__(WG) void k_sx_scan(const Slot *S)
     block_scan_array<double>(d.isx_tsum, d.isx_tile, g.nt);
 }
 
+// (min, max) of 1/S_instr over each segment of SEG_BINS bins (one wave per
+// segment): bounds that decide most one-bin candidate tests without the
+// table value of the source's bin.
+__global__ __launch_bounds__(WG) void k_isx_seg(const Slot *S)
+{
+    const Slot &sl = S[blockIdx.y];
+    if (!sl.active) return;
+    const Grid g = sl.g;
+    const Dev d = sl.d;
+    const int seg = blockIdx.x * (WG / 64) + (threadIdx.x >> 6);
+    const int nseg = (g.B + SEG_BINS - 1) / SEG_BINS;
+    if (seg >= nseg) return;
+    double mn = INFINITY, mx = -INFINITY;
+    for (int k = seg * SEG_BINS + lane_id(); k < min((seg + 1) * SEG_BINS, g.B); k += 64) {
+        const double x = d.isx[k];
+        mn = fmin(mn, x);
+        mx = fmax(mx, x);
+    }
+    for (int o = 32; o >= 1; o >>= 1) {
+        mn = fmin(mn, __shfl_xor(mn, o, 64));
+        mx = fmax(mx, __shfl_xor(mx, o, 64));
+    }
+    if (lane_id() == 0) d.isx_seg[seg] = make_double2(mn, mx);
+}
+
 // ------------------------------------------------------------------ reset
 
 // Clears the per-run state of a slot: control block, tile counters, dirty
@@ -366,7 +391,6 @@ __global__ __launch_bounds__(WG) void k_reset(const Slot *S)
         c->tail_due = 0;
     }
     for (int i = blockIdx.x * WG + threadIdx.x; i < g.nt; i += gridDim.x * WG) {
-        d.btot[i] = 0;
         d.xstamp[i] = 0;          // body 0 converts and filters every tile
         d.sstamp[i] = 0;
         d.Dadj[i].h = 0;
@@ -382,12 +406,14 @@ __global__ __launch_bounds__(WG) void k_reset(const Slot *S)
 // bins, per-bin power q = P/n, track clipped to the grid; rho_0^2 against
 // S_instr; candidate iff rho_0^2 >= (kappa rho_th)^2.
 //
-// Binning without contended global atomics: a count pass tallies binning
-// events per tile in LDS and publishes one atomic per non-empty (block,
-// tile); after a scan of the tile totals, a scatter pass writes every event
-// to its tile's contiguous segment; accumulation blocks then sum up to
-// ACC_EV events of one tile in LDS (exact 128-bit integers) and write the
-// tile's bins, hot tiles through partial sums reduced by a last pass.
+// Binning without global atomics: a count pass tallies the binning events
+// of each block of PREP_SRC sources per tile in LDS and writes that row of
+// counts; a column pass gives every (block, tile) its first slot among the
+// tile's events (the counts of the blocks before it) and the tile totals;
+// after a scan of the totals, a scatter pass writes every event to its
+// tile's contiguous segment; accumulation blocks then sum up to ACC_EV
+// events of one tile in LDS (exact 128-bit integers) and write the tile's
+// bins, hot tiles through partial sums reduced by a last pass.
 
 struct Trk {
     bool ok, live;
@@ -452,8 +478,9 @@ DEVI bool cand_test(const Grid &g, const Dev &d, const Trk &t, double x0)
 DEVI int tile_of(int bin, int tile) { return div_p2(bin, tile); }
 
 // Count pass: events per tile and candidates of this block.  The per-tile
-// counts are 16-bit halves of LDS words (at most 2 PREP_CNT < 2^16 events
-// of a block fall in one tile), which keeps the block's LDS at 16 KB.
+// counts are 16-bit halves of LDS words (at most 2 PREP_SRC < 2^16 events
+// of a block fall in one tile), which keeps the block's LDS at 16 KB; the
+// packed words are the block's row of bhist.
 DEVI void k_prep_count_body(Grid g, Dev d, const float *A, const float *F, const float *FD, uint64_t n)
 {
     __shared__ uint32_t hist[NBK_MAX / 2];
@@ -465,12 +492,12 @@ DEVI void k_prep_count_body(Grid g, Dev d, const float *A, const float *F, const
         samax = 0;
     }
     __syncthreads();
-    const uint64_t base = (uint64_t)blockIdx.x * PREP_CNT;
+    const uint64_t base = (uint64_t)blockIdx.x * PREP_SRC;
     uint32_t cc = 0, bad = 0, amax = 0;
     constexpr int CB = 8;
     // CB sources per thread in flight: loads first, then the tracks and
     // the S_instr gathers of the candidate tests
-    for (int r0 = 0; r0 < PREP_CNT / WG; r0 += CB) {
+    for (int r0 = 0; r0 < PREP_SRC / WG; r0 += CB) {
         float a[CB], f[CB], fd[CB];
 #pragma unroll
         for (int q = 0; q < CB; ++q) {
@@ -491,14 +518,29 @@ DEVI void k_prep_count_body(Grid g, Dev d, const float *A, const float *F, const
         Trk t[CB];
 #pragma unroll
         for (int q = 0; q < CB; ++q) t[q] = track_geom(g, a[q], f[q], fd[q]);
-        double x0[CB];                            // first-bin gathers, all in flight
+        // one-bin tracks: rho_0^2 = (4q) (1/S_instr) lies between (4q) min and
+        // (4q) max of its segment (the product is monotone in 1/S_instr), which
+        // decides the test unless the cut falls between them; the others take
+        // the table values (first-bin gathers all in flight)
+        double2 sb[CB];
 #pragma unroll
-        for (int q = 0; q < CB; ++q) x0[q] = d.isx[t[q].live ? t[q].glo : 0];
+        for (int q = 0; q < CB; ++q) sb[q] = d.isx_seg[t[q].live ? t[q].glo / SEG_BINS : 0];
+        bool cand[CB], exact[CB];
 #pragma unroll
-        for (int q = 0; q < CB; ++q) pin(x0[q]);
-        bool cand[CB];
+        for (int q = 0; q < CB; ++q) {
+            const double q4 = 4.0 * t[q].q;
+            const bool one = t[q].live && t[q].glo == t[q].ghi;
+            const bool yes = one && q4 * sb[q].x >= g.cut2;
+            const bool no = one && q4 * sb[q].y < g.cut2;
+            cand[q] = yes;
+            exact[q] = t[q].live && !yes && !no;
+        }
+        double x0[CB];
 #pragma unroll
-        for (int q = 0; q < CB; ++q) cand[q] = cand_test(g, d, t[q], x0[q]);
+        for (int q = 0; q < CB; ++q) x0[q] = exact[q] ? d.isx[t[q].glo] : 0.0;
+#pragma unroll
+        for (int q = 0; q < CB; ++q)
+            if (exact[q]) cand[q] = cand_test(g, d, t[q], x0[q]);
 #pragma unroll
         for (int q = 0; q < CB; ++q) {
             const uint64_t i = base + (uint64_t)(r0 + q) * WG + threadIdx.x;
@@ -532,17 +574,15 @@ DEVI void k_prep_count_body(Grid g, Dev d, const float *A, const float *F, const
         d.blk_cand[blockIdx.x] = scand;
         d.blk_amax[blockIdx.x] = samax;
     }
-    for (int b = threadIdx.x; b < g.nt; b += WG) {
-        const uint32_t c = (hist[b >> 1] >> (16 * (b & 1))) & 0xFFFFu;
-        if (c) atomicAdd(&d.btot[b], c);
-    }
+    const int hw = (g.nt + 1) / 2;
+    for (int b = threadIdx.x; b < hw; b += WG) d.bhist[(size_t)blockIdx.x * hw + b] = hist[b];
     if (bad) atomicOr(&d.ctl->bad, 1u);
 }
 
 __global__ __launch_bounds__(WG) void k_prep_count(const Slot *S)
 {
     const Slot &sl = S[blockIdx.y];
-    if (!sl.active || (uint64_t)blockIdx.x * PREP_CNT >= sl.n) return;
+    if (!sl.active || (uint64_t)blockIdx.x * PREP_SRC >= sl.n) return;
     const Grid g = sl.g;
     const Dev d = sl.d;
     const float *A = sl.A, *F = sl.F, *FD = sl.FD;
@@ -551,8 +591,65 @@ __global__ __launch_bounds__(WG) void k_prep_count(const Slot *S)
 }
 
 
-// Plan (one block): tile bases, scatter cursors, accumulation blocks and
-// partial-sum slots; clears the tile sums of D.
+// Column pass: for each tile, the exclusive prefix over the prep blocks of
+// its event counts (where each block's events start inside the tile's
+// segment) and the tile's total.  A block takes 64 tiles (one per lane; the
+// loads and stores of consecutive tiles are coalesced) and its 16 waves
+// split the prep blocks into ranges: each wave sums its range, a prefix
+// over the waves gives each range its start, and each wave walks its range
+// again writing the offsets.
+__global__ __launch_bounds__(CS_WG) void k_prep_colscan(const Slot *S)
+{
+    constexpr int NV = CS_WG / 64;
+    __shared__ uint32_t part[NV][64];
+    const Slot &sl = S[blockIdx.y];
+    if (!sl.active) return;
+    const Grid g = sl.g;
+    const Dev d = sl.d;
+    const int lane = lane_id(), w = threadIdx.x >> 6;
+    const int tile = blockIdx.x * 64 + lane;
+    const bool ok = tile < g.nt;
+    const int col = ok ? tile : g.nt - 1;                      // a valid column; results dropped
+    const int nb = (int)((sl.n + PREP_SRC - 1) / PREP_SRC);
+    const int per = (nb + NV - 1) / NV;
+    const int b0 = min(w * per, nb), b1 = min(b0 + per, nb);
+    const size_t row = 2 * (size_t)((g.nt + 1) / 2);          // 16-bit counts per bhist row
+    const uint16_t *h16 = reinterpret_cast<const uint16_t *>(d.bhist);
+    constexpr int U = 16;
+    uint32_t sum = 0;
+    for (int bb = b0; bb < b1; bb += U) {
+        uint32_t c[U];
+#pragma unroll
+        for (int q = 0; q < U; ++q) c[q] = h16[(size_t)min(bb + q, b1 - 1) * row + col];
+#pragma unroll
+        for (int q = 0; q < U; ++q) sum += bb + q < b1 ? c[q] : 0u;
+    }
+    part[w][lane] = sum;
+    __syncthreads();
+    uint32_t run = 0, tot = 0;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const uint32_t x = part[v][lane];
+        run += v < w ? x : 0u;
+        tot += x;
+    }
+    if (w == 0 && ok) d.btot[tile] = tot;
+    for (int bb = b0; bb < b1; bb += U) {
+        uint32_t c[U];
+#pragma unroll
+        for (int q = 0; q < U; ++q) c[q] = h16[(size_t)min(bb + q, b1 - 1) * row + col];
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            if (bb + q < b1) {
+                if (ok) d.boff[(size_t)(bb + q) * g.nt + tile] = run;
+                run += c[q];
+            }
+        }
+    }
+}
+
+// Plan (one block): tile bases, accumulation blocks and partial-sum slots;
+// clears the tile sums of D.
 __global__ __launch_bounds__(WG) void k_prep_plan(const Slot *S)
 {
     __shared__ uint32_t sh[WG / 64];
@@ -564,7 +661,7 @@ __global__ __launch_bounds__(WG) void k_prep_plan(const Slot *S)
     // largest A and the candidates of the count blocks: their exclusive
     // prefix is each scatter block's first candidate slot
     {
-        const int nb = (int)((sl.n + PREP_CNT - 1) / PREP_CNT);
+        const int nb = (int)((sl.n + PREP_SRC - 1) / PREP_SRC);
         uint32_t am = 0;
         for (int b = threadIdx.x; b < nb; b += WG) am = max(am, d.blk_amax[b]);
         for (int s = 32; s >= 1; s >>= 1) am = max(am, (uint32_t)__shfl_xor((int)am, s, 64));
@@ -592,7 +689,6 @@ __global__ __launch_bounds__(WG) void k_prep_plan(const Slot *S)
         const uint32_t es = block_excl_scan(ns, sh, &ts);
         if (b < g.nt) {
             d.bbase[b] = carry_e + ee;
-            d.cursor[b] = carry_e + ee;
             d.nch[b] = nc;
             d.chunk_base[b] = carry_c + ec;
             d.slot_base[b] = carry_s + es;
@@ -614,63 +710,22 @@ __global__ __launch_bounds__(WG) void k_prep_plan(const Slot *S)
     }
 }
 
-// Scatter pass: recount, reserve each tile's range once, write the events
-// and the candidate records.
+// Scatter pass: the block's events start, inside each tile's segment, at
+// the slot the column pass gave it; it writes the events and the candidate
+// records.
 DEVI void k_prep_scatter_body(Grid g, Dev d, const float *A, const float *F, const float *FD, uint64_t n)
 {
     __shared__ uint32_t cur[NBK_MAX];
     __shared__ uint32_t scand, cbase;
-    for (int b = threadIdx.x; b < g.nt; b += WG) cur[b] = 0;
-    if (threadIdx.x == 0) scand = 0;
+    for (int b = threadIdx.x; b < g.nt; b += WG) cur[b] = d.bbase[b] + d.boff[(size_t)blockIdx.x * g.nt + b];
+    if (threadIdx.x == 0) {
+        cbase = d.blk_cand[blockIdx.x];
+        scand = 0;
+    }
     __syncthreads();
     const int L = fx_exp(d.ctl->amax_bits, g.T);
     const uint64_t base = (uint64_t)blockIdx.x * PREP_SRC;
     constexpr int SB = 8;                    // sources per thread in flight
-    uint32_t cc = 0;
-    for (int r0 = 0; r0 < PREP_SRC / WG; r0 += SB) {
-        float a[SB], f[SB], fd[SB];
-        uint64_t cw[SB];                         // candidate-flag words of the sources
-#pragma unroll
-        for (int q = 0; q < SB; ++q) {
-            const uint64_t i = base + (uint64_t)(r0 + q) * WG + threadIdx.x;
-            const bool in = i < n;
-            const uint64_t ic = in ? i : n - 1;        // unconditional loads: all in flight at once
-            const float av = A[ic], fv = F[ic], fdv = FD[ic];
-            a[q] = in ? av : 0.0f;
-            f[q] = in ? fv : 1.0f;
-            fd[q] = in ? fdv : 0.0f;
-            cw[q] = d.cbits[ic >> 6];
-        }
-#pragma unroll
-        for (int q = 0; q < SB; ++q) {
-            pin(a[q]);
-            pin(f[q]);
-            pin(fd[q]);
-            pin(cw[q]);
-        }
-#pragma unroll
-        for (int q = 0; q < SB; ++q) {
-            const uint64_t i = base + (uint64_t)(r0 + q) * WG + threadIdx.x;
-            if (i >= n) continue;
-            const Trk t = track_geom(g, a[q], f[q], fd[q]);
-            if (!t.ok) continue;
-            if (t.live) {
-                atomicAdd(&cur[tile_of(t.glo, g.tile)], 1u);
-                if (t.glo != t.ghi && t.ghi + 1 < g.B) atomicAdd(&cur[tile_of(t.ghi + 1, g.tile)], 1u);
-            }
-            cc += (uint32_t)(cw[q] >> (i & 63)) & 1u;
-        }
-    }
-    for (int s = 32; s >= 1; s >>= 1) cc += (uint32_t)__shfl_xor((int)cc, s, 64);
-    if (lane_id() == 0 && cc) atomicAdd(&scand, cc);
-    __syncthreads();
-    for (int b = threadIdx.x; b < g.nt; b += WG)
-        if (cur[b]) cur[b] = atomicAdd(&d.cursor[b], cur[b]);
-    if (threadIdx.x == 0) {
-        cbase = d.blk_cand[blockIdx.x * (PREP_SRC / PREP_CNT)];
-        scand = 0;
-    }
-    __syncthreads();
     for (int r0 = 0; r0 < PREP_SRC / WG; r0 += SB) {
         float a[SB], f[SB], fd[SB];
         uint64_t cw[SB];                         // candidate-flag words of the sources
@@ -2013,6 +2068,8 @@ hipError_t launch_grid_tables(const Slot *ds, const Dims &dm, hipStream_t st)
     k_sinstr<<<dim3((dm.maxB + WG - 1) / WG, dm.ns), WG, 0, st>>>(ds);
     k_inv_prefix<<<dim3(dm.maxnt, dm.ns), WG, 0, st>>>(ds);
     k_sx_scan<<<dim3(1, dm.ns), WG, 0, st>>>(ds);
+    const int nseg = (dm.maxB + SEG_BINS - 1) / SEG_BINS;
+    k_isx_seg<<<dim3((nseg + WG / 64 - 1) / (WG / 64), dm.ns), WG, 0, st>>>(ds);
     return hipGetLastError();
 }
 
@@ -2026,7 +2083,8 @@ hipError_t launch_reset(const Slot *ds, const Dims &dm, hipStream_t st)
 
 hipError_t launch_prep(const Slot *ds, const Dims &dm, hipStream_t st)
 {
-    if (dm.count_blocks > 0) k_prep_count<<<dim3(dm.count_blocks, dm.ns), WG, 0, st>>>(ds);
+    if (dm.prep_blocks > 0) k_prep_count<<<dim3(dm.prep_blocks, dm.ns), WG, 0, st>>>(ds);
+    k_prep_colscan<<<dim3((dm.maxnt + 63) / 64, dm.ns), CS_WG, 0, st>>>(ds);
     k_prep_plan<<<dim3(1, dm.ns), WG, 0, st>>>(ds);
     if (dm.prep_blocks > 0) k_prep_scatter<<<dim3(dm.prep_blocks, dm.ns), WG, 0, st>>>(ds);
     k_accum<<<dim3(dm.accum_blocks, dm.ns), WG, 0, st>>>(ds);
