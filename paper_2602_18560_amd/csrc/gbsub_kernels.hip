@@ -518,20 +518,32 @@ DEVI void k_prep_count_body(Grid g, Dev d, const float *A, const float *F, const
         Trk t[CB];
 #pragma unroll
         for (int q = 0; q < CB; ++q) t[q] = track_geom(g, a[q], f[q], fd[q]);
-        // one-bin tracks: rho_0^2 = (4q) (1/S_instr) lies between (4q) min and
-        // (4q) max of its segment (the product is monotone in 1/S_instr), which
-        // decides the test unless the cut falls between them; the others take
-        // the table values (first-bin gathers all in flight)
-        double2 sb[CB];
+        // Bounds from the (min, max) of 1/S_instr over the segments under the
+        // track decide most tests without the table values.  One bin:
+        // rho_0^2 = (4q) (1/S_instr) lies between (4q) min and (4q) max (the
+        // product is monotone).  2 .. NARROW bins (at most two segments): the
+        // fp64 sum of the n values lies within n min (1 - n 2^-53) and
+        // n max (1 + n 2^-53), so a margin of 1e-12 on n min and n max is
+        // safe.  Otherwise, or if the cut falls between the bounds, the table
+        // values decide (their gathers all in flight).
+        double2 sb[CB], se[CB];
 #pragma unroll
-        for (int q = 0; q < CB; ++q) sb[q] = d.isx_seg[t[q].live ? t[q].glo / SEG_BINS : 0];
+        for (int q = 0; q < CB; ++q) {
+            sb[q] = d.isx_seg[t[q].live ? t[q].glo / SEG_BINS : 0];
+            se[q] = d.isx_seg[t[q].live ? t[q].ghi / SEG_BINS : 0];
+        }
         bool cand[CB], exact[CB];
 #pragma unroll
         for (int q = 0; q < CB; ++q) {
             const double q4 = 4.0 * t[q].q;
-            const bool one = t[q].live && t[q].glo == t[q].ghi;
-            const bool yes = one && q4 * sb[q].x >= g.cut2;
-            const bool no = one && q4 * sb[q].y < g.cut2;
+            const int nb = t[q].ghi - t[q].glo + 1;
+            const bool one = t[q].live && nb == 1;
+            const bool few = t[q].live && nb > 1 && nb <= NARROW;
+            const double mn = fmin(sb[q].x, se[q].x), mx = fmax(sb[q].y, se[q].y);
+            const double lo = few ? q4 * ((double)nb * mn) * (1.0 - 1e-12) : q4 * mn;
+            const double hi = few ? q4 * ((double)nb * mx) * (1.0 + 1e-12) : q4 * mx;
+            const bool yes = (one || few) && lo >= g.cut2;
+            const bool no = (one || few) && hi < g.cut2;
             cand[q] = yes;
             exact[q] = t[q].live && !yes && !no;
         }
