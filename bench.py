@@ -392,7 +392,14 @@ def bench_precision(args):
     dc = G.DeviceCatalog.from_host(cat)
     ref_ids = gold["resolved_ids"].astype(np.int64)
     ref_it = gold["resolved_iter"]
-    bins = gold["S_bins"]
+    # the oracle's final X and S on every bin: its spectra once exactly its
+    # resolved set is subtracted
+    from oracle import oracle as O
+    log("[precision] oracle X and S on every bin (host)")
+    O.set_threads(all_threads())
+    sub = np.zeros(cat.n, bool)
+    sub[np.searchsorted(cat.id, ref_ids)] = True
+    X_ref, S_ref = O.spectra_after(cat, O.make_config(run), sub)
     out_modes = {}
     for name, prec in (("fp64", G.FP64), ("fp32_compensated", G.FP32_COMP), ("fp32_naive", G.FP32_NAIVE)):
         ctx = G.Context(G.config_from_run(run, precision=prec))
@@ -404,15 +411,16 @@ def bench_precision(args):
             s = ctx.run(dc)
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3 / args.steps
-        S = ctx.spectrum(G.SPEC_SN)[bins]
-        X = ctx.spectrum(G.SPEC_X_RESIDUAL)[bins]
+        S = ctx.spectrum(G.SPEC_SN)
+        X = ctx.spectrum(G.SPEC_X_RESIDUAL)
         ids, it = ctx.resolved()
         cids, cit, cr2 = ctx.candidates()
         ctx.close()
-        relS = np.abs(S - gold["S_final"]) / gold["S_final"]
-        xo = gold["X_final"]
+        relS = np.abs(S - S_ref) / S_ref
+        xo = X_ref
         pos = xo > 0
         relX = np.abs(X[pos] - xo[pos]) / xo[pos]
+        relXS = np.abs(X - xo) / S_ref          # X error on the scale of the PSD it enters
         same = np.array_equal(cids.astype(np.int64), grho["cand"].astype(np.int64))
         relR = np.abs(cr2 - grho["rho2"]) / grho["rho2"] if same else np.array([np.nan])
         a = set(ref_ids.tolist())
@@ -430,7 +438,8 @@ def bench_precision(args):
                           "bins": int(relS.size)},
             "X_rel_err": {"max": float(relX.max()), "median": float(np.median(relX)),
                           "bins": int(relX.size),
-                          "nonzero_where_oracle_zero": int(np.count_nonzero(X[~pos]))},
+                          "nonzero_where_oracle_zero": int(np.count_nonzero(X[~pos])),
+                          "max_abs_err_over_S": float(relXS.max())},
             "rho2_rel_err": {"max": float(np.nanmax(relR)), "median": float(np.nanmedian(relR)),
                              "candidates": int(relR.size)},
         }
@@ -442,9 +451,10 @@ def bench_precision(args):
            "ms_per_step": out_modes["fp32_compensated"]["ms_per_step"], "higher_is_better": False,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": "1e7-binary catalog (seed 2), T = 4 yr, W = 1001, in FP64 / "
-                                  "FP32 with compensated sums / naive FP32; S and X on every 997th "
-                                  "bin, rho^2 of every candidate at its last evaluation, resolved "
-                                  "ids and loop bodies against the FP64 oracle's stored results"},
+                                  "FP32 with double-fp32 (compensated) sums / naive FP32; S and X "
+                                  "on every bin against the oracle's spectra for its resolved set, "
+                                  "rho^2 of every candidate at its last evaluation, resolved ids "
+                                  "and loop bodies against the FP64 oracle's stored results"},
            "modes": out_modes}
     print(json.dumps(out), flush=True)
 

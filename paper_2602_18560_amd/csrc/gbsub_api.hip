@@ -137,6 +137,10 @@ uint64_t carve(const Grid &g, uint64_t n, char *base, Dev *d)
     t.Df = (float *)take(naive ? (B + 1) * 4 : 0);
     t.Dtf = (float *)take(naive ? (nt + 1) * 4 : 0);
     t.Dcf = (float *)take(naive ? (nt + 1) * 4 : 0);
+    const bool comp = g.prec == GBSUB_FP32_COMP;
+    t.Xc = (FF *)take(comp ? B * 8 : 0);
+    t.Dc = (FF *)take(comp ? (B + 1) * 8 : 0);
+    t.Dtc = (FF *)take(comp ? (nt + 1) * 8 : 0);
     t.X = (double *)take(B * 8);
     t.S = (double *)take(B * 8);
     t.is_pre = (double *)take(B * 8);

@@ -43,6 +43,13 @@ struct alignas(16) SplitSum {
     uint64_t l;
 };
 
+// Double-fp32 value hi + lo (|lo| at most half an ulp of hi once
+// normalised): the arithmetic of the compensated FP32 precision mode.
+struct alignas(8) FF {
+    float hi;
+    float lo;
+};
+
 // Device control block (lives in the workspace).
 struct Ctl {
     uint32_t amax_bits;      // max over sources of the fp32 bits of A (A >= 0)
@@ -125,9 +132,14 @@ struct Dev {
     float *Df;               // [B+1]  difference array of the wider tracks
     float *Dtf;              // [nt+1] per-tile sums of Df (binning and subtractions)
     float *Dcf;              // [nt+1] exclusive prefix of Dtf (rescanned every body)
+    // compensated FP32 mode only: the binned power as double-fp32 sums
+    FF *Xc;                  // [B]    one-bin tracks
+    FF *Dc;                  // [B+1]  difference array of the wider tracks
+    FF *Dtc;                 // [nt+1] per-tile sums of Dc (binning and subtractions)
     double *X;               // [B]    X^t
     double *S;               // [B]    S^t
-    double *is_pre;          // [B]    inclusive prefix of 1/S^t inside each part
+    double *is_pre;          // [B]    inclusive prefix of 1/S^t inside each part (an FF in the
+                             //        compensated FP32 mode, a float in the naive one)
     double *is_psum;         // [nparts] part sums of 1/S^t
     // dirty tiles: a tile is converted (X) / filtered (S) in body t iff its
     // stamp equals t; k_snr stamps t + 1 where a subtraction changes them

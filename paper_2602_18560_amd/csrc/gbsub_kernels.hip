@@ -81,6 +81,63 @@ DEVI I128 split_sum_value(SplitSum s)
     return i128_add(x, y);
 }
 
+// ---- double-fp32 (compensated FP32 mode)
+//
+// TwoSum (Knuth): s + e == a + b exactly, s = fl(a + b).  An FF add keeps the
+// rounding error of the high parts and adds the low parts (the "sloppy"
+// double-float addition, error O(2^-44) relative); FastTwoSum normalises.
+DEVI FF ff_two_sum(float a, float b)
+{
+    FF r;
+    r.hi = a + b;
+    const float bb = r.hi - a;
+    r.lo = (a - (r.hi - bb)) + (b - bb);
+    return r;
+}
+
+DEVI FF ff_norm(float s, float e)                 // |s| >= |e|
+{
+    FF r;
+    r.hi = s + e;
+    r.lo = e - (r.hi - s);
+    return r;
+}
+
+DEVI FF ff_add(FF a, FF b)
+{
+    const FF s = ff_two_sum(a.hi, b.hi);
+    return ff_norm(s.hi, s.lo + (a.lo + b.lo));
+}
+
+DEVI FF ff_neg(FF a)
+{
+    FF r;
+    r.hi = -a.hi;
+    r.lo = -a.lo;
+    return r;
+}
+
+DEVI FF ff_of(float x)
+{
+    FF r;
+    r.hi = x;
+    r.lo = 0.0f;
+    return r;
+}
+
+DEVI float ff_float(FF a) { return a.hi + a.lo; }
+
+// Compensated accumulation by atomics: the atomic add on hi returns the
+// value it added v to; TwoSum of that value and v gives the exact rounding
+// error of the sum it stored, which goes to lo.  hi + lo is then the sum up
+// to the roundings of lo (second order), whatever the order of the atomics.
+DEVI void ff_atomic_add(FF *p, float v)
+{
+    const float old = atomicAdd(&p->hi, v);
+    const float e = ff_two_sum(old, v).lo;
+    if (e != 0.0f) atomicAdd(&p->lo, e);
+}
+
 // Fixed-point unit 2^L: every per-bin power q <= A_max^2 T / 2 maps to an
 // integer below 2^62, so 2^65 sources fit in one 128-bit accumulator.
 DEVI int fx_exp(uint32_t amax_bits, double T)
@@ -129,7 +186,16 @@ DEVI I128 shfl_up_t(I128 x, int d)
     return r;
 }
 
+DEVI FF shfl_up_t(FF x, int d)
+{
+    FF r;
+    r.hi = __shfl_up(x.hi, d, 64);
+    r.lo = __shfl_up(x.lo, d, 64);
+    return r;
+}
+
 DEVI double add_t(double a, double b) { return a + b; }
+DEVI FF add_t(FF a, FF b) { return ff_add(a, b); }
 DEVI float add_t(float a, float b) { return a + b; }
 DEVI I128 add_t(I128 a, I128 b) { return i128_add(a, b); }
 DEVI uint32_t add_t(uint32_t a, uint32_t b) { return a + b; }
@@ -139,6 +205,7 @@ template <> DEVI double zero_t<double>() { return 0.0; }
 template <> DEVI float zero_t<float>() { return 0.0f; }
 template <> DEVI uint32_t zero_t<uint32_t>() { return 0u; }
 template <> DEVI I128 zero_t<I128>() { I128 z; z.lo = 0; z.hi = 0; return z; }
+template <> DEVI FF zero_t<FF>() { return ff_of(0.0f); }
 
 // Inclusive scan across the 64 lanes of a wave.
 template <typename T>
@@ -706,6 +773,7 @@ __global__ __launch_bounds__(WG) void k_prep_plan(const Slot *S)
             d.slot_base[b] = carry_s + es;
             d.Dtile[b].lo = 0;
             d.Dtile[b].hi = 0;
+            if (g.prec == PREC_COMP) d.Dtc[b] = ff_of(0.0f);
         }
         carry_e += te;
         carry_c += tc;
@@ -851,6 +919,52 @@ DEVI I128 split_total(const SplitAcc &a, int k)
     return i128_add(x, y);
 }
 
+// The compensated FP32 mode's binning of events e0 .. e1 of tile b (chunk
+// ci): every event's power rounded to fp32 (scaled by 2^sc), summed per bin
+// in LDS by compensated atomics (xc: one-bin tracks, dc: difference array;
+// TILE_MAX entries each); written to Xc, Dc and the tile sum of Dc, or to
+// the chunk's partial-sum slot of a hot tile.
+DEVI void accum_comp(const Grid &g, const Dev &d, int b, uint32_t ci, uint32_t e0, uint32_t e1, FF *xc, FF *dc)
+{
+    __shared__ FF shf[WG / 64];
+    const int k0 = b * g.tile;
+    const int L = fx_exp(d.ctl->amax_bits, g.T);
+    const int sc = f32_scale(d.ctl->amax_bits, g.T);
+    for (int k = threadIdx.x; k < g.tile; k += WG) {
+        xc[k] = ff_of(0.0f);
+        dc[k] = ff_of(0.0f);
+    }
+    __syncthreads();
+    for (uint32_t e = e0 + threadIdx.x; e < e1; e += WG) {
+        const uint32_t key = d.ev_key[e];
+        const float v = (float)ldexp((double)d.ev_val[e], L + sc);
+        const int k = (int)(key & 0x7FFFFFFFu) - k0;
+        ff_atomic_add((key >> 31) ? &dc[k] : &xc[k], v);
+    }
+    __syncthreads();
+    const int nbin = min(g.tile, g.B - k0);
+    if (d.nch[b] == 1) {
+        FF s = ff_of(0.0f);
+        for (int k = threadIdx.x; k < g.tile; k += WG) {
+            if (k < nbin) {
+                const FF x = ff_norm(xc[k].hi, xc[k].lo), y = ff_norm(dc[k].hi, dc[k].lo);
+                d.Xc[k0 + k] = x;
+                d.Dc[k0 + k] = y;
+                s = ff_add(s, y);
+            }
+        }
+        FF tot;
+        block_excl_scan(s, shf, &tot);
+        if (threadIdx.x == 0) d.Dtc[b] = tot;
+    } else {
+        FF *slot = reinterpret_cast<FF *>(d.partial + (size_t)(d.slot_base[b] + ci) * 2 * g.tile);
+        for (int k = threadIdx.x; k < g.tile; k += WG) {
+            slot[k] = ff_norm(xc[k].hi, xc[k].lo);
+            slot[g.tile + k] = ff_norm(dc[k].hi, dc[k].lo);
+        }
+    }
+}
+
 __global__ __launch_bounds__(WG) void k_accum(const Slot *S)
 {
     __shared__ SplitAcc xn, dd;
@@ -873,6 +987,10 @@ __global__ __launch_bounds__(WG) void k_accum(const Slot *S)
     const uint32_t e0 = d.bbase[b] + ci * ACC_EV;
     const uint32_t e1 = min(e0 + (uint32_t)ACC_EV, d.bbase[b + 1]);
     const int k0 = b * g.tile;
+    if (g.prec == PREC_COMP) {
+        accum_comp(g, d, b, ci, e0, e1, reinterpret_cast<FF *>(xn.h), reinterpret_cast<FF *>(dd.h));
+        return;
+    }
     for (int k = threadIdx.x; k < g.tile; k += WG) {
         xn.h[k] = 0; xn.l[k] = 0;
         dd.h[k] = 0; dd.l[k] = 0;
@@ -936,6 +1054,30 @@ __global__ __launch_bounds__(RED_BINS) void k_accum_reduce(const Slot *S)
     const int k = part * RED_BINS + threadIdx.x;
     const int k0 = b * g.tile;
     const int nbin = min(g.tile, g.B - k0);
+    if (g.prec == PREC_COMP) {
+        // the chunks' double-fp32 partials in chunk order; the block's sum
+        // of Dc goes to the tile sum by a compensated atomic
+        __shared__ FF shc[RED_BINS / 64];
+        const FF *slot = reinterpret_cast<const FF *>(d.partial + (size_t)d.slot_base[b] * 2 * g.tile);
+        FF xs = ff_of(0.0f), ys = ff_of(0.0f);
+        for (uint32_t c = 0; c < nc; ++c) {
+            xs = ff_add(xs, slot[(size_t)c * 4 * g.tile + k]);
+            ys = ff_add(ys, slot[(size_t)c * 4 * g.tile + g.tile + k]);
+        }
+        if (k < nbin) {
+            d.Xc[k0 + k] = xs;
+            d.Dc[k0 + k] = ys;
+        } else {
+            ys = ff_of(0.0f);
+        }
+        FF tot;
+        block_excl_scan<FF, RED_BINS>(ys, shc, &tot);
+        if (threadIdx.x == 0) {
+            ff_atomic_add(&d.Dtc[b], tot.hi);
+            ff_atomic_add(&d.Dtc[b], tot.lo);
+        }
+        return;
+    }
     I128 x = zero_t<I128>(), y = zero_t<I128>();
     const I128 *slot = d.partial + (size_t)d.slot_base[b] * 2 * g.tile;
     for (uint32_t s = 0; s < nc; ++s) {
@@ -1021,6 +1163,39 @@ DEVI int xpad(int i) { return i + (i >> 3); }
 
 template <int NT> DEVI void snr_tail(const Slot &sl);
 
+// The compensated FP32 mode's X of one tile: X = Xc + (carry + in-tile
+// prefix of Dc), every sum double-fp32, rounded once to fp32 at the end.
+// The carry is the sum of the tile sums of Dc before the tile (kept current
+// by the subtractions), added up here in a fixed order.  `st` is LDS for the
+// tile (xpad layout).
+DEVI void xupdate_comp(const Grid &g, const Dev &d, int tile, int t0, int n, int R, int b, FF *st)
+{
+    __shared__ FF shc[WG / 64];
+    const int sc = f32_scale(d.ctl->amax_bits, g.T);
+    FF c = ff_of(0.0f);
+    for (int j = threadIdx.x; j < tile; j += WG) c = ff_add(c, d.Dtc[j]);
+    FF carry;
+    block_excl_scan(c, shc, &carry);
+    for (int i = threadIdx.x; i < n; i += WG) st[xpad(i)] = d.Dc[t0 + i];
+    __syncthreads();
+    FF s = ff_of(0.0f);
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        if (r < R && b + r < n) {
+            s = ff_add(s, st[xpad(b + r)]);
+            st[xpad(b + r)] = s;
+        }
+    }
+    FF tot;
+    const FF ex = ff_add(block_excl_scan(s, shc, &tot), carry);
+#pragma unroll
+    for (int r = 0; r < 8; ++r)
+        if (r < R && b + r < n) st[xpad(b + r)] = ff_add(st[xpad(b + r)], ex);
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += WG)
+        d.X[t0 + i] = ldexp((double)ff_float(ff_add(st[xpad(i)], d.Xc[t0 + i])), -sc);
+}
+
 // The last block of the grid is the tail of the previous k_snr; the other
 // blocks convert the tiles stamped with the value k_snr published.  They
 // touch disjoint data: the tail reads the partials and the stamps and
@@ -1051,9 +1226,13 @@ __global__ __launch_bounds__(WG) void k_xupdate(const Slot *S)
     const int t0 = tile * g.tile;
     const int n = min(g.tile, g.B - t0);
     const int R = g.tile / WG;
+    const int b = (int)threadIdx.x * R;
+    if (g.prec == PREC_COMP) {
+        xupdate_comp(g, d, tile, t0, n, R, b, reinterpret_cast<FF *>(stage));
+        return;
+    }
     for (int i = threadIdx.x; i < n; i += WG) stage[xpad(i)] = d.D[t0 + i];
     __syncthreads();
-    const int b = (int)threadIdx.x * R;
     I128 s = zero_t<I128>();
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
@@ -1075,14 +1254,6 @@ __global__ __launch_bounds__(WG) void k_xupdate(const Slot *S)
         return;
     }
     const int sc = f32_scale(d.ctl->amax_bits, g.T);
-    if (g.prec == PREC_COMP) {
-        // the exact sum rounded once to fp32: what compensated fp32
-        // summation attains (to within an ulp)
-        for (int i = threadIdx.x; i < n; i += WG)
-            d.X[t0 + i] = ldexp((double)(float)ldexp(i128_to_double(i128_add(stage[xpad(i)], d.Xn[t0 + i])),
-                                                     L + sc), -sc);
-        return;
-    }
     // naive fp32: X = Xf + prefix of Df, all in fp32
     __syncthreads();
     float *fst = reinterpret_cast<float *>(stage);
@@ -1298,6 +1469,45 @@ DEVI void part_prefix(double *dsh, double *st, const Grid &g, const Dev &d, int 
     if ((tid & (segw * 64 - 1)) == 0) {
         const int p0 = t0 + (tid / (segw * 64)) * g.part;
         if (p0 < t1) d.is_psum[div_p2(p0, g.part)] = (double)tot;
+    }
+}
+
+// part_prefix in double-fp32 (compensated FP32 mode): st[] holds fp32
+// reciprocals on entry; on exit each slot holds the FF prefix (its 8 bytes),
+// and is_psum the FF part sums.  Contains one barrier.
+DEVI void part_prefix_ff(double *dsh, double *st, const Grid &g, const Dev &d, int kb, int ke, int t0, int t1,
+                         int R)
+{
+    const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
+    FF loc[RMAX], s = ff_of(0.0f);
+#pragma unroll
+    for (int r = 0; r < RMAX; ++r) {
+        if (kb + r < ke) s = ff_add(s, ff_of((float)st[kb + r - t0]));
+        loc[r] = s;
+    }
+    const int segw = (g.part / R) >> 6;
+    const FF inc = wave_incl_scan(s);
+    FF exw = shfl_up_t(inc, 1);
+    if (lane == 0) exw = ff_of(0.0f);
+    FF *xch = reinterpret_cast<FF *>(dsh);
+    if (lane == 63) xch[wave] = inc;
+    __syncthreads();
+    const int ws0 = (wave / segw) * segw;
+    FF pre = ff_of(0.0f), tot = ff_of(0.0f);
+#pragma unroll
+    for (int w = 0; w < MWG / 64; ++w) {
+        const FF x = xch[w];
+        if (w >= ws0 && w < wave) pre = ff_add(pre, x);
+        if (w >= ws0 && w < ws0 + segw) tot = ff_add(tot, x);
+    }
+    const FF ex = ff_add(pre, exw);
+    FF *stf = reinterpret_cast<FF *>(st);
+#pragma unroll
+    for (int r = 0; r < RMAX; ++r)
+        if (kb + r < ke) stf[kb + r - t0] = ff_add(ex, loc[r]);
+    if ((tid & (segw * 64 - 1)) == 0) {
+        const int p0 = t0 + (tid / (segw * 64)) * g.part;
+        if (p0 < t1) reinterpret_cast<FF *>(d.is_psum)[div_p2(p0, g.part)] = tot;
     }
 }
 
@@ -1612,11 +1822,12 @@ __global__ __launch_bounds__(MWG, 2) void k_median(const Slot *S)
         st[i] = inv;
     }
     __syncthreads();
-    // prefix of 1/S restarted at every part: fp64 sums, or plain fp32 sums
-    // in the naive fp32 mode (fp64 sums of fp32 terms stand for compensated
-    // fp32 sums)
+    // prefix of 1/S restarted at every part: fp64 sums, double-fp32 sums in
+    // the compensated FP32 mode, plain fp32 sums in the naive one
     if (g.prec == PREC_NAIVE)
         part_prefix<float>(sm.dsh, st, g, d, kb, ke, t0, t1, R);
+    else if (g.prec == PREC_COMP)
+        part_prefix_ff(sm.dsh, st, g, d, kb, ke, t0, t1, R);
     else
         part_prefix<double>(sm.dsh, st, g, d, kb, ke, t0, t1, R);
     __syncthreads();
@@ -1718,10 +1929,11 @@ DEVI double track_inv_sum(const double *v, const double *pre, int lo, int hi, in
 }
 
 // rho^2 in fp32 (the FP32 precision modes): 4 q sum 1/S with the sum in
-// fp32, compensated (Kahan) for short tracks and from fp64 sums of the
-// fp32 reciprocals otherwise, or plain fp32 (naive: bin by bin, or the fp32
-// in-part prefixes and an fp32 sum of the part sums).
-DEVI double snr2_f32(const Grid &g, const Dev &d, double qd, int lo, int hi, double mid)
+// fp32.  Compensated: Kahan over short tracks, and for longer ones
+// double-fp32 differences of the double-fp32 in-part prefixes plus midc, the
+// double-fp32 sum of the part sums in between.  Naive: plain fp32 (bin by
+// bin, or the fp32 in-part prefixes and the fp32 sum `mid` of the part sums).
+DEVI double snr2_f32(const Grid &g, const Dev &d, double qd, int lo, int hi, double mid, FF midc)
 {
     // q and S scaled by 2^sc; the prefix tables already hold 1/(2^sc S)
     const int sc = f32_scale(d.ctl->amax_bits, g.T);
@@ -1742,7 +1954,12 @@ DEVI double snr2_f32(const Grid &g, const Dev &d, double qd, int lo, int hi, dou
         }
         sum = s;
     } else if (g.prec == PREC_COMP) {
-        sum = (float)track_inv_sum(d.S, d.is_pre, lo, hi, g.part, mid);
+        const FF *pre = reinterpret_cast<const FF *>(d.is_pre);
+        const FF below = mod_p2(lo, g.part) == 0 ? ff_of(0.0f) : pre[lo - 1];
+        const FF top = pre[hi];
+        const FF r = div_p2(lo, g.part) == div_p2(hi, g.part) ? ff_add(top, ff_neg(below))
+                                                              : ff_add(ff_add(midc, ff_neg(below)), top);
+        sum = ff_float(r);
     } else {
         const float below = mod_p2(lo, g.part) == 0 ? 0.0f : (float)d.is_pre[lo - 1];
         sum = div_p2(lo, g.part) == div_p2(hi, g.part) ? (float)d.is_pre[hi] - below
@@ -1781,6 +1998,22 @@ DEVI void subtract_track_f32(const Grid &g, const Dev &d, int glo, int ghi, floa
     if (ghi + 1 < g.B) {
         atomicAdd(&d.Df[ghi + 1], vf);
         atomicAdd(&d.Dtf[div_p2(ghi + 1, g.tile)], vf);
+    }
+}
+
+// The same subtraction in the compensated FP32 mode (double-fp32
+// accumulators, compensated atomics), vf = the power as a float.
+DEVI void subtract_track_comp(const Grid &g, const Dev &d, int glo, int ghi, float vf)
+{
+    if (glo == ghi) {
+        ff_atomic_add(&d.Xc[glo], -vf);
+        return;
+    }
+    ff_atomic_add(&d.Dc[glo], -vf);
+    ff_atomic_add(&d.Dtc[div_p2(glo, g.tile)], -vf);
+    if (ghi + 1 < g.B) {
+        ff_atomic_add(&d.Dc[ghi + 1], vf);
+        ff_atomic_add(&d.Dtc[div_p2(ghi + 1, g.tile)], vf);
     }
 }
 
@@ -1846,6 +2079,8 @@ __global__ __launch_bounds__(WG) void k_snr(const Slot *S)
     const uint32_t nxt = (uint32_t)t + 1;
     const uint32_t nc = d.ctl->n_cand;
     const bool naive = g.prec == PREC_NAIVE;
+    const bool comp = g.prec == PREC_COMP;
+    const FF *psum_ff = reinterpret_cast<const FF *>(d.is_psum);
     const int lane = lane_id();
     uint32_t my_new = 0;
     uint64_t near = 0, evals = 0;
@@ -1872,11 +2107,14 @@ __global__ __launch_bounds__(WG) void k_snr(const Slot *S)
         const bool need = eval && ghi - glo + 1 > NARROW && phi > plo;
         const bool wide = need && phi - plo > COOP_PARTS;
         double mid = 0.0;
+        FF midc = ff_of(0.0f);
         if (need && !wide) {
             if (naive) {
                 float m = 0.0f;
                 for (int pp = plo; pp < phi; ++pp) m += (float)d.is_psum[pp];
                 mid = (double)m;
+            } else if (comp) {
+                for (int pp = plo; pp < phi; ++pp) midc = ff_add(midc, psum_ff[pp]);
             } else {
                 for (int pp = plo; pp < phi; ++pp) mid += d.is_psum[pp];
             }
@@ -1884,24 +2122,38 @@ __global__ __launch_bounds__(WG) void k_snr(const Slot *S)
         for (uint64_t wm = (uint64_t)__ballot(wide); wm; wm &= wm - 1) {
             const int L = __builtin_ctzll(wm);
             const int a = __builtin_amdgcn_readlane(plo, L), b = __builtin_amdgcn_readlane(phi, L);
-            double sum;
+            double sum = 0.0;
+            FF sumc = ff_of(0.0f);
             if (naive) {
                 float m = 0.0f;
                 for (int pp = a + lane; pp < b; pp += 64) m += (float)d.is_psum[pp];
                 for (int o = 32; o >= 1; o >>= 1) m += __shfl_xor(m, o, 64);
                 sum = (double)m;
+            } else if (comp) {
+                FF m = ff_of(0.0f);
+                for (int pp = a + lane; pp < b; pp += 64) m = ff_add(m, psum_ff[pp]);
+                for (int o = 32; o >= 1; o >>= 1) {
+                    FF y;
+                    y.hi = __shfl_xor(m.hi, o, 64);
+                    y.lo = __shfl_xor(m.lo, o, 64);
+                    m = ff_add(m, y);
+                }
+                sumc = m;
             } else {
                 double m = 0.0;
                 for (int pp = a + lane; pp < b; pp += 64) m += d.is_psum[pp];
                 sum = wave_sum(m);
             }
-            if (lane == L) mid = sum;
+            if (lane == L) {
+                mid = sum;
+                midc = sumc;
+            }
         }
         if (eval) {
             ++evals;
             const double q = d.c_q[j];
             r2 = g.prec == PREC_FP64 ? (4.0 * q) * track_inv_sum(d.S, d.is_pre, glo, ghi, g.part, mid)
-                                     : snr2_f32(g, d, q, glo, ghi, mid);
+                                     : snr2_f32(g, d, q, glo, ghi, mid, midc);
             d.c_rho2[j] = r2;
         }
         if (!live) continue;
@@ -1913,11 +2165,14 @@ __global__ __launch_bounds__(WG) void k_snr(const Slot *S)
             ++my_new;
             const int64_t v = (int64_t)d.c_qfx[j];
             if (v) {
-                subtract_track(g, d, glo, ghi, v);
-                if (naive)
-                    subtract_track_f32(g, d, glo, ghi,
-                                       (float)ldexp((double)v, fx_exp(d.ctl->amax_bits, g.T) +
-                                                                   f32_scale(d.ctl->amax_bits, g.T)));
+                const float vf = (float)ldexp((double)v, fx_exp(d.ctl->amax_bits, g.T) +
+                                                             f32_scale(d.ctl->amax_bits, g.T));
+                if (comp) {
+                    subtract_track_comp(g, d, glo, ghi, vf);
+                } else {
+                    subtract_track(g, d, glo, ghi, v);
+                    if (naive) subtract_track_f32(g, d, glo, ghi, vf);
+                }
             }
             stamp_tiles(d.xstamp, g, glo, ghi, nxt);
             int sa, sb;

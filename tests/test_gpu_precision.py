@@ -1,7 +1,9 @@
 """FP32 precision modes of the loop (gbsub_config.precision) against the FP64
 oracle.  FP64 itself is the parity bar (test_gpu_parity.py); these modes are
-measured, not pinned: compensated FP32 must stay within the error that fp32
-rounding explains, naive FP32 must run to completion on the same candidates.
+measured, not pinned: compensated FP32 (double-fp32 sums) must stay within the error that fp32
+rounding explains, with resolve decisions that differ from the oracle's
+only within that error of the threshold; naive FP32 must run to completion
+on the same candidates.
 """
 import sys
 
@@ -40,6 +42,31 @@ def flips(ids, ro, cat):
     return len(ref ^ got)
 
 
+# Bars of the compensated FP32 mode (double-fp32 sums, fp32 S and 1/S):
+# S = C med + S_instr takes about four fp32 roundings (the scaled inputs,
+# the product, the sum: < 5 * 2^-24 = 3e-7); the double-fp32 bin sums and
+# prefixes add errors of order 2^-44 of the sums they carry.  rho^2 = 4 q
+# sum 1/S takes the same S errors plus the roundings of q, of 1/S and of the
+# final product.  1e-6 covers both with a margin.  A resolve decision can
+# then differ from the oracle's only for a source whose oracle rho lies
+# within 1e-6 of the threshold (rho^2 within 2e-6).
+S_MAX = 1e-6
+RHO2_MAX = 1e-6
+
+
+def _near_band_sources(cat, run):
+    """Sources whose oracle rho^2 is within 2e-6 relative of rho_th^2 at some
+    evaluation (the only ones the FP32 bar lets flip)."""
+    ref = O.run(cat, O.make_config(run), spectra=False, trace=True, trace_fields=("cand", "rho2"))
+    th2 = run.snr_threshold ** 2
+    near = set()
+    for rec in ref.trace:
+        ev = rec["rho2"] >= 0
+        close = ev & (np.abs(rec["rho2"] / th2 - 1.0) <= 2e-6)
+        near.update(cat.id[rec["cand"][close]].tolist())
+    return ref, near
+
+
 @pytest.mark.parametrize("which", ["catalog_1e4", "dense"])
 def test_fp32_compensated_within_fp32_rounding(which):
     cat, run = catalog_1e4() if which == "catalog_1e4" else dense()
@@ -47,15 +74,15 @@ def test_fp32_compensated_within_fp32_rounding(which):
     ro = O.run(cat, O.make_config(run))
     s, S, (ids, it), (cids, cit, cr2) = gpu_run(cat, run, precision=G.FP32_COMP)
     assert s.n_candidates == ro.n_candidates
-    # S carries one fp32 rounding of X, of the median product and of the sum
     rel = np.abs(S - ro.S_final) / ro.S_final
+    ref, near = _near_band_sources(cat, run)
+    flipped = set(cat.id[ro.iter_of >= 0].tolist()) ^ set(ids.tolist())
     say(f"  S rel err max {rel.max():.2e} median {np.median(rel):.2e}; "
-        f"flips {flips(ids, ro, cat)} of {int((ro.iter_of >= 0).sum())}")
-    assert np.median(rel) < 1e-6
-    assert flips(ids, ro, cat) <= max(2, (ro.iter_of >= 0).sum() // 1000)
-    # rho^2 in fp32: the candidates that were evaluated in the same bodies
-    # agree to fp32 accuracy
-    ref = O.run(cat, O.make_config(run), spectra=False, trace=True, trace_fields=("cand", "rho2"))
+        f"flips {len(flipped)} of {int((ro.iter_of >= 0).sum())} ({len(near)} in the near band)")
+    assert rel.max() < S_MAX
+    assert flipped <= near
+    # rho^2 of every candidate at its last evaluation (the same bodies when
+    # no decision flipped)
     last = np.full(ref.trace[0]["cand"].shape[0], np.nan)
     for rec in ref.trace:
         ev = rec["rho2"] >= 0
@@ -63,8 +90,9 @@ def test_fp32_compensated_within_fp32_rounding(which):
     order = np.argsort(ref.trace[0]["cand"])
     np.testing.assert_array_equal(cids, cat.id[ref.trace[0]["cand"][order]])
     r = np.abs(cr2 - last[order]) / last[order]
-    say(f"  rho^2 rel err median {np.median(r):.2e}")
-    assert np.median(r) < 1e-5
+    say(f"  rho^2 rel err max {r.max():.2e} median {np.median(r):.2e}")
+    if not flipped:
+        assert r.max() < RHO2_MAX
 
 
 def test_fp32_naive_runs_on_the_same_candidates():
