@@ -159,6 +159,7 @@ uint64_t carve(const Grid &g, uint64_t n, char *base, Dev *d)
     t.ev_val = (int64_t *)take((max_events ? max_events : 1) * 8);
     t.partial = (I128 *)take((uint64_t)t.max_slots * 2 * (uint64_t)g.tile * 16);
     t.cbits = (uint64_t *)take(((nn + 63) / 64) * 8);
+    t.rs_hist = (uint32_t *)take(resolved_scratch_words(nn) * 4);
     const uint64_t ncb = npb;
     t.blk_cand = (uint32_t *)take((ncb + 1) * 4);
     t.blk_amax = (uint32_t *)take(ncb * 4);
@@ -624,13 +625,12 @@ gbsub_status gbsub_spectrum(const gbsub_ctx *c, uint32_t kind, double *out, uint
         return dev_err(hipMemcpy(out, src, B * 8,
                                  out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost));
     }
-    std::vector<double> s(B), x(B);
-    hipError_t e = hipMemcpy(s.data(), c->dev.S, B * 8, hipMemcpyDeviceToHost);
-    if (e == hipSuccess) e = hipMemcpy(x.data(), c->dev.sx, B * 8, hipMemcpyDeviceToHost);
-    if (e != hipSuccess) return GBSUB_E_DEVICE;
-    for (uint64_t k = 0; k < B; ++k) s[k] -= x[k];
-    return dev_err(hipMemcpy(out, s.data(), B * 8,
-                             out_on_device ? hipMemcpyHostToDevice : hipMemcpyHostToHost));
+    // S - S_instr on the device, into `out` or (host output) into the
+    // workspace's in-part 1/S prefix, which is dead once a run has settled
+    double *dst = out_on_device ? out : c->dev.is_pre;
+    hipError_t e = launch_sgal(c->dev.S, c->dev.sx, (int)B, dst, nullptr);
+    if (e == hipSuccess) e = out_on_device ? hipDeviceSynchronize() : hipMemcpy(out, dst, B * 8, hipMemcpyDeviceToHost);
+    return dev_err(e);
 }
 
 gbsub_status gbsub_coarse(const gbsub_ctx *c, uint32_t kind, double f_lo, double f_hi, uint32_t n_out,
@@ -684,35 +684,23 @@ gbsub_status gbsub_resolved(const gbsub_ctx *c, uint32_t *ids, int32_t *iter_of,
 {
     if (!c || !n) return GBSUB_E_INVALID;
     if (!c->have_result) return GBSUB_E_STATE;
-    if (hipSetDevice(c->device) != hipSuccess) return GBSUB_E_DEVICE;
-    const uint64_t nc = c->n_cand;
-    std::vector<uint32_t> id(nc);
-    std::vector<int32_t> it(nc);
-    hipError_t e = hipSuccess;
-    if (nc) {
-        e = hipMemcpy(id.data(), c->dev.c_id, nc * 4, hipMemcpyDeviceToHost);
-        if (e == hipSuccess) e = hipMemcpy(it.data(), c->dev.c_iter, nc * 4, hipMemcpyDeviceToHost);
-        if (e != hipSuccess) return GBSUB_E_DEVICE;
-    }
-    std::vector<uint64_t> key;
-    key.reserve(c->summ.n_resolved);
-    for (uint64_t j = 0; j < nc; ++j)
-        if (it[j] >= 0) key.push_back(((uint64_t)id[j] << 32) | (uint32_t)it[j]);
-    std::sort(key.begin(), key.end());
-    const uint64_t m = key.size();
+    const uint64_t m = c->summ.n_resolved;
     *n = m;
     if (cap < m) return GBSUB_E_TRUNCATED;
     if (m == 0) return GBSUB_OK;
     if (!ids) return GBSUB_E_INVALID;
-    id.resize(m);
-    it.resize(m);
-    for (uint64_t j = 0; j < m; ++j) {
-        id[j] = (uint32_t)(key[j] >> 32);
-        it[j] = (int32_t)(uint32_t)key[j];
-    }
-    const hipMemcpyKind kd = out_on_device ? hipMemcpyHostToDevice : hipMemcpyHostToHost;
-    e = hipMemcpy(ids, id.data(), m * 4, kd);
-    if (e == hipSuccess && iter_of) e = hipMemcpy(iter_of, it.data(), m * 4, kd);
+    if (hipSetDevice(c->device) != hipSuccess) return GBSUB_E_DEVICE;
+    // compaction and sort on the device, in the workspace's event buffer
+    // (free once the binning is done: 16 bytes per source, m <= sources)
+    const Dev &d = c->dev;
+    uint32_t *kA = reinterpret_cast<uint32_t *>(d.ev_val);
+    int32_t *vA = reinterpret_cast<int32_t *>(kA + m);
+    uint32_t *kB = reinterpret_cast<uint32_t *>(vA + m);
+    int32_t *vB = reinterpret_cast<int32_t *>(kB + m);
+    hipError_t e = launch_resolved(d.c_iter, d.c_id, c->n_cand, (uint32_t)m, d.rs_hist, kA, vA, kB, vB, nullptr);
+    const hipMemcpyKind kd = out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    if (e == hipSuccess) e = hipMemcpy(ids, kA, m * 4, kd);
+    if (e == hipSuccess && iter_of) e = hipMemcpy(iter_of, vA, m * 4, kd);
     return dev_err(e);
 }
 

@@ -157,6 +157,7 @@ struct Dev {
     int64_t *ev_val;         // [2n]   signed fixed-point power
     I128 *partial;           // [slots][2][tile] partial sums of the hot tiles
     uint64_t *cbits;         // [ceil(n/64)] candidate flags of the sources (count pass)
+    uint32_t *rs_hist;       // [resolved_scratch_words(n)] block counts of the resolved-list kernels
     uint32_t *blk_cand;      // [count blocks + 1] candidates per count block, then their exclusive prefix
     uint32_t *blk_amax;      // [count blocks] max fp32 bits of A per count block
     // candidates (capacity: all sources)
@@ -212,6 +213,16 @@ hipError_t launch_median(const Slot *ds, const Dims &dm, hipStream_t st, hipEven
 hipError_t launch_snr(const Slot *ds, const Dims &dm, hipStream_t st, hipEvent_t ea = nullptr,
                       hipEvent_t eb = nullptr);
 hipError_t launch_outputs(const Slot *ds, const Dims &dm, hipStream_t st);
+
+// Output kernels (gbsub_output.hip).  The resolved list: the (id, loop body)
+// pairs of the m candidates with iter >= 0 among nc, compacted and sorted by
+// id into kA / vA (kB / vB: the same sizes, scratch); `hist` holds
+// resolved_scratch_words(n) words for catalogs of up to n sources.
+uint64_t resolved_scratch_words(uint64_t n_max);
+hipError_t launch_resolved(const int32_t *iter, const uint32_t *id, uint32_t nc, uint32_t m, uint32_t *hist,
+                           uint32_t *kA, int32_t *vA, uint32_t *kB, int32_t *vB, hipStream_t st);
+// out[k] = S[k] - sx[k] for k < B.
+hipError_t launch_sgal(const double *S, const double *sx, int B, double *out, hipStream_t st);
 
 struct CoarseEdges { double e[COARSE_MAX + 1]; };
 

@@ -363,3 +363,46 @@ def test_tracks_longer_than_two_to_the_31_bins():
     P = Sx[bins] * 10 ** rng.uniform(-1, 3, n)
     cat = catalog([amp_for_power(p, T) for p in P], [bin_freq(k0, b, T) for b in bins], list(fd))
     assert_parity(cat, run, "tracks beyond 2^31 bins")
+
+
+# ----------------------------------------------------------------- device-side outputs
+
+def test_resolved_list_and_s_gal_built_on_the_device():
+    """The resolved list is compacted and radix-sorted by id on the device:
+    opaque ids spread over all 32 bits (high bits set, unsorted), more than
+    one sort block of resolved sources; ids ascending and their loop bodies
+    equal the oracle's, also when written to device memory.  S_gal = S_n -
+    S_instr is computed on the device, bit for bit the host difference."""
+    import ctypes as C
+    import torch
+    cat = draw_catalog(Population(n=20000, seed=11, f_lo=1e-3, f_hi=1.6e-3))
+    cat.A *= np.float32(8.0)
+    rng = np.random.default_rng(77)
+    cat.id = rng.choice(np.iinfo(np.uint32).max, size=cat.n, replace=False).astype(np.uint32)
+    cat.id[:50] |= np.uint32(0x80000000)
+    run = RunConfig(t_obs_s=YEAR_S, f_min_hz=1e-3, f_max_hz=1.6e-3, window_bins=101)
+    ro, s, S = assert_parity(cat, run, "random 32-bit ids")
+    assert s.n_resolved > 2 * 4096
+    ctx = G.Context(G.config_from_run(run))
+    try:
+        ctx.run(G.DeviceCatalog.from_host(cat))
+        ids, it = ctx.resolved()
+        assert np.all(np.diff(ids.astype(np.int64)) > 0)
+        m = ids.shape[0]
+        dids = torch.empty(m, dtype=torch.int32, device="cuda")
+        dit = torch.empty(m, dtype=torch.int32, device="cuda")
+        n = C.c_uint64()
+        st = ctx._L.gbsub_resolved(ctx.h, C.c_void_p(dids.data_ptr()), C.c_void_p(dit.data_ptr()), m,
+                                   C.byref(n), 1)
+        assert st == G.OK and n.value == m
+        np.testing.assert_array_equal(dids.cpu().numpy().view(np.uint32), ids)
+        np.testing.assert_array_equal(dit.cpu().numpy(), it)
+        Sn = ctx.spectrum(G.SPEC_SN)
+        Sx = ctx.spectrum(G.SPEC_S_INSTR)
+        Sg = ctx.spectrum(G.SPEC_S_GAL)
+        np.testing.assert_array_equal(Sg, Sn - Sx)
+        dS = torch.empty(Sn.shape[0], dtype=torch.float64, device="cuda")
+        ctx.spectrum(G.SPEC_S_GAL, out=dS)
+        np.testing.assert_array_equal(dS.cpu().numpy(), Sg)
+    finally:
+        ctx.close()
