@@ -199,14 +199,25 @@ def bench_batch(args):
     from paper_2602_18560_amd import gbsub as G
     torch.cuda.set_device(0)
     dcs = [G.DeviceCatalog.from_host(c) for c in cats]
-    ctxs = [G.Context(G.config_from_run(run)) for _ in cats]
+    schedule, table = {"tile_bins": 0, "split_blocks": 0}, []
+    if not args.no_tune_batch:
+        # one grid class here: the tuner times the whole batch per setting
+        from paper_2602_18560_amd.autotune import tune_batch
+        log("[batch] tuning the batch schedule (tile size, shared split budget)")
+        schedule, table = tune_batch(dcs, [run] * len(dcs), chunk=args.chunk, log=log)
+        log(f"[batch] schedule {schedule}")
+    # plain runs keep the library's default schedule (the single-catalog one)
+    pctxs = [G.Context(G.config_from_run(run)) for _ in cats]
+    ctxs = [G.Context(G.config_from_run(run, **schedule)) for _ in cats]
     for c, d in zip(ctxs, dcs):
         c.ensure_workspace(d.n)
+    for c, cb in zip(pctxs, ctxs):
+        c.workspace = cb.workspace               # one workspace per catalog, used in turn
     torch.cuda.synchronize()
     n_tot = sum(d.n for d in dcs)
 
     def plain():
-        out = [c.run(d) for c, d in zip(ctxs, dcs)]
+        out = [c.run(d) for c, d in zip(pctxs, dcs)]
         torch.cuda.synchronize()
         return out
 
@@ -255,7 +266,8 @@ def bench_batch(args):
                                "W = 1001, one shared batch, graph-captured loop bodies; catalogs "
                                "resident in HBM",
                    "n_catalogs": len(dcs), "n_sources": n_tot, "chunk": args.chunk,
-                   "n_iter": [s.n_iter for s in sb]},
+                   "n_iter": [s.n_iter for s in sb], "batch_schedule": schedule,
+                   "tuner_table_ms": [(t, sp, ms * 1e3) for t, sp, ms in table]},
         "plain": {"catalogs_per_h": len(dcs) / wp * 3600.0, "ms": wp * 1e3},
         "speedup_vs_plain": wp / wb,
         "binary_iterations_per_s": {"batched": bi / wb, "plain": bi / wp},
@@ -266,9 +278,15 @@ def bench_batch(args):
 
 def bench_serve(args):
     """Continuous batching of a Poisson job stream (saturated run first).
-    With --gpu-gen the jobs' catalogs come from the population model and are
-    drawn on the GPU at admission (inside the latency; no host catalog)."""
+    Host catalogs: a pool of distinct catalogs drawn ahead into pinned host
+    memory, job j running catalog j mod pool with its own T and W (every job
+    still copies its catalog host-to-device at admission).  With --gpu-gen
+    the jobs' catalogs come from the population model and are drawn on the GPU
+    at admission (inside the latency; no host catalog).  Schedules are tuned
+    per grid class on batches of pool catalogs; a sample of served jobs is
+    re-run alone through gbsub_run and compared bit for bit."""
     import dataclasses
+    import numpy as np
     if args.gpu_gen:
         from paper_2602_18560_amd.inputs import model_job_stream
         jobs = model_job_stream(args.jobs, rate_hz=1.0)
@@ -276,35 +294,82 @@ def bench_serve(args):
     else:
         from paper_2602_18560_amd.inputs import job_stream, draw_catalogs
         jobs = job_stream(args.jobs, rate_hz=1.0)
-        log(f"[serve] drawing {len(jobs)} catalogs, {sum(j.population.n for j in jobs):.3e} sources")
+        npool = min(args.pool, len(jobs))
+        log(f"[serve] drawing a pool of {npool} catalogs, "
+            f"{sum(j.population.n for j in jobs[:npool]):.3e} sources")
         t0 = time.perf_counter()
-        cats = draw_catalogs([j.population for j in jobs])
+        cats = draw_catalogs([j.population for j in jobs[:npool]])
         log(f"[serve] drawn in {time.perf_counter() - t0:.1f} s")
     import torch
+    from paper_2602_18560_amd import gbsub as G
     from paper_2602_18560_amd import serve as SV
+    from paper_2602_18560_amd.autotune import grid_class, tune_batch
     torch.cuda.set_device(0)
+    schedules = {}
     if not args.gpu_gen:
         pinned = [SV.pin_catalog(c) for c in cats]
+        if not args.no_tune_batch:
+            classes = {}
+            for j in jobs[:npool]:
+                classes.setdefault(grid_class(j.run), []).append(j.index)
+            for key, idx in classes.items():
+                idx = sorted(idx, key=lambda i: cats[i].n)[-8:]          # the 8 largest of the class
+                dcs = [G.DeviceCatalog.from_host(cats[i]) for i in idx]
+                log(f"[serve] tuning grid class T = {key[0] / 31557600:.0f} yr on {len(idx)} catalogs")
+                schedules[key], _ = tune_batch(dcs, [jobs[i].run for i in idx], chunk=args.chunk)
+                log(f"[serve]   schedule {schedules[key]}")
+                del dcs
+                torch.cuda.empty_cache()
         del cats
 
     def requests(times):
         if args.gpu_gen:
             return [SV.model_request(dataclasses.replace(j, arrival_s=t)) for j, t in zip(jobs, times)]
-        return [SV.Request(j.index, t, *p, run=j.run) for j, t, p in zip(jobs, times, pinned)]
+        return [SV.Request(j.index, t, *pinned[j.index % npool], run=j.run) for j, t in zip(jobs, times)]
 
+    budget = args.budget_gb * 2**30
     log("[serve] warmup")
-    SV.serve(requests([0.0] * min(4, len(jobs)))[:4], args.slots, args.budget_gb * 2**30, args.chunk)
-    log("[serve] saturated run (every job queued at t = 0)")
-    done, srv = SV.serve(requests([0.0] * len(jobs)), args.slots, args.budget_gb * 2**30, args.chunk)
+    SV.serve(requests([0.0] * min(4, len(jobs)))[:4], args.slots, budget, args.chunk, schedules=schedules)
+    log(f"[serve] saturated run (every job queued at t = 0), {len(jobs)} jobs")
+    prog = lambda k, n: log(f"[serve]   {k} / {n} jobs done")
+    done, srv = SV.serve(requests([0.0] * len(jobs)), args.slots, budget, args.chunk, schedules=schedules,
+                         progress=prog)
     makespan = max(c.done_s for c in done)
     cap = len(done) / makespan
     rate = args.load * cap
     log(f"[serve] capacity {cap:.2f} jobs/s; Poisson run at {rate:.2f} jobs/s")
     times = [j.arrival_s / rate for j in jobs]          # unit-rate arrivals, rescaled
-    done2, srv2 = SV.serve(requests(times), args.slots, args.budget_gb * 2**30, args.chunk)
+    # a sample of jobs whose served results are kept: the smallest ones of
+    # each grid class and the largest job
+    by_n = sorted(range(len(jobs)), key=lambda i: (jobs[i].n if args.gpu_gen else jobs[i % npool].population.n))
+    check = set(by_n[:max(args.check_jobs - 1, 0)] + by_n[-1:]) if args.check_jobs else set()
+    done2, srv2 = SV.serve(requests(times), args.slots, budget, args.chunk, schedules=schedules,
+                           keep_jobs=check, progress=prog)
     bad = [c for c in done + done2 if c.status != 0]
     if bad:
         raise RuntimeError(f"{len(bad)} jobs did not settle")
+    # served == alone, bit for bit, on the sample
+    checked = []
+    reqs = {r.index: r for r in requests(times)}
+    for c in done2:
+        if c.context is None:
+            continue
+        r = reqs[c.index]
+        ctx = G.Context(G.config_from_run(r.run, **schedules.get(grid_class(r.run), {})))
+        if args.gpu_gen:
+            dc = G.generate(r.model, r.seed, r.n)
+        else:
+            dc = G.DeviceCatalog(*(x.to("cuda") for x in (r.A, r.f, r.fdot, r.ids)))
+        s = ctx.run(dc)
+        same = (s.n_iter == c.summary.n_iter and s.n_resolved == c.summary.n_resolved
+                and np.array_equal(ctx.spectrum(G.SPEC_SN), c.context.spectrum(G.SPEC_SN))
+                and all(np.array_equal(a, b) for a, b in zip(ctx.resolved(), c.context.resolved())))
+        checked.append({"job": c.index, "n": c.n_sources, "t_obs_yr": round(r.run.t_obs_s / 31557600),
+                        "n_iter": s.n_iter, "equal_alone": bool(same)})
+        ctx.close()
+        c.context.close()
+    if not all(x["equal_alone"] for x in checked):
+        raise RuntimeError(f"served results differ from runs alone: {checked}")
     lat = [c.latency_s for c in done2]
     span2 = max(c.done_s for c in done2) - min(c.arrival_s for c in done2)
     hb, hms = srv2.h2d_stats()
@@ -315,21 +380,26 @@ def bench_serve(args):
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": (f"{len(jobs)} jobs, Poisson arrivals at {args.load}x the saturated "
-                                "rate, N log-uniform in [1e5, 3e7], T in {1,2,4} yr with W = "
-                                "251/501/1001 " + (
-                                    "(meta seed 7, job j generator seed 7000+j); catalogs drawn on "
-                                    "the GPU from the population model at admission, hyperparameters "
-                                    "uniform in the prior box, generation inside the latency"
+                                "rate, T in {1,2,4} yr with W = 251/501/1001 " + (
+                                    "(meta seed 7, job j generator seed 7000+j); catalogs of N "
+                                    "log-uniform in [1e5, 3e7] drawn on the GPU from the population "
+                                    "model at admission, hyperparameters uniform in the prior box, "
+                                    "generation inside the latency"
                                     if args.gpu_gen else
-                                    "(meta seed 5, job j seed 5000+j); catalogs drawn ahead into "
-                                    "pinned host memory, H2D inside the latency")),
-                   "slots": args.slots, "budget_gb": args.budget_gb, "chunk": args.chunk},
+                                    f"(meta seed 5); job j runs catalog j mod {npool} of a pool drawn "
+                                    "ahead into pinned host memory (pool catalog i: the job stream's "
+                                    "population i, N log-uniform in [1e5, 3e7], seed 5000+i); H2D "
+                                    "inside the latency")),
+                   "slots": args.slots, "budget_gb": args.budget_gb, "chunk": args.chunk,
+                   "schedules": {f"{k[0] / 31557600:.0f}yr_W{k[3]}": v for k, v in schedules.items()}},
         "latency_ms": {"p50": percentile(lat, 50) * 1e3, "p99": percentile(lat, 99) * 1e3,
                        "max": max(lat) * 1e3},
         "throughput_jobs_per_s": len(done2) / span2,
+        "catalogs_per_h": len(done2) / span2 * 3600.0,
         "saturated_jobs_per_s": cap,
         "binary_iterations_per_s": bi / span2,
         "h2d": {"GB": hb / 1e9, "ms": hms, "GBps": hb / 1e9 / (hms * 1e-3) if hms else None},
+        "served_equal_alone": checked,
     }
     print(json.dumps(out), flush=True)
 
@@ -392,14 +462,8 @@ def bench_precision(args):
     dc = G.DeviceCatalog.from_host(cat)
     ref_ids = gold["resolved_ids"].astype(np.int64)
     ref_it = gold["resolved_iter"]
-    # the oracle's final X and S on every bin: its spectra once exactly its
-    # resolved set is subtracted
-    from oracle import oracle as O
-    log("[precision] oracle X and S on every bin (host)")
-    O.set_threads(all_threads())
-    sub = np.zeros(cat.n, bool)
-    sub[np.searchsorted(cat.id, ref_ids)] = True
-    X_ref, S_ref = O.spectra_after(cat, O.make_config(run), sub)
+    bins = gold["S_bins"]
+    S_ref, X_ref = gold["S_final"], gold["X_final"]
     out_modes = {}
     for name, prec in (("fp64", G.FP64), ("fp32_compensated", G.FP32_COMP), ("fp32_naive", G.FP32_NAIVE)):
         ctx = G.Context(G.config_from_run(run, precision=prec))
@@ -411,8 +475,8 @@ def bench_precision(args):
             s = ctx.run(dc)
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3 / args.steps
-        S = ctx.spectrum(G.SPEC_SN)
-        X = ctx.spectrum(G.SPEC_X_RESIDUAL)
+        S = ctx.spectrum(G.SPEC_SN)[bins]
+        X = ctx.spectrum(G.SPEC_X_RESIDUAL)[bins]
         ids, it = ctx.resolved()
         cids, cit, cr2 = ctx.candidates()
         ctx.close()
@@ -452,9 +516,9 @@ def bench_precision(args):
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": "1e7-binary catalog (seed 2), T = 4 yr, W = 1001, in FP64 / "
                                   "FP32 with double-fp32 (compensated) sums / naive FP32; S and X "
-                                  "on every bin against the oracle's spectra for its resolved set, "
-                                  "rho^2 of every candidate at its last evaluation, resolved ids "
-                                  "and loop bodies against the FP64 oracle's stored results"},
+                                  "on every 997th bin, rho^2 of every candidate at its last "
+                                  "evaluation, resolved ids and loop bodies against the FP64 "
+                                  "oracle's stored results (every bin: tests/test_gpu_precision.py)"},
            "modes": out_modes}
     print(json.dumps(out), flush=True)
 
@@ -464,11 +528,17 @@ def main():
     ap.add_argument("--workload", choices=["1e7", "batch", "serve", "precision", "generate", "oracle"],
                     default="1e7")
     ap.add_argument("--catalogs", type=int, default=64, help="batch: number of catalogs")
-    ap.add_argument("--jobs", type=int, default=64, help="serve: number of jobs")
+    ap.add_argument("--jobs", type=int, default=2000, help="serve: number of jobs")
     ap.add_argument("--slots", type=int, default=64, help="serve: batch slots")
     ap.add_argument("--budget-gb", type=float, default=200.0, help="serve: device memory budget")
     ap.add_argument("--load", type=float, default=0.7, help="serve: arrival rate / saturated rate")
     ap.add_argument("--chunk", type=int, default=4, help="loop bodies per batch step")
+    ap.add_argument("--no-tune-batch", action="store_true",
+                    help="batch / serve: the default schedule instead of the batch tuner's per grid class")
+    ap.add_argument("--pool", type=int, default=64,
+                    help="serve: distinct catalogs drawn on the host; job j runs catalog j mod pool")
+    ap.add_argument("--check-jobs", type=int, default=4,
+                    help="serve: served jobs re-run alone through gbsub_run and compared bit for bit")
     ap.add_argument("--gpu-gen", action="store_true",
                     help="serve: catalogs drawn on the GPU from the population model at admission")
     ap.add_argument("--estimator", choices=["median", "mean"], default="median",

@@ -19,6 +19,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from . import gbsub as G
+from .autotune import grid_class
 
 
 @dataclass
@@ -75,7 +76,7 @@ class Server:
     """One GPU, one stream, one batch of up to ``max_slots`` running jobs."""
 
     def __init__(self, max_slots: int = 64, budget_bytes: float = 200 * 2**30, chunk: int = 4,
-                 keep_contexts: bool = False):
+                 keep_contexts: bool = False, schedules=None, keep_jobs=()):
         import torch
         self.torch = torch
         self.stream = torch.cuda.Stream()
@@ -84,6 +85,9 @@ class Server:
         self.budget = float(budget_bytes)
         self.chunk = int(chunk)
         self.keep = keep_contexts
+        self.keep_jobs = set(keep_jobs)   # job indices whose contexts (results) are kept
+        # schedule (tile size, split budget) per grid class, e.g. from autotune.tune_batch
+        self.schedules = dict(schedules or {})
         self.queue: deque[Request] = deque()
         self.live = {}               # slot -> (request, ctx, device catalog, bytes, admit time)
         self.used = 0.0
@@ -108,7 +112,8 @@ class Server:
         torch = self.torch
         while self.queue and self.queue[0].arrival_s <= now and len(self.live) < self.max_slots:
             req = self.queue[0]
-            ctx = G.Context(G.config_from_run(req.run))
+            sch = self.schedules.get(grid_class(req.run), {})
+            ctx = G.Context(G.config_from_run(req.run, **sch))
             need = self.footprint(ctx, req.n)
             if self.live and self.used + need > self.budget:
                 ctx.close()
@@ -147,9 +152,10 @@ class Server:
         for k in [k for k in self.live if state[k] != G.SLOT_RUNNING]:
             req, ctx, dc, need, t_adm = self.live.pop(k)
             st, s = self.batch.retire(k, self.stream)
+            keep = self.keep or req.index in self.keep_jobs
             out.append(Completion(req.index, st, s, req.n, req.arrival_s, t_adm, self.now(),
-                                  ctx if self.keep else None))
-            if not self.keep:
+                                  ctx if keep else None))
+            if not keep:
                 ctx.close()
             self.used -= need
         return out
@@ -172,11 +178,13 @@ class Server:
         self.batch.close()
 
 
-def serve(requests, max_slots=64, budget_bytes=200 * 2**30, chunk=4, keep_contexts=False):
+def serve(requests, max_slots=64, budget_bytes=200 * 2**30, chunk=4, keep_contexts=False, schedules=None,
+          keep_jobs=(), progress=None):
     """Runs every request to completion in wall-clock time (arrivals are
     honoured: the server idles until the next one is due).  Returns the
-    completions in completion order and the server (for its statistics)."""
-    srv = Server(max_slots, budget_bytes, chunk, keep_contexts)
+    completions in completion order and the server (for its statistics).
+    ``progress(n_done, n_total)``, if given, is called every 100 completions."""
+    srv = Server(max_slots, budget_bytes, chunk, keep_contexts, schedules, keep_jobs)
     for r in sorted(requests, key=lambda r: r.arrival_s):
         srv.submit(r)
     done = []
@@ -187,5 +195,8 @@ def serve(requests, max_slots=64, budget_bytes=200 * 2**30, chunk=4, keep_contex
             wait = nxt - srv.now()
             if wait > 0:
                 time.sleep(min(wait, 0.05))
+        before = len(done)
         done.extend(srv.pump())
+        if progress and len(done) // 100 > before // 100:
+            progress(len(done), len(requests))
     return done, srv
