@@ -78,7 +78,10 @@ typedef struct {
     double   kappa;            /* candidate cut, default 1/rho_th */
     double   median_scale;     /* C, default 729/512 = (1 - 2/18)^-3 */
     uint32_t track_model;      /* GBSUB_TRACK_SWEEP (default) | GBSUB_TRACK_SINGLE */
-    uint32_t precision;        /* GBSUB_FP64 (default) | GBSUB_FP32_COMP | GBSUB_FP32_NAIVE */
+    uint32_t precision;        /* loop arithmetic: GBSUB_FP64 (default: exact 128-bit fixed-point bin
+                                  sums, fp64 S and SNR sums) | GBSUB_FP32_COMP (double-fp32 bin sums,
+                                  prefixes and SNR sums, fp32 S) | GBSUB_FP32_NAIVE (plain fp32 sums
+                                  by float atomics); median estimator only for the FP32 modes */
     uint32_t max_iter;         /* maximum loop bodies; 0 = n_candidates + 1 */
     uint32_t reserved0;
     double   oms_pm;           /* SciRDv1 OMS level P, default 15 (pm/sqrt(Hz)) */
@@ -133,7 +136,13 @@ gbsub_status gbsub_create(const gbsub_config *cfg, gbsub_ctx **out);
 gbsub_status gbsub_workspace_size(const gbsub_ctx *ctx, uint64_t n_sources, uint64_t *bytes);
 
 /* Runs the whole subtraction on `cat` (host pointer to a struct holding
- * device pointers).  `workspace` is a DEVICE pointer to at least
+ * device pointers): appendix "Subtraction algorithm" end to end -- the
+ * initial SNR against S_instr and the candidate cut (its steps 2-3), then
+ * loop bodies t = 0, 1, ... of {running-median PSD estimate S^t (Eq.
+ * "running median"), rho^2 of every unresolved candidate against S^t (Eq.
+ * "SNR inner product"), subtraction of every source with rho > rho_th (steps
+ * 6-9)} until a body subtracts nothing (step 10; n_iter counts the bodies,
+ * the last one included).  `workspace` is a DEVICE pointer to at least
  * gbsub_workspace_size() bytes, 256-byte aligned, owned by the caller and
  * holding the results until the next run or destroy.  All work is enqueued
  * on `stream`; the call returns after it has completed.  While it runs, the
@@ -168,14 +177,22 @@ gbsub_status gbsub_run_static(gbsub_ctx *ctx, const gbsub_catalog *cat, void *st
 
 /* Copies spectrum `kind` (GBSUB_SPEC_*) of the last successful run, B fp64
  * values in grid order, to `out` (host pointer if out_on_device == 0, device
- * pointer otherwise).  *n_bins (host) receives B.  TRUNCATED if cap < B,
+ * pointer otherwise): S_n, the frequency series of the estimated PSD on the
+ * 1/T_obs grid that the paper's statement of the problem returns (Sec.
+ * "Coarse-graining of the data"), at the loop's fixed point; X, the binned
+ * power of the sources left in the data; S_gal = S_n - S_instr (computed on
+ * the device); S_instr (appendices "LISA instrumental noise" and
+ * "Characteristic strain").  *n_bins (host) receives B.  TRUNCATED if cap < B,
  * STATE if no run has completed. */
 gbsub_status gbsub_spectrum(const gbsub_ctx *ctx, uint32_t kind, double *out, uint64_t cap,
                             uint64_t *n_bins, int out_on_device);
 
-/* Copies the resolved sources of the last successful run: ids[j] (uint32)
- * in ascending id order, and iter_of[j] (int32, may be NULL) = the loop body
- * t in which ids[j] was subtracted.  Host pointers if out_on_device == 0,
+/* Copies the resolved sources of the last successful run (the sources the
+ * appendix "Subtraction algorithm" takes out of the data, step 9, with the
+ * loop body of each): ids[j] (uint32) in ascending id order, and iter_of[j]
+ * (int32, may be NULL) = the loop body t in which ids[j] was subtracted.
+ * Built on the device (compaction of the candidate records, radix sort by
+ * id) in the run's workspace; the run's spectra are untouched.  Host pointers if out_on_device == 0,
  * device pointers otherwise.  *n (host) receives the count; TRUNCATED if
  * cap is smaller.  STATE if no run has completed. */
 gbsub_status gbsub_resolved(const gbsub_ctx *ctx, uint32_t *ids, int32_t *iter_of, uint64_t cap,
@@ -242,7 +259,7 @@ enum {
     GBSUB_KF_PREP = 2,           /* candidate cut, binning, fixed-point accumulation */
     GBSUB_KF_XUPDATE = 3,        /* X from the fixed-point accumulators */
     GBSUB_KF_MEDIAN = 4,         /* running median, S = C med + S_instr, in-part prefix of 1/S */
-    GBSUB_KF_SNR = 5,            /* prefix of the part sums of 1/S, rho^2, decisions,
+    GBSUB_KF_SNR = 5,            /* rho^2 (the part sums of 1/S under each track), decisions,
                                     subtraction, dirty tiles, settle test */
     GBSUB_KF_OUTPUT = 6,         /* candidate ids */
     GBSUB_KF_COUNT = 7
