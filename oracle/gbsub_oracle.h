@@ -128,6 +128,28 @@ int     orc_spectra_after(const orc_config *c, int64_t n, const float *A, const 
 int     orc_run(const orc_config *c, int64_t n, const float *A, const float *f, const float *fdot,
                 orc_io *io, orc_summary *sum);
 
+/* Complex-template data model (template_oracle.c; Sec. "Simulations",
+ * appendix "Subtraction algorithm", Eq. "vectorized-subtraction"): N-sample
+ * templates U (re, im interleaved, j = -N/2 .. N/2-1 at DFT index q + j),
+ * one complex series per channel A and E. */
+#define ORC_CX_NF 128
+typedef struct {
+    int32_t *iter_of;       /* [n] */
+    uint8_t *is_candidate;  /* [n] */
+    double  *rho0_sq;       /* [n]  rho^2 against S_instr (both channels) */
+    double  *rho2_last;     /* [n]  rho^2 at the last evaluation (candidates only) */
+    int64_t *q;             /* [n]  central DFT index, INT64_MIN if no template */
+    double  *S_final;       /* [2][n_bins]  S_A, S_E */
+    double  *X_final;       /* [2][n_bins]  X_A, X_E */
+    double  *h_final;       /* [2][n_bins][2]  h_A, h_E (re, im) */
+    double   near_band;     /* 1e-6 by default if <= 0 */
+} orc_cx_io;
+/* U[2N] and *q of one source (INT64_MIN and U = 0 if it has no template on
+ * the grid); ORC_E_INVALID for an invalid entry. */
+int     orc_cx_template(const orc_config *c, float A, float f, float fdot, int64_t *q, double *U);
+int     orc_cx_run(const orc_config *c, int64_t n, const float *A, const float *f, const float *fdot,
+                   const float *phi_a, const float *phi_e, orc_cx_io *io, orc_summary *sum);
+
 /* ---------------------------------------------------------------- population model
  * (population_oracle.c; Sec. "Population model", Table "priors", appendix
  * "Copulas") */

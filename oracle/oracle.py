@@ -17,6 +17,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "gbsub_oracle.c")
 POP_SRC = os.path.join(HERE, "population_oracle.c")
+CX_SRC = os.path.join(HERE, "template_oracle.c")
 HDR = os.path.join(HERE, "gbsub_oracle.h")
 BUILD_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(BUILD_DIR, "libgbsub_oracle.so")
@@ -30,11 +31,12 @@ def build(force: bool = False) -> str:
     """Compile the oracle (gcc, -O2, no FMA contraction, OpenMP)."""
     os.makedirs(BUILD_DIR, exist_ok=True)
     if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= max(
-            os.path.getmtime(SRC), os.path.getmtime(POP_SRC), os.path.getmtime(HDR)):
+            os.path.getmtime(SRC), os.path.getmtime(POP_SRC), os.path.getmtime(CX_SRC),
+            os.path.getmtime(HDR)):
         return LIB
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
-           "-fPIC", "-shared", "-Wall", "-o", tmp, SRC, POP_SRC, "-lm"]
+           "-fPIC", "-shared", "-Wall", "-o", tmp, SRC, POP_SRC, CX_SRC, "-lm"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
     return LIB
@@ -383,3 +385,100 @@ def pop_draw(pop: Population, seed: int, n: int, first: int = 0):
     if rc != OK:
         raise ValueError(f"orc_pop_draw: {rc}")
     return A, f, fd, ids
+
+
+# ---------------------------------------------------------------- complex-template data model
+
+CX_NF = 128
+
+
+class CxIO(C.Structure):
+    _fields_ = [("iter_of", C.c_void_p), ("is_candidate", C.c_void_p), ("rho0_sq", C.c_void_p),
+                ("rho2_last", C.c_void_p), ("q", C.c_void_p), ("S_final", C.c_void_p),
+                ("X_final", C.c_void_p), ("h_final", C.c_void_p), ("near_band", C.c_double)]
+
+
+def _cx_lib():
+    L = lib()
+    if not getattr(L, "_cx_ready", False):
+        L.orc_cx_template.argtypes = [C.POINTER(Config), C.c_float, C.c_float, C.c_float,
+                                      C.POINTER(C.c_int64), C.c_void_p]
+        L.orc_cx_template.restype = C.c_int
+        L.orc_cx_run.argtypes = [C.POINTER(Config), C.c_int64] + [C.c_void_p] * 5 + [
+            C.POINTER(CxIO), C.POINTER(Summary)]
+        L.orc_cx_run.restype = C.c_int
+        L._cx_ready = True
+    return L
+
+
+NO_TEMPLATE = -(1 << 63)
+
+
+def cx_template(cfg: Config, A: float, f: float, fdot: float):
+    """(q, U): the central DFT index and the CX_NF complex template values
+    U_j, j = -CX_NF/2 .. CX_NF/2-1 (q = NO_TEMPLATE and U = 0 if the source
+    has no template)."""
+    q = C.c_int64()
+    U = np.zeros(2 * CX_NF, np.float64)
+    rc = _cx_lib().orc_cx_template(C.byref(cfg), float(A), float(f), float(fdot), C.byref(q),
+                                   U.ctypes.data)
+    if rc != OK:
+        raise ValueError("invalid source")
+    return q.value, U[0::2] + 1j * U[1::2]
+
+
+@dataclass
+class CxResult:
+    status: int
+    n_iter: int
+    n_bins: int
+    k0: int
+    n_candidates: int
+    n_resolved: int
+    n_near: int
+    min_rel_margin: float
+    iter_of: np.ndarray          # int32 [n]
+    is_candidate: np.ndarray     # bool [n]
+    rho0_sq: np.ndarray          # [n]
+    rho2_last: np.ndarray        # [n] (nan for non-candidates)
+    q: np.ndarray                # int64 [n]
+    S_final: np.ndarray | None   # [2, B]
+    X_final: np.ndarray | None   # [2, B]
+    h_final: np.ndarray | None   # complex [2, B]
+
+
+def cx_run(catalog, phi_a, phi_e, cfg: Config, *, spectra: bool = True) -> CxResult:
+    """The subtraction on the complex-template data model (template_oracle.c)."""
+    A = np.ascontiguousarray(catalog.A, np.float32)
+    f = np.ascontiguousarray(catalog.f, np.float32)
+    fd = np.ascontiguousarray(catalog.fdot, np.float32)
+    pa = np.ascontiguousarray(phi_a, np.float32)
+    pe = np.ascontiguousarray(phi_e, np.float32)
+    n = A.shape[0]
+    assert pa.shape == (n,) and pe.shape == (n,)
+    k0, B = grid(cfg.t_obs_s, cfg.f_min_hz, cfg.f_max_hz)
+    m = max(n, 1)
+    iter_of = np.empty(m, np.int32)
+    is_c = np.zeros(m, np.uint8)
+    rho0 = np.zeros(m)
+    rho2 = np.full(m, np.nan)
+    q = np.zeros(m, np.int64)
+    io = CxIO()
+    io.iter_of, io.is_candidate, io.rho0_sq = iter_of.ctypes.data, is_c.ctypes.data, rho0.ctypes.data
+    io.rho2_last, io.q = rho2.ctypes.data, q.ctypes.data
+    S = X = h = None
+    if spectra:
+        S = np.empty((2, B))
+        X = np.empty((2, B))
+        h = np.empty((2, B, 2))
+        io.S_final, io.X_final, io.h_final = S.ctypes.data, X.ctypes.data, h.ctypes.data
+    io.near_band = 1e-6
+    summ = Summary()
+    rc = _cx_lib().orc_cx_run(C.byref(cfg), n, A.ctypes.data, f.ctypes.data, fd.ctypes.data,
+                              pa.ctypes.data, pe.ctypes.data, C.byref(io), C.byref(summ))
+    return CxResult(status=rc, n_iter=summ.n_iter, n_bins=summ.n_bins, k0=summ.k0,
+                    n_candidates=summ.n_candidates, n_resolved=summ.n_resolved, n_near=summ.n_near,
+                    min_rel_margin=summ.min_rel_margin, iter_of=iter_of[:n].copy(),
+                    is_candidate=is_c[:n].astype(bool), rho0_sq=rho0[:n].copy(),
+                    rho2_last=rho2[:n].copy(), q=q[:n].copy(), S_final=S, X_final=X,
+                    h_final=None if h is None else h[..., 0] + 1j * h[..., 1])

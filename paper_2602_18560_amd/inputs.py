@@ -139,6 +139,42 @@ def catalog_1e7(n: int = 10_000_000):
     return draw_catalog(pop), run
 
 
+def template_phases(n: int, seed: int):
+    """Per-source phases (phi_A, phi_E) of the complex-template data model:
+    independent and uniform on [0, 2 pi), fp32.  Stream seed + 7919 of numpy
+    PCG64, so the phases do not reuse the catalog's own draws."""
+    rng = np.random.default_rng(seed + 7919)
+    ph = rng.uniform(0.0, 2.0 * math.pi, size=(2, n)).astype(np.float32)
+    return ph[0].copy(), ph[1].copy()
+
+
+def catalog_cx_1e4():
+    """The 1e4 catalog (seed 0; T = 1 yr, [0.3, 10] mHz, W = 251) with its
+    template phases: the oracle-scale case of the complex-template model."""
+    cat, run = catalog_1e4()
+    pa, pe = template_phases(cat.n, 0)
+    return cat, pa, pe, run
+
+
+def catalog_cx_2e5():
+    """2e5 sources by the same recipe (seed 11) on the 1e4 catalog's grid
+    (T = 1 yr, [0.3, 10] mHz, W = 251): the mid-size parity case of the
+    complex-template model."""
+    pop = Population(n=200_000, seed=11, f_lo=3e-4, f_hi=1e-2)
+    run = RunConfig(t_obs_s=1 * YEAR_S, f_min_hz=3e-4, f_max_hz=1e-2, window_bins=251)
+    cat = draw_catalog(pop)
+    pa, pe = template_phases(cat.n, 11)
+    return cat, pa, pe, run
+
+
+def catalog_cx_1e7():
+    """The 1e7 catalog (seed 2; T = 4 yr, [0.1, 30] mHz, W = 1001) with its
+    template phases: the measured workload of the complex-template model."""
+    cat, run = catalog_1e7()
+    pa, pe = template_phases(cat.n, 2)
+    return cat, pa, pe, run
+
+
 def _meta_population(rng, n: int, seed: int, f_lo=1e-4, f_hi=3e-2) -> Population:
     return Population(n=n, seed=seed, f_lo=f_lo, f_hi=f_hi,
                       gamma=float(rng.uniform(2.0, 4.0)), k=float(rng.uniform(1.0, 3.0)),
