@@ -354,6 +354,75 @@ gbsub_status gbsub_batch_retire(gbsub_batch *b, uint32_t slot, void *stream, gbs
 /* Releases the batch (NULL is ignored); caller memory is not touched. */
 void gbsub_batch_destroy(gbsub_batch *b);
 
+/* ---------------------------------------------------------------- complex-template data model
+ * The data as the paper holds it (Sec. "Simulations"; appendix "Subtraction
+ * algorithm", Eq. "vectorized-subtraction"): one complex frequency series
+ * per TDI channel A and E (T is insensitive), the sum of every source's
+ * frequency-domain template of GBSUB_CX_NF = 128 samples around its central
+ * frequency; resolved sources are scattered out of it.  The paper's
+ * templates come from gbgpu; this library uses a sky-averaged fast/slow
+ * template of its own: with q = floor((f + fdot T/2) T + 1/2),
+ * delta = f T - q and d = fdot T^2, U_j = (T/128) sum_n s_n e^{-2 pi i m n/128}
+ * (m = j mod 128, j = -64..63, at grid bin q + j - k0) of the samples
+ * s_n = (A/2) e^{2 pi i (delta x + d x^2/2)}, x = n/128; channel c carries
+ * e^{i phi_c} U.  Per channel, X_c = (2/T)|h_c|^2 and S_c = C median_W(X_c)
+ * + S_instr (or the running mean); rho^2 = (4/T) sum_c sum_j |U_j|^2 / S_c.
+ * A source with |fdot| T^2 >= 2^20 or |(f + fdot T/2) T| >= 2^52 has no
+ * template.  Runs use the context's configuration (grid, window, estimator,
+ * thresholds, max_iter; FP64 only: the data are exact 64-bit fixed point,
+ * so a subtracted template cancels to the last bit); grids of at most
+ * 8192 x 1024 bins. */
+#define GBSUB_CX_NF 128
+enum { GBSUB_SPEC_H_RESIDUAL = 4 };   /* gbsub_cx_spectrum: h_c, 2B fp64 (re, im interleaved) */
+
+typedef struct {
+    uint64_t        n;
+    const float    *A;        /* device pointers to n entries each, as gbsub_catalog */
+    const float    *f;
+    const float    *fdot;
+    const float    *phi_a;    /* phase of the A channel (rad), finite */
+    const float    *phi_e;    /* phase of the E channel (rad), finite */
+    const uint32_t *id;
+} gbsub_cx_catalog;
+
+/* Bytes of device workspace gbsub_cx_run needs for n_sources on this
+ * context's grid (*bytes, host).  INVALID if the grid has more than
+ * 8192 x 1024 bins or the context is not FP64. */
+gbsub_status gbsub_cx_workspace_size(const gbsub_ctx *ctx, uint64_t n_sources, uint64_t *bytes);
+
+/* The subtraction of the appendix "Subtraction algorithm" on the complex
+ * data: every template injected into h_A, h_E; rho_0^2 against S_instr in
+ * both channels and the candidate cut; then loop bodies {X_c and S_c of each
+ * channel, rho^2 of every unresolved candidate, the templates of every
+ * source with rho > rho_th scattered out of h (Eq. "vectorized-subtraction")}
+ * until a body subtracts nothing.  Arguments, workspace ownership, stream
+ * use and errors as gbsub_run (the workspace from gbsub_cx_workspace_size);
+ * results are read with gbsub_cx_spectrum and gbsub_cx_resolved and stay in
+ * the workspace until the next complex-template run of this context. */
+gbsub_status gbsub_cx_run(gbsub_ctx *ctx, const gbsub_cx_catalog *cat, void *workspace, uint64_t ws_bytes,
+                          void *stream, gbsub_summary *out);
+
+/* Spectrum `kind` of channel `channel` (0 = A, 1 = E) of the last
+ * complex-template run: GBSUB_SPEC_SN, _X_RESIDUAL, _S_GAL, _S_INSTR (B fp64
+ * values) or GBSUB_SPEC_H_RESIDUAL (the data left after the subtraction,
+ * 2B fp64 values: re, im of each bin).  Pointers and errors as
+ * gbsub_spectrum; cap counts fp64 values. */
+gbsub_status gbsub_cx_spectrum(const gbsub_ctx *ctx, uint32_t channel, uint32_t kind, double *out, uint64_t cap,
+                               uint64_t *n_bins, int out_on_device);
+
+/* The resolved sources of the last complex-template run (ids ascending,
+ * with their loop body), as gbsub_resolved. */
+gbsub_status gbsub_cx_resolved(const gbsub_ctx *ctx, uint32_t *ids, int32_t *iter_of, uint64_t cap, uint64_t *n,
+                               int out_on_device);
+
+/* Templates of n sources on the device (Sec. "Simulations", the model above):
+ * q[i] (int64, central DFT index; INT64_MIN if the source has no template)
+ * and U[i][128][2] (fp64 re, im of U_j, j = -64..63).  A, f, fdot, q, U are
+ * device pointers; enqueued on `stream`, which the call synchronizes.
+ * INVALID for null pointers with n > 0. */
+gbsub_status gbsub_cx_templates(const gbsub_ctx *ctx, uint64_t n, const float *A, const float *f,
+                                const float *fdot, int64_t *q, double *U, void *stream);
+
 /* Releases the context (NULL is ignored).  Does not touch caller memory.
  * A context that holds a batch slot must be retired from the batch first. */
 void gbsub_destroy(gbsub_ctx *ctx);

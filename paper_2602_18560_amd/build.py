@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIB_DIR, "libgbsub.so")
-SOURCES = ["gbsub_kernels.hip", "gbsub_population.hip", "gbsub_output.hip", "gbsub_api.hip"]
+SOURCES = ["gbsub_kernels.hip", "gbsub_population.hip", "gbsub_output.hip", "gbsub_cx.hip", "gbsub_api.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [

@@ -43,6 +43,12 @@ struct gbsub_ctx {
     uint32_t *host_prog;   // pinned, device-mapped: bodies finished << 1 | settled, written by the tail
     uint32_t *dev_prog;    // the same word as the kernels address it
     int batch_slot;    // slot held in a batch, -1 if none
+    // results of the last complex-template run
+    bool cx_have_result;
+    CxDev cx;
+    gbsub_summary cx_summ;
+    uint32_t cx_n;
+    Slot *host_cx_slots;   // pinned staging of the two channel descriptors
     // profiling: bit k of `profiling` selects kernel family k
     uint32_t profiling;
     struct Rec { int kid; int64_t t; hipEvent_t a, b; };
@@ -408,15 +414,20 @@ gbsub_status gbsub_create(const gbsub_config *cfg, gbsub_ctx **out)
     c->host_prog = nullptr;
     c->dev_prog = nullptr;
     c->batch_slot = -1;
+    c->cx_have_result = false;
+    c->cx_n = 0;
+    c->host_cx_slots = nullptr;
     c->profiling = 0;
     c->ev_used = 0;
     c->clear_stats();
     if (hipHostMalloc((void **)&c->host_ctl, sizeof(Ctl), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void **)&c->host_slot, sizeof(Slot), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&c->host_cx_slots, 2 * sizeof(Slot), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void **)&c->host_prog, 64, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
         hipHostGetDevicePointer((void **)&c->dev_prog, c->host_prog, 0) != hipSuccess) {
         if (c->host_ctl) (void)hipHostFree(c->host_ctl);
         if (c->host_slot) (void)hipHostFree(c->host_slot);
+        if (c->host_cx_slots) (void)hipHostFree(c->host_cx_slots);
         if (c->host_prog) (void)hipHostFree(c->host_prog);
         delete c;
         return GBSUB_E_DEVICE;
@@ -435,6 +446,7 @@ void gbsub_destroy(gbsub_ctx *c)
     if (!c) return;
     if (c->host_ctl) (void)hipHostFree(c->host_ctl);
     if (c->host_slot) (void)hipHostFree(c->host_slot);
+    if (c->host_cx_slots) (void)hipHostFree(c->host_cx_slots);
     if (c->host_prog) (void)hipHostFree(c->host_prog);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     delete c;
@@ -732,6 +744,191 @@ gbsub_status gbsub_candidates(const gbsub_ctx *c, uint32_t *ids, int32_t *iter_o
         if (rho2) rho2[q] = r2[j];
     }
     return GBSUB_OK;
+}
+
+// ---------------------------------------------------------------- complex-template data model
+
+namespace {
+
+gbsub_status cx_grid_ok(const gbsub_ctx *c)
+{
+    if (c->g.prec != PREC_FP64) return GBSUB_E_INVALID;
+    if ((uint64_t)c->g.B > (uint64_t)CX_NTC_MAX * CX_TILE) return GBSUB_E_INVALID;
+    return GBSUB_OK;
+}
+
+}  // namespace
+
+gbsub_status gbsub_cx_workspace_size(const gbsub_ctx *c, uint64_t n, uint64_t *bytes)
+{
+    if (!c || !bytes || n >= (1ull << 31)) return GBSUB_E_INVALID;
+    if (cx_grid_ok(c) != GBSUB_OK) return GBSUB_E_INVALID;
+    *bytes = cx_carve(c->g, n, nullptr, nullptr);
+    return GBSUB_OK;
+}
+
+gbsub_status gbsub_cx_run(gbsub_ctx *c, const gbsub_cx_catalog *cat, void *ws, uint64_t ws_bytes, void *stream,
+                          gbsub_summary *out)
+{
+    if (!c || !cat || !ws) return GBSUB_E_INVALID;
+    if (cx_grid_ok(c) != GBSUB_OK) return GBSUB_E_INVALID;
+    if (cat->n >= (1ull << 31)) return GBSUB_E_INVALID;
+    if (cat->n > 0 && (!cat->A || !cat->f || !cat->fdot || !cat->phi_a || !cat->phi_e || !cat->id))
+        return GBSUB_E_INVALID;
+    if (((uintptr_t)ws & 255u) != 0 || ws_bytes < cx_carve(c->g, cat->n, nullptr, nullptr)) return GBSUB_E_INVALID;
+    if (c->batch_slot >= 0) return GBSUB_E_STATE;
+    c->cx_have_result = false;
+    if (use_device(c->device) != GBSUB_OK) return GBSUB_E_DEVICE;
+    hipStream_t st = (hipStream_t)stream;
+    const Grid &g = c->g;
+    CxDev d;
+    cx_carve(g, cat->n, (char *)ws, &d);
+    // the A and E channels as two descriptors of the median kernels
+    for (int ch = 0; ch < 2; ++ch) {
+        Slot sl{};
+        sl.g = g;
+        sl.d.sx = d.sx;
+        sl.d.X = d.X + (size_t)ch * g.B;
+        sl.d.S = d.S + (size_t)ch * g.B;
+        sl.d.is_pre = d.is_pre + (size_t)ch * g.B;
+        sl.d.is_psum = d.is_psum + (size_t)ch * g.nparts;
+        sl.d.xstamp = d.xstamp;
+        sl.d.sstamp = d.sstamp;
+        sl.d.ctl = d.ctl;
+        sl.n = cat->n;
+        sl.active = 1;
+        c->host_cx_slots[ch] = sl;
+    }
+    CxIn in{cat->A, cat->f, cat->fdot, cat->phi_a, cat->phi_e, cat->id, (uint32_t)cat->n, c->dev_prog};
+    volatile uint32_t *prog = c->host_prog;
+    *prog = 0;
+    auto fail = [&](gbsub_status s) {
+        (void)hipStreamSynchronize(st);
+        return s;
+    };
+    hipError_t e = hipMemcpyAsync(d.slots, c->host_cx_slots, 2 * sizeof(Slot), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = cx_launch_prep(g, d, in, st);
+    if (e != hipSuccess) return fail(GBSUB_E_DEVICE);
+    // loop bodies paced by the progress word, as in gbsub_run
+    constexpr uint64_t AHEAD = 2;
+    const uint64_t guard = (uint64_t)cat->n + 2 + (c->cfg.max_iter ? c->cfg.max_iter : 0);
+    uint64_t t = 0;
+    uint32_t seen_prev = 0;
+    auto quiet_since = std::chrono::steady_clock::now();
+    for (;;) {
+        const uint32_t w = *prog;
+        if (w & 1u) break;
+        const uint32_t seen = w >> 1;
+        if (t < (uint64_t)seen + AHEAD) {
+            if (t > guard) return fail(GBSUB_E_DEVICE);
+            if (cx_launch_body(g, d, in, st) != hipSuccess) return fail(GBSUB_E_DEVICE);
+            ++t;
+            continue;
+        }
+        const auto now = std::chrono::steady_clock::now();
+        if (seen != seen_prev) {
+            seen_prev = seen;
+            quiet_since = now;
+            continue;
+        }
+        if (now - quiet_since < std::chrono::microseconds(200)) {
+            std::this_thread::yield();
+            continue;
+        }
+        quiet_since = now;
+        const hipError_t q = hipStreamQuery(st);
+        if (q == hipErrorNotReady) continue;
+        if (q != hipSuccess) return fail(GBSUB_E_DEVICE);
+        e = hipMemcpyAsync(c->host_ctl, d.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return fail(GBSUB_E_DEVICE);
+        if (c->host_ctl->done) break;
+        if (t > guard) return GBSUB_E_DEVICE;
+        if (cx_launch_body(g, d, in, st) != hipSuccess) return fail(GBSUB_E_DEVICE);
+        ++t;
+    }
+    e = cx_launch_outputs(g, d, in, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->host_ctl, d.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return fail(GBSUB_E_DEVICE);
+    const Ctl &h = *c->host_ctl;
+    if (h.bad) return GBSUB_E_INVALID;
+    gbsub_summary s = summary_of(g, h);
+    s.n_candidates = h.cand_cursor;
+    if (out) *out = s;
+    if (h.status == 6) return GBSUB_E_MAXITER;
+    c->cx = d;
+    c->cx_summ = s;
+    c->cx_n = (uint32_t)cat->n;
+    c->cx_have_result = true;
+    return GBSUB_OK;
+}
+
+gbsub_status gbsub_cx_spectrum(const gbsub_ctx *c, uint32_t channel, uint32_t kind, double *out, uint64_t cap,
+                               uint64_t *n_bins, int out_on_device)
+{
+    if (!c || !n_bins || channel > 1) return GBSUB_E_INVALID;
+    if (!c->cx_have_result) return GBSUB_E_STATE;
+    const uint64_t B = (uint64_t)c->g.B;
+    *n_bins = B;
+    if (kind > GBSUB_SPEC_H_RESIDUAL) return GBSUB_E_INVALID;
+    const uint64_t need = kind == GBSUB_SPEC_H_RESIDUAL ? 2 * B : B;
+    if (cap < need) return GBSUB_E_TRUNCATED;
+    if (!out) return GBSUB_E_INVALID;
+    if (hipSetDevice(c->device) != hipSuccess) return GBSUB_E_DEVICE;
+    const CxDev &d = c->cx;
+    const hipMemcpyKind kd = out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    const size_t off = (size_t)channel * B;
+    if (kind == GBSUB_SPEC_SN) return dev_err(hipMemcpy(out, d.S + off, B * 8, kd));
+    if (kind == GBSUB_SPEC_X_RESIDUAL) return dev_err(hipMemcpy(out, d.X + off, B * 8, kd));
+    if (kind == GBSUB_SPEC_S_INSTR) return dev_err(hipMemcpy(out, d.sx, B * 8, kd));
+    // device-computed kinds, into `out` or (host output) into the workspace's
+    // in-part 1/S prefixes, dead once a run has settled (2B doubles)
+    double *tmp = d.is_pre;
+    hipError_t e;
+    if (kind == GBSUB_SPEC_S_GAL) {
+        double *dst = out_on_device ? out : tmp;
+        e = launch_sgal(d.S + off, d.sx, (int)B, dst, nullptr);
+        if (e == hipSuccess) e = out_on_device ? hipDeviceSynchronize() : hipMemcpy(out, dst, B * 8, kd);
+        return dev_err(e);
+    }
+    // h of the channel: 2B doubles, through the prefix scratch (2B doubles)
+    double *dst = out_on_device ? out : tmp;
+    e = cx_launch_h(c->g, d, c->cx_n, (int)channel, dst, nullptr);
+    if (e == hipSuccess) e = out_on_device ? hipDeviceSynchronize() : hipMemcpy(out, dst, 2 * B * 8, kd);
+    return dev_err(e);
+}
+
+gbsub_status gbsub_cx_resolved(const gbsub_ctx *c, uint32_t *ids, int32_t *iter_of, uint64_t cap, uint64_t *n,
+                               int out_on_device)
+{
+    if (!c || !n) return GBSUB_E_INVALID;
+    if (!c->cx_have_result) return GBSUB_E_STATE;
+    const uint64_t m = c->cx_summ.n_resolved;
+    *n = m;
+    if (cap < m) return GBSUB_E_TRUNCATED;
+    if (m == 0) return GBSUB_OK;
+    if (!ids) return GBSUB_E_INVALID;
+    if (hipSetDevice(c->device) != hipSuccess) return GBSUB_E_DEVICE;
+    const CxDev &d = c->cx;
+    hipError_t e = launch_resolved(d.c_iter, d.c_id, (uint32_t)c->cx_summ.n_candidates, (uint32_t)m, d.rs_hist, d.kA,
+                                   d.vA, d.kB, d.vB, nullptr);
+    const hipMemcpyKind kd = out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    if (e == hipSuccess) e = hipMemcpy(ids, d.kA, m * 4, kd);
+    if (e == hipSuccess && iter_of) e = hipMemcpy(iter_of, d.vA, m * 4, kd);
+    return dev_err(e);
+}
+
+gbsub_status gbsub_cx_templates(const gbsub_ctx *c, uint64_t n, const float *A, const float *f, const float *fdot,
+                                int64_t *q, double *U, void *stream)
+{
+    if (!c || n >= (1ull << 31)) return GBSUB_E_INVALID;
+    if (n > 0 && (!A || !f || !fdot || !q || !U)) return GBSUB_E_INVALID;
+    if (use_device(c->device) != GBSUB_OK) return GBSUB_E_DEVICE;
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = cx_launch_templates(c->g, A, f, fdot, (uint32_t)n, q, U, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    return dev_err(e);
 }
 
 gbsub_status gbsub_set_profiling(gbsub_ctx *c, uint32_t families)

@@ -71,6 +71,7 @@ struct Ctl {
     uint32_t med_split;      // next median launch: one block per part (1) or per tile (0)
     uint32_t xupd;           // stamp of the tiles the next k_xupdate converts
     uint32_t tail_due;       // k_snr has run; its partials await the tail
+    uint32_t n_new_body;     // complex-template model: sources subtracted by the running body
 };
 
 // Per-block partial results of k_snr (combined by the tail: the last block
@@ -223,6 +224,57 @@ hipError_t launch_resolved(const int32_t *iter, const uint32_t *id, uint32_t nc,
                            uint32_t *kA, int32_t *vA, uint32_t *kB, int32_t *vB, hipStream_t st);
 // out[k] = S[k] - sx[k] for k < B.
 hipError_t launch_sgal(const double *S, const double *sx, int B, double *out, hipStream_t st);
+
+// ---- complex-template data model (gbsub_cx.hip)
+constexpr int CX_NF = 128;          // samples per template
+constexpr int CX_TILE = 1024;       // bins per binning tile of the injection
+constexpr int CX_NTC_MAX = 8192;    // binning tiles at most (B <= CX_NTC_MAX * CX_TILE)
+
+// Pointers into the workspace of a complex-template run.
+struct CxDev {
+    Slot *slots;             // [2] median descriptors of the A and E channels
+    Ctl *ctl;                // shared by both channels
+    double *sx;              // [B] S_instr
+    double *X;               // [2][B] periodograms (2/T)|h_c|^2
+    double *S;               // [2][B] PSD estimates
+    double *is_pre;          // [2][B] in-part prefixes of 1/S (written by the median kernel)
+    double *is_psum;         // [2][nparts] part sums of 1/S
+    int64_t *h;              // [4][B] re h_A, im h_A, re h_E, im h_E in fixed point (unit 2^-E)
+    uint32_t *xstamp;        // [nt] tiles whose X is recomputed in body t
+    uint32_t *sstamp;        // [nt] tiles whose S is recomputed in body t
+    uint32_t *tcnt;          // [ntc+1] sources per binning tile, then their exclusive prefix
+    uint32_t *tcur;          // [ntc] scatter cursors
+    uint32_t *cbase;         // [ntc+1] first injection chunk of each binning tile
+    uint32_t *order;         // [n] source indices grouped by binning tile
+    uint32_t *c_src;         // [n] candidates (slot order of discovery)
+    int32_t *c_iter;         // [n] loop body that subtracted it, -1 while unresolved
+    uint32_t *c_id;          // [n] its id (written at the end of a run)
+    double *c_rho2;          // [n] rho^2 at the last evaluation
+    uint32_t *rs_hist;       // resolved-list scratch
+    uint32_t *kA, *kB;       // [n] each: resolved-list keys
+    int32_t *vA, *vB;        // [n] each: resolved-list values
+    int32_t ntc;             // binning tiles
+    int32_t pad;
+};
+
+// Bytes of the workspace of a complex-template run of n sources on grid g
+// (with base: the layout is written to *d).
+uint64_t cx_carve(const Grid &g, uint64_t n, char *base, CxDev *d);
+// The run's kernels (all enqueue on st).  `prog`: host-mapped progress word.
+struct CxIn {
+    const float *A, *F, *FD, *PA, *PE;
+    const uint32_t *ids;
+    uint32_t n;
+    uint32_t *prog;
+};
+hipError_t cx_launch_prep(const Grid &g, const CxDev &d, const CxIn &in, hipStream_t st);
+hipError_t cx_launch_body(const Grid &g, const CxDev &d, const CxIn &in, hipStream_t st);
+hipError_t cx_launch_outputs(const Grid &g, const CxDev &d, const CxIn &in, hipStream_t st);
+// h_ch in fp64, re and im of bin k at out[2k], out[2k + 1].
+hipError_t cx_launch_h(const Grid &g, const CxDev &d, uint32_t n, int ch, double *out, hipStream_t st);
+// Templates of n sources: q[i] (INT64_MIN: none) and U[i][CX_NF] (re, im).
+hipError_t cx_launch_templates(const Grid &g, const float *A, const float *F, const float *FD, uint32_t n,
+                               int64_t *q, double *U, hipStream_t st);
 
 struct CoarseEdges { double e[COARSE_MAX + 1]; };
 

@@ -27,7 +27,11 @@ EXPORTS = ["gbsub_default_config", "gbsub_create", "gbsub_workspace_size", "gbsu
            "gbsub_status_str",
            "gbsub_set_profiling", "gbsub_kernel_stats", "gbsub_batch_table_size",
            "gbsub_batch_create", "gbsub_batch_admit", "gbsub_batch_step", "gbsub_batch_poll",
-           "gbsub_batch_retire", "gbsub_batch_destroy", "gbsub_generate", "gbsub_run_static"]
+           "gbsub_batch_retire", "gbsub_batch_destroy", "gbsub_generate", "gbsub_run_static",
+           "gbsub_cx_workspace_size", "gbsub_cx_run", "gbsub_cx_spectrum", "gbsub_cx_resolved",
+           "gbsub_cx_templates"]
+CX_NF = 128                       # GBSUB_CX_NF
+SPEC_H_RESIDUAL = 4               # GBSUB_SPEC_H_RESIDUAL
 STATIC_WORKSPACE_BYTES = 64 << 20   # GBSUB_STATIC_WORKSPACE_BYTES
 SLOT_RUNNING, SLOT_SETTLED, SLOT_MAXITER, SLOT_INVALID, SLOT_FREE = 0, 1, 2, 3, 255
 (KF_TABLES, KF_RESET, KF_PREP, KF_XUPDATE, KF_MEDIAN, KF_SNR, KF_OUTPUT) = range(7)
@@ -59,6 +63,11 @@ class PopulationStruct(C.Structure):
 class CatalogStruct(C.Structure):
     _fields_ = [("n", C.c_uint64), ("A", C.c_void_p), ("f", C.c_void_p), ("fdot", C.c_void_p),
                 ("id", C.c_void_p)]
+
+
+class CxCatalogStruct(C.Structure):
+    _fields_ = [("n", C.c_uint64), ("A", C.c_void_p), ("f", C.c_void_p), ("fdot", C.c_void_p),
+                ("phi_a", C.c_void_p), ("phi_e", C.c_void_p), ("id", C.c_void_p)]
 
 
 class KernelStat(C.Structure):
@@ -126,6 +135,18 @@ def load(path: str | None = None):
     L.gbsub_batch_destroy.restype = None
     L.gbsub_generate.argtypes = [C.POINTER(PopulationStruct), C.c_uint64, C.c_uint64, C.c_uint64,
                                  C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+    L.gbsub_cx_workspace_size.argtypes = [C.c_void_p, C.c_uint64, C.POINTER(C.c_uint64)]
+    L.gbsub_cx_run.argtypes = [C.c_void_p, C.POINTER(CxCatalogStruct), C.c_void_p, C.c_uint64,
+                               C.c_void_p, C.POINTER(SummaryStruct)]
+    L.gbsub_cx_spectrum.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, C.c_void_p, C.c_uint64,
+                                    C.POINTER(C.c_uint64), C.c_int]
+    L.gbsub_cx_resolved.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64,
+                                    C.POINTER(C.c_uint64), C.c_int]
+    L.gbsub_cx_templates.argtypes = [C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p, C.c_void_p,
+                                     C.c_void_p, C.c_void_p, C.c_void_p]
+    for name in ("gbsub_cx_workspace_size", "gbsub_cx_run", "gbsub_cx_spectrum", "gbsub_cx_resolved",
+                 "gbsub_cx_templates"):
+        getattr(L, name).restype = C.c_int
     for name in ("gbsub_create", "gbsub_workspace_size", "gbsub_run", "gbsub_run_static", "gbsub_spectrum",
                  "gbsub_resolved", "gbsub_candidates", "gbsub_coarse", "gbsub_set_profiling",
                  "gbsub_kernel_stats",
@@ -200,6 +221,31 @@ class DeviceCatalog:
                 raise ValueError("catalog arrays must be contiguous 4-byte GPU tensors of length n")
         return CatalogStruct(self.n, self.A.data_ptr(), self.f.data_ptr(), self.fdot.data_ptr(),
                              self.id.data_ptr())
+
+
+class DeviceCxCatalog(DeviceCatalog):
+    """A catalog of the complex-template model on the GPU: A, f, fdot and the
+    channel phases phi_a, phi_e (fp32), id (int32 view of uint32)."""
+
+    def __init__(self, A, f, fdot, phi_a, phi_e, ids):
+        super().__init__(A, f, fdot, ids)
+        self.phi_a, self.phi_e = phi_a, phi_e
+
+    @classmethod
+    def from_host(cls, cat, phi_a, phi_e, device="cuda"):
+        torch = _torch()
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(device)
+        return cls(t(cat.A.astype(np.float32)), t(cat.f.astype(np.float32)), t(cat.fdot.astype(np.float32)),
+                   t(np.asarray(phi_a, np.float32)), t(np.asarray(phi_e, np.float32)),
+                   t(cat.id.astype(np.uint32).view(np.int32)))
+
+    def cx_struct(self) -> CxCatalogStruct:
+        self.struct()                          # checks A, f, fdot, id
+        for x in (self.phi_a, self.phi_e):
+            if not (x.is_cuda and x.is_contiguous() and x.element_size() == 4 and x.shape[0] == self.n):
+                raise ValueError("phase arrays must be contiguous fp32 GPU tensors of length n")
+        return CxCatalogStruct(self.n, self.A.data_ptr(), self.f.data_ptr(), self.fdot.data_ptr(),
+                               self.phi_a.data_ptr(), self.phi_e.data_ptr(), self.id.data_ptr())
 
 
 class Context:
@@ -353,6 +399,88 @@ class Context:
         if st != OK:
             raise GbsubError(st, "gbsub_resolved")
         return ids, it
+
+
+class CxRun:
+    """Complex-template runs (gbsub_cx_*) on a context."""
+
+    def __init__(self, ctx: Context):
+        self.ctx = ctx
+        self._L = ctx._L
+        self.workspace = None
+
+    def workspace_size(self, n: int) -> int:
+        b = C.c_uint64()
+        st = self._L.gbsub_cx_workspace_size(self.ctx.h, int(n), C.byref(b))
+        if st != OK:
+            raise GbsubError(st, "gbsub_cx_workspace_size")
+        return b.value
+
+    def ensure_workspace(self, n: int, device="cuda"):
+        torch = _torch()
+        need = self.workspace_size(n)
+        if self.workspace is None or self.workspace.numel() < need + 256:
+            self.workspace = torch.empty(need + 256, dtype=torch.uint8, device=device)
+        return self.workspace
+
+    def run_raw(self, cat: DeviceCxCatalog, ws=None, stream=None) -> tuple[int, Summary]:
+        torch = _torch()
+        ws = self.ensure_workspace(cat.n) if ws is None else ws
+        ptr, nbytes = self.ctx._ws_ptr(ws)
+        s = SummaryStruct()
+        sp = (stream or torch.cuda.current_stream()).cuda_stream
+        cs = cat.cx_struct()
+        st = self._L.gbsub_cx_run(self.ctx.h, C.byref(cs), C.c_void_p(ptr), nbytes, C.c_void_p(sp),
+                                  C.byref(s))
+        return st, _summary(s)
+
+    def run(self, cat: DeviceCxCatalog, ws=None, stream=None) -> Summary:
+        st, s = self.run_raw(cat, ws, stream)
+        if st != OK:
+            raise GbsubError(st, "gbsub_cx_run")
+        return s
+
+    def spectrum(self, channel: int, kind: int = SPEC_SN) -> np.ndarray:
+        """Host copy of a spectrum of channel 0 (A) or 1 (E); SPEC_H_RESIDUAL
+        gives the complex data left (complex128 [B])."""
+        n = C.c_uint64()
+        st = self._L.gbsub_cx_spectrum(self.ctx.h, channel, kind, None, 0, C.byref(n), 0)
+        if st not in (OK, E_TRUNCATED):
+            raise GbsubError(st, "gbsub_cx_spectrum")
+        m = 2 * n.value if kind == SPEC_H_RESIDUAL else n.value
+        buf = np.empty(m, np.float64)
+        st = self._L.gbsub_cx_spectrum(self.ctx.h, channel, kind, buf.ctypes.data, m, C.byref(n), 0)
+        if st != OK:
+            raise GbsubError(st, "gbsub_cx_spectrum")
+        return buf[0::2] + 1j * buf[1::2] if kind == SPEC_H_RESIDUAL else buf
+
+    def resolved(self):
+        n = C.c_uint64()
+        st = self._L.gbsub_cx_resolved(self.ctx.h, None, None, 0, C.byref(n), 0)
+        if st not in (OK, E_TRUNCATED):
+            raise GbsubError(st, "gbsub_cx_resolved")
+        ids = np.empty(n.value, np.uint32)
+        it = np.empty(n.value, np.int32)
+        st = self._L.gbsub_cx_resolved(self.ctx.h, ids.ctypes.data, it.ctypes.data, ids.shape[0],
+                                       C.byref(n), 0)
+        if st != OK:
+            raise GbsubError(st, "gbsub_cx_resolved")
+        return ids, it
+
+    def templates(self, A, f, fdot, stream=None):
+        """(q int64 [n], U complex128 [n, CX_NF]) of the sources in GPU tensors A, f, fdot (fp32)."""
+        torch = _torch()
+        n = int(A.shape[0])
+        q = torch.empty(max(n, 1), dtype=torch.int64, device=A.device)
+        U = torch.empty((max(n, 1), CX_NF, 2), dtype=torch.float64, device=A.device)
+        sp = (stream or torch.cuda.current_stream()).cuda_stream
+        st = self._L.gbsub_cx_templates(self.ctx.h, n, C.c_void_p(A.data_ptr()), C.c_void_p(f.data_ptr()),
+                                        C.c_void_p(fdot.data_ptr()), C.c_void_p(q.data_ptr()),
+                                        C.c_void_p(U.data_ptr()), C.c_void_p(sp))
+        if st != OK:
+            raise GbsubError(st, "gbsub_cx_templates")
+        Uh = U[:n].cpu().numpy()
+        return q[:n].cpu().numpy(), Uh[..., 0] + 1j * Uh[..., 1]
 
 
 def _summary(s: SummaryStruct) -> Summary:

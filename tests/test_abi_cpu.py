@@ -33,6 +33,7 @@ def test_struct_layouts_match_header():
     # sizes implied by the header's field order (no padding by construction)
     assert C.sizeof(G.Config) == 104
     assert C.sizeof(G.CatalogStruct) == 40
+    assert C.sizeof(G.CxCatalogStruct) == 56
     assert C.sizeof(G.SummaryStruct) == 48
     assert C.sizeof(G.KernelStat) == 64
 
