@@ -523,9 +523,107 @@ def bench_precision(args):
     print(json.dumps(out), flush=True)
 
 
+# Algorithmic work per unit of the complex-template model's kernel families.
+# HBM-bound: bytes per unit.  Template-bound (FFT synthesis of a 128-sample
+# template in fp64): counted flops per template -- the 128-point complex FFT
+# 5 N log2 N = 4480, the sample phases and scaling 128 x 8 = 1024, the
+# power-weighted sum 128 x 5 = 640; the two sincospi per lane are not counted.
+CX_ALGO = {
+    "xupdate": ("hbm", 48.0),        # per bin: read 4 int64 of h, write X_A, X_E
+    "median": ("hbm", 24.0),         # per output bin and channel: read X and S_instr, write S
+    "prep": ("alu", 6144.0),         # per source: one template (injection and candidate cut)
+    "snr": ("alu", 6144.0),          # per candidate evaluation: one template
+}
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+
+
+def bench_cx(args):
+    """The complex-template data model (gbsub_cx_run) on the 1e7 catalog with
+    its channel phases: whole runs, inputs resident in HBM."""
+    import numpy as np
+    import torch
+    from paper_2602_18560_amd import gbsub as G
+    from paper_2602_18560_amd.inputs import catalog_cx_1e7
+    log("[cx] drawing the 1e7-binary catalog and its template phases")
+    cat, pa, pe, run = catalog_cx_1e7()
+    if args.n != 10_000_000:
+        sub = np.arange(int(args.n))
+        cat, pa, pe = cat.subset(sub), pa[sub], pe[sub]
+    torch.cuda.set_device(0)
+    dc = G.DeviceCxCatalog.from_host(cat, pa, pe)
+    ctx = G.Context(G.config_from_run(run))
+    cx = G.CxRun(ctx)
+    cx.ensure_workspace(cat.n)
+    for _ in range(max(args.warmup, 1)):
+        s = cx.run(dc)
+    torch.cuda.synchronize()
+    log(f"[cx] n_iter={s.n_iter} candidates={s.n_candidates} resolved={s.n_resolved}; timing {args.steps} runs")
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        s = cx.run(dc)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    # one more run with HIP events around every kernel family
+    ctx.set_profiling(True)
+    cx.run(dc)
+    torch.cuda.synchronize()
+    stats = ctx.kernel_stats()
+    ctx.set_profiling(False)
+    ctx.close()
+    fams = {}
+    for name, st in stats.items():
+        if name not in CX_ALGO or st["launches"] == 0:
+            continue
+        bound, per = CX_ALGO[name]
+        avg_ms = st["total_ms"] / st["launches"]
+        units = st["units"] / st["launches"]
+        if bound == "hbm":
+            ach, peak, unit = per * units / (avg_ms * 1e-3) / 1e9, 8000.0, "GB/s"
+        else:
+            ach, peak, unit = per * units / (avg_ms * 1e-3) / 1e12, FP64_VECTOR_PEAK_TFLOPS, "TFLOP/s"
+        fams[name] = {"launches": st["launches"], "total_ms": st["total_ms"], "avg_launch_ms": avg_ms,
+                      "units_per_launch": units, "bound": bound, "achieved": ach, "peak": peak, "unit": unit,
+                      "frac": ach / peak}
+    dom = max(fams, key=lambda k: fams[k]["total_ms"])
+    d = fams[dom]
+    roof = {"bound": d["bound"], "achieved": d["achieved"], "peak": d["peak"], "unit": d["unit"],
+            "frac": d["frac"], "traffic": None, "kernel": dom, "avg_launch_ms": d["avg_launch_ms"]}
+    out = {"metric": "binary-iterations/s", "value": cat.n * s.n_iter / (ms * 1e-3),
+           "unit": "binary-iterations/s", "n_gpus": 1, "steps": args.steps, "warmup": max(args.warmup, 1),
+           "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"complex-template data model: {cat.n}-binary catalog (seed 2, phases "
+                                  "seed 2), T = 4 yr, [0.1, 30] mHz (3,774,290 bins), 128-sample templates "
+                                  "in A and E, running median W = 1001 per channel, rho_th = 7",
+                      "n_iter": s.n_iter, "n_candidates": s.n_candidates, "n_resolved": s.n_resolved},
+           "roofline": roof, "families": fams}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cx_cpu_baseline(cat, pa, pe, run)
+    print(json.dumps(out), flush=True)
+
+
+def cx_cpu_baseline(cat, pa, pe, run, n_sub=100_000):
+    """The complex-template oracle on the first n_sub sources of the same
+    catalog and grid, one loop body."""
+    from oracle import oracle as O
+    threads = O.set_threads(all_threads())
+    sub = slice(0, min(n_sub, cat.n))
+    from paper_2602_18560_amd.inputs import Catalog
+    c2 = Catalog(cat.A[sub], cat.f[sub], cat.fdot[sub], cat.id[sub])
+    cfg = O.make_config(run, max_iter=1)
+    t0 = time.perf_counter()
+    r = O.cx_run(c2, pa[sub], pe[sub], cfg, spectra=False)
+    dt = time.perf_counter() - t0
+    return {"value": c2.n * r.n_iter / dt, "unit": "binary-iterations/s", "cores": threads, "kind": "oracle",
+            "host_cpu": host_cpu()["model"],
+            "sample": f"the first {c2.n} sources of the same catalog on the same grid, {r.n_iter} loop body "
+                      f"(templates, injection, candidate cut, per-channel running median over all bins, SNR), "
+                      f"{dt:.1f} s on {threads} threads"}
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", choices=["1e7", "batch", "serve", "precision", "generate", "oracle"],
+    ap.add_argument("--workload", choices=["1e7", "batch", "serve", "precision", "generate", "oracle", "cx"],
                     default="1e7")
     ap.add_argument("--catalogs", type=int, default=64, help="batch: number of catalogs")
     ap.add_argument("--jobs", type=int, default=2000, help="serve: number of jobs")
@@ -575,6 +673,8 @@ def main():
         return bench_generate(args)
     if args.workload == "oracle":
         return bench_oracle(args)
+    if args.workload == "cx":
+        return bench_cx(args)
 
     import numpy as np
     import torch

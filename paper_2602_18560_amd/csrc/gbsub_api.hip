@@ -806,9 +806,18 @@ gbsub_status gbsub_cx_run(gbsub_ctx *c, const gbsub_cx_catalog *cat, void *ws, u
         (void)hipStreamSynchronize(st);
         return s;
     };
+    c->ev_used = 0;
+    c->recs.clear();
     hipError_t e = hipMemcpyAsync(d.slots, c->host_cx_slots, 2 * sizeof(Slot), hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = cx_launch_prep(g, d, in, st);
+    if (e == hipSuccess) e = c->timed(K_PREP, -1, st, [&] { return cx_launch_prep(g, d, in, st); });
     if (e != hipSuccess) return fail(GBSUB_E_DEVICE);
+    auto body = [&](int64_t ti) {
+        hipError_t r = c->timed(K_XUPDATE, ti, st, [&] { return cx_launch_power(g, d, in, st); });
+        if (r == hipSuccess)
+            r = c->timed_ext(K_MEDIAN, ti, [&](hipEvent_t a, hipEvent_t b) { return cx_launch_psd(g, d, st, a, b); });
+        if (r == hipSuccess) r = c->timed(K_SNR, ti, st, [&] { return cx_launch_snr(g, d, in, st); });
+        return r;
+    };
     // loop bodies paced by the progress word, as in gbsub_run
     constexpr uint64_t AHEAD = 2;
     const uint64_t guard = (uint64_t)cat->n + 2 + (c->cfg.max_iter ? c->cfg.max_iter : 0);
@@ -821,7 +830,7 @@ gbsub_status gbsub_cx_run(gbsub_ctx *c, const gbsub_cx_catalog *cat, void *ws, u
         const uint32_t seen = w >> 1;
         if (t < (uint64_t)seen + AHEAD) {
             if (t > guard) return fail(GBSUB_E_DEVICE);
-            if (cx_launch_body(g, d, in, st) != hipSuccess) return fail(GBSUB_E_DEVICE);
+            if (body((int64_t)t) != hipSuccess) return fail(GBSUB_E_DEVICE);
             ++t;
             continue;
         }
@@ -844,7 +853,7 @@ gbsub_status gbsub_cx_run(gbsub_ctx *c, const gbsub_cx_catalog *cat, void *ws, u
         if (e != hipSuccess) return fail(GBSUB_E_DEVICE);
         if (c->host_ctl->done) break;
         if (t > guard) return GBSUB_E_DEVICE;
-        if (cx_launch_body(g, d, in, st) != hipSuccess) return fail(GBSUB_E_DEVICE);
+        if (body((int64_t)t) != hipSuccess) return fail(GBSUB_E_DEVICE);
         ++t;
     }
     e = cx_launch_outputs(g, d, in, st);
@@ -853,6 +862,20 @@ gbsub_status gbsub_cx_run(gbsub_ctx *c, const gbsub_cx_catalog *cat, void *ws, u
     if (e != hipSuccess) return fail(GBSUB_E_DEVICE);
     const Ctl &h = *c->host_ctl;
     if (h.bad) return GBSUB_E_INVALID;
+    if (c->profiling) {
+        for (const auto &r : c->recs) {
+            if (r.t >= (int64_t)h.n_iter) continue;        // bodies enqueued past the settled one
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) return GBSUB_E_DEVICE;
+            c->k_ms[r.kid] += ms;
+            c->k_launches[r.kid] += 1;
+        }
+        const uint32_t m = c->profiling;
+        if (m >> K_PREP & 1u) c->k_units[K_PREP] += (double)cat->n;
+        if (m >> K_XUPDATE & 1u) c->k_units[K_XUPDATE] += (double)h.units_x;
+        if (m >> K_MEDIAN & 1u) c->k_units[K_MEDIAN] += 2.0 * (double)h.units_med;   // both channels
+        if (m >> K_SNR & 1u) c->k_units[K_SNR] += (double)h.units_snr;
+    }
     gbsub_summary s = summary_of(g, h);
     s.n_candidates = h.cand_cursor;
     if (out) *out = s;

@@ -717,10 +717,14 @@ hipError_t cx_launch_prep(const Grid &g, const CxDev &d, const CxIn &in, hipStre
     return hipGetLastError();
 }
 
-hipError_t cx_launch_body(const Grid &g, const CxDev &d, const CxIn &in, hipStream_t st)
+hipError_t cx_launch_power(const Grid &g, const CxDev &d, const CxIn &in, hipStream_t st)
 {
-    const KArgs a = args_of(g, d, in);
-    k_cx_power<<<g.nt, WG, 0, st>>>(a);
+    k_cx_power<<<g.nt, WG, 0, st>>>(args_of(g, d, in));
+    return hipGetLastError();
+}
+
+hipError_t cx_launch_psd(const Grid &g, const CxDev &d, hipStream_t st, hipEvent_t ea, hipEvent_t eb)
+{
     Dims dm{};
     dm.ns = 2;
     dm.maxB = g.B;
@@ -728,8 +732,12 @@ hipError_t cx_launch_body(const Grid &g, const CxDev &d, const CxIn &in, hipStre
     dm.maxtile = g.tile;
     dm.maxparts = g.nparts;
     dm.est_mask = 1u << g.est;
-    hipError_t e = launch_median(d.slots, dm, st);
-    if (e != hipSuccess) return e;
+    return launch_median(d.slots, dm, st, ea, eb);
+}
+
+hipError_t cx_launch_snr(const Grid &g, const CxDev &d, const CxIn &in, hipStream_t st)
+{
+    const KArgs a = args_of(g, d, in);
     k_cx_snr<<<SNR_GRID, WG, 0, st>>>(a);
     k_cx_tail<<<1, WG, 0, st>>>(a);
     return hipGetLastError();

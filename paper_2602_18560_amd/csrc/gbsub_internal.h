@@ -268,7 +268,13 @@ struct CxIn {
     uint32_t *prog;
 };
 hipError_t cx_launch_prep(const Grid &g, const CxDev &d, const CxIn &in, hipStream_t st);
-hipError_t cx_launch_body(const Grid &g, const CxDev &d, const CxIn &in, hipStream_t st);
+// A loop body: X update, the PSD of both channels (the median or mean
+// kernels; optional events stamped by the dispatch), SNR + subtraction and
+// the tail.
+hipError_t cx_launch_power(const Grid &g, const CxDev &d, const CxIn &in, hipStream_t st);
+hipError_t cx_launch_psd(const Grid &g, const CxDev &d, hipStream_t st, hipEvent_t ea = nullptr,
+                         hipEvent_t eb = nullptr);
+hipError_t cx_launch_snr(const Grid &g, const CxDev &d, const CxIn &in, hipStream_t st);
 hipError_t cx_launch_outputs(const Grid &g, const CxDev &d, const CxIn &in, hipStream_t st);
 // h_ch in fp64, re and im of bin k at out[2k], out[2k + 1].
 hipError_t cx_launch_h(const Grid &g, const CxDev &d, uint32_t n, int ch, double *out, hipStream_t st);

@@ -45,6 +45,7 @@ def kernel_source_hash() -> str:
 
 
 def short(name: str) -> str:
+    name = name.replace("(anonymous namespace)::", "")
     return name.split("(")[0].replace("gbs::", "")
 
 
