@@ -53,7 +53,7 @@ constexpr int NF = CX_NF;
 constexpr int HALO = NF / 2;                  // template reach on each side of its centre
 constexpr int CXW = CX_TILE + NF;             // LDS window of an injection block
 constexpr int SRC_PB = 4096;                  // sources per block of the count and scatter passes
-constexpr int CH = 512;                       // sources per injection block at most
+constexpr int CH = 4096;                      // sources per injection block at most
 constexpr int SNR_GRID = 2048;                // blocks of the SNR launch
 constexpr int PLAN_T = 1024;                  // threads of the one-block plan
 
@@ -139,17 +139,32 @@ __device__ __forceinline__ void wave_template(double A, double delta, double d, 
     const double2 a = make_double2(hA * c0, hA * s0), b = make_double2(hA * c1, hA * s1);
     double2 y0 = cadd(a, b);
     double2 y1 = cmul(csub(a, b), tw[l]);
+    // Butterflies without branches: top lanes take v + p (twiddle 1, which
+    // leaves the sum exact), bottom lanes (p - v) w; both as p + sgn v.
 #pragma unroll
-    for (int span = 32; span >= 1; span >>= 1) {
+    for (int span = 32; span >= 4; span >>= 1) {
         const double2 p0 = shfl_xor2(y0, span), p1 = shfl_xor2(y1, span);
-        if ((l & span) == 0) {
-            y0 = cadd(y0, p0);
-            y1 = cadd(y1, p1);
-        } else {
-            const double2 w = tw[(l & (span - 1)) * (64 / span)];
-            y0 = cmul(csub(p0, y0), w);
-            y1 = cmul(csub(p1, y1), w);
-        }
+        const bool bottom = (l & span) != 0;
+        const double sg = bottom ? -1.0 : 1.0;
+        const double2 w = bottom ? tw[(l & (span - 1)) * (64 / span)] : make_double2(1.0, 0.0);
+        y0 = cmul(make_double2(fma(sg, y0.x, p0.x), fma(sg, y0.y, p0.y)), w);
+        y1 = cmul(make_double2(fma(sg, y1.x, p1.x), fma(sg, y1.y, p1.y)), w);
+    }
+    // span 2: twiddles 1 and -i (a swap and a sign); span 1: twiddle 1
+    {
+        const double2 p0 = shfl_xor2(y0, 2), p1 = shfl_xor2(y1, 2);
+        const double sg = (l & 2) ? -1.0 : 1.0;
+        const double2 d0 = make_double2(fma(sg, y0.x, p0.x), fma(sg, y0.y, p0.y));
+        const double2 d1 = make_double2(fma(sg, y1.x, p1.x), fma(sg, y1.y, p1.y));
+        const bool rot = (l & 3) == 3;
+        y0 = rot ? make_double2(d0.y, -d0.x) : d0;
+        y1 = rot ? make_double2(d1.y, -d1.x) : d1;
+    }
+    {
+        const double2 p0 = shfl_xor2(y0, 1), p1 = shfl_xor2(y1, 1);
+        const double sg = (l & 1) ? -1.0 : 1.0;
+        y0 = make_double2(fma(sg, y0.x, p0.x), fma(sg, y0.y, p0.y));
+        y1 = make_double2(fma(sg, y1.x, p1.x), fma(sg, y1.y, p1.y));
     }
     const double sc = T / NF;
     *ue = make_double2(y0.x * sc, y0.y * sc);
@@ -231,7 +246,9 @@ __global__ __launch_bounds__(WG) void k_cx_sinstr(KArgs a)
 {
     const int k = blockIdx.x * WG + threadIdx.x;
     if (k >= a.g.B) return;
-    a.d.sx[k] = sinstr_dev((double)(a.g.k0 + k) / a.g.T, a.g.oms_pm, a.g.tm_fm, a.g.arm_m);
+    const double v = sinstr_dev((double)(a.g.k0 + k) / a.g.T, a.g.oms_pm, a.g.tm_fm, a.g.arm_m);
+    a.d.sx[k] = v;
+    a.d.isx[k] = 1.0 / v;
 }
 
 // Sources per binning tile (LDS histogram per block), the largest amplitude
@@ -367,9 +384,57 @@ __global__ __launch_bounds__(WG) void k_cx_scatter(KArgs a)
     }
 }
 
+// Per-source constants of a template, one source per lane: index, centre
+// bin, delta, d, A and the channel rotations (cos, sin of phi_A and phi_E).
+struct SrcConsts {
+    uint32_t i;
+    int qb;
+    double delta, d, A, ca, sa, ce, se;
+};
+
+__device__ __forceinline__ SrcConsts src_consts(const Grid &g, const CxIn &in, uint32_t i, bool rot)
+{
+    SrcConsts c;
+    c.i = i;
+    c.qb = centre_bin(g, in.F[i], in.FD[i], &c.delta, &c.d);
+    c.A = (double)in.A[i];
+    c.ca = c.sa = c.ce = c.se = 0.0;
+    if (rot) {
+        sincos((double)in.PA[i], &c.sa, &c.ca);
+        sincos((double)in.PE[i], &c.se, &c.ce);
+    }
+    return c;
+}
+
+// Lane k's constants (k wave-uniform), on every lane.
+__device__ __forceinline__ double rl(double v, int k)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), k);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), k);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ SrcConsts bcast(const SrcConsts &c, int k)
+{
+    SrcConsts r;
+    r.i = (uint32_t)__builtin_amdgcn_readlane((int)c.i, k);
+    r.qb = __builtin_amdgcn_readlane(c.qb, k);
+    r.delta = rl(c.delta, k);
+    r.d = rl(c.d, k);
+    r.A = rl(c.A, k);
+    r.ca = rl(c.ca, k);
+    r.sa = rl(c.sa, k);
+    r.ce = rl(c.ce, k);
+    r.se = rl(c.se, k);
+    return r;
+}
+
 // Injection: h += every template (both channels), and the candidate cut
 // rho_0^2 = (8/T) sum_j |U_j|^2 / S_instr >= (kappa rho_th)^2.  One block per
-// chunk of at most CH sources of one binning tile; one wave per source.
+// chunk of at most CH sources of one binning tile; each wave takes 64
+// sources at a time, their constants computed one per lane, then one
+// template after the other by the whole wave.
 __global__ __launch_bounds__(WG) void k_cx_inject(KArgs a)
 {
     __shared__ long long acc[4][CXW];
@@ -396,40 +461,40 @@ __global__ __launch_bounds__(WG) void k_cx_inject(KArgs a)
     int je, jo;
     lane_offsets(&je, &jo);
     const double cut2 = g.cut2, T = g.T;
-    for (uint32_t s = s0 + (threadIdx.x >> 6); s < s1; s += WG / 64) {
-        const uint32_t i = d.order[s];
-        const float A = in.A[i];
-        double delta, dd;
-        const int qb = centre_bin(g, in.F[i], in.FD[i], &delta, &dd);
-        double2 ue, uo;
-        wave_template((double)A, delta, dd, T, tw, &ue, &uo);
-        const int be = qb + je, bo = qb + jo;
-        const bool ine = be >= 0 && be < g.B, ino = bo >= 0 && bo < g.B;
-        const double pe = ue.x * ue.x + ue.y * ue.y, po = uo.x * uo.x + uo.y * uo.y;
-        double r0 = (ine ? pe / d.sx[be] : 0.0) + (ino ? po / d.sx[bo] : 0.0);
-        r0 = (8.0 / T) * wave_sum(r0);
-        if (r0 >= cut2 && lane() == 0) {
-            const uint32_t slot = atomicAdd(&d.ctl->cand_cursor, 1u);
-            d.c_src[slot] = i;
-            d.c_iter[slot] = -1;
-            d.c_rho2[slot] = r0;
-        }
-        double sa, ca, se, ce;
-        sincos((double)in.PA[i], &sa, &ca);
-        sincos((double)in.PE[i], &se, &ce);
-        if (ine) {
-            unsigned long long *p = (unsigned long long *)&acc[0][be - w0];
-            atomicAdd(p, (unsigned long long)fx(ca * ue.x - sa * ue.y, E));
-            atomicAdd(p + CXW, (unsigned long long)fx(sa * ue.x + ca * ue.y, E));
-            atomicAdd(p + 2 * CXW, (unsigned long long)fx(ce * ue.x - se * ue.y, E));
-            atomicAdd(p + 3 * CXW, (unsigned long long)fx(se * ue.x + ce * ue.y, E));
-        }
-        if (ino) {
-            unsigned long long *p = (unsigned long long *)&acc[0][bo - w0];
-            atomicAdd(p, (unsigned long long)fx(ca * uo.x - sa * uo.y, E));
-            atomicAdd(p + CXW, (unsigned long long)fx(sa * uo.x + ca * uo.y, E));
-            atomicAdd(p + 2 * CXW, (unsigned long long)fx(ce * uo.x - se * uo.y, E));
-            atomicAdd(p + 3 * CXW, (unsigned long long)fx(se * uo.x + ce * uo.y, E));
+    const int wave = threadIdx.x >> 6;
+    for (uint32_t base = s0 + 64u * (uint32_t)wave; base < s1; base += 64u * (WG / 64)) {
+        const uint32_t s = base + (uint32_t)lane();
+        const SrcConsts mine = src_consts(g, in, d.order[s < s1 ? s : s0], true);
+        const int cnt = (int)min(64u, s1 - base);
+        for (int k = 0; k < cnt; ++k) {
+            const SrcConsts c = bcast(mine, k);
+            double2 ue, uo;
+            wave_template(c.A, c.delta, c.d, T, tw, &ue, &uo);
+            const int be = c.qb + je, bo = c.qb + jo;
+            const bool ine = be >= 0 && be < g.B, ino = bo >= 0 && bo < g.B;
+            const double pe = ue.x * ue.x + ue.y * ue.y, po = uo.x * uo.x + uo.y * uo.y;
+            double r0 = (ine ? pe * d.isx[be] : 0.0) + (ino ? po * d.isx[bo] : 0.0);
+            r0 = (8.0 / T) * wave_sum(r0);
+            if (r0 >= cut2 && lane() == 0) {
+                const uint32_t slot = atomicAdd(&d.ctl->cand_cursor, 1u);
+                d.c_src[slot] = c.i;
+                d.c_iter[slot] = -1;
+                d.c_rho2[slot] = r0;
+            }
+            if (ine) {
+                unsigned long long *p = (unsigned long long *)&acc[0][be - w0];
+                atomicAdd(p, (unsigned long long)fx(c.ca * ue.x - c.sa * ue.y, E));
+                atomicAdd(p + CXW, (unsigned long long)fx(c.sa * ue.x + c.ca * ue.y, E));
+                atomicAdd(p + 2 * CXW, (unsigned long long)fx(c.ce * ue.x - c.se * ue.y, E));
+                atomicAdd(p + 3 * CXW, (unsigned long long)fx(c.se * ue.x + c.ce * ue.y, E));
+            }
+            if (ino) {
+                unsigned long long *p = (unsigned long long *)&acc[0][bo - w0];
+                atomicAdd(p, (unsigned long long)fx(c.ca * uo.x - c.sa * uo.y, E));
+                atomicAdd(p + CXW, (unsigned long long)fx(c.sa * uo.x + c.ca * uo.y, E));
+                atomicAdd(p + 2 * CXW, (unsigned long long)fx(c.ce * uo.x - c.se * uo.y, E));
+                atomicAdd(p + 3 * CXW, (unsigned long long)fx(c.se * uo.x + c.ce * uo.y, E));
+            }
         }
     }
     __syncthreads();
@@ -471,7 +536,9 @@ __global__ __launch_bounds__(WG) void k_cx_power(KArgs a)
 // refiltered in this body (or stamped for the next one by a subtraction of
 // this launch: re-evaluating against an unchanged S gives the same value);
 // rho^2 > rho_th^2 subtracts its templates from h at once and stamps the
-// tiles whose X and S change.  One wave per candidate.
+// tiles whose X and S change.  Each wave takes 64 candidates at a time: the
+// lanes find which need an evaluation and their constants, then the wave
+// evaluates them one after the other.
 __global__ __launch_bounds__(WG) void k_cx_snr(KArgs a)
 {
     __shared__ double2 tw[NF];
@@ -492,55 +559,72 @@ __global__ __launch_bounds__(WG) void k_cx_snr(KArgs a)
     const uint32_t waves = gridDim.x * (WG / 64);
     uint32_t my_new = 0, my_near = 0, evals = 0;
     double minm = INFINITY;
-    for (uint32_t j = blockIdx.x * (WG / 64) + (threadIdx.x >> 6); j < nc; j += waves) {
-        if (d.c_iter[j] >= 0) continue;
-        const uint32_t i = d.c_src[j];
-        double delta, dd;
-        const int qb = centre_bin(g, in.F[i], in.FD[i], &delta, &dd);
-        const int lo = max(qb - HALO, 0), hi = min(qb + HALO - 1, g.B - 1);
-        if (t > 0) {
-            bool changed = false;
-            for (int tl = div_p2(lo, g.tile); tl <= div_p2(hi, g.tile); ++tl) changed |= d.sstamp[tl] >= t;
-            if (!changed) continue;
+    for (uint32_t base = (blockIdx.x * (WG / 64) + (threadIdx.x >> 6)) * 64u; base < nc; base += waves * 64u) {
+        const uint32_t j = base + (uint32_t)lane();
+        bool need = j < nc && d.c_iter[j] < 0;
+        SrcConsts mine{};
+        if (need) {
+            mine = src_consts(g, in, d.c_src[j], false);
+            if (t > 0) {
+                const int lo = max(mine.qb - HALO, 0), hi = min(mine.qb + HALO - 1, g.B - 1);
+                bool changed = false;
+                for (int tl = div_p2(lo, g.tile); tl <= div_p2(hi, g.tile); ++tl) changed |= d.sstamp[tl] >= t;
+                need = changed;
+            }
         }
-        ++evals;
-        double2 ue, uo;
-        wave_template((double)in.A[i], delta, dd, T, tw, &ue, &uo);
-        const int be = qb + je, bo = qb + jo;
-        const bool ine = be >= 0 && be < g.B, ino = bo >= 0 && bo < g.B;
-        const double pe = ue.x * ue.x + ue.y * ue.y, po = uo.x * uo.x + uo.y * uo.y;
-        double r = (ine ? pe * (1.0 / d.S[be] + 1.0 / d.S[B + be]) : 0.0) +
-                   (ino ? po * (1.0 / d.S[bo] + 1.0 / d.S[B + bo]) : 0.0);
-        const double r2 = (4.0 / T) * wave_sum(r);
-        const double rel = fabs(sqrt(r2) / g.rth - 1.0);
-        minm = fmin(minm, rel);
-        my_near += rel <= 1e-6;
-        if (lane() == 0) d.c_rho2[j] = r2;
-        if (!(r2 > g.rth2)) continue;
-        ++my_new;
-        if (lane() == 0) d.c_iter[j] = (int32_t)t;
-        double sa, ca, se, ce;
-        sincos((double)in.PA[i], &sa, &ca);
-        sincos((double)in.PE[i], &se, &ce);
-        if (ine) {
-            unsigned long long *p = (unsigned long long *)&d.h[be];
-            atomicAdd(p, (unsigned long long)-fx(ca * ue.x - sa * ue.y, E));
-            atomicAdd(p + B, (unsigned long long)-fx(sa * ue.x + ca * ue.y, E));
-            atomicAdd(p + 2 * B, (unsigned long long)-fx(ce * ue.x - se * ue.y, E));
-            atomicAdd(p + 3 * B, (unsigned long long)-fx(se * ue.x + ce * ue.y, E));
-        }
-        if (ino) {
-            unsigned long long *p = (unsigned long long *)&d.h[bo];
-            atomicAdd(p, (unsigned long long)-fx(ca * uo.x - sa * uo.y, E));
-            atomicAdd(p + B, (unsigned long long)-fx(sa * uo.x + ca * uo.y, E));
-            atomicAdd(p + 2 * B, (unsigned long long)-fx(ce * uo.x - se * uo.y, E));
-            atomicAdd(p + 3 * B, (unsigned long long)-fx(se * uo.x + ce * uo.y, E));
-        }
-        if (lane() == 0) {
-            stamp_tiles(d.xstamp, g, lo, hi, nxt);
-            int sa_, sb_;
-            window_reach(g, lo, hi, &sa_, &sb_);
-            stamp_tiles(d.sstamp, g, sa_, sb_, nxt);
+        uint64_t todo = (uint64_t)__ballot(need);
+        while (todo) {
+            const int k = (int)__builtin_ctzll(todo);
+            todo &= todo - 1;
+            const SrcConsts cs = bcast(mine, k);
+            const uint32_t jk = base + (uint32_t)k;
+            ++evals;
+            double2 ue, uo;
+            wave_template(cs.A, cs.delta, cs.d, T, tw, &ue, &uo);
+            const int be = cs.qb + je, bo = cs.qb + jo;
+            const bool ine = be >= 0 && be < g.B, ino = bo >= 0 && bo < g.B;
+            const double pe = ue.x * ue.x + ue.y * ue.y, po = uo.x * uo.x + uo.y * uo.y;
+            double r = 0.0;
+            if (ine) {
+                const double sA = d.S[be], sE = d.S[B + be];
+                r += pe * ((sA + sE) / (sA * sE));
+            }
+            if (ino) {
+                const double sA = d.S[bo], sE = d.S[B + bo];
+                r += po * ((sA + sE) / (sA * sE));
+            }
+            const double r2 = (4.0 / T) * wave_sum(r);
+            const double rel = fabs(sqrt(r2) / g.rth - 1.0);
+            minm = fmin(minm, rel);
+            my_near += rel <= 1e-6;
+            if (lane() == 0) d.c_rho2[jk] = r2;
+            if (!(r2 > g.rth2)) continue;
+            ++my_new;
+            if (lane() == 0) d.c_iter[jk] = (int32_t)t;
+            double sa, ca, se, ce;
+            sincos((double)in.PA[cs.i], &sa, &ca);
+            sincos((double)in.PE[cs.i], &se, &ce);
+            if (ine) {
+                unsigned long long *p = (unsigned long long *)&d.h[be];
+                atomicAdd(p, (unsigned long long)-fx(ca * ue.x - sa * ue.y, E));
+                atomicAdd(p + B, (unsigned long long)-fx(sa * ue.x + ca * ue.y, E));
+                atomicAdd(p + 2 * B, (unsigned long long)-fx(ce * ue.x - se * ue.y, E));
+                atomicAdd(p + 3 * B, (unsigned long long)-fx(se * ue.x + ce * ue.y, E));
+            }
+            if (ino) {
+                unsigned long long *p = (unsigned long long *)&d.h[bo];
+                atomicAdd(p, (unsigned long long)-fx(ca * uo.x - sa * uo.y, E));
+                atomicAdd(p + B, (unsigned long long)-fx(sa * uo.x + ca * uo.y, E));
+                atomicAdd(p + 2 * B, (unsigned long long)-fx(ce * uo.x - se * uo.y, E));
+                atomicAdd(p + 3 * B, (unsigned long long)-fx(se * uo.x + ce * uo.y, E));
+            }
+            if (lane() == 0) {
+                const int lo = max(cs.qb - HALO, 0), hi = min(cs.qb + HALO - 1, g.B - 1);
+                stamp_tiles(d.xstamp, g, lo, hi, nxt);
+                int sa_, sb_;
+                window_reach(g, lo, hi, &sa_, &sb_);
+                stamp_tiles(d.sstamp, g, sa_, sb_, nxt);
+            }
         }
     }
     if (lane() == 0) {
@@ -678,6 +762,7 @@ uint64_t cx_carve(const Grid &g, uint64_t n, char *base, CxDev *out)
     d.slots = (Slot *)take(2 * sizeof(Slot));
     d.ctl = (Ctl *)take(sizeof(Ctl));
     d.sx = (double *)take(B * 8);
+    d.isx = (double *)take(B * 8);
     d.X = (double *)take(2 * B * 8);
     d.S = (double *)take(2 * B * 8);
     d.is_pre = (double *)take(2 * B * 8);

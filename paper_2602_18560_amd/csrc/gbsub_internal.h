@@ -235,6 +235,7 @@ struct CxDev {
     Slot *slots;             // [2] median descriptors of the A and E channels
     Ctl *ctl;                // shared by both channels
     double *sx;              // [B] S_instr
+    double *isx;             // [B] 1 / S_instr
     double *X;               // [2][B] periodograms (2/T)|h_c|^2
     double *S;               // [2][B] PSD estimates
     double *is_pre;          // [2][B] in-part prefixes of 1/S (written by the median kernel)
