@@ -415,6 +415,14 @@ gbsub_status gbsub_cx_spectrum(const gbsub_ctx *ctx, uint32_t channel, uint32_t 
 gbsub_status gbsub_cx_resolved(const gbsub_ctx *ctx, uint32_t *ids, int32_t *iter_of, uint64_t cap, uint64_t *n,
                                int out_on_device);
 
+/* Every candidate of the last complex-template run, in ascending id, as
+ * gbsub_candidates: ids[], the loop body that resolved it (iter_of, -1 if
+ * never; may be NULL) and rho^2 at its last evaluation (rho2; may be NULL).
+ * HOST pointers of `cap` entries; TRUNCATED if cap is smaller; STATE if no
+ * complex-template run has completed. */
+gbsub_status gbsub_cx_candidates(const gbsub_ctx *ctx, uint32_t *ids, int32_t *iter_of, double *rho2, uint64_t cap,
+                                 uint64_t *n);
+
 /* Templates of n sources on the device (Sec. "Simulations", the model above):
  * q[i] (int64, central DFT index; INT64_MIN if the source has no template)
  * and U[i][128][2] (fp64 re, im of U_j, j = -64..63).  A, f, fdot, q, U are

@@ -942,6 +942,37 @@ gbsub_status gbsub_cx_resolved(const gbsub_ctx *c, uint32_t *ids, int32_t *iter_
     return dev_err(e);
 }
 
+gbsub_status gbsub_cx_candidates(const gbsub_ctx *c, uint32_t *ids, int32_t *iter_of, double *rho2, uint64_t cap,
+                                 uint64_t *n)
+{
+    if (!c || !n) return GBSUB_E_INVALID;
+    if (!c->cx_have_result) return GBSUB_E_STATE;
+    if (hipSetDevice(c->device) != hipSuccess) return GBSUB_E_DEVICE;
+    const uint64_t nc = c->cx_summ.n_candidates;
+    *n = nc;
+    if (cap < nc) return GBSUB_E_TRUNCATED;
+    if (nc == 0) return GBSUB_OK;
+    if (!ids) return GBSUB_E_INVALID;
+    std::vector<uint32_t> id(nc);
+    std::vector<int32_t> it(nc);
+    std::vector<double> r2(nc);
+    hipError_t e = hipMemcpy(id.data(), c->cx.c_id, nc * 4, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(it.data(), c->cx.c_iter, nc * 4, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(r2.data(), c->cx.c_rho2, nc * 8, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return GBSUB_E_DEVICE;
+    // candidate slots are handed out in order of discovery: order them by id
+    std::vector<uint64_t> order(nc);
+    for (uint64_t j = 0; j < nc; ++j) order[j] = ((uint64_t)id[j] << 32) | (uint32_t)j;
+    std::sort(order.begin(), order.end());
+    for (uint64_t q = 0; q < nc; ++q) {
+        const uint32_t j = (uint32_t)order[q];
+        ids[q] = id[j];
+        if (iter_of) iter_of[q] = it[j];
+        if (rho2) rho2[q] = r2[j];
+    }
+    return GBSUB_OK;
+}
+
 gbsub_status gbsub_cx_templates(const gbsub_ctx *c, uint64_t n, const float *A, const float *f, const float *fdot,
                                 int64_t *q, double *U, void *stream)
 {

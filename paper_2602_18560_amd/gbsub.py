@@ -29,7 +29,7 @@ EXPORTS = ["gbsub_default_config", "gbsub_create", "gbsub_workspace_size", "gbsu
            "gbsub_batch_create", "gbsub_batch_admit", "gbsub_batch_step", "gbsub_batch_poll",
            "gbsub_batch_retire", "gbsub_batch_destroy", "gbsub_generate", "gbsub_run_static",
            "gbsub_cx_workspace_size", "gbsub_cx_run", "gbsub_cx_spectrum", "gbsub_cx_resolved",
-           "gbsub_cx_templates"]
+           "gbsub_cx_templates", "gbsub_cx_candidates"]
 CX_NF = 128                       # GBSUB_CX_NF
 SPEC_H_RESIDUAL = 4               # GBSUB_SPEC_H_RESIDUAL
 STATIC_WORKSPACE_BYTES = 64 << 20   # GBSUB_STATIC_WORKSPACE_BYTES
@@ -144,8 +144,10 @@ def load(path: str | None = None):
                                     C.POINTER(C.c_uint64), C.c_int]
     L.gbsub_cx_templates.argtypes = [C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p, C.c_void_p,
                                      C.c_void_p, C.c_void_p, C.c_void_p]
+    L.gbsub_cx_candidates.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64,
+                                      C.POINTER(C.c_uint64)]
     for name in ("gbsub_cx_workspace_size", "gbsub_cx_run", "gbsub_cx_spectrum", "gbsub_cx_resolved",
-                 "gbsub_cx_templates"):
+                 "gbsub_cx_templates", "gbsub_cx_candidates"):
         getattr(L, name).restype = C.c_int
     for name in ("gbsub_create", "gbsub_workspace_size", "gbsub_run", "gbsub_run_static", "gbsub_spectrum",
                  "gbsub_resolved", "gbsub_candidates", "gbsub_coarse", "gbsub_set_profiling",
@@ -466,6 +468,21 @@ class CxRun:
         if st != OK:
             raise GbsubError(st, "gbsub_cx_resolved")
         return ids, it
+
+    def candidates(self):
+        """(ids uint32 ascending, iter_of int32, rho^2 at the last evaluation)."""
+        n = C.c_uint64()
+        st = self._L.gbsub_cx_candidates(self.ctx.h, None, None, None, 0, C.byref(n))
+        if st not in (OK, E_TRUNCATED):
+            raise GbsubError(st, "gbsub_cx_candidates")
+        ids = np.empty(n.value, np.uint32)
+        it = np.empty(n.value, np.int32)
+        r2 = np.empty(n.value, np.float64)
+        st = self._L.gbsub_cx_candidates(self.ctx.h, ids.ctypes.data, it.ctypes.data, r2.ctypes.data,
+                                         ids.shape[0], C.byref(n))
+        if st != OK:
+            raise GbsubError(st, "gbsub_cx_candidates")
+        return ids, it, r2
 
     def templates(self, A, f, fdot, stream=None):
         """(q int64 [n], U complex128 [n, CX_NF]) of the sources in GPU tensors A, f, fdot (fp32)."""

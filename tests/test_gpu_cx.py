@@ -1,8 +1,9 @@
 """GPU parity of the complex-template data model (gbsub_cx_*) against the
 FP64 oracle (oracle/template_oracle.c).
 
-Bar: identical candidate count, resolved set, loop body of each resolved
-source and loop count (a source whose oracle SNR lies within 1e-6 relative
+Bar: identical candidate set, resolved set, loop body of each resolved
+source and loop count, rho^2 of every candidate at its last evaluation
+within 1e-9 relative (a source whose oracle SNR lies within 1e-6 relative
 of the threshold may differ and is reported); S_A and S_E within 1e-9
 relative per bin; X and h within 1e-9 of the largest value of their channel
 (the GPU holds h as exact 64-bit fixed point with a unit of ~2^-62 of the
@@ -26,6 +27,7 @@ pytestmark = pytest.mark.gpu
 S_RTOL = 1e-9
 X_ATOL = 1e-9
 U_ATOL = 1e-12
+RHO2_RTOL = 1e-9
 NEAR = 1e-6
 
 
@@ -58,6 +60,7 @@ def gpu_cx(cat, pa, pe, run, **kw):
             o.Sx = cx.spectrum(0, G.SPEC_S_INSTR)
             o.Sgal = np.stack([cx.spectrum(c, G.SPEC_S_GAL) for c in (0, 1)])
             o.ids, o.it = cx.resolved()
+            o.cids, o.cit, o.cr2 = cx.candidates()
         return o
     finally:
         ctx.close()
@@ -87,6 +90,12 @@ def assert_cx_parity(cat, pa, pe, run, name, **kw):
         assert all(near[int(np.nonzero(cat.id == v)[0][0])] for v in diff)
         return ro, g
     assert s.n_near_threshold == ro.n_near
+    # every candidate: the same set, body and rho^2 at its last evaluation
+    cand = np.nonzero(ro.is_candidate)[0]
+    corder = np.argsort(cat.id[cand], kind="stable")
+    assert np.array_equal(g.cids, cat.id[cand][corder])
+    assert np.array_equal(g.cit, ro.iter_of[cand][corder])
+    np.testing.assert_allclose(g.cr2, ro.rho2_last[cand][corder], rtol=RHO2_RTOL, atol=0)
     np.testing.assert_allclose(g.S, ro.S_final, rtol=S_RTOL, atol=0)
     for ch in (0, 1):
         scale = max(ro.X_final[ch].max(), 1e-300)
