@@ -653,7 +653,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=10_000_000, help="catalog size (default: 1e7)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=3)
+    ap.add_argument("--cpu-iters", type=int, default=9)
     ap.add_argument("--oracle-bodies-single", type=int, default=1,
                     help="oracle workload: loop bodies of the one-thread 1e7 run")
     ap.add_argument("--oracle-bodies-batch", type=int, default=2,

@@ -197,6 +197,48 @@ def test_running_mean_estimator(W):
     assert_cx_parity(cat, pa, pe, run, f"mean W={W}")
 
 
+@pytest.mark.parametrize("tile,split", [(256, 0), (512, 1 << 20), (2048, 1)])
+def test_tiles_and_split_modes(tile, split):
+    """Other tiles and split budgets (every body split, or never): the
+    dirty-tile stamps and the split decision of the tail serve both channels."""
+    cat, pa, pe, run = catalog_cx_1e4()
+    assert_cx_parity(cat, pa, pe, run, f"tile {tile} split {split}", tile_bins=tile, split_blocks=split)
+
+
+def test_max_iter_guard():
+    cat, pa, pe, run = catalog_cx_1e4()
+    ctx = G.Context(G.config_from_run(run, max_iter=1))
+    try:
+        st, s = G.CxRun(ctx).run_raw(G.DeviceCxCatalog.from_host(cat, pa, pe))
+    finally:
+        ctx.close()
+    assert st == G.E_MAXITER and s.n_iter == 1
+
+
+def test_results_before_a_run_and_truncation():
+    cat, pa, pe, run = catalog_cx_1e4()
+    ctx = G.Context(G.config_from_run(run))
+    try:
+        L = ctx._L
+        n = G.C.c_uint64()
+        assert L.gbsub_cx_spectrum(ctx.h, 0, G.SPEC_SN, None, 0, G.C.byref(n), 0) == G.E_STATE
+        assert L.gbsub_cx_resolved(ctx.h, None, None, 0, G.C.byref(n), 0) == G.E_STATE
+        cx = G.CxRun(ctx)
+        cx.run(G.DeviceCxCatalog.from_host(cat, pa, pe))
+        buf = np.empty(10)
+        assert L.gbsub_cx_spectrum(ctx.h, 0, G.SPEC_SN, buf.ctypes.data, 10, G.C.byref(n), 0) == G.E_TRUNCATED
+        assert n.value == cat_bins(run)
+        assert L.gbsub_cx_spectrum(ctx.h, 2, G.SPEC_SN, buf.ctypes.data, 10, G.C.byref(n), 0) == G.E_INVALID
+        # the power-model results of this context are untouched by a template-model run
+        assert L.gbsub_spectrum(ctx.h, G.SPEC_SN, None, 0, G.C.byref(n), 0) == G.E_STATE
+    finally:
+        ctx.close()
+
+
+def cat_bins(run):
+    return O.grid(run.t_obs_s, run.f_min_hz, run.f_max_hz)[1]
+
+
 def test_everything_resolved_leaves_the_instrument_exactly():
     """Bright, well separated sources all resolve in body 0: the exact
     fixed-point subtraction leaves h = 0 bit for bit, so X = 0 and
