@@ -397,8 +397,10 @@ gbsub_status gbsub_cx_workspace_size(const gbsub_ctx *ctx, uint64_t n_sources, u
  * source with rho > rho_th scattered out of h (Eq. "vectorized-subtraction")}
  * until a body subtracts nothing.  Arguments, workspace ownership, stream
  * use and errors as gbsub_run (the workspace from gbsub_cx_workspace_size);
- * results are read with gbsub_cx_spectrum and gbsub_cx_resolved and stay in
- * the workspace until the next complex-template run of this context. */
+ * results are read with gbsub_cx_spectrum, gbsub_cx_resolved and
+ * gbsub_cx_candidates and stay in the workspace until the next
+ * complex-template run of this context or until the caller reuses that
+ * memory (a power-model run in the same buffer overwrites them). */
 gbsub_status gbsub_cx_run(gbsub_ctx *ctx, const gbsub_cx_catalog *cat, void *workspace, uint64_t ws_bytes,
                           void *stream, gbsub_summary *out);
 
