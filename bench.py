@@ -10,7 +10,7 @@ sample of the same workload.
 
   python bench.py [--gpus 1] [--steps 20] [--warmup 3]
 
-Two more workloads print one JSON line each:
+Other workloads print one JSON line each:
   --workload batch   64 catalogs (N log-uniform in [1e5, 2e7], per-catalog
                      hyperparameters, T = 4 yr, W = 1001): catalogs/h through
                      one shared batch against the same catalogs run one by one;
@@ -23,7 +23,9 @@ Two more workloads print one JSON line each:
   --workload generate    catalogs drawn on the GPU from the population model;
   --workload oracle      the FP64 oracle alone on the host cores (one thread
                      and all threads, 1e4 and 1e7 catalogs, a subset of the
-                     64-catalog batch).
+                     64-catalog batch);
+  --workload cx          the complex-template data model (gbsub_cx_run) on the
+                     1e7-binary catalog with its channel phases.
 """
 from __future__ import annotations
 

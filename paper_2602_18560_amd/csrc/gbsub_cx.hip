@@ -23,8 +23,8 @@
 //    stage inside the lane, then two 64-point FFTs across the lanes by
 //    xor-shuffles; twiddles from a 128-entry table in LDS.  Templates are
 //    recomputed wherever they are needed (injection, every SNR evaluation,
-//    subtraction) instead of stored: 2 KB per candidate of HBM traffic per
-//    evaluation costs more than the ~100 wave instructions that recompute it.
+//    subtraction) instead of stored (2 KB per candidate, 20 GB for 1e7
+//    sources): about 350 VALU instructions of one wave per template.
 //  * h is exact fixed point (int64, unit 2^-E with E from the largest
 //    amplitude and the source count), so injection and subtraction are
 //    order-independent integer adds and a subtracted template cancels to the
@@ -34,7 +34,10 @@
 //    histograms, one scan, a scatter with per-block range reservations);
 //    each block accumulates up to CH sources of one tile into an LDS window
 //    of the tile plus the template reach on each side, then adds the window
-//    to h with one global atomic per touched word.
+//    to h with one global atomic per touched word.  Each wave takes 64
+//    sources at a time: their constants are computed one per lane and
+//    broadcast by readlane while the wave synthesises one template after
+//    the other.
 //  * The per-channel PSD is the power model's median (or mean) kernel, run
 //    over a two-slot descriptor table (A and E), with the same dirty-tile
 //    stamps; a body is X update, PSD, SNR + subtraction, and a one-block tail.
