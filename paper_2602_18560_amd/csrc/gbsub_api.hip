@@ -1026,7 +1026,10 @@ struct gbsub_batch {
     uint32_t n_run;                    // entries of run_table
     bool run_dirty;                    // the running set changed since run_table was written
     Dims run_dims;                     // launch extents of run_table
-    Ctl *host_ctls;                    // pinned
+    Ctl *host_ctls;                    // pinned, one per slot
+    Ctl *host_run_ctls;                // pinned, one per entry of run_table
+    Ctl *ctl_stage;                    // device: the control blocks of run_table, gathered
+    std::vector<uint32_t> run_slot;    // slot of each entry of run_table
     std::vector<gbsub_ctx *> owner;
     std::vector<void *> ws;            // each slot's workspace
     std::vector<uint8_t> state;
@@ -1067,7 +1070,9 @@ hipError_t enqueue_bodies(const Slot *ds, const Dims &dm, uint32_t n, hipStream_
 gbsub_status gbsub_batch_table_size(uint32_t max_slots, uint64_t *bytes)
 {
     if (!bytes || max_slots < 1 || max_slots > 4096) return GBSUB_E_INVALID;
-    *bytes = align_up(2 * (uint64_t)max_slots * sizeof(Slot));   // all slots, then the running ones
+    // all slots, then the running ones, then a staging copy of the running
+    // slots' control blocks for the polls
+    *bytes = align_up(2 * (uint64_t)max_slots * sizeof(Slot) + (uint64_t)max_slots * sizeof(Ctl));
     return GBSUB_OK;
 }
 
@@ -1087,6 +1092,9 @@ gbsub_status gbsub_batch_create(uint32_t max_slots, void *table, uint64_t table_
     b->device = dev;
     b->table = (Slot *)table;
     b->run_table = (Slot *)table + max_slots;
+    b->ctl_stage = reinterpret_cast<Ctl *>((Slot *)table + 2 * (size_t)max_slots);
+    b->host_run_ctls = nullptr;
+    b->run_slot.assign(max_slots, 0u);
     b->host_table = nullptr;
     b->host_run = nullptr;
     b->n_run = 0;
@@ -1102,7 +1110,8 @@ gbsub_status gbsub_batch_create(uint32_t max_slots, void *table, uint64_t table_
     b->graph_stream = nullptr;
     if (hipHostMalloc((void **)&b->host_table, sizeof(Slot) * max_slots, hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void **)&b->host_run, sizeof(Slot) * max_slots, hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void **)&b->host_ctls, sizeof(Ctl) * max_slots, hipHostMallocDefault) != hipSuccess) {
+        hipHostMalloc((void **)&b->host_ctls, sizeof(Ctl) * max_slots, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&b->host_run_ctls, sizeof(Ctl) * max_slots, hipHostMallocDefault) != hipSuccess) {
         gbsub_batch_destroy(b);
         return GBSUB_E_DEVICE;
     }
@@ -1124,6 +1133,7 @@ void gbsub_batch_destroy(gbsub_batch *b)
     if (b->host_table) (void)hipHostFree(b->host_table);
     if (b->host_run) (void)hipHostFree(b->host_run);
     if (b->host_ctls) (void)hipHostFree(b->host_ctls);
+    if (b->host_run_ctls) (void)hipHostFree(b->host_run_ctls);
     delete b;
 }
 
@@ -1178,7 +1188,10 @@ gbsub_status gbsub_batch_step(gbsub_batch *b, uint32_t n, void *stream)
         if (hipStreamSynchronize(st) != hipSuccess) return GBSUB_E_DEVICE;   // host_run is free
         uint32_t m = 0;
         for (uint32_t k = 0; k < b->max_slots; ++k)
-            if (b->owner[k] && b->state[k] == GBSUB_SLOT_RUNNING) b->host_run[m++] = b->host_table[k];
+            if (b->owner[k] && b->state[k] == GBSUB_SLOT_RUNNING) {
+                b->run_slot[m] = k;
+                b->host_run[m++] = b->host_table[k];
+            }
         Dims rd{};
         for (uint32_t i = 0; i < m; ++i) {
             Slot &sl = b->host_run[i];
@@ -1221,11 +1234,22 @@ gbsub_status gbsub_batch_poll(gbsub_batch *b, void *stream, uint8_t *state, uint
     if (use_device(b->device) != GBSUB_OK) return GBSUB_E_DEVICE;
     hipStream_t st = (hipStream_t)stream;
     hipError_t e = hipSuccess;
-    for (uint32_t k = 0; k < b->max_slots && e == hipSuccess; ++k)
-        if (b->owner[k])
-            e = hipMemcpyAsync(&b->host_ctls[k], b->host_table[k].d.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st);
+    const bool gathered = !b->run_dirty && b->n_run > 0;
+    if (gathered) {
+        // only the slots of the last steps can have changed: their control
+        // blocks gathered by one kernel, then one copy
+        e = launch_gather_ctl(b->run_table, b->n_run, b->ctl_stage, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(b->host_run_ctls, b->ctl_stage, sizeof(Ctl) * b->n_run, hipMemcpyDeviceToHost, st);
+    } else {
+        for (uint32_t k = 0; k < b->max_slots && e == hipSuccess; ++k)
+            if (b->owner[k])
+                e = hipMemcpyAsync(&b->host_ctls[k], b->host_table[k].d.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st);
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return GBSUB_E_DEVICE;
+    if (gathered)
+        for (uint32_t i = 0; i < b->n_run; ++i) b->host_ctls[b->run_slot[i]] = b->host_run_ctls[i];
     uint32_t running = 0;
     for (uint32_t k = 0; k < b->max_slots; ++k) {
         if (b->owner[k]) {

@@ -224,6 +224,8 @@ hipError_t launch_resolved(const int32_t *iter, const uint32_t *id, uint32_t nc,
                            uint32_t *kA, int32_t *vA, uint32_t *kB, int32_t *vB, hipStream_t st);
 // out[k] = S[k] - sx[k] for k < B.
 hipError_t launch_sgal(const double *S, const double *sx, int B, double *out, hipStream_t st);
+// out[i] = the control block of slot i of the device table, i < n (one launch).
+hipError_t launch_gather_ctl(const Slot *table, uint32_t n, Ctl *out, hipStream_t st);
 
 // ---- complex-template data model (gbsub_cx.hip)
 constexpr int CX_NF = 128;          // samples per template

@@ -161,6 +161,15 @@ __global__ __launch_bounds__(OT) void k_rs_scatter(const uint32_t *kin, const in
     }
 }
 
+// The control block of each slot of a descriptor table, into out[i].
+__global__ __launch_bounds__(64) void k_gather_ctl(const Slot *S, Ctl *out)
+{
+    static_assert(sizeof(Ctl) % 8 == 0, "Ctl is copied in 8-byte words");
+    const uint64_t *src = reinterpret_cast<const uint64_t *>(S[blockIdx.x].d.ctl);
+    uint64_t *dst = reinterpret_cast<uint64_t *>(out + blockIdx.x);
+    for (int w = threadIdx.x; w < (int)(sizeof(Ctl) / 8); w += 64) dst[w] = src[w];
+}
+
 __global__ __launch_bounds__(OT) void k_sgal(const double *S, const double *sx, int B, double *out)
 {
     const int k = blockIdx.x * OT + threadIdx.x;
@@ -189,6 +198,13 @@ hipError_t launch_resolved(const int32_t *iter, const uint32_t *id, uint32_t nc,
         k_scan_u32<<<1, SCAN_T, 0, st>>>(hist, 256 * nb);
         k_rs_scatter<<<nb, OT, 0, st>>>(ki, vi, m, 8 * pass, hist, nb, ko, vo);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_ctl(const Slot *table, uint32_t n, Ctl *out, hipStream_t st)
+{
+    if (n == 0) return hipSuccess;
+    k_gather_ctl<<<n, 64, 0, st>>>(table, out);
     return hipGetLastError();
 }
 
