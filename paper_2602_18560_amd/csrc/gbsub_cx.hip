@@ -254,6 +254,19 @@ __global__ __launch_bounds__(WG) void k_cx_sinstr(KArgs a)
     a.d.isx[k] = 1.0 / v;
 }
 
+// Largest 1/S_instr of each 128-bin segment (one wave per segment).
+__global__ __launch_bounds__(WG) void k_cx_isxmax(KArgs a)
+{
+    const int seg = blockIdx.x * (WG / 64) + (threadIdx.x >> 6);
+    const int nseg = (a.g.B + NF - 1) / NF;
+    if (seg >= nseg) return;
+    const int k0 = seg * NF + lane(), k1 = k0 + 64;
+    double m = k0 < a.g.B ? a.d.isx[k0] : 0.0;
+    if (k1 < a.g.B) m = fmax(m, a.d.isx[k1]);
+    for (int o = 32; o >= 1; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+    if (lane() == 0) a.d.isx_max[seg] = m;
+}
+
 // Sources per binning tile (LDS histogram per block), the largest amplitude
 // of the valid entries (it sets the fixed-point unit, a function of the
 // catalog's size and amplitudes only), and the validity of every entry.
@@ -475,9 +488,17 @@ __global__ __launch_bounds__(WG) void k_cx_inject(KArgs a)
             wave_template(c.A, c.delta, c.d, T, tw, &ue, &uo);
             const int be = c.qb + je, bo = c.qb + jo;
             const bool ine = be >= 0 && be < g.B, ino = bo >= 0 && bo < g.B;
-            const double pe = ue.x * ue.x + ue.y * ue.y, po = uo.x * uo.x + uo.y * uo.y;
-            double r0 = (ine ? pe * d.isx[be] : 0.0) + (ino ? po * d.isx[bo] : 0.0);
-            r0 = (8.0 / T) * wave_sum(r0);
+            // the candidate cut: sum_j |U_j|^2 = T^2 A^2 / 4 (Parseval), so
+            // rho_0^2 <= 2 T A^2 max 1/S_instr over the template's (at most
+            // two) segments; below the cut by that bound, no exact sum
+            const int s0 = max(c.qb - HALO, 0) / NF, s1 = min(c.qb + HALO - 1, g.B - 1) / NF;
+            const double bound = 2.0 * T * (c.A * c.A) * fmax(d.isx_max[s0], d.isx_max[s1]);
+            double r0 = 0.0;
+            if (bound * (1.0 + 1e-9) >= cut2) {
+                const double pe = ue.x * ue.x + ue.y * ue.y, po = uo.x * uo.x + uo.y * uo.y;
+                r0 = (ine ? pe * d.isx[be] : 0.0) + (ino ? po * d.isx[bo] : 0.0);
+                r0 = (8.0 / T) * wave_sum(r0);
+            }
             if (r0 >= cut2 && lane() == 0) {
                 const uint32_t slot = atomicAdd(&d.ctl->cand_cursor, 1u);
                 d.c_src[slot] = c.i;
@@ -766,6 +787,7 @@ uint64_t cx_carve(const Grid &g, uint64_t n, char *base, CxDev *out)
     d.ctl = (Ctl *)take(sizeof(Ctl));
     d.sx = (double *)take(B * 8);
     d.isx = (double *)take(B * 8);
+    d.isx_max = (double *)take(((B + CX_NF - 1) / CX_NF) * 8);
     d.X = (double *)take(2 * B * 8);
     d.S = (double *)take(2 * B * 8);
     d.is_pre = (double *)take(2 * B * 8);
@@ -795,6 +817,8 @@ hipError_t cx_launch_prep(const Grid &g, const CxDev &d, const CxIn &in, hipStre
     const KArgs a = args_of(g, d, in);
     k_cx_reset<<<1024, WG, 0, st>>>(a);
     k_cx_sinstr<<<(g.B + WG - 1) / WG, WG, 0, st>>>(a);
+    const int nseg = (g.B + NF - 1) / NF;
+    k_cx_isxmax<<<(nseg + WG / 64 - 1) / (WG / 64), WG, 0, st>>>(a);
     const uint32_t nb = (in.n + SRC_PB - 1) / SRC_PB;
     if (nb) k_cx_count<<<nb, WG, 0, st>>>(a);
     k_cx_plan<<<1, PLAN_T, 0, st>>>(a);

@@ -238,6 +238,7 @@ struct CxDev {
     Ctl *ctl;                // shared by both channels
     double *sx;              // [B] S_instr
     double *isx;             // [B] 1 / S_instr
+    double *isx_max;         // [ceil(B/128)] largest 1/S_instr of each 128-bin segment
     double *X;               // [2][B] periodograms (2/T)|h_c|^2
     double *S;               // [2][B] PSD estimates
     double *is_pre;          // [2][B] in-part prefixes of 1/S (written by the median kernel)
