@@ -153,6 +153,7 @@ uint64_t carve(const Grid &g, uint64_t n, char *base, Dev *d)
     t.is_psum = (double *)take((uint64_t)g.nparts * 8);
     t.xstamp = (uint32_t *)take(nt * 4);
     t.sstamp = (uint32_t *)take(nt * 4);
+    t.sdl = (uint32_t *)take(nt * 4);
     t.btot = (uint32_t *)take(nt * 4);
     const uint64_t npb = (nn + PREP_SRC - 1) / PREP_SRC;
     t.bhist = (uint32_t *)take(npb * ((nt + 1) / 2) * 4);
@@ -794,6 +795,7 @@ gbsub_status gbsub_cx_run(gbsub_ctx *c, const gbsub_cx_catalog *cat, void *ws, u
         sl.d.is_psum = d.is_psum + (size_t)ch * g.nparts;
         sl.d.xstamp = d.xstamp;
         sl.d.sstamp = d.sstamp;
+        sl.d.sdl = d.sdl;
         sl.d.ctl = d.ctl;
         sl.n = cat->n;
         sl.active = 1;

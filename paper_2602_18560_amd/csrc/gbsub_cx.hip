@@ -219,6 +219,7 @@ __global__ __launch_bounds__(WG) void k_cx_reset(KArgs a)
     for (size_t k = i0; k < (size_t)g.nt; k += stride) {
         d.xstamp[k] = 0;
         d.sstamp[k] = 0;
+        d.sdl[k] = (uint32_t)k;
     }
     if (i0 == 0) {
         Ctl *c = d.ctl;
@@ -239,6 +240,7 @@ __global__ __launch_bounds__(WG) void k_cx_reset(KArgs a)
         c->units_snr = 0;
         c->status = 0;
         c->med_split = (uint32_t)g.nt <= g.split_tiles;
+        c->n_sdl = (uint32_t)g.nt;
         c->xupd = 0;
         c->tail_due = 0;
         c->n_new_body = 0;
@@ -669,13 +671,32 @@ __global__ __launch_bounds__(WG) void k_cx_tail(KArgs a)
     const CxDev &d = a.d;
     Ctl *c = d.ctl;
     if (c->done) return;
+    __shared__ uint32_t s_wl[WG / 64];
     const uint32_t t = c->iter, nxt = t + 1;
     uint32_t nds = 0;
     uint64_t units = 0;
-    for (int tl = threadIdx.x; tl < g.nt; tl += WG) {
-        const bool sd = d.sstamp[tl] == nxt;
-        nds += sd;
-        if (d.xstamp[tl] == nxt) units += (uint64_t)min(g.tile, g.B - tl * g.tile);
+    // the tiles the next PSD launch filters, listed in tile order
+    uint32_t listed = 0;
+    for (int base = 0; base < g.nt; base += WG) {
+        const int tl = base + (int)threadIdx.x;
+        bool sd = false;
+        if (tl < g.nt) {
+            sd = d.sstamp[tl] == nxt;
+            nds += sd;
+            if (d.xstamp[tl] == nxt) units += (uint64_t)min(g.tile, g.B - tl * g.tile);
+        }
+        const uint64_t m = (uint64_t)__ballot(sd);
+        if (lane() == 0) s_wl[threadIdx.x >> 6] = (uint32_t)__popcll(m);
+        __syncthreads();
+        uint32_t pre = 0, tot = 0;
+#pragma unroll
+        for (int v = 0; v < WG / 64; ++v) {
+            pre += v < (int)(threadIdx.x >> 6) ? s_wl[v] : 0u;
+            tot += s_wl[v];
+        }
+        if (sd) d.sdl[listed + pre + (uint32_t)__popcll(m & ((1ull << lane()) - 1ull))] = (uint32_t)tl;
+        listed += tot;
+        __syncthreads();
     }
     for (int o = 32; o >= 1; o >>= 1) {
         nds += (uint32_t)__shfl_xor((int)nds, o, 64);
@@ -711,6 +732,7 @@ __global__ __launch_bounds__(WG) void k_cx_tail(KArgs a)
         } else {
             c->iter = nxt;
             c->med_split = s_nds[0] <= g.split_tiles;
+            c->n_sdl = s_nds[0];
             c->units_x += s_units[0];
             c->units_med += s_units[0];
         }
@@ -795,6 +817,7 @@ uint64_t cx_carve(const Grid &g, uint64_t n, char *base, CxDev *out)
     d.h = (int64_t *)take(4 * B * 8);
     d.xstamp = (uint32_t *)take(nt * 4);
     d.sstamp = (uint32_t *)take(nt * 4);
+    d.sdl = (uint32_t *)take(nt * 4);
     d.tcnt = (uint32_t *)take(((uint64_t)d.ntc + 1) * 4);
     d.tcur = (uint32_t *)take((uint64_t)d.ntc * 4);
     d.cbase = (uint32_t *)take(((uint64_t)d.ntc + 1) * 4);

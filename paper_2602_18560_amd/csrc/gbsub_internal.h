@@ -26,6 +26,7 @@ enum Prec { PREC_FP64 = 0, PREC_COMP = 1, PREC_NAIVE = 2 };   // Grid::prec (= g
 constexpr int COARSE_MAX = 256;    // coarse-graining bins at most
 constexpr int PART_MAX = 512;      // outputs of a median block in split mode (prefix-of-1/S granule)
 constexpr int SPLIT_BLOCKS = 512;  // split the median into parts while dirty tiles x parts fit this
+constexpr int MED_GRID = 2048;     // blocks of a median launch (per slot); they stride over the dirty list
 
 // Signed 128-bit fixed-point accumulator (two's complement: hi*2^64 + lo).
 // Every power is accumulated as an exact integer multiple of 2^L, so sums
@@ -72,6 +73,7 @@ struct Ctl {
     uint32_t xupd;           // stamp of the tiles the next k_xupdate converts
     uint32_t tail_due;       // k_snr has run; its partials await the tail
     uint32_t n_new_body;     // complex-template model: sources subtracted by the running body
+    uint32_t n_sdl;          // tiles listed in sdl for the next median launch
 };
 
 // Per-block partial results of k_snr (combined by the tail: the last block
@@ -146,6 +148,7 @@ struct Dev {
     // stamp equals t; k_snr stamps t + 1 where a subtraction changes them
     uint32_t *xstamp;        // [nt]
     uint32_t *sstamp;        // [nt]
+    uint32_t *sdl;           // [nt] the tiles the next median launch filters, in tile order
     // binning by tile (multisplit): events sorted by tile
     uint32_t *btot;          // [nt]   events per tile
     uint32_t *bhist;         // [prep blocks][(nt+1)/2] events per (block, tile), two 16-bit counts a word
@@ -246,6 +249,7 @@ struct CxDev {
     int64_t *h;              // [4][B] re h_A, im h_A, re h_E, im h_E in fixed point (unit 2^-E)
     uint32_t *xstamp;        // [nt] tiles whose X is recomputed in body t
     uint32_t *sstamp;        // [nt] tiles whose S is recomputed in body t
+    uint32_t *sdl;           // [nt] the tiles of the next PSD launch, in tile order
     uint32_t *tcnt;          // [ntc+1] sources per binning tile, then their exclusive prefix
     uint32_t *tcur;          // [ntc] scatter cursors
     uint32_t *cbase;         // [ntc+1] first injection chunk of each binning tile

@@ -422,12 +422,14 @@ __global__ __launch_bounds__(WG) void k_reset(const Slot *S)
         c->units_snr = 0;
         c->status = 0;
         c->med_split = (uint32_t)g.nt <= g.split_tiles;   // every tile is dirty
+        c->n_sdl = (uint32_t)g.nt;
         c->xupd = 0;
         c->tail_due = 0;
     }
     for (int i = blockIdx.x * WG + threadIdx.x; i < g.nt; i += gridDim.x * WG) {
         d.xstamp[i] = 0;          // body 0 converts and filters every tile
         d.sstamp[i] = 0;
+        d.sdl[i] = (uint32_t)i;
         d.Dadj[i].h = 0;
         d.Dadj[i].l = 0;
     }
@@ -1479,24 +1481,13 @@ DEVI void part_prefix_ff(double *dsh, double *st, const Grid &g, const Dev &d, i
     }
 }
 
-__global__ __launch_bounds__(MWG, 2) void k_median(const Slot *S)
+// The work of one tile (or part) of a PSD launch.
+DEVI void median_work(MedianSmem &sm, const Slot *slp, int blk, int span)
 {
-    __shared__ MedianSmem sm;
-    const Slot &sl = S[blockIdx.y];
-    if (!sl.active || sl.g.est != 0) return;
-    const Grid g = sl.g;
-    const Dev d = sl.d;
-    if (d.ctl->done || d.ctl->bad) return;
+    const Grid g = slp->g;
+    const Dev d = slp->d;
     const int tid = threadIdx.x;
     const int B = g.B, W = g.W, h = g.h;
-    // One block per tile, or (split mode, chosen by the previous body's SNR
-    // launch when few tiles are dirty) one block per part: more, shorter blocks.
-    const bool split = d.ctl->med_split != 0;
-    const int span = split ? g.part : g.tile;
-    const int blk = blockIdx.x;
-    const int tile = split ? blk / g.np : blk;
-    if (tile >= g.nt || blk * span >= B || d.sstamp[tile] != d.ctl->iter) return;
-
     const int t0 = blk * span;
     const int t1 = min(t0 + span, B);
     const bool whole = B < W;
@@ -1802,6 +1793,57 @@ __global__ __launch_bounds__(MWG, 2) void k_median(const Slot *S)
     for (int i = tid; i < n; i += MWG) d.is_pre[t0 + i] = st[i];
 }
 
+// One block per tile, or (split mode, chosen by the previous body's SNR
+// launch when few tiles are dirty) one block per part: more, shorter
+// blocks; a block whose tile is clean exits.  The launch of one slot.
+__global__ __launch_bounds__(MWG, 2) void k_median(const Slot *S)
+{
+    __shared__ MedianSmem sm;
+    const Slot &sl = S[blockIdx.y];
+    if (!sl.active || sl.g.est != 0) return;
+    const Grid g = sl.g;
+    const Dev d = sl.d;
+    if (d.ctl->done || d.ctl->bad) return;
+    const bool split = d.ctl->med_split != 0;
+    const int span = split ? g.part : g.tile;
+    const int blk = blockIdx.x;
+    const int tile = split ? blk / g.np : blk;
+    if (tile >= g.nt || blk * span >= g.B || d.sstamp[tile] != d.ctl->iter) return;
+    median_work(sm, &sl, blk, span);
+}
+
+// Not inlined: the listed launch loops over the tiles, and the loop must
+// not change the registers the work gets.
+__device__ __noinline__ void median_entry(MedianSmem &sm, const Slot *slp, int blk, int span)
+{
+    median_work(sm, slp, blk, span);
+}
+
+__global__ __launch_bounds__(MWG, 4) void k_median_listed(const Slot *S)
+{
+    __shared__ MedianSmem sm;
+    const Slot &sl = S[blockIdx.y];
+    if (!sl.active || sl.g.est != 0) return;
+    const Grid g = sl.g;
+    const Dev d = sl.d;
+    if (d.ctl->done || d.ctl->bad) return;
+    // The launch of several slots (batches, the template model's two
+    // channels): the dirty tiles come listed in tile order by the previous
+    // body's tail (every tile for the first body), and a grid of at most
+    // MED_GRID blocks per slot strides over the list, so the working blocks
+    // are dispatched first and a slot's clean tiles cost no blocks.
+    const bool split = d.ctl->med_split != 0;
+    const int span = split ? g.part : g.tile;
+    const uint32_t n_ent = d.ctl->n_sdl * (split ? (uint32_t)g.np : 1u);
+    for (uint32_t e = blockIdx.x; e < n_ent; e += gridDim.x) {
+        const int tile = (int)d.sdl[split ? e / (uint32_t)g.np : e];
+        const int blk = split ? tile * g.np + (int)(e % (uint32_t)g.np) : tile;
+        if (blk * span >= g.B) continue;
+        median_entry(sm, &sl, blk, span);
+        __syncthreads();                   // LDS is reused by the next entry
+    }
+}
+
 // ------------------------------------------------------------------ running mean
 //
 // S[k] = (1/W) sum_{j in window(k)} (X[j] + S_instr[j])   (the mean form of the
@@ -1815,21 +1857,13 @@ struct MeanSmem {
     double dsh[MWG / 64];
 };
 
-__global__ __launch_bounds__(MWG) void k_mean(const Slot *S)
+// The work of one tile (or part) of a PSD launch.
+DEVI void mean_work(MeanSmem &sm, const Slot *slp, int blk, int span)
 {
-    __shared__ MeanSmem sm;
-    const Slot &sl = S[blockIdx.y];
-    if (!sl.active || sl.g.est != 1) return;
-    const Grid g = sl.g;
-    const Dev d = sl.d;
-    if (d.ctl->done || d.ctl->bad) return;
+    const Grid g = slp->g;
+    const Dev d = slp->d;
     const int tid = threadIdx.x;
     const int B = g.B, W = g.W, h = g.h;
-    const bool split = d.ctl->med_split != 0;
-    const int span = split ? g.part : g.tile;
-    const int blk = blockIdx.x;
-    const int tile = split ? blk / g.np : blk;
-    if (tile >= g.nt || blk * span >= B || d.sstamp[tile] != d.ctl->iter) return;
     const int t0 = blk * span;
     const int t1 = min(t0 + span, B);
     const bool whole = B < W;
@@ -1877,6 +1911,57 @@ __global__ __launch_bounds__(MWG) void k_mean(const Slot *S)
     part_prefix<double>(sm.dsh, sm.stage, g, d, kb, ke, t0, t1, R);
     __syncthreads();
     for (int i = tid; i < n; i += MWG) d.is_pre[t0 + i] = sm.stage[i];
+}
+
+// One block per tile, or (split mode, chosen by the previous body's SNR
+// launch when few tiles are dirty) one block per part: more, shorter
+// blocks; a block whose tile is clean exits.  The launch of one slot.
+__global__ __launch_bounds__(MWG) void k_mean(const Slot *S)
+{
+    __shared__ MeanSmem sm;
+    const Slot &sl = S[blockIdx.y];
+    if (!sl.active || sl.g.est != 1) return;
+    const Grid g = sl.g;
+    const Dev d = sl.d;
+    if (d.ctl->done || d.ctl->bad) return;
+    const bool split = d.ctl->med_split != 0;
+    const int span = split ? g.part : g.tile;
+    const int blk = blockIdx.x;
+    const int tile = split ? blk / g.np : blk;
+    if (tile >= g.nt || blk * span >= g.B || d.sstamp[tile] != d.ctl->iter) return;
+    mean_work(sm, &sl, blk, span);
+}
+
+// Not inlined: the listed launch loops over the tiles, and the loop must
+// not change the registers the work gets.
+__device__ __noinline__ void mean_entry(MeanSmem &sm, const Slot *slp, int blk, int span)
+{
+    mean_work(sm, slp, blk, span);
+}
+
+__global__ __launch_bounds__(MWG) void k_mean_listed(const Slot *S)
+{
+    __shared__ MeanSmem sm;
+    const Slot &sl = S[blockIdx.y];
+    if (!sl.active || sl.g.est != 1) return;
+    const Grid g = sl.g;
+    const Dev d = sl.d;
+    if (d.ctl->done || d.ctl->bad) return;
+    // The launch of several slots (batches, the template model's two
+    // channels): the dirty tiles come listed in tile order by the previous
+    // body's tail (every tile for the first body), and a grid of at most
+    // MED_GRID blocks per slot strides over the list, so the working blocks
+    // are dispatched first and a slot's clean tiles cost no blocks.
+    const bool split = d.ctl->med_split != 0;
+    const int span = split ? g.part : g.tile;
+    const uint32_t n_ent = d.ctl->n_sdl * (split ? (uint32_t)g.np : 1u);
+    for (uint32_t e = blockIdx.x; e < n_ent; e += gridDim.x) {
+        const int tile = (int)d.sdl[split ? e / (uint32_t)g.np : e];
+        const int blk = split ? tile * g.np + (int)(e % (uint32_t)g.np) : tile;
+        if (blk * span >= g.B) continue;
+        mean_entry(sm, &sl, blk, span);
+        __syncthreads();                   // LDS is reused by the next entry
+    }
 }
 
 // ------------------------------------------------------------------ SNR, decisions, subtraction
@@ -2176,6 +2261,7 @@ template <int NT> DEVI void snr_tail(const Slot &sl)
     constexpr int NW = NT / 64;
     __shared__ uint64_t s_red[5][NW];     // new, near, evals, ux, us
     __shared__ uint32_t s_nds[NW];
+    __shared__ uint32_t s_wl[NW];
     __shared__ double s_min[NW];
     const Grid g = sl.g;
     const Dev d = sl.d;
@@ -2193,13 +2279,35 @@ template <int NT> DEVI void snr_tail(const Slot &sl)
         evals += p.evals;
         minm = fmin(minm, p.minm);
     }
-    for (int tl = threadIdx.x; tl < g.nt; tl += NT) {
-        const uint64_t width = (uint64_t)min(g.tile, g.B - tl * g.tile);
-        if (d.xstamp[tl] == nxt) ux += width;
-        if (d.sstamp[tl] == nxt) {
-            us += width;
-            ++nds;
+    // stamped-tile counts, and the list of the tiles to filter in the next
+    // body in tile order (per round of NT tiles: a ballot and a prefix over
+    // the waves)
+    uint32_t listed = 0;                  // block-uniform
+    for (int base = 0; base < g.nt; base += NT) {
+        const int tl = base + (int)threadIdx.x;
+        bool sd = false;
+        if (tl < g.nt) {
+            const uint64_t width = (uint64_t)min(g.tile, g.B - tl * g.tile);
+            if (d.xstamp[tl] == nxt) ux += width;
+            sd = d.sstamp[tl] == nxt;
+            if (sd) {
+                us += width;
+                ++nds;
+            }
         }
+        const uint64_t m = (uint64_t)__ballot(sd);
+        if (lane_id() == 0) s_wl[threadIdx.x >> 6] = (uint32_t)__popcll(m);
+        __syncthreads();
+        uint32_t pre = 0, tot = 0;
+#pragma unroll
+        for (int v = 0; v < NW; ++v) {
+            const uint32_t x = s_wl[v];
+            pre += v < (int)(threadIdx.x >> 6) ? x : 0u;
+            tot += x;
+        }
+        if (sd) d.sdl[listed + pre + (uint32_t)__popcll(m & ((1ull << lane_id()) - 1ull))] = (uint32_t)tl;
+        listed += tot;
+        __syncthreads();
     }
     for (int s = 32; s >= 1; s >>= 1) {
         nw += (uint64_t)__shfl_xor((long long)nw, s, 64);
@@ -2231,6 +2339,7 @@ template <int NT> DEVI void snr_tail(const Slot &sl)
     const uint32_t n_new = (uint32_t)s_red[0][0];
     c->tail_due = 0;
     c->med_split = s_nds[0] <= g.split_tiles;
+    c->n_sdl = s_nds[0];
     if (t < NEW_CAP) d.n_new[t] = n_new;
     c->n_resolved += n_new;
     c->n_near += s_red[1][0];
@@ -2333,9 +2442,14 @@ hipError_t launch_median(const Slot *ds, const Dims &dm, hipStream_t st, hipEven
 {
     const bool med = dm.est_mask & 1u, mean = dm.est_mask & 2u;
     hipError_t e = hipSuccess;
-    if (med) e = go((const void *)k_median, dim3(dm.maxparts, dm.ns), dim3(MWG), st, ea, mean ? nullptr : eb, ds);
-    if (mean && e == hipSuccess)
-        e = go((const void *)k_mean, dim3(dm.maxparts, dm.ns), dim3(MWG), st, med ? nullptr : ea, eb, ds);
+    // one slot: a block per part; several: the listed launch (its blocks stride
+    // over each slot's dirty tiles)
+    const bool listed = dm.ns > 1;
+    const unsigned gx = (unsigned)(listed ? min(dm.maxparts, MED_GRID) : dm.maxparts);
+    const void *km = listed ? (const void *)k_median_listed : (const void *)k_median;
+    const void *kn = listed ? (const void *)k_mean_listed : (const void *)k_mean;
+    if (med) e = go(km, dim3(gx, dm.ns), dim3(MWG), st, ea, mean ? nullptr : eb, ds);
+    if (mean && e == hipSuccess) e = go(kn, dim3(gx, dm.ns), dim3(MWG), st, med ? nullptr : ea, eb, ds);
     return e;
 }
 
