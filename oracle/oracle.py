@@ -28,7 +28,7 @@ TRACK_SWEEP, TRACK_SINGLE = 0, 1
 
 
 def build(force: bool = False) -> str:
-    """Compile the oracle (gcc, -O2, no FMA contraction, OpenMP)."""
+    """Compile the oracle (gcc, -O2, no FMA contraction, OpenMP, libquadmath)."""
     os.makedirs(BUILD_DIR, exist_ok=True)
     if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= max(
             os.path.getmtime(SRC), os.path.getmtime(POP_SRC), os.path.getmtime(CX_SRC),
@@ -36,7 +36,7 @@ def build(force: bool = False) -> str:
         return LIB
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
-           "-fPIC", "-shared", "-Wall", "-o", tmp, SRC, POP_SRC, CX_SRC, "-lm"]
+           "-fPIC", "-shared", "-Wall", "-o", tmp, SRC, POP_SRC, CX_SRC, "-lquadmath", "-lm"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
     return LIB

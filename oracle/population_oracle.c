@@ -16,11 +16,12 @@
  * the 64-bit seed, counter = (source index, block); uniforms on (0, 1) with
  * 53 bits; normals by the Box-Muller transform.  Every step below is the
  * plain statement of its definition; the inverse Gamma CDF is found by
- * bisection to the last bit.
+ * bisection to the last bit, on P summed in binary128.
  */
 #include "gbsub_oracle.h"
 
 #include <math.h>
+#include <quadmath.h>
 #include <stdint.h>
 
 static const double PI = 3.14159265358979323846;
@@ -69,49 +70,37 @@ static double u53(uint32_t hi, uint32_t lo)
 /* Phi(z), the standard normal CDF */
 static double norm_cdf(double z) { return 0.5 * erfc(-z / sqrt(2.0)); }
 
-/* Regularized lower incomplete gamma P(a, x) = gamma(a, x) / Gamma(a):
- * the power series of gamma(a, x) for x < a + 1, else 1 - Q with Q from
- * Legendre's continued fraction of Gamma(a, x) (modified Lentz). */
-double orc_gamma_p(double a, double x)
+/* Regularized lower incomplete gamma P(a, x) = gamma(a, x) / Gamma(a), in
+ * binary128: x^a e^-x times the series sum_k x^k / Gamma(a + k + 1), which
+ * converges for every x and has only positive terms (DLMF 8.7.1), so nothing
+ * cancels, not even where P is within an ulp of 1.  Summed until the terms,
+ * past their peak at k ~ x - a, fall below 2^-120 of the sum. */
+static __float128 gamma_p_q(double a, double x)
 {
-    if (!(x > 0.0)) return 0.0;
-    const double lnpre = a * log(x) - x - lgamma(a);
-    if (x < a + 1.0) {
-        double term = 1.0 / a, sum = term;
-        for (int n = 1; n < 100000; ++n) {
-            term *= x / (a + n);
-            sum += term;
-            if (fabs(term) < fabs(sum) * 1e-17) break;
-        }
-        return sum * exp(lnpre);
+    if (!(x > 0.0)) return 0;
+    const __float128 aq = a, xq = x;
+    __float128 term = expq(aq * logq(xq) - xq - lgammaq(aq + 1)), sum = term;
+    for (int k = 1; k < 1000000; ++k) {
+        term *= xq / (aq + k);
+        sum += term;
+        if (k > x && term < sum * 0x1p-120Q) break;
     }
-    const double tiny = 1e-300;
-    double b = x + 1.0 - a, c = 1.0 / tiny, d = 1.0 / b, h = d;
-    for (int i = 1; i < 100000; ++i) {
-        const double an = -i * (i - a);
-        b += 2.0;
-        d = an * d + b;
-        if (fabs(d) < tiny) d = tiny;
-        c = b + an / c;
-        if (fabs(c) < tiny) c = tiny;
-        d = 1.0 / d;
-        const double del = d * c;
-        h *= del;
-        if (fabs(del - 1.0) <= 4e-16) break;
-    }
-    return 1.0 - exp(lnpre) * h;
+    return sum;
 }
 
+double orc_gamma_p(double a, double x) { return (double)gamma_p_q(a, x); }
+
 /* x with P(shape, rate * x) = p, by bisection until the bracket stops
- * shrinking (the last representable bit). */
+ * shrinking (the last representable bit); P is compared in binary128. */
 double orc_gamma_quantile(double shape, double rate, double p)
 {
+    const __float128 pq = p;
     double lo = 0.0, hi = 1.0;
-    while (orc_gamma_p(shape, hi) < p) hi *= 2.0;
+    while (gamma_p_q(shape, hi) < pq) hi *= 2.0;
     for (int it = 0; it < 2000; ++it) {
         const double mid = 0.5 * (lo + hi);
         if (mid <= lo || mid >= hi) break;
-        if (orc_gamma_p(shape, mid) < p) lo = mid; else hi = mid;
+        if (gamma_p_q(shape, mid) < pq) lo = mid; else hi = mid;
     }
     return 0.5 * (lo + hi) / rate;
 }
