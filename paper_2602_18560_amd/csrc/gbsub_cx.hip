@@ -20,11 +20,15 @@
 //
 // Design for gfx950:
 //  * A template is one wave's work: two samples per lane, the first radix-2
-//    stage inside the lane, then two 64-point FFTs across the lanes by
-//    xor-shuffles; twiddles from a 128-entry table in LDS.  Templates are
-//    recomputed wherever they are needed (injection, every SNR evaluation,
-//    subtraction) instead of stored (2 KB per candidate, 20 GB for 1e7
-//    sources): about 350 VALU instructions of one wave per template.
+//    stage inside the lane, then two 64-point FFTs across the lanes.  The
+//    exchanges run on the VALU, not through the LDS crossbar: row swaps
+//    (v_permlane32_swap, v_permlane16_swap) for spans 32 and 16, DPP moves
+//    for spans 8 .. 1.  exp(2 pi i t) is a 16-entry LDS table (one bank row:
+//    no conflicts) times short Taylor polynomials; twiddles and signs are
+//    lane constants in registers.  Templates are recomputed wherever they
+//    are needed (injection, every SNR evaluation, subtraction) instead of
+//    stored (2 KB per candidate, 20 GB for 1e7 sources): about 280 VALU
+//    instructions of one wave per template.
 //  * h is exact fixed point (int64, unit 2^-E with E from the largest
 //    amplitude and the source count), so injection and subtraction are
 //    order-independent integer adds and a subtracted template cancels to the
@@ -33,11 +37,12 @@
 //  * Injection is binned: sources are grouped by 1024-bin tile (LDS
 //    histograms, one scan, a scatter with per-block range reservations);
 //    each block accumulates up to CH sources of one tile into an LDS window
-//    of the tile plus the template reach on each side, then adds the window
-//    to h with one global atomic per touched word.  Each wave takes 64
-//    sources at a time: their constants are computed one per lane and
-//    broadcast by readlane while the wave synthesises one template after
-//    the other.
+//    of the tile plus the template reach on each side (even and odd bins
+//    apart, so the 64 lanes of one atomic add hit consecutive words), then
+//    adds the window to h with one global atomic per touched word.  Each
+//    wave takes an equal share of the chunk, 64 sources at a time: their
+//    constants are computed one per lane and broadcast by readlane while
+//    the wave synthesises one template after the other.
 //  * The per-channel PSD is the power model's median (or mean) kernel, run
 //    over a two-slot descriptor table (A and E), with the same dirty-tile
 //    stamps; a body is X update, PSD, SNR + subtraction, and a one-block tail.
@@ -70,32 +75,90 @@ __device__ __forceinline__ int lane() { return __lane_id(); }
 
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
-__device__ __forceinline__ double2 cmul(double2 a, double2 b)
+// Exchanges between lane pairs (l, l ^ span) without the LDS crossbar.
+// Spans 32 and 16: the row swaps v_permlane32_swap / v_permlane16_swap of a
+// register with itself leave on both lanes of a pair the first lane's value
+// (first result) and the second lane's (second result).  Spans 8 .. 1: DPP
+// moves within rows of 16 lanes give the partner's value (span 4 as a
+// half-row mirror, l ^ 7, then a quad reversal, l ^ 3).
+template <int SPAN> __device__ __forceinline__ int dpp_xor(int v)
 {
-    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-__device__ __forceinline__ double2 shfl_xor2(double2 v, int m)
-{
-    return make_double2(__shfl_xor(v.x, m, 64), __shfl_xor(v.y, m, 64));
+    static_assert(SPAN == 8 || SPAN == 4 || SPAN == 2 || SPAN == 1, "DPP spans");
+    // every lane of the wave is active and every source lane is in range:
+    // the moves need no old value (bound_ctrl)
+    if constexpr (SPAN == 8) {
+        return __builtin_amdgcn_mov_dpp(v, 0x128, 0xf, 0xf, true);      // row_ror:8
+    } else if constexpr (SPAN == 4) {
+        const int t = __builtin_amdgcn_mov_dpp(v, 0x141, 0xf, 0xf, true); // row_half_mirror
+        return __builtin_amdgcn_mov_dpp(t, 0x1B, 0xf, 0xf, true);      // quad_perm [3,2,1,0]
+    } else if constexpr (SPAN == 2) {
+        return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xf, 0xf, true);      // quad_perm [2,3,0,1]
+    } else {
+        return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xf, 0xf, true);      // quad_perm [1,0,3,2]
+    }
 }
 
-// Sum over the wave, the same value on every lane (lane 0's).
+template <int SPAN> __device__ __forceinline__ double partner(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = dpp_xor<SPAN>((int)(b & 0xffffffffll)), hi = dpp_xor<SPAN>((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <int SPAN> __device__ __forceinline__ void pair_of(double v, double *first, double *second)
+{
+    static_assert(SPAN == 32 || SPAN == 16, "row-swap spans");
+    const long long b = __double_as_longlong(v);
+    const unsigned lo = (unsigned)(b & 0xffffffffll), hi = (unsigned)(b >> 32);
+    unsigned f_lo, s_lo, f_hi, s_hi;
+    if constexpr (SPAN == 32) {
+        const auto rl = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+        const auto rh = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+        f_lo = rl[0]; s_lo = rl[1]; f_hi = rh[0]; s_hi = rh[1];
+    } else {
+        const auto rl = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+        const auto rh = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+        f_lo = rl[0]; s_lo = rl[1]; f_hi = rh[0]; s_hi = rh[1];
+    }
+    *first = __longlong_as_double(((long long)f_hi << 32) | f_lo);
+    *second = __longlong_as_double(((long long)s_hi << 32) | s_lo);
+}
+
+// Sum over the wave, the same value on every lane (a butterfly: both lanes
+// of a pair add the same two values).
 __device__ __forceinline__ double wave_sum(double v)
 {
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-    return __shfl(v, 0, 64);
+    double f, s;
+    pair_of<32>(v, &f, &s);
+    v = f + s;
+    pair_of<16>(v, &f, &s);
+    v = f + s;
+    v += partner<8>(v);
+    v += partner<4>(v);
+    v += partner<2>(v);
+    v += partner<1>(v);
+    return v;
 }
 
 // Fixed-point exponent E: every template component is at most A T / 2, so
-// the sum over all n sources of |component| 2^E stays below 2^62.
+// with m = max(n, 4096) sources the sum of the n components of one word
+// stays below 2^62 and a single component below 2^50 (which the rounding
+// of fxm needs).
 __device__ __forceinline__ int cx_exp(uint32_t amax_bits, uint32_t n, double T)
 {
-    const double v = (double)n * (double)__uint_as_float(amax_bits) * (T * 0.5);
+    const double v = (double)max(n, 4096u) * (double)__uint_as_float(amax_bits) * (T * 0.5);
     if (!(v > 0.0)) return 0;
     return 61 - ilogb(v);
 }
 
-__device__ __forceinline__ long long fx(double v, int E) { return __double2ll_rn(ldexp(v, E)); }
+// v (already in units of 2^-E, |v| < 2^51) rounded to the nearest integer,
+// ties to even: v + 1.5 2^52 lies in [2^52, 2^53), where the spacing of
+// doubles is 1, so the addition rounds v and its low mantissa bits hold the
+// integer plus 2^51.
+__device__ __forceinline__ long long fxm(double v)
+{
+    return __double_as_longlong(v + 6755399441055744.0) - 0x4338000000000000ll;
+}
 
 // Central DFT index q, delta = f T - q and d = fdot T^2 (the operations of
 // the definition, in this order); false if the source has no template
@@ -111,52 +174,160 @@ __device__ __forceinline__ bool cx_centre(double f, double fd, double T, double 
     return true;
 }
 
-// Twiddles tw[r] = exp(-2 pi i r / 128), set by the block's first 128 threads.
-__device__ __forceinline__ void set_twiddles(double2 *tw)
+constexpr int NEX = 16;                        // entries of the exp(2 pi i k / NEX) table
+
+// ex[k] = exp(2 pi i k / 16), set by the block's first threads.  The 16
+// entries fill one row of LDS banks: the lanes of a wave read them without
+// bank conflicts.
+__device__ __forceinline__ void set_cis_table(double2 *ex)
 {
-    if (threadIdx.x < NF) {
+    if (threadIdx.x < NEX) {
         double s, c;
-        sincospi((double)threadIdx.x / (NF / 2), &s, &c);
-        tw[threadIdx.x] = make_double2(c, -s);
+        sincospi((double)threadIdx.x / (NEX / 2), &s, &c);
+        ex[threadIdx.x] = make_double2(c, s);
     }
 }
 
+// exp(2 pi i t) for |t| < 2^26 turns: t = k/16 + r with k = rint(16 t) and
+// |r| <= 1/32 (both exact), the table entry of k mod 16 times the Taylor
+// polynomials of cos and sin at x = 2 pi r (|x| <= pi/16; the first omitted
+// terms are below 2e-19).
+__device__ __forceinline__ double2 cis_turns(double t, const double2 *ex)
+{
+    const double kd = rint(t * (double)NEX);
+    const double r = fma(kd, -1.0 / NEX, t);
+    const double2 e = ex[(int)kd & (NEX - 1)];
+    const double x = r * 6.283185307179586;
+    const double z = x * x;
+    double c = fma(z, 1.0 / 479001600.0, -1.0 / 3628800.0);
+    c = fma(z, c, 1.0 / 40320.0);
+    c = fma(z, c, -1.0 / 720.0);
+    c = fma(z, c, 1.0 / 24.0);
+    c = fma(z, c, -0.5);
+    c = fma(z, c, 1.0);
+    double p = fma(z, -1.0 / 39916800.0, 1.0 / 362880.0);
+    p = fma(z, p, -1.0 / 5040.0);
+    p = fma(z, p, 1.0 / 120.0);
+    p = fma(z, p, -1.0 / 6.0);
+    const double sn = fma(x * z, p, x);
+    return make_double2(fma(c, e.x, -(sn * e.y)), fma(c, e.y, sn * e.x));
+}
+
+__device__ __forceinline__ double2 cmulf(double2 a, double2 b)
+{
+    return make_double2(fma(a.x, b.x, -(a.y * b.y)), fma(a.x, b.y, a.y * b.x));
+}
+
+// A lane's constants of the wave FFT: its sample times x = n/128 (n = l and
+// l + 64) with their squares, the twiddle of the first stage, and for the
+// stages of spans 32 .. 4 the sign (+1 on the lane of the pair's first
+// element, -1 on the other) and the twiddle exp(-2 pi i m / 128) the second
+// element takes (1 on the first).
+struct LaneFft {
+    double x0, x0q, x1, x1q;
+    double2 w1, w[4];
+    double sg[6];
+};
+
+__device__ __forceinline__ double2 twiddle(int m)
+{
+    double s, c;
+    sincospi((double)m / (NF / 2), &s, &c);
+    return make_double2(c, -s);
+}
+
+__device__ __forceinline__ LaneFft lane_fft()
+{
+    LaneFft L;
+    const int l = lane();
+    L.x0 = (double)l / NF;
+    L.x1 = (double)(l + NF / 2) / NF;
+    L.x0q = L.x0 * L.x0;
+    L.x1q = L.x1 * L.x1;
+    L.w1 = twiddle(l);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int span = 32 >> k;
+        const bool bottom = (l & span) != 0;
+        L.w[k] = bottom ? twiddle((l & (span - 1)) * (64 / span)) : make_double2(1.0, 0.0);
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) L.sg[k] = (l & (32 >> k)) ? -1.0 : 1.0;
+    return L;
+}
+
+// Per-source constants of a template: index, centre bin, the phase
+// delta x + dh x^2 in turns (dh = d/2), the scale sc = (A/2) (T/128) 2^E of
+// the samples, and the channel rotations exp(i phi_A) = (ca, sa) and
+// exp(i phi_E) = (ce, se); need: the template may reach the candidate cut
+// (injection).
+struct SrcConsts {
+    uint32_t i;
+    int qb;
+    int need;
+    double delta, dh, sc, ca, sa, ce, se;
+};
+
 // The template of one source, by the whole wave: on return lane l holds
-// ue = U at m = 2 r and uo = U at m = 2 r + 1, r = bitrev6(l).  Samples n = l
-// and l + 64; the first decimation-in-frequency stage (n, n + 64) inside the
-// lane gives the even and odd outputs as two 64-point DFTs, each finished
-// across the lanes in six stages.
-__device__ __forceinline__ void wave_template(double A, double delta, double d, double T, const double2 *tw,
+// ue = 2^E U at m = 2 r and uo = 2^E U at m = 2 r + 1, r = bitrev6(l) (U
+// itself when sc = (A/2)(T/128)).  The phase is the definition's operations
+// in their order (delta x, (d/2) x^2, their sum), so it is the same double
+// as in a plain evaluation.
+// Samples n = l and l + 64; the first decimation-in-frequency stage (n,
+// n + 64) inside the lane gives the even and odd outputs as two 64-point
+// DFTs, each finished across the lanes in six stages.
+__device__ __forceinline__ void wave_template(const SrcConsts &c, const LaneFft &L, const double2 *ex,
                                               double2 *ue, double2 *uo)
 {
     const int l = lane();
-    const double x0 = (double)l / NF, x1 = (double)(l + NF / 2) / NF;
-    double t0 = delta * x0 + (d * 0.5) * (x0 * x0);
-    double t1 = delta * x1 + (d * 0.5) * (x1 * x1);
-    t0 = t0 - floor(t0);
-    t1 = t1 - floor(t1);
-    double s0, c0, s1, c1;
-    sincospi(2.0 * t0, &s0, &c0);
-    sincospi(2.0 * t1, &s1, &c1);
-    const double hA = A * 0.5;
-    const double2 a = make_double2(hA * c0, hA * s0), b = make_double2(hA * c1, hA * s1);
+    const double2 e0 = cis_turns(c.delta * L.x0 + c.dh * L.x0q, ex);
+    const double2 e1 = cis_turns(c.delta * L.x1 + c.dh * L.x1q, ex);
+    const double2 a = make_double2(c.sc * e0.x, c.sc * e0.y), b = make_double2(c.sc * e1.x, c.sc * e1.y);
     double2 y0 = cadd(a, b);
-    double2 y1 = cmul(csub(a, b), tw[l]);
-    // Butterflies without branches: top lanes take v + p (twiddle 1, which
-    // leaves the sum exact), bottom lanes (p - v) w; both as p + sgn v.
-#pragma unroll
-    for (int span = 32; span >= 4; span >>= 1) {
-        const double2 p0 = shfl_xor2(y0, span), p1 = shfl_xor2(y1, span);
-        const bool bottom = (l & span) != 0;
-        const double sg = bottom ? -1.0 : 1.0;
-        const double2 w = bottom ? tw[(l & (span - 1)) * (64 / span)] : make_double2(1.0, 0.0);
-        y0 = cmul(make_double2(fma(sg, y0.x, p0.x), fma(sg, y0.y, p0.y)), w);
-        y1 = cmul(make_double2(fma(sg, y1.x, p1.x), fma(sg, y1.y, p1.y)), w);
+    double2 y1 = cmulf(csub(a, b), L.w1);
+    // Butterflies without branches: the pair's first lane takes a + b
+    // (twiddle 1, which leaves the sum exact), the second (a - b) w; both as
+    // (a + sg b) w, with a and b from a row swap (spans 32, 16) or as the
+    // partner's value p and the own v, p + sg v (spans 8 .. 1).
+    {
+        double2 f0, s0, f1, s1;
+        pair_of<32>(y0.x, &f0.x, &s0.x);
+        pair_of<32>(y0.y, &f0.y, &s0.y);
+        pair_of<32>(y1.x, &f1.x, &s1.x);
+        pair_of<32>(y1.y, &f1.y, &s1.y);
+        const double sg = L.sg[0];
+        y0 = cmulf(make_double2(fma(sg, s0.x, f0.x), fma(sg, s0.y, f0.y)), L.w[0]);
+        y1 = cmulf(make_double2(fma(sg, s1.x, f1.x), fma(sg, s1.y, f1.y)), L.w[0]);
+    }
+    {
+        double2 f0, s0, f1, s1;
+        pair_of<16>(y0.x, &f0.x, &s0.x);
+        pair_of<16>(y0.y, &f0.y, &s0.y);
+        pair_of<16>(y1.x, &f1.x, &s1.x);
+        pair_of<16>(y1.y, &f1.y, &s1.y);
+        const double sg = L.sg[1];
+        y0 = cmulf(make_double2(fma(sg, s0.x, f0.x), fma(sg, s0.y, f0.y)), L.w[1]);
+        y1 = cmulf(make_double2(fma(sg, s1.x, f1.x), fma(sg, s1.y, f1.y)), L.w[1]);
+    }
+    {
+        const double2 p0 = make_double2(partner<8>(y0.x), partner<8>(y0.y));
+        const double2 p1 = make_double2(partner<8>(y1.x), partner<8>(y1.y));
+        const double sg = L.sg[2];
+        y0 = cmulf(make_double2(fma(sg, y0.x, p0.x), fma(sg, y0.y, p0.y)), L.w[2]);
+        y1 = cmulf(make_double2(fma(sg, y1.x, p1.x), fma(sg, y1.y, p1.y)), L.w[2]);
+    }
+    {
+        const double2 p0 = make_double2(partner<4>(y0.x), partner<4>(y0.y));
+        const double2 p1 = make_double2(partner<4>(y1.x), partner<4>(y1.y));
+        const double sg = L.sg[3];
+        y0 = cmulf(make_double2(fma(sg, y0.x, p0.x), fma(sg, y0.y, p0.y)), L.w[3]);
+        y1 = cmulf(make_double2(fma(sg, y1.x, p1.x), fma(sg, y1.y, p1.y)), L.w[3]);
     }
     // span 2: twiddles 1 and -i (a swap and a sign); span 1: twiddle 1
     {
-        const double2 p0 = shfl_xor2(y0, 2), p1 = shfl_xor2(y1, 2);
-        const double sg = (l & 2) ? -1.0 : 1.0;
+        const double2 p0 = make_double2(partner<2>(y0.x), partner<2>(y0.y));
+        const double2 p1 = make_double2(partner<2>(y1.x), partner<2>(y1.y));
+        const double sg = L.sg[4];
         const double2 d0 = make_double2(fma(sg, y0.x, p0.x), fma(sg, y0.y, p0.y));
         const double2 d1 = make_double2(fma(sg, y1.x, p1.x), fma(sg, y1.y, p1.y));
         const bool rot = (l & 3) == 3;
@@ -164,14 +335,20 @@ __device__ __forceinline__ void wave_template(double A, double delta, double d, 
         y1 = rot ? make_double2(d1.y, -d1.x) : d1;
     }
     {
-        const double2 p0 = shfl_xor2(y0, 1), p1 = shfl_xor2(y1, 1);
-        const double sg = (l & 1) ? -1.0 : 1.0;
+        const double2 p0 = make_double2(partner<1>(y0.x), partner<1>(y0.y));
+        const double2 p1 = make_double2(partner<1>(y1.x), partner<1>(y1.y));
+        const double sg = L.sg[5];
         y0 = make_double2(fma(sg, y0.x, p0.x), fma(sg, y0.y, p0.y));
         y1 = make_double2(fma(sg, y1.x, p1.x), fma(sg, y1.y, p1.y));
     }
-    const double sc = T / NF;
-    *ue = make_double2(y0.x * sc, y0.y * sc);
-    *uo = make_double2(y1.x * sc, y1.y * sc);
+    *ue = y0;
+    *uo = y1;
+}
+
+// The value of a channel with rotation (c, s) = exp(i phi_c): exp(i phi_c) v.
+__device__ __forceinline__ double2 rot(double2 v, double c, double s)
+{
+    return cmulf(v, make_double2(c, s));
 }
 
 // Template offsets j (in -64 .. 63) of a lane's two values.
@@ -402,25 +579,26 @@ __global__ __launch_bounds__(WG) void k_cx_scatter(KArgs a)
     }
 }
 
-// Per-source constants of a template, one source per lane: index, centre
-// bin, delta, d, A and the channel rotations (cos, sin of phi_A and phi_E).
-struct SrcConsts {
-    uint32_t i;
-    int qb;
-    double delta, d, A, ca, sa, ce, se;
-};
+// The channel rotations of source i.
+__device__ __forceinline__ void rotations(const CxIn &in, uint32_t i, SrcConsts *c)
+{
+    sincos((double)in.PA[i], &c->sa, &c->ca);
+    sincos((double)in.PE[i], &c->se, &c->ce);
+}
 
-__device__ __forceinline__ SrcConsts src_consts(const Grid &g, const CxIn &in, uint32_t i, bool rot)
+// The constants of source i (one source per lane) with fixed-point
+// exponent E; the channel rotations only when rot.
+__device__ __forceinline__ SrcConsts src_consts(const Grid &g, const CxIn &in, uint32_t i, int E, bool rot)
 {
     SrcConsts c;
+    double d;
     c.i = i;
-    c.qb = centre_bin(g, in.F[i], in.FD[i], &c.delta, &c.d);
-    c.A = (double)in.A[i];
+    c.need = 1;
+    c.qb = centre_bin(g, in.F[i], in.FD[i], &c.delta, &d);
+    c.dh = d * 0.5;
+    c.sc = ldexp(((double)in.A[i] * 0.5) * (g.T / NF), E);
     c.ca = c.sa = c.ce = c.se = 0.0;
-    if (rot) {
-        sincos((double)in.PA[i], &c.sa, &c.ca);
-        sincos((double)in.PE[i], &c.se, &c.ce);
-    }
+    if (rot) rotations(in, i, &c);
     return c;
 }
 
@@ -438,9 +616,10 @@ __device__ __forceinline__ SrcConsts bcast(const SrcConsts &c, int k)
     SrcConsts r;
     r.i = (uint32_t)__builtin_amdgcn_readlane((int)c.i, k);
     r.qb = __builtin_amdgcn_readlane(c.qb, k);
+    r.need = __builtin_amdgcn_readlane(c.need, k);
     r.delta = rl(c.delta, k);
-    r.d = rl(c.d, k);
-    r.A = rl(c.A, k);
+    r.dh = rl(c.dh, k);
+    r.sc = rl(c.sc, k);
     r.ca = rl(c.ca, k);
     r.sa = rl(c.sa, k);
     r.ce = rl(c.ce, k);
@@ -455,8 +634,10 @@ __device__ __forceinline__ SrcConsts bcast(const SrcConsts &c, int k)
 // template after the other by the whole wave.
 __global__ __launch_bounds__(WG) void k_cx_inject(KArgs a)
 {
-    __shared__ long long acc[4][CXW];
-    __shared__ double2 tw[NF];
+    // per channel word, the window's even bins then its odd bins (w0 is
+    // even): the 64 lanes of one atomic add hit 64 consecutive words
+    __shared__ long long acc[4][2][CXW / 2];
+    __shared__ double2 ex[NEX];
     const Grid &g = a.g;
     const CxDev &d = a.d;
     const CxIn &in = a.in;
@@ -471,55 +652,65 @@ __global__ __launch_bounds__(WG) void k_cx_inject(KArgs a)
     const int tile = lo;
     const uint32_t s0 = d.tcnt[tile] + (b - d.cbase[tile]) * (uint32_t)CH;
     const uint32_t s1 = min(s0 + (uint32_t)CH, d.tcnt[tile + 1]);
-    for (int k = threadIdx.x; k < 4 * CXW; k += WG) (&acc[0][0])[k] = 0;
-    set_twiddles(tw);
+    for (int k = threadIdx.x; k < 4 * CXW; k += WG) (&acc[0][0][0])[k] = 0;
+    set_cis_table(ex);
+    const LaneFft L = lane_fft();
     __syncthreads();
     const int E = cx_exp(d.ctl->amax_bits, in.n, g.T);
-    const int w0 = tile * CX_TILE - HALO;        // grid bin of acc[.][0]
+    const int w0 = tile * CX_TILE - HALO;        // grid bin of the window's first bin
     int je, jo;
     lane_offsets(&je, &jo);
     const double cut2 = g.cut2, T = g.T;
-    const int wave = threadIdx.x >> 6;
-    for (uint32_t base = s0 + 64u * (uint32_t)wave; base < s1; base += 64u * (WG / 64)) {
+    // rho_0^2 of the 2^E-scaled values: (8/T) 2^-2E sum
+    const double r0s = ldexp(8.0 / T, -2 * E);
+    // each wave takes an equal share of the chunk, 64 sources at a time
+    const uint32_t wave = threadIdx.x >> 6, share = (s1 - s0 + WG / 64 - 1) / (WG / 64);
+    const uint32_t v0 = s0 + wave * share, v1 = min(v0 + share, s1);
+    for (uint32_t base = v0; base < v1; base += 64u) {
         const uint32_t s = base + (uint32_t)lane();
-        const SrcConsts mine = src_consts(g, in, d.order[s < s1 ? s : s0], true);
-        const int cnt = (int)min(64u, s1 - base);
-        for (int k = 0; k < cnt; ++k) {
-            const SrcConsts c = bcast(mine, k);
-            double2 ue, uo;
-            wave_template(c.A, c.delta, c.d, T, tw, &ue, &uo);
-            const int be = c.qb + je, bo = c.qb + jo;
-            const bool ine = be >= 0 && be < g.B, ino = bo >= 0 && bo < g.B;
+        SrcConsts mine = src_consts(g, in, d.order[s < v1 ? s : v0], E, true);
+        {
             // the candidate cut: sum_j |U_j|^2 = T^2 A^2 / 4 (Parseval), so
             // rho_0^2 <= 2 T A^2 max 1/S_instr over the template's (at most
             // two) segments; below the cut by that bound, no exact sum
-            const int s0 = max(c.qb - HALO, 0) / NF, s1 = min(c.qb + HALO - 1, g.B - 1) / NF;
-            const double bound = 2.0 * T * (c.A * c.A) * fmax(d.isx_max[s0], d.isx_max[s1]);
-            double r0 = 0.0;
-            if (bound * (1.0 + 1e-9) >= cut2) {
+            const double A = (double)in.A[mine.i];
+            const int g0 = max(mine.qb - HALO, 0) / NF, g1 = min(mine.qb + HALO - 1, g.B - 1) / NF;
+            const double bound = 2.0 * T * (A * A) * fmax(d.isx_max[g0], d.isx_max[g1]);
+            mine.need = bound * (1.0 + 1e-9) >= cut2;
+        }
+        const int cnt = (int)min(64u, v1 - base);
+        for (int k = 0; k < cnt; ++k) {
+            const SrcConsts c = bcast(mine, k);
+            double2 ue, uo;
+            wave_template(c, L, ex, &ue, &uo);
+            const int be = c.qb + je, bo = c.qb + jo;
+            const bool ine = be >= 0 && be < g.B, ino = bo >= 0 && bo < g.B;
+            if (c.need) {
                 const double pe = ue.x * ue.x + ue.y * ue.y, po = uo.x * uo.x + uo.y * uo.y;
-                r0 = (ine ? pe * d.isx[be] : 0.0) + (ino ? po * d.isx[bo] : 0.0);
-                r0 = (8.0 / T) * wave_sum(r0);
-            }
-            if (r0 >= cut2 && lane() == 0) {
-                const uint32_t slot = atomicAdd(&d.ctl->cand_cursor, 1u);
-                d.c_src[slot] = c.i;
-                d.c_iter[slot] = -1;
-                d.c_rho2[slot] = r0;
+                double r = (ine ? pe * d.isx[be] : 0.0) + (ino ? po * d.isx[bo] : 0.0);
+                const double r0 = r0s * wave_sum(r);
+                if (r0 >= cut2 && lane() == 0) {
+                    const uint32_t slot = atomicAdd(&d.ctl->cand_cursor, 1u);
+                    d.c_src[slot] = c.i;
+                    d.c_iter[slot] = -1;
+                    d.c_rho2[slot] = r0;
+                }
             }
             if (ine) {
-                unsigned long long *p = (unsigned long long *)&acc[0][be - w0];
-                atomicAdd(p, (unsigned long long)fx(c.ca * ue.x - c.sa * ue.y, E));
-                atomicAdd(p + CXW, (unsigned long long)fx(c.sa * ue.x + c.ca * ue.y, E));
-                atomicAdd(p + 2 * CXW, (unsigned long long)fx(c.ce * ue.x - c.se * ue.y, E));
-                atomicAdd(p + 3 * CXW, (unsigned long long)fx(c.se * ue.x + c.ce * ue.y, E));
+                const double2 va = rot(ue, c.ca, c.sa), ve = rot(ue, c.ce, c.se);
+                unsigned long long *p = (unsigned long long *)&acc[0][(be - w0) & 1][(be - w0) >> 1];
+                atomicAdd(p, (unsigned long long)fxm(va.x));
+                atomicAdd(p + CXW, (unsigned long long)fxm(va.y));
+                atomicAdd(p + 2 * CXW, (unsigned long long)fxm(ve.x));
+                atomicAdd(p + 3 * CXW, (unsigned long long)fxm(ve.y));
             }
             if (ino) {
-                unsigned long long *p = (unsigned long long *)&acc[0][bo - w0];
-                atomicAdd(p, (unsigned long long)fx(c.ca * uo.x - c.sa * uo.y, E));
-                atomicAdd(p + CXW, (unsigned long long)fx(c.sa * uo.x + c.ca * uo.y, E));
-                atomicAdd(p + 2 * CXW, (unsigned long long)fx(c.ce * uo.x - c.se * uo.y, E));
-                atomicAdd(p + 3 * CXW, (unsigned long long)fx(c.se * uo.x + c.ce * uo.y, E));
+                const double2 va = rot(uo, c.ca, c.sa), ve = rot(uo, c.ce, c.se);
+                unsigned long long *p = (unsigned long long *)&acc[0][(bo - w0) & 1][(bo - w0) >> 1];
+                atomicAdd(p, (unsigned long long)fxm(va.x));
+                atomicAdd(p + CXW, (unsigned long long)fxm(va.y));
+                atomicAdd(p + 2 * CXW, (unsigned long long)fxm(ve.x));
+                atomicAdd(p + 3 * CXW, (unsigned long long)fxm(ve.y));
             }
         }
     }
@@ -529,7 +720,7 @@ __global__ __launch_bounds__(WG) void k_cx_inject(KArgs a)
         if (bin < 0 || bin >= g.B) continue;
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-            const long long v = acc[c][k];
+            const long long v = acc[c][k & 1][k >> 1];
             if (v) atomicAdd((unsigned long long *)&d.h[(size_t)c * g.B + bin], (unsigned long long)v);
         }
     }
@@ -567,18 +758,21 @@ __global__ __launch_bounds__(WG) void k_cx_power(KArgs a)
 // evaluates them one after the other.
 __global__ __launch_bounds__(WG) void k_cx_snr(KArgs a)
 {
-    __shared__ double2 tw[NF];
+    __shared__ double2 ex[NEX];
     const Grid &g = a.g;
     const CxDev &d = a.d;
     const CxIn &in = a.in;
     Ctl *c = d.ctl;
-    set_twiddles(tw);
+    set_cis_table(ex);
+    const LaneFft L = lane_fft();
     __syncthreads();
     if (c->done || c->bad) return;
     const uint32_t t = c->iter, nxt = t + 1;
     const uint32_t nc = c->cand_cursor;
     const int E = cx_exp(c->amax_bits, in.n, g.T);
     const double T = g.T;
+    // rho^2 of the 2^E-scaled values: (4/T) 2^-2E sum
+    const double rs = ldexp(4.0 / T, -2 * E);
     const size_t B = (size_t)g.B;
     int je, jo;
     lane_offsets(&je, &jo);
@@ -590,7 +784,7 @@ __global__ __launch_bounds__(WG) void k_cx_snr(KArgs a)
         bool need = j < nc && d.c_iter[j] < 0;
         SrcConsts mine{};
         if (need) {
-            mine = src_consts(g, in, d.c_src[j], false);
+            mine = src_consts(g, in, d.c_src[j], E, false);
             if (t > 0) {
                 const int lo = max(mine.qb - HALO, 0), hi = min(mine.qb + HALO - 1, g.B - 1);
                 bool changed = false;
@@ -606,7 +800,7 @@ __global__ __launch_bounds__(WG) void k_cx_snr(KArgs a)
             const uint32_t jk = base + (uint32_t)k;
             ++evals;
             double2 ue, uo;
-            wave_template(cs.A, cs.delta, cs.d, T, tw, &ue, &uo);
+            wave_template(cs, L, ex, &ue, &uo);
             const int be = cs.qb + je, bo = cs.qb + jo;
             const bool ine = be >= 0 && be < g.B, ino = bo >= 0 && bo < g.B;
             const double pe = ue.x * ue.x + ue.y * ue.y, po = uo.x * uo.x + uo.y * uo.y;
@@ -619,7 +813,7 @@ __global__ __launch_bounds__(WG) void k_cx_snr(KArgs a)
                 const double sA = d.S[bo], sE = d.S[B + bo];
                 r += po * ((sA + sE) / (sA * sE));
             }
-            const double r2 = (4.0 / T) * wave_sum(r);
+            const double r2 = rs * wave_sum(r);
             const double rel = fabs(sqrt(r2) / g.rth - 1.0);
             minm = fmin(minm, rel);
             my_near += rel <= 1e-6;
@@ -627,22 +821,23 @@ __global__ __launch_bounds__(WG) void k_cx_snr(KArgs a)
             if (!(r2 > g.rth2)) continue;
             ++my_new;
             if (lane() == 0) d.c_iter[jk] = (int32_t)t;
-            double sa, ca, se, ce;
-            sincos((double)in.PA[cs.i], &sa, &ca);
-            sincos((double)in.PE[cs.i], &se, &ce);
+            SrcConsts rc;
+            rotations(in, cs.i, &rc);
             if (ine) {
+                const double2 va = rot(ue, rc.ca, rc.sa), ve = rot(ue, rc.ce, rc.se);
                 unsigned long long *p = (unsigned long long *)&d.h[be];
-                atomicAdd(p, (unsigned long long)-fx(ca * ue.x - sa * ue.y, E));
-                atomicAdd(p + B, (unsigned long long)-fx(sa * ue.x + ca * ue.y, E));
-                atomicAdd(p + 2 * B, (unsigned long long)-fx(ce * ue.x - se * ue.y, E));
-                atomicAdd(p + 3 * B, (unsigned long long)-fx(se * ue.x + ce * ue.y, E));
+                atomicAdd(p, (unsigned long long)-fxm(va.x));
+                atomicAdd(p + B, (unsigned long long)-fxm(va.y));
+                atomicAdd(p + 2 * B, (unsigned long long)-fxm(ve.x));
+                atomicAdd(p + 3 * B, (unsigned long long)-fxm(ve.y));
             }
             if (ino) {
+                const double2 va = rot(uo, rc.ca, rc.sa), ve = rot(uo, rc.ce, rc.se);
                 unsigned long long *p = (unsigned long long *)&d.h[bo];
-                atomicAdd(p, (unsigned long long)-fx(ca * uo.x - sa * uo.y, E));
-                atomicAdd(p + B, (unsigned long long)-fx(sa * uo.x + ca * uo.y, E));
-                atomicAdd(p + 2 * B, (unsigned long long)-fx(ce * uo.x - se * uo.y, E));
-                atomicAdd(p + 3 * B, (unsigned long long)-fx(se * uo.x + ce * uo.y, E));
+                atomicAdd(p, (unsigned long long)-fxm(va.x));
+                atomicAdd(p + B, (unsigned long long)-fxm(va.y));
+                atomicAdd(p + 2 * B, (unsigned long long)-fxm(ve.x));
+                atomicAdd(p + 3 * B, (unsigned long long)-fxm(ve.y));
             }
             if (lane() == 0) {
                 const int lo = max(cs.qb - HALO, 0), hi = min(cs.qb + HALO - 1, g.B - 1);
@@ -770,17 +965,23 @@ __global__ __launch_bounds__(WG) void k_cx_hout(KArgs a, int ch, double *out)
 __global__ __launch_bounds__(WG) void k_cx_templates(Grid g, const float *A, const float *F, const float *FD,
                                                      uint32_t n, int64_t *q, double *U)
 {
-    __shared__ double2 tw[NF];
-    set_twiddles(tw);
+    __shared__ double2 ex[NEX];
+    set_cis_table(ex);
+    const LaneFft L = lane_fft();
     __syncthreads();
     int je, jo;
     lane_offsets(&je, &jo);
     const uint32_t waves = gridDim.x * (WG / 64);
     for (uint32_t i = blockIdx.x * (WG / 64) + (threadIdx.x >> 6); i < n; i += waves) {
-        double qd, delta, dd;
-        const bool ok = cx_centre((double)F[i], (double)FD[i], g.T, &qd, &delta, &dd);
+        double qd, dd;
+        SrcConsts c{};
+        const bool ok = cx_centre((double)F[i], (double)FD[i], g.T, &qd, &c.delta, &dd);
         double2 ue = make_double2(0.0, 0.0), uo = ue;
-        if (ok) wave_template((double)A[i], delta, dd, g.T, tw, &ue, &uo);
+        if (ok) {
+            c.dh = dd * 0.5;
+            c.sc = ((double)A[i] * 0.5) * (g.T / NF);
+            wave_template(c, L, ex, &ue, &uo);
+        }
         if (lane() == 0) q[i] = ok ? (int64_t)qd : INT64_MIN;
         double *u = U + (size_t)i * 2 * NF;
         u[2 * (je + HALO)] = ue.x;
