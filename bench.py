@@ -529,7 +529,8 @@ def bench_precision(args):
 # HBM-bound: bytes per unit.  Template-bound (FFT synthesis of a 128-sample
 # template in fp64): counted flops per template -- the 128-point complex FFT
 # 5 N log2 N = 4480, the sample phases and scaling 128 x 8 = 1024, the
-# power-weighted sum 128 x 5 = 640; the two sincospi per lane are not counted.
+# power-weighted sum 128 x 5 = 640; the evaluations of exp(2 pi i t) per
+# sample are not counted.
 CX_ALGO = {
     "xupdate": ("hbm", 48.0),        # per bin: read 4 int64 of h, write X_A, X_E
     "median": ("hbm", 24.0),         # per output bin and channel: read X and S_instr, write S
