@@ -22,13 +22,15 @@
 //  * A template is one wave's work: two samples per lane, the first radix-2
 //    stage inside the lane, then two 64-point FFTs across the lanes.  The
 //    exchanges run on the VALU, not through the LDS crossbar: row swaps
-//    (v_permlane32_swap, v_permlane16_swap) for spans 32 and 16, DPP moves
-//    for spans 8 .. 1.  exp(2 pi i t) is a 16-entry LDS table (one bank row:
-//    no conflicts) times short Taylor polynomials; twiddles and signs are
-//    lane constants in registers.  Templates are recomputed wherever they
-//    are needed (injection, every SNR evaluation, subtraction) instead of
-//    stored (2 KB per candidate, 20 GB for 1e7 sources): about 280 VALU
-//    instructions of one wave per template.
+//    (v_permlane32_swap, v_permlane16_swap) of the two FFTs' registers for
+//    spans 32 and 16, after which each lane computes whole butterflies, and
+//    DPP moves for spans 8 .. 1 (the lanes hold their positions permuted so
+//    that span 4 is one half-row mirror).  exp(2 pi i t) is a 16-entry LDS
+//    table (one bank row: no conflicts) times short Taylor polynomials;
+//    twiddles and signs are lane constants in registers.  Templates are
+//    recomputed wherever they are needed (injection, every SNR evaluation,
+//    subtraction) instead of stored (2 KB per candidate, 20 GB for 1e7
+//    sources): about 240 VALU instructions of one wave per template.
 //  * h is exact fixed point (int64, unit 2^-E with E from the largest
 //    amplitude and the source count), so injection and subtraction are
 //    order-independent integer adds and a subtracted template cancels to the
@@ -38,7 +40,7 @@
 //    histograms, one scan, a scatter with per-block range reservations);
 //    each block accumulates up to CH sources of one tile into an LDS window
 //    of the tile plus the template reach on each side (even and odd bins
-//    apart, so the 64 lanes of one atomic add hit consecutive words), then
+//    apart: the lanes of one atomic add hit pairs of neighbouring words), then
 //    adds the window to h with one global atomic per touched word.  Each
 //    wave takes an equal share of the chunk, 64 sources at a time: their
 //    constants are computed one per lane and broadcast by readlane while
@@ -75,66 +77,70 @@ __device__ __forceinline__ int lane() { return __lane_id(); }
 
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
-// Exchanges between lane pairs (l, l ^ span) without the LDS crossbar.
-// Spans 32 and 16: the row swaps v_permlane32_swap / v_permlane16_swap of a
-// register with itself leave on both lanes of a pair the first lane's value
-// (first result) and the second lane's (second result).  Spans 8 .. 1: DPP
-// moves within rows of 16 lanes give the partner's value (span 4 as a
-// half-row mirror, l ^ 7, then a quad reversal, l ^ 3).
-template <int SPAN> __device__ __forceinline__ int dpp_xor(int v)
+// Exchanges between lanes without the LDS crossbar.
+//  * Row swaps (gfx950): v_permlane32_swap(P, Q) leaves P = [P lanes 0-31,
+//    Q lanes 0-31] and Q = [P lanes 32-63, Q lanes 32-63];
+//    v_permlane16_swap(P, Q) does the same on rows of 16 lanes, P = [P row 0,
+//    Q row 0, P row 2, Q row 2] and Q = [P row 1, Q row 1, P row 3, Q row 3].
+//  * DPP moves within rows of 16 lanes: lane l reads lane l ^ 8 (row rotate
+//    by 8), l ^ 7 (half-row mirror), l ^ 2 and l ^ 1 (quad permutes).
+template <int SPAN> __device__ __forceinline__ void row_swap(double *P, double *Q)
 {
-    static_assert(SPAN == 8 || SPAN == 4 || SPAN == 2 || SPAN == 1, "DPP spans");
-    // every lane of the wave is active and every source lane is in range:
-    // the moves need no old value (bound_ctrl)
-    if constexpr (SPAN == 8) {
-        return __builtin_amdgcn_mov_dpp(v, 0x128, 0xf, 0xf, true);      // row_ror:8
-    } else if constexpr (SPAN == 4) {
-        const int t = __builtin_amdgcn_mov_dpp(v, 0x141, 0xf, 0xf, true); // row_half_mirror
-        return __builtin_amdgcn_mov_dpp(t, 0x1B, 0xf, 0xf, true);      // quad_perm [3,2,1,0]
-    } else if constexpr (SPAN == 2) {
-        return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xf, 0xf, true);      // quad_perm [2,3,0,1]
+    static_assert(SPAN == 32 || SPAN == 16, "row-swap spans");
+    const long long bp = __double_as_longlong(*P), bq = __double_as_longlong(*Q);
+    const unsigned plo = (unsigned)(bp & 0xffffffffll), phi = (unsigned)(bp >> 32);
+    const unsigned qlo = (unsigned)(bq & 0xffffffffll), qhi = (unsigned)(bq >> 32);
+    unsigned p0, q0, p1, q1;
+    if constexpr (SPAN == 32) {
+        const auto rl = __builtin_amdgcn_permlane32_swap(plo, qlo, false, false);
+        const auto rh = __builtin_amdgcn_permlane32_swap(phi, qhi, false, false);
+        p0 = rl[0]; q0 = rl[1]; p1 = rh[0]; q1 = rh[1];
     } else {
-        return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xf, 0xf, true);      // quad_perm [1,0,3,2]
+        const auto rl = __builtin_amdgcn_permlane16_swap(plo, qlo, false, false);
+        const auto rh = __builtin_amdgcn_permlane16_swap(phi, qhi, false, false);
+        p0 = rl[0]; q0 = rl[1]; p1 = rh[0]; q1 = rh[1];
     }
+    *P = __longlong_as_double(((long long)p1 << 32) | p0);
+    *Q = __longlong_as_double(((long long)q1 << 32) | q0);
 }
 
-template <int SPAN> __device__ __forceinline__ double partner(double v)
+// DPP patterns: 8 = l ^ 8, 7 = l ^ 7, 2 = l ^ 2, 1 = l ^ 1.  Every lane of
+// the wave is active and every source lane is in range: the moves need no
+// old value (bound_ctrl).
+template <int PAT> __device__ __forceinline__ int dpp_move(int v)
+{
+    static_assert(PAT == 8 || PAT == 7 || PAT == 2 || PAT == 1, "DPP patterns");
+    if constexpr (PAT == 8) return __builtin_amdgcn_mov_dpp(v, 0x128, 0xf, 0xf, true);   // row_ror:8
+    else if constexpr (PAT == 7) return __builtin_amdgcn_mov_dpp(v, 0x141, 0xf, 0xf, true); // row_half_mirror
+    else if constexpr (PAT == 2) return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xf, 0xf, true);  // quad_perm [2,3,0,1]
+    else return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xf, 0xf, true);                        // quad_perm [1,0,3,2]
+}
+
+template <int PAT> __device__ __forceinline__ double partner(double v)
 {
     const long long b = __double_as_longlong(v);
-    const int lo = dpp_xor<SPAN>((int)(b & 0xffffffffll)), hi = dpp_xor<SPAN>((int)(b >> 32));
+    const int lo = dpp_move<PAT>((int)(b & 0xffffffffll)), hi = dpp_move<PAT>((int)(b >> 32));
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-template <int SPAN> __device__ __forceinline__ void pair_of(double v, double *first, double *second)
+template <int PAT> __device__ __forceinline__ double2 partner2(double2 v)
 {
-    static_assert(SPAN == 32 || SPAN == 16, "row-swap spans");
-    const long long b = __double_as_longlong(v);
-    const unsigned lo = (unsigned)(b & 0xffffffffll), hi = (unsigned)(b >> 32);
-    unsigned f_lo, s_lo, f_hi, s_hi;
-    if constexpr (SPAN == 32) {
-        const auto rl = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
-        const auto rh = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
-        f_lo = rl[0]; s_lo = rl[1]; f_hi = rh[0]; s_hi = rh[1];
-    } else {
-        const auto rl = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
-        const auto rh = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
-        f_lo = rl[0]; s_lo = rl[1]; f_hi = rh[0]; s_hi = rh[1];
-    }
-    *first = __longlong_as_double(((long long)f_hi << 32) | f_lo);
-    *second = __longlong_as_double(((long long)s_hi << 32) | s_lo);
+    return make_double2(partner<PAT>(v.x), partner<PAT>(v.y));
 }
 
-// Sum over the wave, the same value on every lane (a butterfly: both lanes
-// of a pair add the same two values).
+// Sum over the wave, the same value on every lane: a butterfly over lane
+// pairs that differ in bit 5, bit 4, bit 3, bits 0-2, bit 1 and bit 0 (both
+// lanes of a pair add the same two values).
 __device__ __forceinline__ double wave_sum(double v)
 {
-    double f, s;
-    pair_of<32>(v, &f, &s);
-    v = f + s;
-    pair_of<16>(v, &f, &s);
-    v = f + s;
+    double w = v;
+    row_swap<32>(&v, &w);
+    v += w;
+    w = v;
+    row_swap<16>(&v, &w);
+    v += w;
     v += partner<8>(v);
-    v += partner<4>(v);
+    v += partner<7>(v);
     v += partner<2>(v);
     v += partner<1>(v);
     return v;
@@ -218,18 +224,25 @@ __device__ __forceinline__ double2 cmulf(double2 a, double2 b)
     return make_double2(fma(a.x, b.x, -(a.y * b.y)), fma(a.x, b.y, a.y * b.x));
 }
 
-// A lane's constants of the wave FFT: its sample times x = n/128 (n = l and
-// l + 64) with their squares, the twiddle of the first stage, and for the
-// stages of spans 32 .. 4 the sign (+1 on the lane of the pair's first
-// element, -1 on the other) and the twiddle exp(-2 pi i m / 128) the second
-// element takes (1 on the first).
+// The wave FFT.  Lane l holds the samples n = ell and ell + 64, where ell is
+// l with its low three bits b mapped to b ^ 3 when b >= 4 (an involution):
+// then the lanes that hold the positions ell and ell ^ 4 are l and l ^ 7,
+// one DPP move apart, while positions ell ^ 8, ell ^ 2 and ell ^ 1 stay at
+// l ^ 8, l ^ 2 and l ^ 1.
+__device__ __forceinline__ int lane_pos(int l) { return l ^ ((l & 4) ? 3 : 0); }
+
+// A lane's constants: its sample times x = n/128 with their squares, the
+// twiddles of the in-lane stage (128 points), of the two row-swap stages
+// (64 and 32 points, full butterflies in every lane) and of the spans 8
+// and 4 (1 on the lane of the pair's first element), and the signs of the
+// spans 8 .. 1 (+1 on the first element's lane, -1 on the other).
 struct LaneFft {
     double x0, x0q, x1, x1q;
-    double2 w1, w[4];
-    double sg[6];
+    double2 w1, wa, wb, w8, w4;
+    double sg8, sg4, sg2, sg1;
 };
 
-__device__ __forceinline__ double2 twiddle(int m)
+__device__ __forceinline__ double2 twiddle(int m)   // exp(-2 pi i m / 128)
 {
     double s, c;
     sincospi((double)m / (NF / 2), &s, &c);
@@ -239,20 +252,20 @@ __device__ __forceinline__ double2 twiddle(int m)
 __device__ __forceinline__ LaneFft lane_fft()
 {
     LaneFft L;
-    const int l = lane();
-    L.x0 = (double)l / NF;
-    L.x1 = (double)(l + NF / 2) / NF;
+    const int e = lane_pos(lane()), u = e & 15;
+    L.x0 = (double)e / NF;
+    L.x1 = (double)(e + NF / 2) / NF;
     L.x0q = L.x0 * L.x0;
     L.x1q = L.x1 * L.x1;
-    L.w1 = twiddle(l);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int span = 32 >> k;
-        const bool bottom = (l & span) != 0;
-        L.w[k] = bottom ? twiddle((l & (span - 1)) * (64 / span)) : make_double2(1.0, 0.0);
-    }
-#pragma unroll
-    for (int k = 0; k < 6; ++k) L.sg[k] = (l & (32 >> k)) ? -1.0 : 1.0;
+    L.w1 = twiddle(e);                       // W_128^e
+    L.wa = twiddle(2 * (e & 31));            // W_64^(e mod 32)
+    L.wb = twiddle(4 * u);                   // W_32^(e mod 16)
+    L.w8 = (u & 8) ? twiddle(8 * (u & 7)) : make_double2(1.0, 0.0);    // W_16
+    L.w4 = (u & 4) ? twiddle(16 * (u & 3)) : make_double2(1.0, 0.0);   // W_8
+    L.sg8 = (u & 8) ? -1.0 : 1.0;
+    L.sg4 = (u & 4) ? -1.0 : 1.0;
+    L.sg2 = (u & 2) ? -1.0 : 1.0;
+    L.sg1 = (u & 1) ? -1.0 : 1.0;
     return L;
 }
 
@@ -268,81 +281,69 @@ struct SrcConsts {
     double delta, dh, sc, ca, sa, ce, se;
 };
 
-// The template of one source, by the whole wave: on return lane l holds
-// ue = 2^E U at m = 2 r and uo = 2^E U at m = 2 r + 1, r = bitrev6(l) (U
-// itself when sc = (A/2)(T/128)).  The phase is the definition's operations
-// in their order (delta x, (d/2) x^2, their sum), so it is the same double
-// as in a plain evaluation.
-// Samples n = l and l + 64; the first decimation-in-frequency stage (n,
-// n + 64) inside the lane gives the even and odd outputs as two 64-point
-// DFTs, each finished across the lanes in six stages.
+// The template of one source, by the whole wave: on return each lane holds
+// two values of 2^E U (U itself when sc = (A/2)(T/128)), at the offsets
+// lane_offsets gives.  The phase is the definition's operations in their
+// order (delta x, (d/2) x^2, their sum), so it is the same double as in a
+// plain evaluation.  Decimation in frequency: the first stage (n, n + 64)
+// inside the lane gives the even and odd outputs as two 64-point DFTs a and
+// b (registers P = a, Q = b).  The spans 32 and 16 are row swaps of P with
+// Q, after which every lane holds both elements of one butterfly (of a or
+// of b) and computes both outputs; the spans 8 .. 1 exchange within each
+// register (the partner's value p and the own v give p + sg v, times the
+// twiddle, so the first lane gets the sum and the second the difference).
 __device__ __forceinline__ void wave_template(const SrcConsts &c, const LaneFft &L, const double2 *ex,
                                               double2 *ue, double2 *uo)
 {
-    const int l = lane();
     const double2 e0 = cis_turns(c.delta * L.x0 + c.dh * L.x0q, ex);
     const double2 e1 = cis_turns(c.delta * L.x1 + c.dh * L.x1q, ex);
     const double2 a = make_double2(c.sc * e0.x, c.sc * e0.y), b = make_double2(c.sc * e1.x, c.sc * e1.y);
-    double2 y0 = cadd(a, b);
-    double2 y1 = cmulf(csub(a, b), L.w1);
-    // Butterflies without branches: the pair's first lane takes a + b
-    // (twiddle 1, which leaves the sum exact), the second (a - b) w; both as
-    // (a + sg b) w, with a and b from a row swap (spans 32, 16) or as the
-    // partner's value p and the own v, p + sg v (spans 8 .. 1).
+    double2 P = cadd(a, b);
+    double2 Q = cmulf(csub(a, b), L.w1);
+    // span 32, then 16: full butterflies (twiddle 1 on the sum)
+    row_swap<32>(&P.x, &Q.x);
+    row_swap<32>(&P.y, &Q.y);
     {
-        double2 f0, s0, f1, s1;
-        pair_of<32>(y0.x, &f0.x, &s0.x);
-        pair_of<32>(y0.y, &f0.y, &s0.y);
-        pair_of<32>(y1.x, &f1.x, &s1.x);
-        pair_of<32>(y1.y, &f1.y, &s1.y);
-        const double sg = L.sg[0];
-        y0 = cmulf(make_double2(fma(sg, s0.x, f0.x), fma(sg, s0.y, f0.y)), L.w[0]);
-        y1 = cmulf(make_double2(fma(sg, s1.x, f1.x), fma(sg, s1.y, f1.y)), L.w[0]);
+        const double2 t = cadd(P, Q);
+        Q = cmulf(csub(P, Q), L.wa);
+        P = t;
+    }
+    row_swap<16>(&P.x, &Q.x);
+    row_swap<16>(&P.y, &Q.y);
+    {
+        const double2 t = cadd(P, Q);
+        Q = cmulf(csub(P, Q), L.wb);
+        P = t;
+    }
+    // spans 8 and 4 (the latter between lanes l and l ^ 7)
+    {
+        const double2 p0 = partner2<8>(P), p1 = partner2<8>(Q);
+        const double sg = L.sg8;
+        P = cmulf(make_double2(fma(sg, P.x, p0.x), fma(sg, P.y, p0.y)), L.w8);
+        Q = cmulf(make_double2(fma(sg, Q.x, p1.x), fma(sg, Q.y, p1.y)), L.w8);
     }
     {
-        double2 f0, s0, f1, s1;
-        pair_of<16>(y0.x, &f0.x, &s0.x);
-        pair_of<16>(y0.y, &f0.y, &s0.y);
-        pair_of<16>(y1.x, &f1.x, &s1.x);
-        pair_of<16>(y1.y, &f1.y, &s1.y);
-        const double sg = L.sg[1];
-        y0 = cmulf(make_double2(fma(sg, s0.x, f0.x), fma(sg, s0.y, f0.y)), L.w[1]);
-        y1 = cmulf(make_double2(fma(sg, s1.x, f1.x), fma(sg, s1.y, f1.y)), L.w[1]);
-    }
-    {
-        const double2 p0 = make_double2(partner<8>(y0.x), partner<8>(y0.y));
-        const double2 p1 = make_double2(partner<8>(y1.x), partner<8>(y1.y));
-        const double sg = L.sg[2];
-        y0 = cmulf(make_double2(fma(sg, y0.x, p0.x), fma(sg, y0.y, p0.y)), L.w[2]);
-        y1 = cmulf(make_double2(fma(sg, y1.x, p1.x), fma(sg, y1.y, p1.y)), L.w[2]);
-    }
-    {
-        const double2 p0 = make_double2(partner<4>(y0.x), partner<4>(y0.y));
-        const double2 p1 = make_double2(partner<4>(y1.x), partner<4>(y1.y));
-        const double sg = L.sg[3];
-        y0 = cmulf(make_double2(fma(sg, y0.x, p0.x), fma(sg, y0.y, p0.y)), L.w[3]);
-        y1 = cmulf(make_double2(fma(sg, y1.x, p1.x), fma(sg, y1.y, p1.y)), L.w[3]);
+        const double2 p0 = partner2<7>(P), p1 = partner2<7>(Q);
+        const double sg = L.sg4;
+        P = cmulf(make_double2(fma(sg, P.x, p0.x), fma(sg, P.y, p0.y)), L.w4);
+        Q = cmulf(make_double2(fma(sg, Q.x, p1.x), fma(sg, Q.y, p1.y)), L.w4);
     }
     // span 2: twiddles 1 and -i (a swap and a sign); span 1: twiddle 1
     {
-        const double2 p0 = make_double2(partner<2>(y0.x), partner<2>(y0.y));
-        const double2 p1 = make_double2(partner<2>(y1.x), partner<2>(y1.y));
-        const double sg = L.sg[4];
-        const double2 d0 = make_double2(fma(sg, y0.x, p0.x), fma(sg, y0.y, p0.y));
-        const double2 d1 = make_double2(fma(sg, y1.x, p1.x), fma(sg, y1.y, p1.y));
-        const bool rot = (l & 3) == 3;
-        y0 = rot ? make_double2(d0.y, -d0.x) : d0;
-        y1 = rot ? make_double2(d1.y, -d1.x) : d1;
+        const double2 p0 = partner2<2>(P), p1 = partner2<2>(Q);
+        const double sg = L.sg2;
+        const double2 d0 = make_double2(fma(sg, P.x, p0.x), fma(sg, P.y, p0.y));
+        const double2 d1 = make_double2(fma(sg, Q.x, p1.x), fma(sg, Q.y, p1.y));
+        const bool rot = (lane_pos(lane()) & 3) == 3;
+        P = rot ? make_double2(d0.y, -d0.x) : d0;
+        Q = rot ? make_double2(d1.y, -d1.x) : d1;
     }
     {
-        const double2 p0 = make_double2(partner<1>(y0.x), partner<1>(y0.y));
-        const double2 p1 = make_double2(partner<1>(y1.x), partner<1>(y1.y));
-        const double sg = L.sg[5];
-        y0 = make_double2(fma(sg, y0.x, p0.x), fma(sg, y0.y, p0.y));
-        y1 = make_double2(fma(sg, y1.x, p1.x), fma(sg, y1.y, p1.y));
+        const double2 p0 = partner2<1>(P), p1 = partner2<1>(Q);
+        const double sg = L.sg1;
+        *ue = make_double2(fma(sg, P.x, p0.x), fma(sg, P.y, p0.y));
+        *uo = make_double2(fma(sg, Q.x, p1.x), fma(sg, Q.y, p1.y));
     }
-    *ue = y0;
-    *uo = y1;
 }
 
 // The value of a channel with rotation (c, s) = exp(i phi_c): exp(i phi_c) v.
@@ -351,13 +352,19 @@ __device__ __forceinline__ double2 rot(double2 v, double c, double s)
     return cmulf(v, make_double2(c, s));
 }
 
-// Template offsets j (in -64 .. 63) of a lane's two values.
+// Template offsets j (in -64 .. 63) of a lane's two values.  After the
+// FFT, register P of lane l (row r = l / 16) holds DFT a (rows 0, 1) or b
+// (rows 2, 3) at position i = 32 (r mod 2) + (ell mod 16), and Q the same DFT
+// at i + 16; position i of a 64-point decimation-in-frequency output is
+// frequency bitrev6(i), and a and b are the even and odd outputs.
 __device__ __forceinline__ void lane_offsets(int *je, int *jo)
 {
-    const int r = (int)(__brev((unsigned)lane()) >> 26);
-    const int me = 2 * r, mo = 2 * r + 1;
-    *je = me < NF / 2 ? me : me - NF;
-    *jo = mo < NF / 2 ? mo : mo - NF;
+    const int l = lane(), r = l >> 4;
+    const int ip = 32 * (r & 1) + (lane_pos(l) & 15), iq = ip + 16;
+    const int odd = r >= 2 ? 1 : 0;
+    const int mp = 2 * (int)(__brev((unsigned)ip) >> 26) + odd, mq = 2 * (int)(__brev((unsigned)iq) >> 26) + odd;
+    *je = mp < NF / 2 ? mp : mp - NF;
+    *jo = mq < NF / 2 ? mq : mq - NF;
 }
 
 // A source's entry: valid (finite A >= 0, f > 0, finite fdot and phases).
@@ -635,7 +642,7 @@ __device__ __forceinline__ SrcConsts bcast(const SrcConsts &c, int k)
 __global__ __launch_bounds__(WG) void k_cx_inject(KArgs a)
 {
     // per channel word, the window's even bins then its odd bins (w0 is
-    // even): the 64 lanes of one atomic add hit 64 consecutive words
+    // even): the lanes of one atomic add hit pairs of neighbouring words
     __shared__ long long acc[4][2][CXW / 2];
     __shared__ double2 ex[NEX];
     const Grid &g = a.g;
@@ -678,11 +685,8 @@ __global__ __launch_bounds__(WG) void k_cx_inject(KArgs a)
             const double bound = 2.0 * T * (A * A) * fmax(d.isx_max[g0], d.isx_max[g1]);
             mine.need = bound * (1.0 + 1e-9) >= cut2;
         }
-        const int cnt = (int)min(64u, v1 - base);
-        for (int k = 0; k < cnt; ++k) {
-            const SrcConsts c = bcast(mine, k);
-            double2 ue, uo;
-            wave_template(c, L, ex, &ue, &uo);
+        // the candidate cut and the template's values into the window
+        auto add = [&](const SrcConsts &c, const double2 &ue, const double2 &uo) {
             const int be = c.qb + je, bo = c.qb + jo;
             const bool ine = be >= 0 && be < g.B, ino = bo >= 0 && bo < g.B;
             if (c.need) {
@@ -712,6 +716,13 @@ __global__ __launch_bounds__(WG) void k_cx_inject(KArgs a)
                 atomicAdd(p + 2 * CXW, (unsigned long long)fxm(ve.x));
                 atomicAdd(p + 3 * CXW, (unsigned long long)fxm(ve.y));
             }
+        };
+        const int cnt = (int)min(64u, v1 - base);
+        for (int k = 0; k < cnt; ++k) {
+            const SrcConsts c = bcast(mine, k);
+            double2 ue, uo;
+            wave_template(c, L, ex, &ue, &uo);
+            add(c, ue, uo);
         }
     }
     __syncthreads();
@@ -799,20 +810,18 @@ __global__ __launch_bounds__(WG) void k_cx_snr(KArgs a)
             const SrcConsts cs = bcast(mine, k);
             const uint32_t jk = base + (uint32_t)k;
             ++evals;
-            double2 ue, uo;
-            wave_template(cs, L, ex, &ue, &uo);
             const int be = cs.qb + je, bo = cs.qb + jo;
             const bool ine = be >= 0 && be < g.B, ino = bo >= 0 && bo < g.B;
+            // the PSD under the template, loaded before the synthesis hides
+            // their latency (off-grid lanes read bin 0 and drop it)
+            const int bec = ine ? be : 0, boc = ino ? bo : 0;
+            const double sAe = d.S[bec], sEe = d.S[B + bec], sAo = d.S[boc], sEo = d.S[B + boc];
+            double2 ue, uo;
+            wave_template(cs, L, ex, &ue, &uo);
             const double pe = ue.x * ue.x + ue.y * ue.y, po = uo.x * uo.x + uo.y * uo.y;
             double r = 0.0;
-            if (ine) {
-                const double sA = d.S[be], sE = d.S[B + be];
-                r += pe * ((sA + sE) / (sA * sE));
-            }
-            if (ino) {
-                const double sA = d.S[bo], sE = d.S[B + bo];
-                r += po * ((sA + sE) / (sA * sE));
-            }
+            if (ine) r += pe * ((sAe + sEe) / (sAe * sEe));
+            if (ino) r += po * ((sAo + sEo) / (sAo * sEo));
             const double r2 = rs * wave_sum(r);
             const double rel = fabs(sqrt(r2) / g.rth - 1.0);
             minm = fmin(minm, rel);
