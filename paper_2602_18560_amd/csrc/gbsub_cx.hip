@@ -698,6 +698,7 @@ __global__ __launch_bounds__(WG) void k_cx_inject(KArgs a)
                     d.c_src[slot] = c.i;
                     d.c_iter[slot] = -1;
                     d.c_rho2[slot] = r0;
+                    d.c_qb[slot] = c.qb;
                 }
             }
             if (ine) {
@@ -793,16 +794,16 @@ __global__ __launch_bounds__(WG) void k_cx_snr(KArgs a)
     for (uint32_t base = (blockIdx.x * (WG / 64) + (threadIdx.x >> 6)) * 64u; base < nc; base += waves * 64u) {
         const uint32_t j = base + (uint32_t)lane();
         bool need = j < nc && d.c_iter[j] < 0;
-        SrcConsts mine{};
-        if (need) {
-            mine = src_consts(g, in, d.c_src[j], E, false);
-            if (t > 0) {
-                const int lo = max(mine.qb - HALO, 0), hi = min(mine.qb + HALO - 1, g.B - 1);
-                bool changed = false;
-                for (int tl = div_p2(lo, g.tile); tl <= div_p2(hi, g.tile); ++tl) changed |= d.sstamp[tl] >= t;
-                need = changed;
-            }
+        if (need && t > 0) {
+            const int qb = d.c_qb[j];
+            const int lo = max(qb - HALO, 0), hi = min(qb + HALO - 1, g.B - 1);
+            bool changed = false;
+            for (int tl = div_p2(lo, g.tile); tl <= div_p2(hi, g.tile); ++tl) changed |= d.sstamp[tl] >= t;
+            need = changed;
         }
+        // the constants only of the candidates evaluated
+        SrcConsts mine{};
+        if (need) mine = src_consts(g, in, d.c_src[j], E, false);
         uint64_t todo = (uint64_t)__ballot(need);
         while (todo) {
             const int k = (int)__builtin_ctzll(todo);
@@ -1036,6 +1037,7 @@ uint64_t cx_carve(const Grid &g, uint64_t n, char *base, CxDev *out)
     d.c_iter = (int32_t *)take(nn * 4);
     d.c_id = (uint32_t *)take(nn * 4);
     d.c_rho2 = (double *)take(nn * 8);
+    d.c_qb = (int32_t *)take(nn * 4);
     d.rs_hist = (uint32_t *)take(resolved_scratch_words(nn) * 4);
     d.kA = (uint32_t *)take(nn * 4);
     d.vA = (int32_t *)take(nn * 4);

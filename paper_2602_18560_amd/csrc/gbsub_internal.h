@@ -258,6 +258,7 @@ struct CxDev {
     int32_t *c_iter;         // [n] loop body that subtracted it, -1 while unresolved
     uint32_t *c_id;          // [n] its id (written at the end of a run)
     double *c_rho2;          // [n] rho^2 at the last evaluation
+    int32_t *c_qb;           // [n] its template's centre bin (the SNR pass's dirty-tile test)
     uint32_t *rs_hist;       // resolved-list scratch
     uint32_t *kA, *kB;       // [n] each: resolved-list keys
     int32_t *vA, *vB;        // [n] each: resolved-list values
