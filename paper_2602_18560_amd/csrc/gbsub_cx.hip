@@ -776,7 +776,6 @@ __global__ __launch_bounds__(WG) void k_cx_snr(KArgs a)
     const CxIn &in = a.in;
     Ctl *c = d.ctl;
     set_cis_table(ex);
-    const LaneFft L = lane_fft();
     __syncthreads();
     if (c->done || c->bad) return;
     const uint32_t t = c->iter, nxt = t + 1;
@@ -805,6 +804,10 @@ __global__ __launch_bounds__(WG) void k_cx_snr(KArgs a)
         SrcConsts mine{};
         if (need) mine = src_consts(g, in, d.c_src[j], E, false);
         uint64_t todo = (uint64_t)__ballot(need);
+        if (!todo) continue;
+        // the FFT's lane constants only for waves with evaluations (in late
+        // bodies most have none)
+        const LaneFft L = lane_fft();
         while (todo) {
             const int k = (int)__builtin_ctzll(todo);
             todo &= todo - 1;
