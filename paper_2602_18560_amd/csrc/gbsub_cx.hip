@@ -63,7 +63,7 @@ constexpr int NF = CX_NF;
 constexpr int HALO = NF / 2;                  // template reach on each side of its centre
 constexpr int CXW = CX_TILE + NF;             // LDS window of an injection block
 constexpr int SRC_PB = 4096;                  // sources per block of the count and scatter passes
-constexpr int CH = 4096;                      // sources per injection block at most
+constexpr int CH = 8192;                      // sources per injection block at most
 constexpr int SNR_GRID = 2048;                // blocks of the SNR launch
 constexpr int PLAN_T = 1024;                  // threads of the one-block plan
 
