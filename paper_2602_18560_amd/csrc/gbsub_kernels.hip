@@ -1687,48 +1687,39 @@ DEVI void median_work(MedianSmem &sm, const Slot *slp, int blk, int span)
         }
 
         // ---- median of each window: the h-th smallest rank (0-based) among
-        // positions [a, a + W) of the union.  The levels give its bucket and
-        // its index among the window's elements in the bucket; the bucket's
-        // 32 sorted elements are then tested against the window.
+        // positions [a, a + W) of the union.  A thread's first window: the
+        // levels give its bucket and its index among the window's elements
+        // in the bucket; the bucket's 32 sorted elements are then tested
+        // against the window.  Each next window of the thread is the
+        // previous one moved by one position (or the same one, at a grid
+        // edge): one element leaves, one enters, and the median stays or
+        // becomes the nearest element above or below it in sorted order
+        // whose position lies in the new window, found by walking the
+        // sorted words (at most SLIDE_MAX steps, else the levels again).
+        // The sorted order is (fp64 value, position) in lexicographic
+        // order, so comparisons with the median need no ranks.
         auto rank0 = [&](int lvl, int x) -> int {      // zeros among positions < x
             const WWord e = sm.u.wm.w[lvl][x >> 6];
             const uint64_t m = ~e.bits & ((1ull << (x & 63)) - 1ull);
             return (int)e.zpre + __popcll(m);
         };
-        int qa[RMAX], qlo[RMAX], qhi[RMAX], qk[RMAX];
-        uint32_t qr[RMAX];
-#pragma unroll
-        for (int r = 0; r < RMAX; ++r) {
-            const int k = min(kb + r, ke - 1);          // past the run: repeat its last window
-            const int a = kb < ke ? win_start(k, B, W, h) - u0 : 0;
-            qa[r] = a;
-            qlo[r] = a;
-            qhi[r] = a + W;
-            qk[r] = h;
-            qr[r] = 0;
-        }
-        for (int lvl = LB - 1; lvl >= WB; --lvl) {
-            const int Z = (int)sm.u.wm.zt[lvl];
-#pragma unroll
-            for (int r = 0; r < RMAX; ++r) {
-                if (r >= R) break;                      // R is the same for the whole block
-                const int zl = rank0(lvl, qlo[r]), zh = rank0(lvl, qhi[r]);
+        auto query = [&](int a) -> int {               // sorted index of the median of [a, a + W)
+            int lo = a, hi = a + W, kk = h, base = 0;
+            for (int lvl = LB - 1; lvl >= WB; --lvl) {
+                const int Z = (int)sm.u.wm.zt[lvl];
+                const int zl = rank0(lvl, lo), zh = rank0(lvl, hi);
                 const int zeros = zh - zl;
-                if (qk[r] < zeros) {
-                    qlo[r] = zl;
-                    qhi[r] = zh;
+                if (kk < zeros) {
+                    lo = zl;
+                    hi = zh;
                 } else {
-                    qk[r] -= zeros;
-                    qlo[r] = Z + qlo[r] - zl;
-                    qhi[r] = Z + qhi[r] - zh;
-                    qr[r] |= 1u << lvl;
+                    kk -= zeros;
+                    lo = Z + lo - zl;
+                    hi = Z + hi - zh;
+                    base |= 1 << lvl;
                 }
             }
-        }
-#pragma unroll
-        for (int r = 0; r < RMAX; ++r) {
-            if (r >= R) break;
-            const int base = (int)qr[r];                // first rank of the bucket (MMAX is a multiple of 32)
+            // base: first rank of the bucket (MMAX is a multiple of 32)
             uint32_t mask = 0;
 #pragma unroll
             for (int i0 = 0; i0 < 32; i0 += 4) {
@@ -1736,25 +1727,69 @@ DEVI void median_work(MedianSmem &sm, const Slot *slp, int blk, int span)
                 const uint32_t qq[4] = {q4.x, q4.y, q4.z, q4.w};
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
-                    const bool act = base + i0 + c < M && (qq[c] & 0xFFFu) - (uint32_t)qa[r] < (uint32_t)W;
+                    const bool act = base + i0 + c < M && (qq[c] & 0xFFFu) - (uint32_t)a < (uint32_t)W;
                     mask |= (uint32_t)act << (i0 + c);
                 }
             }
-            // position of the (qk+1)-th set bit
-            int k = qk[r], pos = 0;
+            // position of the (kk+1)-th set bit
+            int pos = 0;
 #pragma unroll
             for (int wdt = 16; wdt >= 1; wdt >>= 1) {
                 const int c = __popc(mask & ((1u << wdt) - 1u));
-                if (k >= c) {
-                    k -= c;
+                if (kk >= c) {
+                    kk -= c;
                     mask >>= wdt;
                     pos += wdt;
                 }
             }
-            qr[r] = (uint32_t)(base + pos);
+            return base + pos;
+        };
+        // (value bits, position) of union position p before that of q
+        auto before = [&](int p, int q) -> bool {
+            const uint64_t bp = (uint64_t)__double_as_longlong(sm.xv[p]);
+            const uint64_t bq = (uint64_t)__double_as_longlong(sm.xv[q]);
+            return bp < bq || (bp == bq && p < q);
+        };
+        constexpr int SLIDE_MAX = 32;
+        int qm[RMAX];
+        int ap = kb < ke ? win_start(min(kb, ke - 1), B, W, h) - u0 : 0;
+        qm[0] = query(ap);
+#pragma unroll
+        for (int r = 1; r < RMAX; ++r) {
+            if (r >= R) break;                          // R is the same for the whole block
+            const int k = min(kb + r, ke - 1);          // past the run: repeat its last window
+            const int a = kb < ke ? win_start(k, B, W, h) - u0 : 0;
+            int m = qm[r - 1];
+            if (a != ap) {                              // a == ap + 1: ap leaves, ap + W enters
+                const int pm = (int)(sw[m] & 0xFFFu);
+                const int po = ap, pi = ap + W;
+                int dir = 0;                            // +1: the next element above; -1: below
+                if (po == pm) {
+                    dir = before(pi, pm) ? -1 : 1;
+                } else {
+                    const bool ob = before(po, pm), ib = before(pi, pm);
+                    if (ob != ib) dir = ob ? 1 : -1;
+                }
+                if (dir != 0) {
+                    // an element on that side lies in the new window (the one
+                    // that entered, or the one below or above that took the
+                    // median's place), so the walk stays inside [0, M)
+                    int c = m, found = -1;
+                    for (int st = 0; st < SLIDE_MAX; ++st) {
+                        c += dir;
+                        if ((sw[c] & 0xFFFu) - (uint32_t)a < (uint32_t)W) {
+                            found = c;
+                            break;
+                        }
+                    }
+                    m = found >= 0 ? found : query(a);
+                }
+            }
+            qm[r] = m;
+            ap = a;
         }
 #pragma unroll
-        for (int r = 0; r < RMAX; ++r) med[r] = (kb + r < ke) ? sm.xv[sw[qr[r]] & 0xFFFu] : 0.0;
+        for (int r = 0; r < RMAX; ++r) med[r] = (kb + r < ke && r < R) ? sm.xv[sw[qm[r]] & 0xFFFu] : 0.0;
     }
 
     // ---- S = C med + S_instr; in-tile prefix of 1/S and the tile sum.  The
